@@ -1,0 +1,99 @@
+"""Congestion metrics, fitness, descriptor cell and elite archive (oracle; test
+infrastructure only).  FP64, written straight from the definitions."""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+
+def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
+               n1: Optional[np.ndarray] = None, island: Optional[np.ndarray] = None) -> dict:
+    """Fitness function heuristics section: with f^max_e = max over outages of
+    |f^(o)_e| and the clip Pi(x) = max(x, 0),
+
+      lambda_o  = sum_e Pi(f^max_e - fbar_e)      (N-1 overload energy)
+      lambda_c  = sum_e 1(f^max_e > fbar_e)       (N-1 critical branches, strict)
+      lambda_c0 = sum_e 1(|f^n0_e| > fbar_e)      (N-0 critical branches, strict)
+
+    Multi-timestep reading: sums run over timesteps as well; the maximum
+    loading rho = max_{e,t} f^max_e(t) / fbar_e.  The arg-max (e*, t*, l*) is the
+    lexicographically smallest index triple attaining max |f^(l)_e(t)| / fbar_e.
+
+    fmax, f0: [|M|, T]; limit: [|M|]; n1: [|C|, |M|, T] (NaN for skipped l).
+    """
+    lim = limit[:, None]
+    over = np.maximum(fmax - lim, 0.0)
+    res = {
+        "overload_mw": float(over.sum()),
+        "n_crit_n1": int((fmax > lim).sum()),
+        "n_crit_n0": int((np.abs(f0) > lim).sum()),
+    }
+    ratio = fmax / lim
+    res["max_loading"] = float(ratio.max()) if ratio.size else 0.0
+    res["worst"] = None
+    if n1 is not None and ratio.size:
+        # smallest (e, t) attaining the maximum ratio
+        best = res["max_loading"]
+        E, T = ratio.shape
+        found = None
+        for e in range(E):
+            for t in range(T):
+                if ratio[e, t] == best:
+                    found = (e, t)
+                    break
+            if found is not None:
+                break
+        e, t = found
+        col = np.abs(n1[:, e, t])
+        col = np.where(np.isnan(col), -np.inf, col)
+        if island is not None:
+            col = np.where(island, -np.inf, col)
+        l_best = None
+        if np.isfinite(col).any():
+            top = col.max()
+            l_best = int(np.flatnonzero(col == top)[0])
+        res["worst"] = (e, t, l_best if l_best is not None else -1)
+    return res
+
+
+def fitness_f1(overload_mw: float, n_crit_n0: int, n_crit_n1: int,
+               w_c0: float = 200.0, w_c: float = 50.0) -> float:
+    """High-level loop section: lambda_f1 = -(lambda_o + 200 lambda_c0 + 50 lambda_c),
+    maximised."""
+    return -(overload_mw + w_c0 * n_crit_n0 + w_c * n_crit_n1)
+
+
+def descriptor_cell(n_switched: int, max_loading: float, load_edges: np.ndarray,
+                    n_count_bins: int = 32) -> int:
+    """Two-axis MapElites cell: (number of switched elements, max-loading bin).
+
+    count axis: min(k + s, n_count_bins - 1) (each opening and each split counts 1);
+    load axis:  number of edges <= rho (edges ascending), so n_load_bins =
+                len(load_edges) + 1 bins with clamping at both ends.
+    """
+    n_load_bins = len(load_edges) + 1
+    count = min(int(n_switched), n_count_bins - 1)
+    b = 0
+    for edge in load_edges:
+        if edge <= max_loading:
+            b += 1
+    return count * n_load_bins + b
+
+
+def archive_insert_sequential(best_fit: np.ndarray, best_id: np.ndarray, fitness, cells,
+                              ok, id_base: int = 0):
+    """Unbatched insertion (High-level loop): candidates are offered one at a time
+    in batch order; each cell keeps one elite, replaced only by a strictly
+    better fitness.  Empty cells have best_id == -1.  Islanded or invalid
+    candidates (ok == False) never enter."""
+    best_fit = np.array(best_fit, dtype=np.float64, copy=True)
+    best_id = np.array(best_id, dtype=np.int64, copy=True)
+    for i in range(len(fitness)):
+        if not ok[i]:
+            continue
+        c = int(cells[i])
+        if best_id[c] == -1 or fitness[i] > best_fit[c]:
+            best_fit[c] = fitness[i]
+            best_id[c] = id_base + i
+    return best_fit, best_id

@@ -1,0 +1,374 @@
+"""Pins for the FP64 oracle: every check compares it with something that does
+not come from the oracle (closed forms, Kirchhoff's laws, independent graph
+search, the textbook distribution-factor formulas, hand-worked fixtures)."""
+import itertools
+import json
+import os
+from collections import deque
+
+import numpy as np
+import pytest
+
+import gridgen as gg
+import oracle as o
+from oracle.dcflow import Candidate
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _flows(grid, P, in_service=None, slack=0):
+    b = 1.0 / grid.x_pu
+    ins = np.ones(grid.n_branch, bool) if in_service is None else in_service
+    return o.solve_flows(grid.n_bus, grid.from_bus, grid.to_bus, b, ins, P, slack)
+
+
+def _bfs_component(n, fr, to, in_service, start):
+    adj = [[] for _ in range(n)]
+    for e in range(len(fr)):
+        if in_service[e]:
+            adj[fr[e]].append(to[e])
+            adj[to[e]].append(fr[e])
+    seen = {start}
+    q = deque([start])
+    while q:
+        u = q.popleft()
+        for v in adj[u]:
+            if v not in seen:
+                seen.add(v)
+                q.append(v)
+    return seen
+
+
+def _balanced(rng, n, T=1, slack=0):
+    P = rng.normal(0, 40, size=(n, T))
+    P[slack] = 0.0
+    P[slack] = -P.sum(axis=0)
+    return P
+
+
+# --------------------------------------------------------------------- flows
+def test_radial_flows_equal_downstream_sums():
+    """Tree grid: the flow on a branch is the injection sum beyond it (KCL on a cut)."""
+    rng = np.random.default_rng(1)
+    grid = gg.make_grid(25, 24, seed=11)
+    P = _balanced(rng, grid.n_bus, T=3)
+    f = _flows(grid, P)
+    for e in range(grid.n_branch):
+        ins = np.ones(grid.n_branch, bool)
+        ins[e] = False
+        slack_side = _bfs_component(grid.n_bus, grid.from_bus, grid.to_bus, ins, grid.slack)
+        down = [i for i in range(grid.n_bus) if i not in slack_side]
+        s = P[down].sum(axis=0)
+        expect = -s if grid.to_bus[e] in down else s   # into the downstream side
+        np.testing.assert_allclose(f[e], expect, rtol=1e-10, atol=1e-9)
+
+
+def test_kcl_at_every_bus():
+    rng = np.random.default_rng(2)
+    grid = gg.make_grid(60, 95, seed=12)
+    P = _balanced(rng, grid.n_bus, T=2)
+    f = _flows(grid, P)
+    net = np.zeros_like(P)
+    np.add.at(net, grid.from_bus, f)
+    np.add.at(net, grid.to_bus, -f)
+    np.testing.assert_allclose(net, P, atol=1e-9)
+
+
+def test_loop_law_on_every_chord():
+    """DC voltage law: sum of x_e f_e around each fundamental cycle is zero."""
+    rng = np.random.default_rng(3)
+    grid = gg.make_grid(40, 70, seed=13)
+    P = _balanced(rng, grid.n_bus)
+    f = _flows(grid, P)[:, 0]
+    # BFS spanning tree
+    adj = [[] for _ in range(grid.n_bus)]
+    for e in range(grid.n_branch):
+        adj[grid.from_bus[e]].append((grid.to_bus[e], e, +1))
+        adj[grid.to_bus[e]].append((grid.from_bus[e], e, -1))
+    parent = {0: None}
+    q = deque([0])
+    tree = set()
+    while q:
+        u = q.popleft()
+        for v, e, sgn in adj[u]:
+            if v not in parent:
+                parent[v] = (u, e, sgn)
+                tree.add(e)
+                q.append(v)
+
+    def drop(u):   # angle drop from the root to u as sum of x*f along tree edges
+        s = 0.0
+        while parent[u] is not None:
+            p, e, sgn = parent[u]
+            s += sgn * grid.x_pu[e] * f[e]        # theta_p - theta_u
+            u = p
+        return s
+
+    for e in range(grid.n_branch):
+        if e in tree:
+            continue
+        a, b = grid.from_bus[e], grid.to_bus[e]
+        # theta_a - theta_b = drop(b) - drop(a) must equal x_e f_e
+        assert abs((drop(b) - drop(a)) - grid.x_pu[e] * f[e]) < 1e-9
+
+
+def test_parallel_line_current_divider():
+    x1, x2 = 0.1, 0.3
+    P = np.array([[-100.0], [100.0]])
+    f = o.solve_flows(2, [1, 1], [0, 0], [1 / x1, 1 / x2], np.ones(2, bool), P, 0)
+    np.testing.assert_allclose(f[:, 0], [100 * x2 / (x1 + x2), 100 * x1 / (x1 + x2)], rtol=1e-12)
+
+
+def test_superposition_and_slack_invariance():
+    rng = np.random.default_rng(4)
+    grid = gg.make_grid(50, 80, seed=14)
+    P, Q = _balanced(rng, 50), _balanced(rng, 50)
+    fa, fb = _flows(grid, P), _flows(grid, Q)
+    np.testing.assert_allclose(_flows(grid, 2.5 * P - 0.5 * Q), 2.5 * fa - 0.5 * fb, atol=1e-9)
+    # balanced injections: flows do not depend on which bus is the angle reference
+    np.testing.assert_allclose(_flows(grid, P, slack=17), fa, atol=1e-9)
+
+
+# ---------------------------------------------------------------- islanding
+def test_islanding_tree_and_cycle():
+    tree = gg.make_grid(10, 9, seed=5)
+    for e in range(9):
+        ins = np.ones(9, bool)
+        ins[e] = False
+        assert not o.is_connected(10, tree.from_bus, tree.to_bus, ins)
+    n = 8
+    fr, to = np.arange(n), (np.arange(n) + 1) % n
+    for e in range(n):
+        ins = np.ones(n, bool)
+        ins[e] = False
+        assert o.is_connected(n, fr, to, ins)
+    for e1, e2 in itertools.combinations(range(n), 2):
+        ins = np.ones(n, bool)
+        ins[[e1, e2]] = False
+        assert not o.is_connected(n, fr, to, ins)
+
+
+def test_islanding_exhaustive_two_branch_outages_30bus():
+    """All C(41,2) + 41 + 1 opening sets on the 30-bus grid versus an independent BFS."""
+    grid = gg.make_grid(30, 41, 0x5EED0001)
+    P = gg.make_injections(grid, 1, 0x5EED0002)
+    m = grid.n_branch
+    edges = gg.default_load_edges()
+    sets = [()] + [(e,) for e in range(m)] + list(itertools.combinations(range(m), 2))
+    for K in sets:
+        ins = np.ones(m, bool)
+        ins[list(K)] = False
+        bfs = len(_bfs_component(30, grid.from_bus, grid.to_bus, ins, 0)) == 30
+        cand = Candidate(opened=list(K), splits=[], moved_p=[], n_slots_filled=len(K))
+        res = o.evaluate_candidate(grid, P, [0], [0], cand, edges, keep_n1=False)
+        assert res.islanded == (not bfs), K
+
+
+def test_island_contingencies_are_post_switch_bridges():
+    """Skipped contingencies are exactly the bridges of the post-switch graph
+    (Tarjan's algorithm from the input generator, an independent routine)."""
+    w = gg.build_config(2, B=6, move_frac=0.5)
+    edges = gg.default_load_edges()
+    for c in range(6):
+        cand = o.candidate_from_batch(w.batch, c)
+        res = o.evaluate_candidate(w.grid, w.P, w.M, w.C, cand, edges, keep_n1=False)
+        if res.islanded or not res.valid:
+            continue
+        net = o.post_switch_network(w.grid.n_bus, w.grid.from_bus, w.grid.to_bus,
+                                    1 / w.grid.x_pu, 0, w.P, cand)
+        br = gg.bridges(net.n_node, net.fr, net.to, net.in_service)
+        expect = br[w.C] & net.in_service[w.C]
+        np.testing.assert_array_equal(res.island_cont, expect)
+
+
+# ------------------------------------------------- outages versus closed form
+def _dense_ptdf(grid):
+    n, m = grid.n_bus, grid.n_branch
+    A = np.zeros((m, n))
+    A[np.arange(m), grid.from_bus] = 1.0
+    A[np.arange(m), grid.to_bus] = -1.0
+    b = 1.0 / grid.x_pu
+    L = A.T @ (b[:, None] * A)
+    Linv = np.zeros((n, n))
+    keep = np.arange(n) != grid.slack
+    Linv[np.ix_(keep, keep)] = np.linalg.inv(L[np.ix_(keep, keep)])
+    ptdf = b[:, None] * (A @ Linv)
+    return ptdf, ptdf @ A.T
+
+
+def test_lodf_identity_single_outages():
+    """Re-solved N-1 flows equal f + H_{:,l} f_l / (1 - H_ll) (line outage
+    distribution factors built from a dense inverse)."""
+    w = gg.build_config(1)
+    grid, P = w.grid, w.P
+    _, H = _dense_ptdf(grid)
+    f0 = _flows(grid, P)
+    nb = gg.bridges(grid.n_bus, grid.from_bus, grid.to_bus)
+    edges = gg.default_load_edges()
+    cand = Candidate(opened=[], splits=[], moved_p=[], n_slots_filled=0)
+    res = o.evaluate_candidate(grid, P, np.arange(grid.n_branch), np.arange(grid.n_branch),
+                               cand, edges)
+    for l in range(grid.n_branch):
+        if nb[l]:
+            assert res.island_cont[l]
+            continue
+        expect = f0[:, 0] + H[:, l] * f0[l, 0] / (1.0 - H[l, l])
+        expect[l] = 0.0
+        np.testing.assert_allclose(res.n1_flows[l][:, 0], expect, atol=1e-8)
+
+
+def test_multi_outage_woodbury_identity():
+    """Opening a set K: f' = f + H_{:,K} (I - H_KK)^{-1} f_K, zero on K."""
+    w = gg.build_config(1)
+    grid, P = w.grid, w.P
+    _, H = _dense_ptdf(grid)
+    f0 = _flows(grid, P)[:, 0]
+    edges = gg.default_load_edges()
+    rng = np.random.default_rng(9)
+    nb = np.flatnonzero(~gg.bridges(grid.n_bus, grid.from_bus, grid.to_bus))
+    for _ in range(20):
+        K = sorted(rng.choice(nb, size=3, replace=False).tolist())
+        cand = Candidate(opened=K, splits=[], moved_p=[], n_slots_filled=3)
+        res = o.evaluate_candidate(grid, P, [0], [0], cand, edges, keep_n1=False)
+        M_ = np.eye(3) - H[np.ix_(K, K)]
+        if abs(np.linalg.det(M_)) < 1e-10:
+            assert res.islanded
+            continue
+        expect = f0 + H[:, K] @ np.linalg.solve(M_, f0[K])
+        expect[K] = 0.0
+        np.testing.assert_allclose(res.base_flows[:, 0], expect, atol=1e-8)
+
+
+# -------------------------------------------------------------------- splits
+def test_split_moving_one_branch_equals_its_outage():
+    w = gg.build_config(2, B=1)
+    grid, P = w.grid, w.P
+    inc = grid.incident()
+    rng = np.random.default_rng(5)
+    nb = ~gg.bridges(grid.n_bus, grid.from_bus, grid.to_bus)
+    for _ in range(10):
+        bus = int(rng.integers(0, grid.n_bus))
+        cand_br = [e for e in inc[bus] if nb[e]]
+        if len(inc[bus]) < 2 or not cand_br:
+            continue
+        e = int(rng.choice(cand_br))
+        split = Candidate(opened=[], splits=[(bus, [e])], moved_p=[None], n_slots_filled=1)
+        net = o.post_switch_network(grid.n_bus, grid.from_bus, grid.to_bus, 1 / grid.x_pu, 0, P, split)
+        fs = o.solve_flows(net.n_node, net.fr, net.to, net.b, net.in_service, net.P, 0)
+        ins = np.ones(grid.n_branch, bool)
+        ins[e] = False
+        fo = _flows(grid, P, ins)
+        np.testing.assert_allclose(fs, fo, atol=1e-8)
+
+
+def test_split_moving_everything_is_a_relabel():
+    w = gg.build_config(2, B=1)
+    grid, P = w.grid, w.P
+    inc = grid.incident()
+    f0 = _flows(grid, P)
+    for bus in [5, 77, 123, 400]:
+        cand = Candidate(opened=[], splits=[(bus, list(inc[bus]))], moved_p=[P[bus].copy()],
+                         n_slots_filled=1)
+        net = o.post_switch_network(grid.n_bus, grid.from_bus, grid.to_bus, 1 / grid.x_pu, 0, P, cand)
+        # busbar A is left empty: the graph has an isolated node -> islanded by definition
+        assert not o.is_connected(net.n_node, net.fr, net.to, net.in_service)
+        keep = np.ones(net.n_node, bool)
+        keep[bus] = False
+        relabel = -np.ones(net.n_node, int)
+        relabel[keep] = np.arange(net.n_node - 1)
+        fs = o.solve_flows(net.n_node - 1, relabel[net.fr], relabel[net.to], net.b, net.in_service,
+                           net.P[keep], 0)
+        np.testing.assert_allclose(fs, f0, atol=1e-8)
+
+
+def test_split_square_closed_form():
+    g = json.load(open(os.path.join(GOLDEN, "split_square.json")))
+    grid = gg.Grid(n_bus=g["n_bus"], from_bus=np.array(g["from"], np.int32),
+                   to_bus=np.array(g["to"], np.int32), x_pu=np.array(g["x"]),
+                   limit_mw=np.full(4, 100.0))
+    P = np.array(g["P"])[:, None]
+    cand = Candidate(opened=[], splits=[(g["split_bus"], g["moved"])], moved_p=[None],
+                     n_slots_filled=1)
+    res = o.evaluate_candidate(grid, P, [0, 1, 2, 3], [0, 1, 2, 3], cand,
+                               gg.default_load_edges(), keep_n1=True)
+    assert res.valid and not res.islanded
+    np.testing.assert_allclose(res.base_flows[:, 0], g["expected_flows"], atol=1e-10)
+    # the path has only bridges left: every contingency islands except opening
+    # branch 3, which already carries nothing (its loss isolates busbar B)
+    assert res.island_cont.all()
+
+
+def test_moved_injection_changes_only_through_kcl():
+    """Split with a moved injection: KCL holds at both busbars of the split bus."""
+    w = gg.build_config(2, B=20, move_frac=1.0)
+    edges = gg.default_load_edges()
+    for c in range(20):
+        cand = o.candidate_from_batch(w.batch, c)
+        if not cand.splits:
+            continue
+        net = o.post_switch_network(w.grid.n_bus, w.grid.from_bus, w.grid.to_bus,
+                                    1 / w.grid.x_pu, 0, w.P, cand)
+        if not o.is_connected(net.n_node, net.fr, net.to, net.in_service):
+            continue
+        f = o.solve_flows(net.n_node, net.fr, net.to, net.b, net.in_service, net.P, 0)
+        bal = np.zeros_like(net.P)
+        np.add.at(bal, net.fr, f)
+        np.add.at(bal, net.to, -f)
+        np.testing.assert_allclose(bal, net.P, atol=1e-8)
+        return
+    pytest.fail("no usable split candidate drawn")
+
+
+# ------------------------------------------------------ metrics and archive
+def test_metrics_hand_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "metrics_example.json")))
+    fmax, f0, lim = np.array(g["fmax"]), np.array(g["f0"]), np.array(g["limit"])
+    met = o.n1_metrics(fmax, f0, lim)
+    ex = g["expected"]
+    assert met["overload_mw"] == pytest.approx(ex["overload_mw"], abs=1e-12)
+    assert met["n_crit_n1"] == ex["n_crit_n1"]
+    assert met["n_crit_n0"] == ex["n_crit_n0"]
+    assert met["max_loading"] == pytest.approx(ex["max_loading"], abs=1e-12)
+    fit = o.fitness_f1(met["overload_mw"], met["n_crit_n0"], met["n_crit_n1"])
+    assert fit == pytest.approx(ex["fitness_f1"], abs=1e-12)
+    n1 = np.stack([np.zeros_like(fmax), fmax])   # contingency 1 attains fmax
+    met2 = o.n1_metrics(fmax, f0, lim, n1)
+    assert met2["worst"] == (ex["worst_e"], ex["worst_t"], 1)
+
+
+def test_descriptor_cell_edges_and_bijection():
+    edges = np.array([0.5, 1.0, 1.5])
+    assert o.descriptor_cell(0, 0.0, edges, 4) == 0
+    assert o.descriptor_cell(0, 0.5, edges, 4) == 1          # on an edge: upper bin
+    assert o.descriptor_cell(0, 0.4999, edges, 4) == 0
+    assert o.descriptor_cell(1, 9.0, edges, 4) == 1 * 4 + 3   # clamps high
+    assert o.descriptor_cell(99, 1.2, edges, 4) == 3 * 4 + 2  # count clamps to n-1
+    e32 = gg.default_load_edges()
+    seen = set()
+    for k in range(32):
+        for bi in range(32):
+            rho = 0.0 if bi == 0 else e32[bi - 1]
+            seen.add(o.descriptor_cell(k, rho, e32, 32))
+    assert seen == set(range(1024))
+
+
+def test_archive_strict_and_order_invariant():
+    rng = np.random.default_rng(7)
+    B, cells = 300, 16
+    fit = rng.integers(-20, 0, size=B).astype(float)   # many exact ties
+    cell = rng.integers(0, cells, size=B)
+    ok = rng.random(B) > 0.1
+    bf0, bi0 = np.full(cells, -np.inf), np.full(cells, -1, np.int64)
+    bf, bi = o.archive_insert_sequential(bf0, bi0, fit, cell, ok)
+    for c in range(cells):
+        sel = np.flatnonzero((cell == c) & ok)
+        if len(sel) == 0:
+            assert bi[c] == -1
+            continue
+        best = fit[sel].max()
+        assert bf[c] == best and bi[c] == sel[fit[sel] == best][0]   # earliest among ties
+    # offering the same batch again never replaces (strict improvement only)
+    bf2, bi2 = o.archive_insert_sequential(bf, bi, fit, cell, ok, id_base=1000)
+    np.testing.assert_array_equal(bi2, bi)
+    # islanded / invalid candidates never enter
+    assert not np.isin(bi[bi >= 0], np.flatnonzero(~ok)).any()
