@@ -1,0 +1,190 @@
+"""Throughput of the batched DC N-1 topology screen on one MI355X.
+
+One step = one tto_evaluate over the whole candidate batch (set-up, N-1 sweep
+with fused reductions, finalize) plus the archive update, inputs resident in
+HBM.  Default workload: 2000-bus / 3200-branch grid, 24 timesteps, 16384
+candidates of rank 0..8, 1200 monitored x 1600 contingencies, FP32 flows.
+
+Prints one JSON line (see the design notes for the roofline definition).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N-1-evaluated topologies/sec, 2000-bus grid; surrogate-screened vs exact"
+# MI355X: 256 CUs x 64 VALU lanes x 2.4 GHz (non-packed issue rate)
+VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_alg_ops(T, n_mon, n_act, rank):
+    """Minimal VALU lane-instructions of the N-1 sweep for one candidate:
+    per (e, l, t) one FMA and half of a 3-input max (two flows per max), per
+    (e, l) one FMA per rank for H'_el."""
+    return n_mon * n_act * (1.5 * T + rank)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("k_eval.hip", "tto_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2605_10128_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(w, seconds_target=20.0):
+    """Time the oracle as it stands on a bounded sample of the same workload."""
+    import numpy as np
+    import gridgen as gg
+    import oracle
+    cores = min(16, os.cpu_count() or 1)
+    nC = len(w.C)
+    # one candidate per worker, a slice of its contingencies (a few seconds each)
+    n_cont = max(8, min(nC, int(nC * 0.25)))
+    idx = list(range(cores))
+    subset = list(range(n_cont))
+    t0 = time.perf_counter()
+    oracle.evaluate_batch(w.grid, w.P, w.M, w.C, w.batch, gg.default_load_edges(), idx=idx,
+                          processes=cores, keep_n1=False, cont_subset=subset)
+    dt = time.perf_counter() - t0
+    topo_equiv = cores * (n_cont + 1) / (nC + 1)   # N-0 plus the sampled contingency solves
+    return {"value": topo_equiv / dt, "unit": "topologies/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} candidates x {n_cont} of {nC} contingencies (+N-0), "
+                      f"{cores} processes, {dt:.1f} s wall; scaled by (n_cont+1)/(|C|+1)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--flow", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(candidates shard along the batch; see the design notes)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import gridgen as gg
+    from paper_2605_10128_amd import tto
+    from paper_2605_10128_amd.ptdf import build_ptdf
+
+    torch.cuda.set_device(0)
+    spec = gg.CONFIGS[args.config]
+    t0 = time.perf_counter()
+    w = gg.build_config(args.config, B=args.batch)
+    B = w.batch.n_cand
+    log(f"[bench] workload cfg{args.config} B={B} built in {time.perf_counter() - t0:.1f}s")
+    g = w.grid
+    b = 1.0 / g.x_pu
+    ptdf = build_ptdf(g.n_bus, g.from_bus, g.to_bus, b)
+    flow = tto.TTO_FLOW_F32 if args.flow == "f32" else tto.TTO_FLOW_F64
+    gemm = tto.TTO_GEMM_F32 if args.flow == "f32" else tto.TTO_GEMM_F64
+    s = tto.Session(g.n_bus, g.from_bus, g.to_bus, b, g.limit_mw, ptdf, w.M, w.C, w.P.shape[1],
+                    flow_precision=flow, gemm_precision=gemm, max_batch=B)
+    s.set_injections(w.P)
+    s.set_descriptor(gg.default_load_edges())
+    db = tto.device_batch(w.batch)
+    out = s.alloc_outputs(B)
+    arch = s.new_archive()
+    stream = torch.cuda.current_stream()
+    log(f"[bench] grid ready; ws grid {s.grid_bytes/2**30:.2f} GiB batch {s.batch_bytes/2**30:.2f} GiB")
+
+    for i in range(args.warmup):
+        s.evaluate(db, out)
+        s.archive_insert(arch, out, id_base=i * B)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+
+    tto.tto_profile_enable(s.handle, True)
+    sweep_ms, setup_ms, fin_ms = [], [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(args.steps):
+        s.evaluate(db, out)
+        s.archive_insert(arch, out, id_base=(args.warmup + i) * B)
+        ms = tto.tto_profile_read(s.handle)   # waits for this step's events only
+        setup_ms.append(ms[0]); sweep_ms.append(ms[1]); fin_ms.append(ms[2])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    tto.tto_profile_enable(s.handle, False)
+    ms_step = total_ms / args.steps
+    value = B * args.steps / (total_ms / 1e3)
+    log(f"[bench] {ms_step:.3f} ms/step, {value:,.0f} topologies/s; stage ms "
+        f"setup {np.mean(setup_ms):.3f} sweep {np.mean(sweep_ms):.3f} fin {np.mean(fin_ms):.3f}")
+
+    o = {k: v.cpu().numpy() for k, v in out.items()}
+    ok = (o["status"] & 3) == 0
+    r = (w.batch.open != -1).sum(1) + (w.batch.split_bus != -1).sum(1)
+    n_act = len(w.C) - o["n_island_cont"]
+    T = w.P.shape[1]
+    ops = float(sum(sweep_alg_ops(T, len(w.M), int(n_act[c]), int(r[c]))
+                    for c in range(B) if ok[c]))
+    sweep_s = float(np.mean(sweep_ms)) / 1e3
+    achieved = ops / sweep_s / 1e12
+    traffic = None
+    cpath = os.path.join(ROOT, "profiles", f"sweep_cfg{args.config}_{args.flow}_counters.json")
+    if os.path.exists(cpath):
+        cj = json.load(open(cpath))
+        if cj.get("kernel_hash") == kernel_hash():
+            traffic = cj.get("hbm_bytes_per_launch")
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "topologies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.flow == "f32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{spec['name']}: n={g.n_bus}, m={g.n_branch}, T={T}, B={B}, "
+                        f"|M|={len(w.M)}, |C|={len(w.C)}, rank 0..8 (exact evaluation)",
+            "flow_precision": args.flow,
+            "candidates_ok": int(ok.sum()),
+            "islanded": int(((o["status"] & 1) != 0).sum()),
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_sweep",
+            "achieved": achieved,
+            "peak": VALU_PEAK_T,
+            "unit": "T VALU-instr/s",
+            "frac": achieved / VALU_PEAK_T,
+            "traffic": traffic,
+            "sweep_ms": float(np.mean(sweep_ms)),
+            "setup_ms": float(np.mean(setup_ms)),
+            "finalize_ms": float(np.mean(fin_ms)),
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample)")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

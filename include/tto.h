@@ -1,0 +1,276 @@
+/*
+ * tto.h - C ABI of the MI355X (gfx950) batched DC N-1 topology screen.
+ *
+ * The library scores batches of candidate grid topologies the way the
+ * DC-Optimizer of "Transmission Topology Optimization using accelerated
+ * MapElites" does inside its MapElites loop (Alg. 3 "Accelerated MapElites
+ * for TTO": compute N-1 DC loadflows, then lambda and beta, for a batch of new
+ * individuals, then insert into the repertoire):
+ *
+ *   grid PTDF + nodal injections in; candidate branch openings and bus splits
+ *   in; per-candidate base flows, N-1 flow maxima, overload metrics, fitness
+ *   and MapElites descriptor cell out; per-cell elites updated on device.
+ *
+ * Conventions (all entry points):
+ *   - Plain C types only.  "device" pointers point to GPU memory of the
+ *     current HIP device; "host" pointers to CPU memory.
+ *   - Every device buffer is owned by the caller.  The library keeps only a
+ *     small host handle (tto_grid) that remembers pointers into the caller's
+ *     grid workspace; that workspace must stay alive and untouched until
+ *     tto_grid_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls are asynchronous on that stream unless stated otherwise.
+ *   - Every call returns a tto_status; no C++ exception crosses the ABI.  On
+ *     error, tto_last_error() returns a thread-local message.  Argument errors
+ *     are detected on the host before any kernel is launched.  Per-candidate
+ *     problems never fail a batch: they set status bits instead.
+ */
+#ifndef TTO_H
+#define TTO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTO_VERSION_MAJOR 1
+#define TTO_VERSION_MINOR 0
+
+#define TTO_MAX_RANK 8      /* openings + splits per candidate */
+#define TTO_MAX_T 32        /* timesteps per injection set */
+#define TTO_MAX_MOVED 64    /* moved branches summed over a candidate's splits */
+#define TTO_MAX_LOAD_BINS 64
+
+typedef int32_t tto_status;
+enum {
+  TTO_OK = 0,
+  TTO_E_INVALID = -1,     /* NULL pointer, size or enum out of range */
+  TTO_E_GRID = -2,        /* bad grid: index out of range, non-positive
+                             susceptance/limit, disconnected base grid,
+                             duplicate monitored/contingency id */
+  TTO_E_RANK = -3,        /* slot counts beyond TTO_MAX_RANK per kind */
+  TTO_E_WORKSPACE = -4,   /* workspace NULL, misaligned or too small */
+  TTO_E_HIP = -5,         /* a HIP runtime call failed */
+  TTO_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+};
+
+/* Arithmetic of the flows (N-0 and N-1 sweep).  Candidate set-up (the rank-r
+ * bordered system, its LU with the islanding pivot test, the LODF
+ * denominators 1 - H'_ll and the contingency islanding test) is FP64 in every
+ * mode. */
+enum { TTO_FLOW_F64 = 0, TTO_FLOW_F32 = 1 };
+
+/* Arithmetic of the base-flow product f0 = PTDF * P (MFMA); FP32 accumulate
+ * for F32/BF16/F16, FP64 accumulate for F64.  f0 is kept in FP64. */
+enum { TTO_GEMM_F64 = 0, TTO_GEMM_F32 = 1, TTO_GEMM_BF16 = 2, TTO_GEMM_F16 = 3 };
+
+/* Per-candidate status bits. */
+#define TTO_ST_ISLANDED 0x01u  /* post-switch grid is not connected */
+#define TTO_ST_INVALID  0x02u  /* candidate violates the encoding rules */
+#define TTO_ST_REFINED  0x04u  /* FP32 result was near a decision threshold
+                                  and was recomputed in FP64 */
+
+typedef struct tto_grid tto_grid;   /* opaque host handle */
+
+/*
+ * Grid (Problem formulation: node set N, edge set E with limits fbar_e,
+ * outage set O).  DC model: lossless branches, b_e = 1/x_e, flows in MW,
+ * dimensionless PTDF with a zero slack column (Importer: the PTDF of the
+ * pre-optimisation topology is computed once).
+ *
+ *   ptdf          device, row-major [n_branch][n_bus], read only during
+ *                 tto_grid_create (the grid keeps its own copies).
+ *   monitored     host, distinct branch ids whose flows enter the metrics (M).
+ *   contingency   host, distinct branch ids whose single outages form the
+ *                 N-1 set (O).
+ *   max_batch     largest n_cand later passed to tto_evaluate.
+ */
+typedef struct {
+  int32_t n_bus;
+  int32_t n_branch;
+  int32_t slack;
+  int32_t n_timesteps;          /* 1..TTO_MAX_T */
+  const int32_t* from_bus;      /* host [n_branch] */
+  const int32_t* to_bus;        /* host [n_branch] */
+  const double* susceptance;    /* host [n_branch], > 0 */
+  const double* limit_mw;       /* host [n_branch], > 0 */
+  const double* ptdf;           /* device [n_branch * n_bus] */
+  int32_t n_monitored;
+  const int32_t* monitored;     /* host [n_monitored] */
+  int32_t n_contingency;
+  const int32_t* contingency;   /* host [n_contingency] */
+  int32_t flow_precision;       /* TTO_FLOW_* */
+  int32_t gemm_precision;       /* TTO_GEMM_* */
+  int32_t max_batch;            /* >= 1 */
+} tto_grid_desc;
+
+/*
+ * MapElites descriptor and fitness (DC-Optimizer, repertoire design and the
+ * fitness lambda_f1 = -(lambda_o + w_c0 lambda_c0 + w_c lambda_c), weights 200
+ * and 50 in the paper).  Two-axis cell: count axis = number of switched
+ * elements (openings + splits, clamped to n_count_bins-1); load axis = number
+ * of load_edges <= max loading (edges ascending).
+ * cell = count * n_load_bins + load_bin.
+ */
+typedef struct {
+  int32_t n_count_bins;         /* >= 1 */
+  int32_t n_load_bins;          /* 1..TTO_MAX_LOAD_BINS */
+  const double* load_edges;     /* host [n_load_bins - 1], ascending */
+  double w_c0;
+  double w_c;
+} tto_descriptor_cfg;
+
+/*
+ * Candidate batch in the fixed-slot genome encoding (repertoire design: an
+ * individual holds N_a action slots and N_d disconnection slots, empty slots
+ * hold the empty action).  All arrays are device memory.
+ *
+ *   open       [n_cand][n_open_slots]  opened branch id or -1
+ *   split_bus  [n_cand][n_split_slots] split bus id or -1
+ *   moved_off  [n_cand*n_split_slots+1] CSR offsets (may be NULL iff
+ *              n_split_slots == 0)
+ *   moved_br   branch ids moved to busbar B of each split slot
+ *   moved_p_mw [n_cand*n_split_slots][n_timesteps] MW moved from busbar A to
+ *              busbar B, or NULL (nothing moved)
+ *
+ * A candidate is INVALID (status bit) unless: opened ids are in range and
+ * distinct; split buses are in range and distinct; each filled split moves a
+ * non-empty list of distinct branches incident to its bus, none of them
+ * opened; filled slots <= TTO_MAX_RANK; moved branches <= TTO_MAX_MOVED.
+ * Moved lists of empty split slots are ignored.  The slack role stays on
+ * busbar A.
+ */
+typedef struct {
+  int32_t n_cand;
+  int32_t n_open_slots;         /* 0..TTO_MAX_RANK */
+  int32_t n_split_slots;        /* 0..TTO_MAX_RANK */
+  const int32_t* open;
+  const int32_t* split_bus;
+  const int32_t* moved_off;
+  const int32_t* moved_br;
+  const double* moved_p_mw;
+} tto_batch;
+
+/*
+ * Outputs, device memory, one entry per candidate unless noted; any pointer
+ * may be NULL to skip that output.  Metrics follow the Fitness function
+ * heuristics section with timesteps summed (lambda_o, lambda_c, lambda_c0)
+ * or maximised (max loading, arg-max).  For islanded or invalid candidates
+ * only `status` and `cell` (= -1) and `fitness` (= -inf) are defined.
+ *
+ *   overload_mw    lambda_o = sum_{t,e in M} max(f^max_e(t) - fbar_e, 0)
+ *   n_crit_n1      lambda_c = #{(e,t): f^max_e(t) > fbar_e}
+ *   n_crit_n0      lambda_c0 = #{(e,t): |f'_e(t)| > fbar_e}
+ *   max_loading    max_{e,t} f^max_e(t) / fbar_e
+ *   worst_*        branch id e*, contingency branch id l*, timestep t* of the
+ *                  maximum loading (smallest (e, t, l) on exact ties; l* = -1
+ *                  when every contingency islands)
+ *   n_island_cont  contingencies skipped because they island the grid
+ *   base_flows     [n_cand][n_branch][n_timesteps] post-switch N-0 flows
+ *   fmax           [n_cand][n_monitored][n_timesteps]
+ *   n1_flows       [n_cand][n_contingency][n_monitored][n_timesteps]; NaN
+ *                  for islanding contingencies (debug-sized batches only)
+ */
+typedef struct {
+  uint8_t* status;
+  int32_t* n_island_cont;
+  double* overload_mw;
+  int32_t* n_crit_n1;
+  int32_t* n_crit_n0;
+  double* max_loading;
+  int32_t* worst_branch;
+  int32_t* worst_cont;
+  int32_t* worst_t;
+  double* fitness;
+  int32_t* cell;
+  double* base_flows;
+  double* fmax;
+  double* n1_flows;
+} tto_outputs;
+
+/* Library version; returns TTO_OK. */
+tto_status tto_version(int32_t* major, int32_t* minor);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* tto_last_error(void);
+
+/*
+ * Device workspace sizes for a grid description (host only, no GPU work).
+ * grid_bytes: persistent grid workspace for tto_grid_create.
+ * batch_bytes: scratch for one tto_evaluate / tto_archive_insert call with
+ * up to desc->max_batch candidates.  Both need 256-byte alignment.
+ */
+tto_status tto_workspace_bytes(const tto_grid_desc* desc, size_t* grid_bytes,
+                               size_t* batch_bytes);
+
+/*
+ * Validate the grid on the host (index ranges, b > 0, limits > 0, distinct
+ * M and C ids, connected base grid via union-find) and build the device
+ * tables in grid_ws: H = PTDF * A^T in FP64 (row- and column-major), the
+ * monitored x contingency block of H in FP32 and FP64 (contingency-major),
+ * the PTDF copy in the GEMM precision.  Synchronises `stream`.  On success
+ * *out receives a handle to free with tto_grid_destroy.  The default
+ * descriptor is 32 x 32 cells, geometric load edges 0.25..64, weights 200/50.
+ */
+tto_status tto_grid_create(const tto_grid_desc* desc, void* grid_ws, size_t grid_bytes,
+                           void* stream, tto_grid** out);
+
+/* Free the host handle (device memory stays with the caller). */
+void tto_grid_destroy(tto_grid* grid);
+
+/*
+ * Install nodal injections p_mw (device, row-major [n_bus][n_timesteps], MW,
+ * generation positive; balancing is the caller's duty) and compute the base
+ * flows f0 = PTDF * P with the MFMA GEMM in the grid's GEMM precision.
+ * Asynchronous on `stream`; p_mw may be freed once the stream has passed.
+ */
+tto_status tto_set_injections(tto_grid* grid, const double* p_mw, void* stream);
+
+/* Copy f0 (device [n_branch][n_timesteps], FP64) into out_mw. Asynchronous. */
+tto_status tto_get_base_flows(tto_grid* grid, double* out_mw, void* stream);
+
+/* Replace the descriptor/fitness settings.  Synchronous (small upload). */
+tto_status tto_set_descriptor(tto_grid* grid, const tto_descriptor_cfg* cfg);
+
+/*
+ * Score a batch (DC-Optimizer: batched N-1 DC loadflow, lambda and beta).
+ * Runs on `stream` without host synchronisation; batch_ws must hold
+ * batch_bytes from tto_workspace_bytes and may be reused once the stream has
+ * passed.  TTO_E_RANK if a slot count exceeds TTO_MAX_RANK.
+ */
+tto_status tto_evaluate(tto_grid* grid, const tto_batch* batch, const tto_outputs* out,
+                        void* batch_ws, size_t batch_bytes, void* stream);
+
+/*
+ * Per-cell elite update (High-level loop: insert each new individual into the
+ * cell given by beta; one elite per cell).  elite_fitness/elite_id are device
+ * arrays [n_cells]; an empty cell has elite_id == -1.  Among the batch's
+ * candidates whose status has neither ISLANDED nor INVALID set, each cell's
+ * best fitness wins (ties: lowest index), and it replaces the elite only if
+ * the cell is empty or the fitness is strictly greater; the new id is
+ * id_base + index.  Equal to inserting the candidates one at a time in batch
+ * order.  Uses the first 16*n_cells bytes of batch_ws.  Asynchronous.
+ */
+tto_status tto_archive_insert(tto_grid* grid, double* elite_fitness, int64_t* elite_id,
+                              int32_t n_cells, const double* fitness, const int32_t* cell,
+                              const uint8_t* status, int32_t n_cand, int64_t id_base,
+                              void* batch_ws, size_t batch_bytes, void* stream);
+
+/*
+ * Stage timing of tto_evaluate (tracing aid): when enabled, every
+ * tto_evaluate records HIP events on its stream around its three stages
+ * (candidate set-up, N-1 sweep, finalize).  tto_profile_read waits for the
+ * events of the latest tto_evaluate and writes the stage durations in
+ * milliseconds to ms[0..2].  TTO_E_INVALID if profiling is off or nothing was
+ * recorded yet.
+ */
+tto_status tto_profile_enable(tto_grid* grid, int32_t enable);
+tto_status tto_profile_read(tto_grid* grid, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTO_H */

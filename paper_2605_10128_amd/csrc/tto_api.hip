@@ -1,0 +1,390 @@
+// Host side of the C ABI declared in include/tto.h: argument validation,
+// workspace carving, device table construction and kernel launch order.
+#include "tto_common.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace tto;
+
+namespace {
+
+thread_local std::string g_err;
+
+tto_status fail(tto_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+tto_status ok() {
+  g_err.clear();
+  return TTO_OK;
+}
+
+#define HIP_TRY(expr)                                                           \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return fail(TTO_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+// Bump allocator over a caller-owned buffer (base == nullptr: size only).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int gemm_ld(int n) { return ((n + 63) / 64) * 64; }
+int gemm_mpad(int m) { return ((m + 15) / 16) * 16; }
+size_t gemm_esize(int prec) {
+  return prec == TTO_GEMM_F64 ? 8 : prec == TTO_GEMM_F32 ? 4 : 2;
+}
+
+struct GridLayout {
+  int* from; int* to; double* b; double* lim; int* mon; int* cont; double* edges;
+  double* H; double* HT; float* HMC32; double* HMC64; double* f0;
+  void* A; void* PT; float* part32; double* part64;
+  int ksplit;
+};
+
+GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
+  Carver cv(ws);
+  GridLayout L;
+  const size_t m = d->n_branch, n = d->n_bus, T = d->n_timesteps;
+  L.from = cv.take<int>(m);
+  L.to = cv.take<int>(m);
+  L.b = cv.take<double>(m);
+  L.lim = cv.take<double>(m);
+  L.mon = cv.take<int>(d->n_monitored);
+  L.cont = cv.take<int>(std::max(d->n_contingency, 1));
+  L.edges = cv.take<double>(TTO_MAX_LOAD_BINS);
+  L.H = cv.take<double>(m * m);
+  L.HT = cv.take<double>(m * m);
+  L.HMC32 = cv.take<float>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
+  L.HMC64 = cv.take<double>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
+  L.f0 = cv.take<double>(m * T);
+  const size_t ld = gemm_ld(d->n_bus), mp = gemm_mpad(d->n_branch);
+  const size_t es = gemm_esize(d->gemm_precision);
+  L.A = cv.take<char>(mp * ld * es);
+  L.PT = cv.take<char>((size_t)kGemmN * ld * es);
+  L.ksplit = gemm_ksplit(d->n_branch, d->n_bus);
+  if (d->gemm_precision == TTO_GEMM_F64) {
+    L.part32 = nullptr;
+    L.part64 = cv.take<double>((size_t)L.ksplit * m * kGemmN);
+  } else {
+    L.part32 = cv.take<float>((size_t)L.ksplit * m * kGemmN);
+    L.part64 = nullptr;
+  }
+  (void)n;
+  *bytes = cv.off;
+  return L;
+}
+
+template <typename F>
+SweepBufs<F> carve_batch(int B, int nM, int nC, int TT, void* ws, size_t* bytes) {
+  Carver cv(ws);
+  SweepBufs<F> w;
+  w.n_eblk = (nM + 255) / 256;
+  w.info = cv.take<CandInfo>(B);
+  w.fM = cv.take<F>((size_t)B * nM * TT);
+  w.UM = cv.take<F>((size_t)B * nM * kVSlots);
+  w.rec = cv.take<F>((size_t)B * (nC + 1) * rec_stride(TT));
+  w.act = cv.take<int>((size_t)B * (nC + 1));
+  w.slot = cv.take<int>((size_t)B * std::max(nC, 1));
+  w.part = cv.take<Partial>((size_t)B * w.n_eblk);
+  *bytes = cv.off;
+  return w;
+}
+
+size_t batch_bytes_for(const tto_grid_desc* d) {
+  size_t bytes = 0;
+  const int TT = tile_T(d->n_timesteps);
+  if (d->flow_precision == TTO_FLOW_F32)
+    carve_batch<float>(d->max_batch, d->n_monitored, d->n_contingency, TT, nullptr, &bytes);
+  else
+    carve_batch<double>(d->max_batch, d->n_monitored, d->n_contingency, TT, nullptr, &bytes);
+  return std::max(bytes, (size_t)16 * 4096);   // archive scratch for up to 4096 cells
+}
+
+tto_status check_desc(const tto_grid_desc* d) {
+  if (!d) return fail(TTO_E_INVALID, "desc is NULL");
+  if (d->n_bus < 2 || d->n_branch < 1) return fail(TTO_E_INVALID, "need n_bus >= 2 and n_branch >= 1");
+  if (d->slack < 0 || d->slack >= d->n_bus) return fail(TTO_E_GRID, "slack %d out of range", d->slack);
+  if (d->n_timesteps < 1 || d->n_timesteps > TTO_MAX_T)
+    return fail(TTO_E_INVALID, "n_timesteps %d not in 1..%d", d->n_timesteps, TTO_MAX_T);
+  if (d->n_monitored < 1 || d->n_monitored > d->n_branch)
+    return fail(TTO_E_INVALID, "n_monitored %d not in 1..n_branch", d->n_monitored);
+  if (d->n_contingency < 0 || d->n_contingency > d->n_branch)
+    return fail(TTO_E_INVALID, "n_contingency %d not in 0..n_branch", d->n_contingency);
+  if (d->flow_precision != TTO_FLOW_F64 && d->flow_precision != TTO_FLOW_F32)
+    return fail(TTO_E_INVALID, "flow_precision %d unknown", d->flow_precision);
+  if (d->gemm_precision < TTO_GEMM_F64 || d->gemm_precision > TTO_GEMM_F16)
+    return fail(TTO_E_INVALID, "gemm_precision %d unknown", d->gemm_precision);
+  if (d->max_batch < 1 || d->max_batch > 65535)
+    return fail(TTO_E_INVALID, "max_batch %d not in 1..65535", d->max_batch);
+  if (d->n_branch > 65535 || d->n_bus > 65535)
+    return fail(TTO_E_UNSUPPORTED, "grids beyond 65535 buses or branches are not supported");
+  return TTO_OK;
+}
+
+int uf_find(std::vector<int>& p, int a) {
+  while (p[a] != a) { p[a] = p[p[a]]; a = p[a]; }
+  return a;
+}
+
+}  // namespace
+
+struct tto_grid {
+  int device;
+  int n_bus, m, slack, T, TT, nM, nC;
+  int flow_prec, gemm_prec, max_batch;
+  size_t grid_bytes, batch_bytes;
+  GridLayout L;
+  GridDev dev;
+  bool profile = false;
+  bool recorded = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+extern "C" {
+
+tto_status tto_version(int32_t* major, int32_t* minor) {
+  if (major) *major = TTO_VERSION_MAJOR;
+  if (minor) *minor = TTO_VERSION_MINOR;
+  return ok();
+}
+
+const char* tto_last_error(void) { return g_err.c_str(); }
+
+tto_status tto_workspace_bytes(const tto_grid_desc* d, size_t* grid_bytes, size_t* batch_bytes) {
+  tto_status st = check_desc(d);
+  if (st != TTO_OK) return st;
+  if (!grid_bytes || !batch_bytes) return fail(TTO_E_INVALID, "NULL output pointer");
+  carve_grid(d, nullptr, grid_bytes);
+  *batch_bytes = batch_bytes_for(d);
+  return ok();
+}
+
+tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_bytes, void* stream,
+                           tto_grid** out) {
+  tto_status st = check_desc(d);
+  if (st != TTO_OK) return st;
+  if (!out) return fail(TTO_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!d->from_bus || !d->to_bus || !d->susceptance || !d->limit_mw || !d->ptdf || !d->monitored ||
+      (d->n_contingency > 0 && !d->contingency))
+    return fail(TTO_E_INVALID, "a required grid array is NULL");
+  const int n = d->n_bus, m = d->n_branch;
+  for (int e = 0; e < m; ++e) {
+    const int a = d->from_bus[e], b = d->to_bus[e];
+    if (a < 0 || a >= n || b < 0 || b >= n) return fail(TTO_E_GRID, "branch %d endpoint out of range", e);
+    if (a == b) return fail(TTO_E_GRID, "branch %d is a self loop", e);
+    if (!(d->susceptance[e] > 0.0) || !isfinite(d->susceptance[e]))
+      return fail(TTO_E_GRID, "branch %d susceptance must be finite and > 0", e);
+    if (!(d->limit_mw[e] > 0.0) || !isfinite(d->limit_mw[e]))
+      return fail(TTO_E_GRID, "branch %d limit must be finite and > 0", e);
+  }
+  std::vector<char> seen(m, 0);
+  for (int i = 0; i < d->n_monitored; ++i) {
+    const int e = d->monitored[i];
+    if (e < 0 || e >= m || seen[e]) return fail(TTO_E_GRID, "monitored[%d]=%d out of range or repeated", i, e);
+    seen[e] = 1;
+  }
+  std::fill(seen.begin(), seen.end(), 0);
+  for (int i = 0; i < d->n_contingency; ++i) {
+    const int e = d->contingency[i];
+    if (e < 0 || e >= m || seen[e]) return fail(TTO_E_GRID, "contingency[%d]=%d out of range or repeated", i, e);
+    seen[e] = 1;
+  }
+  std::vector<int> par(n);
+  std::iota(par.begin(), par.end(), 0);
+  int comps = n;
+  for (int e = 0; e < m; ++e) {
+    const int ra = uf_find(par, d->from_bus[e]), rb = uf_find(par, d->to_bus[e]);
+    if (ra != rb) { par[ra] = rb; --comps; }
+  }
+  if (comps != 1) return fail(TTO_E_GRID, "base grid is not connected (%d components)", comps);
+
+  size_t need = 0;
+  carve_grid(d, nullptr, &need);
+  if (!grid_ws || ((uintptr_t)grid_ws & 255)) return fail(TTO_E_WORKSPACE, "grid_ws NULL or not 256-byte aligned");
+  if (grid_bytes < need) return fail(TTO_E_WORKSPACE, "grid_ws has %zu bytes, needs %zu", grid_bytes, need);
+
+  hipStream_t s = (hipStream_t)stream;
+  GridLayout L = carve_grid(d, grid_ws, &need);
+  HIP_TRY(hipMemcpyAsync(L.from, d->from_bus, sizeof(int) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(L.to, d->to_bus, sizeof(int) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(L.b, d->susceptance, sizeof(double) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(L.lim, d->limit_mw, sizeof(double) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(L.mon, d->monitored, sizeof(int) * d->n_monitored, hipMemcpyHostToDevice, s));
+  if (d->n_contingency > 0)
+    HIP_TRY(hipMemcpyAsync(L.cont, d->contingency, sizeof(int) * d->n_contingency, hipMemcpyHostToDevice, s));
+  // default descriptor: geometric load edges 0.25 .. 64 (31 inner edges)
+  double edges[31];
+  for (int i = 0; i < 31; ++i) edges[i] = 0.25 * pow(256.0, i / 30.0);
+  HIP_TRY(hipMemcpyAsync(L.edges, edges, sizeof(edges), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_build_H(d->ptdf, L.from, L.to, m, n, L.H, L.HT, s));
+  if (d->n_contingency > 0)
+    HIP_TRY(launch_build_HMC(L.HT, L.mon, L.cont, m, d->n_monitored, d->n_contingency, L.HMC32, L.HMC64, s));
+  HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, d->gemm_precision, L.A, s));
+  HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
+  HIP_TRY(hipStreamSynchronize(s));
+
+  tto_grid* g = new tto_grid();
+  HIP_TRY(hipGetDevice(&g->device));
+  g->n_bus = n; g->m = m; g->slack = d->slack; g->T = d->n_timesteps; g->TT = tile_T(d->n_timesteps);
+  g->nM = d->n_monitored; g->nC = d->n_contingency;
+  g->flow_prec = d->flow_precision; g->gemm_prec = d->gemm_precision; g->max_batch = d->max_batch;
+  g->grid_bytes = need;
+  g->batch_bytes = batch_bytes_for(d);
+  g->L = L;
+  GridDev& v = g->dev;
+  v.n_bus = n; v.n_branch = m; v.slack = d->slack; v.T = g->T; v.TT = g->TT; v.nM = g->nM; v.nC = g->nC;
+  v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.H = L.H; v.HT = L.HT;
+  v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.mon = L.mon; v.cont = L.cont;
+  v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
+  *out = g;
+  return ok();
+}
+
+void tto_grid_destroy(tto_grid* g) {
+  if (!g) return;
+  for (auto& e : g->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete g;
+}
+
+tto_status tto_profile_enable(tto_grid* g, int32_t enable) {
+  if (!g) return fail(TTO_E_INVALID, "grid is NULL");
+  if (enable && !g->ev[0])
+    for (auto& e : g->ev) HIP_TRY(hipEventCreate(&e));
+  g->profile = enable != 0;
+  g->recorded = false;
+  return ok();
+}
+
+tto_status tto_profile_read(tto_grid* g, double* ms) {
+  if (!g || !ms) return fail(TTO_E_INVALID, "grid or ms is NULL");
+  if (!g->profile || !g->recorded) return fail(TTO_E_INVALID, "profiling off or nothing recorded");
+  HIP_TRY(hipEventSynchronize(g->ev[3]));
+  for (int i = 0; i < 3; ++i) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, g->ev[i], g->ev[i + 1]));
+    ms[i] = t;
+  }
+  return ok();
+}
+
+tto_status tto_set_injections(tto_grid* g, const double* p_mw, void* stream) {
+  if (!g || !p_mw) return fail(TTO_E_INVALID, "grid or p_mw is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, g->gemm_prec, g->L.PT, s));
+  HIP_TRY(launch_gemm_f0(g->gemm_prec, g->L.A, g->L.PT, g->m, g->n_bus, g->T, g->L.ksplit,
+                         g->L.part32, g->L.part64, g->L.f0, s));
+  return ok();
+}
+
+tto_status tto_get_base_flows(tto_grid* g, double* out_mw, void* stream) {
+  if (!g || !out_mw) return fail(TTO_E_INVALID, "grid or out_mw is NULL");
+  HIP_TRY(hipMemcpyAsync(out_mw, g->L.f0, sizeof(double) * g->m * g->T, hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return ok();
+}
+
+tto_status tto_set_descriptor(tto_grid* g, const tto_descriptor_cfg* cfg) {
+  if (!g || !cfg) return fail(TTO_E_INVALID, "grid or cfg is NULL");
+  if (cfg->n_count_bins < 1) return fail(TTO_E_INVALID, "n_count_bins must be >= 1");
+  if (cfg->n_load_bins < 1 || cfg->n_load_bins > TTO_MAX_LOAD_BINS)
+    return fail(TTO_E_INVALID, "n_load_bins must be in 1..%d", TTO_MAX_LOAD_BINS);
+  if (cfg->n_load_bins > 1 && !cfg->load_edges) return fail(TTO_E_INVALID, "load_edges is NULL");
+  for (int i = 0; i + 1 < cfg->n_load_bins; ++i) {
+    if (!isfinite(cfg->load_edges[i])) return fail(TTO_E_INVALID, "load_edges[%d] not finite", i);
+    if (i > 0 && cfg->load_edges[i] < cfg->load_edges[i - 1])
+      return fail(TTO_E_INVALID, "load_edges must be ascending");
+  }
+  if (!isfinite(cfg->w_c0) || !isfinite(cfg->w_c)) return fail(TTO_E_INVALID, "weights not finite");
+  if (cfg->n_load_bins > 1)
+    HIP_TRY(hipMemcpy(g->L.edges, cfg->load_edges, sizeof(double) * (cfg->n_load_bins - 1),
+                      hipMemcpyHostToDevice));
+  g->dev.n_count_bins = cfg->n_count_bins;
+  g->dev.n_load_bins = cfg->n_load_bins;
+  g->dev.w_c0 = cfg->w_c0;
+  g->dev.w_c = cfg->w_c;
+  return ok();
+}
+
+tto_status tto_evaluate(tto_grid* g, const tto_batch* bt, const tto_outputs* out, void* batch_ws,
+                        size_t batch_bytes, void* stream) {
+  if (!g || !bt || !out) return fail(TTO_E_INVALID, "grid, batch or outputs is NULL");
+  if (bt->n_cand < 0 || bt->n_cand > g->max_batch)
+    return fail(TTO_E_INVALID, "n_cand %d not in 0..max_batch=%d", bt->n_cand, g->max_batch);
+  if (bt->n_open_slots < 0 || bt->n_open_slots > TTO_MAX_RANK || bt->n_split_slots < 0 ||
+      bt->n_split_slots > TTO_MAX_RANK)
+    return fail(TTO_E_RANK, "slot counts (%d, %d) must each be in 0..%d", bt->n_open_slots,
+                bt->n_split_slots, TTO_MAX_RANK);
+  if (bt->n_open_slots > 0 && !bt->open) return fail(TTO_E_INVALID, "open is NULL");
+  if (bt->n_split_slots > 0 && (!bt->split_bus || !bt->moved_off || !bt->moved_br))
+    return fail(TTO_E_INVALID, "split arrays are NULL");
+  if (!batch_ws || ((uintptr_t)batch_ws & 255)) return fail(TTO_E_WORKSPACE, "batch_ws NULL or not 256-byte aligned");
+  if (batch_bytes < g->batch_bytes)
+    return fail(TTO_E_WORKSPACE, "batch_ws has %zu bytes, needs %zu", batch_bytes, g->batch_bytes);
+  if (bt->n_cand == 0) return ok();
+  if (g->nC == 0 && out->n1_flows) return fail(TTO_E_INVALID, "n1_flows requested with no contingencies");
+  BatchDev b;
+  b.B = bt->n_cand; b.no = bt->n_open_slots; b.ns = bt->n_split_slots;
+  b.open = bt->open; b.sbus = bt->split_bus; b.moff = bt->moved_off; b.mbr = bt->moved_br;
+  b.mp = bt->moved_p_mw;
+  hipStream_t s = (hipStream_t)stream;
+  size_t used = 0;
+  if (g->flow_prec == TTO_FLOW_F32) {
+    SweepBufs<float> w = carve_batch<float>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
+    if (!out->n1_flows) w.slot = nullptr;
+    HIP_TRY(launch_evaluate<float>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr));
+  } else {
+    SweepBufs<double> w = carve_batch<double>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
+    if (!out->n1_flows) w.slot = nullptr;
+    HIP_TRY(launch_evaluate<double>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr));
+  }
+  if (g->profile) g->recorded = true;
+  return ok();
+}
+
+tto_status tto_archive_insert(tto_grid* g, double* elite_fitness, int64_t* elite_id, int32_t n_cells,
+                              const double* fitness, const int32_t* cell, const uint8_t* status,
+                              int32_t n_cand, int64_t id_base, void* batch_ws, size_t batch_bytes,
+                              void* stream) {
+  if (!g || !elite_fitness || !elite_id) return fail(TTO_E_INVALID, "grid or elite arrays NULL");
+  if (n_cells < 1) return fail(TTO_E_INVALID, "n_cells must be >= 1");
+  if (n_cand < 0) return fail(TTO_E_INVALID, "n_cand must be >= 0");
+  if (n_cand > 0 && (!fitness || !cell || !status)) return fail(TTO_E_INVALID, "batch arrays NULL");
+  if (!batch_ws || ((uintptr_t)batch_ws & 255)) return fail(TTO_E_WORKSPACE, "batch_ws NULL or not 256-byte aligned");
+  const size_t need = 16 * (size_t)n_cells;
+  if (batch_bytes < need) return fail(TTO_E_WORKSPACE, "batch_ws has %zu bytes, needs %zu", batch_bytes, need);
+  unsigned long long* key = (unsigned long long*)batch_ws;
+  int* idx = (int*)((char*)batch_ws + 8 * (size_t)n_cells);
+  HIP_TRY(launch_archive(elite_fitness, elite_id, n_cells, fitness, cell, status, n_cand, id_base,
+                         key, idx, (hipStream_t)stream));
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal declarations shared by the HIP translation units of libtto.
+// gfx950 only: 64-lane wavefronts, MFMA, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/tto.h"
+
+namespace tto {
+
+constexpr int kWave = 64;
+constexpr int kMaxRank = TTO_MAX_RANK;
+constexpr int kMaxMoved = TTO_MAX_MOVED;
+constexpr int kVSlots = 8;          // V entries per contingency record
+constexpr double kTauIsland = 1e-9; // |pivot| of the scaled bordered system
+constexpr double kTauCont = 1e-9;   // |1 - H'_ll| of a contingency
+constexpr int kGemmN = 32;          // timestep columns of the f0 GEMM (T padded)
+
+// Record of one active contingency in a candidate's sweep list:
+// phi(t) for t < TT, then V_j for j < 8, padded to a multiple of 4 entries.
+__host__ __device__ constexpr int rec_stride(int TT) { return ((TT + kVSlots + 3) / 4) * 4; }
+
+// Timestep tile used by the templated kernels: smallest supported >= T.
+inline int tile_T(int T) {
+  if (T <= 1) return 1;
+  if (T <= 8) return 8;
+  if (T <= 24) return 24;
+  return 32;
+}
+
+struct GridDev {
+  int n_bus, n_branch, slack, T, TT, nM, nC;
+  const int* from;
+  const int* to;
+  const double* b;
+  const double* lim;
+  const double* H;      // [m][m], H[e*m + l]: flow on e per unit transfer across l
+  const double* HT;     // [m][m], HT[l*m + e] = H[e*m + l]
+  const float* HMC32;   // [nC][nM], H[M[ei], C[li]] with -1 where M[ei] == C[li]
+  const double* HMC64;  // same in FP64
+  const double* f0;     // [m][T] base flows of the unswitched grid
+  const int* mon;       // [nM]
+  const int* cont;      // [nC]
+  const double* edges;  // [n_load_bins - 1]
+  int n_count_bins, n_load_bins;
+  double w_c0, w_c;
+};
+
+struct BatchDev {
+  int B, no, ns;
+  const int* open;
+  const int* sbus;
+  const int* moff;
+  const int* mbr;
+  const double* mp;
+};
+
+// Per-candidate summary written by the set-up kernel.
+struct CandInfo {
+  int status;      // TTO_ST_* bits
+  int r;           // filled slots (openings + splits)
+  int k;           // openings
+  int n_act;       // active (non-islanding) contingencies
+  int n_act_pad;   // n_act rounded up to even (duplicate of the last record)
+  int n_island;    // islanding contingencies
+  int n_crit_n0;   // lambda_c0 from the FP64 post-switch flows
+  int pad_;
+  int open_br[kMaxRank];
+};
+
+// Per (candidate, monitored block) reduction of the sweep.
+struct Partial {
+  double sum_o;     // sum of max(fmax - lim, 0)
+  double best;      // max loading in this block
+  int cnt_c;        // fmax > lim count
+  int best_e;       // monitored index of the max (smallest on ties)
+  int best_t;
+  int pad_;
+};
+
+// Batch workspace views (carved from the caller's batch workspace).
+template <typename F>
+struct SweepBufs {
+  CandInfo* info;   // [B]
+  F* fM;            // [B][nM][TT]
+  F* UM;            // [B][nM][8]
+  F* rec;           // [B][nC+1][rec_stride(TT)]
+  int* act;         // [B][nC+1] contingency index of each record
+  int* slot;        // [B][nC] record of each contingency or -1 (optional)
+  Partial* part;    // [B][n_eblk]
+  int n_eblk;
+};
+
+// ---- launchers (k_grid.hip) -------------------------------------------------
+hipError_t launch_build_H(const double* ptdf, const int* from, const int* to, int m, int n,
+                          double* H, double* HT, hipStream_t s);
+hipError_t launch_build_HMC(const double* HT, const int* mon, const int* cont, int m, int nM,
+                            int nC, float* HMC32, double* HMC64, hipStream_t s);
+hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void* out, hipStream_t s);
+hipError_t launch_pack_injections(const double* p, int n, int T, int prec, void* PT, hipStream_t s);
+hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n, int T,
+                          int ksplit, float* part32, double* part64, double* f0, hipStream_t s);
+int gemm_ksplit(int m, int n);
+
+// ---- launchers (k_eval.hip) -------------------------------------------------
+// ev: NULL or 4 events recorded before set-up, after set-up, after the sweep
+// and after finalize.
+template <typename F>
+hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                           const tto_outputs& out, hipStream_t s, hipEvent_t* ev);
+hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
+                          const int* cell, const uint8_t* status, int B, int64_t id_base,
+                          unsigned long long* key, int* idx, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
+
+}  // namespace tto

@@ -1,0 +1,317 @@
+"""ctypes binding of libtto (include/tto.h): same entry-point names, argument
+marshalling only.  Every step of the evaluation runs in the HIP library; torch
+is used for device memory and streams.  Importing this module fails loudly if
+the built library is missing."""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtto.so")
+
+TTO_OK = 0
+TTO_E_INVALID, TTO_E_GRID, TTO_E_RANK, TTO_E_WORKSPACE, TTO_E_HIP, TTO_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+TTO_FLOW_F64, TTO_FLOW_F32 = 0, 1
+TTO_GEMM_F64, TTO_GEMM_F32, TTO_GEMM_BF16, TTO_GEMM_F16 = 0, 1, 2, 3
+TTO_ST_ISLANDED, TTO_ST_INVALID, TTO_ST_REFINED = 1, 2, 4
+TTO_MAX_RANK, TTO_MAX_T, TTO_MAX_MOVED, TTO_MAX_LOAD_BINS = 8, 32, 64, 64
+
+_vp = ct.c_void_p
+_i32 = ct.c_int32
+
+
+class tto_grid_desc(ct.Structure):
+    _fields_ = [("n_bus", _i32), ("n_branch", _i32), ("slack", _i32), ("n_timesteps", _i32),
+                ("from_bus", _vp), ("to_bus", _vp), ("susceptance", _vp), ("limit_mw", _vp),
+                ("ptdf", _vp), ("n_monitored", _i32), ("monitored", _vp),
+                ("n_contingency", _i32), ("contingency", _vp), ("flow_precision", _i32),
+                ("gemm_precision", _i32), ("max_batch", _i32)]
+
+
+class tto_descriptor_cfg(ct.Structure):
+    _fields_ = [("n_count_bins", _i32), ("n_load_bins", _i32), ("load_edges", _vp),
+                ("w_c0", ct.c_double), ("w_c", ct.c_double)]
+
+
+class tto_batch(ct.Structure):
+    _fields_ = [("n_cand", _i32), ("n_open_slots", _i32), ("n_split_slots", _i32),
+                ("open", _vp), ("split_bus", _vp), ("moved_off", _vp), ("moved_br", _vp),
+                ("moved_p_mw", _vp)]
+
+
+OUTPUT_FIELDS = ["status", "n_island_cont", "overload_mw", "n_crit_n1", "n_crit_n0",
+                 "max_loading", "worst_branch", "worst_cont", "worst_t", "fitness", "cell",
+                 "base_flows", "fmax", "n1_flows"]
+
+
+class tto_outputs(ct.Structure):
+    _fields_ = [(f, _vp) for f in OUTPUT_FIELDS]
+
+
+class TTOError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tto error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libtto.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    lib = ct.CDLL(LIB_PATH)
+    P = ct.POINTER
+    sig = {
+        "tto_version": (_i32, [P(_i32), P(_i32)]),
+        "tto_last_error": (ct.c_char_p, []),
+        "tto_workspace_bytes": (_i32, [P(tto_grid_desc), P(ct.c_size_t), P(ct.c_size_t)]),
+        "tto_grid_create": (_i32, [P(tto_grid_desc), _vp, ct.c_size_t, _vp, P(_vp)]),
+        "tto_grid_destroy": (None, [_vp]),
+        "tto_set_injections": (_i32, [_vp, _vp, _vp]),
+        "tto_get_base_flows": (_i32, [_vp, _vp, _vp]),
+        "tto_set_descriptor": (_i32, [_vp, P(tto_descriptor_cfg)]),
+        "tto_evaluate": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp]),
+        "tto_archive_insert": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, ct.c_int64, _vp,
+                                      ct.c_size_t, _vp]),
+        "tto_profile_enable": (_i32, [_vp, _i32]),
+        "tto_profile_read": (_i32, [_vp, P(ct.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_create",
+            "tto_grid_destroy", "tto_set_injections", "tto_get_base_flows", "tto_set_descriptor",
+            "tto_evaluate", "tto_archive_insert", "tto_profile_enable", "tto_profile_read"]
+
+
+def _check(code: int):
+    if code != TTO_OK:
+        raise TTOError(code, _lib.tto_last_error().decode())
+
+
+# ---- entry points (same names as the C ABI) --------------------------------
+def tto_version():
+    a, b = _i32(), _i32()
+    _check(_lib.tto_version(ct.byref(a), ct.byref(b)))
+    return a.value, b.value
+
+
+def tto_last_error() -> str:
+    return _lib.tto_last_error().decode()
+
+
+def tto_workspace_bytes(desc: tto_grid_desc):
+    g, b = ct.c_size_t(), ct.c_size_t()
+    _check(_lib.tto_workspace_bytes(ct.byref(desc), ct.byref(g), ct.byref(b)))
+    return g.value, b.value
+
+
+def tto_grid_create(desc: tto_grid_desc, grid_ws: int, grid_bytes: int, stream: int) -> int:
+    h = _vp()
+    _check(_lib.tto_grid_create(ct.byref(desc), _vp(grid_ws), grid_bytes, _vp(stream), ct.byref(h)))
+    return h.value
+
+
+def tto_grid_destroy(handle: int):
+    _lib.tto_grid_destroy(_vp(handle))
+
+
+def tto_set_injections(handle: int, p_mw: int, stream: int):
+    _check(_lib.tto_set_injections(_vp(handle), _vp(p_mw), _vp(stream)))
+
+
+def tto_get_base_flows(handle: int, out: int, stream: int):
+    _check(_lib.tto_get_base_flows(_vp(handle), _vp(out), _vp(stream)))
+
+
+def tto_set_descriptor(handle: int, cfg: tto_descriptor_cfg):
+    _check(_lib.tto_set_descriptor(_vp(handle), ct.byref(cfg)))
+
+
+def tto_evaluate(handle: int, batch: tto_batch, outputs: tto_outputs, ws: int, ws_bytes: int,
+                 stream: int):
+    _check(_lib.tto_evaluate(_vp(handle), ct.byref(batch), ct.byref(outputs), _vp(ws), ws_bytes,
+                             _vp(stream)))
+
+
+def tto_archive_insert(handle: int, elite_fit: int, elite_id: int, n_cells: int, fitness: int,
+                       cell: int, status: int, n_cand: int, id_base: int, ws: int, ws_bytes: int,
+                       stream: int):
+    _check(_lib.tto_archive_insert(_vp(handle), _vp(elite_fit), _vp(elite_id), n_cells,
+                                   _vp(fitness), _vp(cell), _vp(status), n_cand, id_base, _vp(ws),
+                                   ws_bytes, _vp(stream)))
+
+
+def tto_profile_enable(handle: int, enable: bool):
+    _check(_lib.tto_profile_enable(_vp(handle), 1 if enable else 0))
+
+
+def tto_profile_read(handle: int):
+    ms = (ct.c_double * 3)()
+    _check(_lib.tto_profile_read(_vp(handle), ms))
+    return list(ms)
+
+
+# ---- torch-backed session (device memory and streams only) -----------------
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+@dataclass
+class DeviceBatch:
+    n_cand: int
+    open: object
+    split_bus: object
+    moved_off: object
+    moved_br: object
+    moved_p: Optional[object]
+
+    @property
+    def n_open_slots(self):
+        return int(self.open.shape[1])
+
+    @property
+    def n_split_slots(self):
+        return int(self.split_bus.shape[1])
+
+    def struct(self) -> tto_batch:
+        return tto_batch(self.n_cand, self.n_open_slots, self.n_split_slots, _ptr(self.open),
+                         _ptr(self.split_bus), _ptr(self.moved_off), _ptr(self.moved_br),
+                         _ptr(self.moved_p))
+
+
+def device_batch(batch, device="cuda") -> DeviceBatch:
+    """Copy a gridgen.Batch (numpy) to device tensors."""
+    import torch
+    op = torch.as_tensor(np.ascontiguousarray(batch.open, dtype=np.int32), device=device)
+    sb = torch.as_tensor(np.ascontiguousarray(batch.split_bus, dtype=np.int32), device=device)
+    mo = torch.as_tensor(np.ascontiguousarray(batch.moved_off, dtype=np.int32), device=device)
+    mb = np.ascontiguousarray(batch.moved_br, dtype=np.int32)
+    mbt = torch.as_tensor(mb if mb.size else np.zeros(1, np.int32), device=device)
+    mp = None
+    if batch.moved_p is not None:
+        mp = torch.as_tensor(np.ascontiguousarray(batch.moved_p, dtype=np.float64), device=device)
+    return DeviceBatch(int(batch.open.shape[0]), op, sb, mo, mbt, mp)
+
+
+class Session:
+    """Owns the torch-allocated workspaces of one grid and calls the C ABI."""
+
+    def __init__(self, n_bus, from_bus, to_bus, susceptance, limit_mw, ptdf, monitored,
+                 contingency, n_timesteps, flow_precision=TTO_FLOW_F32,
+                 gemm_precision=TTO_GEMM_F32, max_batch=4096, slack=0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self._host = dict(
+            from_bus=np.ascontiguousarray(from_bus, dtype=np.int32),
+            to_bus=np.ascontiguousarray(to_bus, dtype=np.int32),
+            b=np.ascontiguousarray(susceptance, dtype=np.float64),
+            lim=np.ascontiguousarray(limit_mw, dtype=np.float64),
+            mon=np.ascontiguousarray(monitored, dtype=np.int32),
+            cont=np.ascontiguousarray(contingency, dtype=np.int32),
+        )
+        h = self._host
+        self.n_bus, self.n_branch, self.T = int(n_bus), len(h["from_bus"]), int(n_timesteps)
+        self.nM, self.nC = len(h["mon"]), len(h["cont"])
+        self.max_batch = int(max_batch)
+        ptdf_t = torch.as_tensor(np.ascontiguousarray(ptdf, dtype=np.float64), device=self.device)
+        cptr = lambda a: a.ctypes.data
+        self.desc = tto_grid_desc(
+            self.n_bus, self.n_branch, int(slack), self.T, cptr(h["from_bus"]), cptr(h["to_bus"]),
+            cptr(h["b"]), cptr(h["lim"]), _ptr(ptdf_t), self.nM, cptr(h["mon"]), self.nC,
+            cptr(h["cont"]) if self.nC else 0, int(flow_precision), int(gemm_precision),
+            self.max_batch)
+        self.grid_bytes, self.batch_bytes = tto_workspace_bytes(self.desc)
+        self.grid_ws = torch.empty(self.grid_bytes, dtype=torch.uint8, device=self.device)
+        self.batch_ws = torch.empty(self.batch_bytes, dtype=torch.uint8, device=self.device)
+        self.handle = tto_grid_create(self.desc, _ptr(self.grid_ws), self.grid_bytes, self.stream)
+        del ptdf_t
+
+    @property
+    def stream(self) -> int:
+        return int(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            tto_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_injections(self, P):
+        t = P if hasattr(P, "data_ptr") else self.torch.as_tensor(
+            np.ascontiguousarray(P, dtype=np.float64), device=self.device)
+        self._P = t
+        tto_set_injections(self.handle, _ptr(t), self.stream)
+
+    def base_flows(self):
+        out = self.torch.empty((self.n_branch, self.T), dtype=self.torch.float64, device=self.device)
+        tto_get_base_flows(self.handle, _ptr(out), self.stream)
+        return out
+
+    def set_descriptor(self, load_edges, n_count_bins=32, w_c0=200.0, w_c=50.0):
+        self._edges = np.ascontiguousarray(load_edges, dtype=np.float64)
+        cfg = tto_descriptor_cfg(int(n_count_bins), len(self._edges) + 1,
+                                 self._edges.ctypes.data if len(self._edges) else 0,
+                                 float(w_c0), float(w_c))
+        tto_set_descriptor(self.handle, cfg)
+        self.n_cells = int(n_count_bins) * (len(self._edges) + 1)
+
+    def alloc_outputs(self, B, base_flows=False, fmax=False, n1=False):
+        torch, d = self.torch, self.device
+        o = dict(
+            status=torch.empty(B, dtype=torch.uint8, device=d),
+            n_island_cont=torch.empty(B, dtype=torch.int32, device=d),
+            overload_mw=torch.empty(B, dtype=torch.float64, device=d),
+            n_crit_n1=torch.empty(B, dtype=torch.int32, device=d),
+            n_crit_n0=torch.empty(B, dtype=torch.int32, device=d),
+            max_loading=torch.empty(B, dtype=torch.float64, device=d),
+            worst_branch=torch.empty(B, dtype=torch.int32, device=d),
+            worst_cont=torch.empty(B, dtype=torch.int32, device=d),
+            worst_t=torch.empty(B, dtype=torch.int32, device=d),
+            fitness=torch.empty(B, dtype=torch.float64, device=d),
+            cell=torch.empty(B, dtype=torch.int32, device=d),
+        )
+        if base_flows:
+            o["base_flows"] = torch.empty((B, self.n_branch, self.T), dtype=torch.float64, device=d)
+        if fmax:
+            o["fmax"] = torch.empty((B, self.nM, self.T), dtype=torch.float64, device=d)
+        if n1:
+            o["n1_flows"] = torch.empty((B, self.nC, self.nM, self.T), dtype=torch.float64, device=d)
+        return o
+
+    def evaluate(self, dbatch: DeviceBatch, outputs=None, **want):
+        if outputs is None:
+            outputs = self.alloc_outputs(dbatch.n_cand, **want)
+        st = tto_outputs(*[_ptr(outputs.get(f)) for f in OUTPUT_FIELDS])
+        tto_evaluate(self.handle, dbatch.struct(), st, _ptr(self.batch_ws), self.batch_bytes,
+                     self.stream)
+        return outputs
+
+    def new_archive(self, n_cells=None):
+        n = self.n_cells if n_cells is None else n_cells
+        fit = self.torch.full((n,), float("-inf"), dtype=self.torch.float64, device=self.device)
+        ids = self.torch.full((n,), -1, dtype=self.torch.int64, device=self.device)
+        return fit, ids
+
+    def archive_insert(self, archive, outputs, id_base=0, n_cand=None):
+        fit, ids = archive
+        B = int(outputs["fitness"].shape[0]) if n_cand is None else n_cand
+        tto_archive_insert(self.handle, _ptr(fit), _ptr(ids), int(fit.shape[0]),
+                           _ptr(outputs["fitness"]), _ptr(outputs["cell"]),
+                           _ptr(outputs["status"]), B, int(id_base), _ptr(self.batch_ws),
+                           self.batch_bytes, self.stream)

@@ -1,0 +1,130 @@
+"""GPU path versus the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import gridgen as gg
+from parity_util import (TOL_F32, TOL_F64, compare, log, make_session, oracle_results,
+                         to_numpy)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tto():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_10128_amd import tto as _tto
+    return _tto
+
+
+def _run(w, tto, flow, gemm=None, **want):
+    import torch
+    s = make_session(w, flow, gemm)
+    db = tto.device_batch(w.batch)
+    out = s.evaluate(db, **want)
+    torch.cuda.synchronize()
+    return s, to_numpy(out)
+
+
+def test_base_flows_all_gemm_precisions(tto):
+    """f0 = PTDF * P on MFMA against the oracle's from-scratch N-0 solve."""
+    import oracle
+    import torch
+    for cfg in (1, 3):
+        w = gg.build_config(cfg, B=1)
+        b = 1.0 / w.grid.x_pu
+        ref = oracle.solve_flows(w.grid.n_bus, w.grid.from_bus, w.grid.to_bus, b,
+                                 np.ones(w.grid.n_branch, bool), w.P, 0)
+        for gemm, tol in ((tto.TTO_GEMM_F64, 1e-8), (tto.TTO_GEMM_F32, 5e-2),
+                          (tto.TTO_GEMM_F16, 10.0), (tto.TTO_GEMM_BF16, 100.0)):
+            log(f"[base flows] cfg{cfg} gemm={gemm}")
+            s = make_session(w, tto.TTO_FLOW_F64, gemm)
+            f0 = s.base_flows()
+            torch.cuda.synchronize()
+            err = np.abs(f0.cpu().numpy() - ref).max()
+            log(f"  max |f0 - oracle| = {err:.3e} MW")
+            assert err <= tol
+
+
+def test_cfg1_fp64_full_parity(tto):
+    """30-bus grid, 64 candidates, FP64: every output against the oracle."""
+    w = gg.build_config(1)
+    log("[cfg1] gpu")
+    s, out = _run(w, tto, tto.TTO_FLOW_F64, base_flows=True, fmax=True, n1=True)
+    idx = list(range(w.batch.n_cand))
+    log("[cfg1] oracle")
+    ores = oracle_results(w, idx)
+    st = compare(w, out, idx, ores, TOL_F64, strict_discrete=True)
+    log(f"[cfg1] checked {st}")
+    assert st["checked"] >= 50
+
+
+@pytest.mark.parametrize("flow", ["f64", "f32"])
+def test_ragged_splits_with_moved_injection(tto, flow):
+    """Multi-timestep (T=3, not a tile size), odd contingency count, monitored
+    count past one block, bus splits with moved injections: full N-1 tensor."""
+    fp = tto.TTO_FLOW_F64 if flow == "f64" else tto.TTO_FLOW_F32
+    w = gg.build_config(2, B=40, move_frac=0.7, n_bus=120, n_branch=300, T=3, n_mon=261,
+                        n_cont=151, kind="cfg2")
+    w.P = gg.make_injections(w.grid, 3, 77)
+    w.batch = gg.make_candidates_cfg2(w.grid, 40, 78, P=w.P, move_frac=0.7)
+    log(f"[ragged {flow}] gpu")
+    s, out = _run(w, tto, fp, base_flows=True, fmax=True, n1=True)
+    idx = list(range(40))
+    ores = oracle_results(w, idx)
+    tol = TOL_F64 if flow == "f64" else TOL_F32
+    st = compare(w, out, idx, ores, tol, strict_discrete=(flow == "f64"))
+    log(f"[ragged {flow}] {st}")
+    assert st["checked"] >= 25
+
+
+def test_cfg2_full_batch_sampled_parity(tto):
+    """500-bus / 800-branch, 4096 candidates in one launch (FP32 flows); the
+    oracle re-solves a sample of candidates spread over the batch."""
+    w = gg.build_config(2)
+    log("[cfg2] gpu f32")
+    s, out = _run(w, tto, tto.TTO_FLOW_F32, fmax=True)
+    idx = list(np.linspace(0, w.batch.n_cand - 1, 24).astype(int))
+    log("[cfg2] oracle sample")
+    ores = oracle_results(w, idx, keep_n1=False)
+    st = compare(w, out, idx, ores, TOL_F32)
+    log(f"[cfg2] {st}")
+    assert st["checked"] >= 18
+    # FP64 flows on the same batch agree with the oracle to 1e-6 MW
+    log("[cfg2] gpu f64")
+    s64, out64 = _run(w, tto, tto.TTO_FLOW_F64, fmax=True)
+    st = compare(w, out64, idx, ores, TOL_F64, strict_discrete=True)
+    log(f"[cfg2 f64] {st}")
+
+
+def test_archive_matches_sequential_insertion(tto):
+    import torch
+    import oracle
+    w = gg.build_config(2, B=2048)
+    s = make_session(w, tto.TTO_FLOW_F32)
+    db = tto.device_batch(w.batch)
+    arch = s.new_archive()
+    host_fit = np.full(s.n_cells, -np.inf)
+    host_id = np.full(s.n_cells, -1, np.int64)
+    for rep in range(2):
+        out = s.evaluate(db)
+        s.archive_insert(arch, out, id_base=rep * 10000)
+        torch.cuda.synchronize()
+        o = to_numpy(out)
+        ok = (o["status"] & 3) == 0
+        host_fit, host_id = oracle.archive_insert_sequential(host_fit, host_id, o["fitness"],
+                                                             o["cell"], ok, id_base=rep * 10000)
+        np.testing.assert_array_equal(arch[1].cpu().numpy(), host_id)
+        np.testing.assert_array_equal(arch[0].cpu().numpy(), host_fit)
+
+
+def test_repeat_runs_bitwise_identical(tto):
+    import torch
+    w = gg.build_config(2, B=512)
+    s = make_session(w, tto.TTO_FLOW_F32)
+    db = tto.device_batch(w.batch)
+    a = to_numpy(s.evaluate(db, fmax=True))
+    b = to_numpy(s.evaluate(db, fmax=True))
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
