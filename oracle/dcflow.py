@@ -192,6 +192,7 @@ def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], 
     n1 = np.full((len(C), len(M), T), np.nan) if keep_n1 else None
     island = np.zeros(len(C), dtype=bool)
     fmax = np.zeros((len(M), T), dtype=np.float64)
+    argl = np.full((len(M), T), -1, dtype=np.int64)   # first contingency attaining fmax
     for li in positions:
         l = int(C[li])
         if not net.in_service[l]:
@@ -206,12 +207,15 @@ def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], 
         fm = fl[M]
         if keep_n1:
             n1[li] = fm
-        fmax = np.maximum(fmax, np.abs(fm))
+        a = np.abs(fm)
+        upd = (a > fmax) | (argl < 0)
+        argl[upd] = li
+        fmax = np.maximum(fmax, a)
     res = CandidateResult(valid=True, islanded=False, base_flows=f0, n1_flows=n1, fmax=fmax,
                           island_cont=island, n_switched=cand.n_slots_filled)
     if cont_subset is None:
         lim = np.asarray(grid.limit_mw, dtype=np.float64)[M]
-        met = n1_metrics(fmax, f0[M], lim, n1 if keep_n1 else None, island)
+        met = n1_metrics(fmax, f0[M], lim, argl)
         res.metrics = met
         res.metrics["n_island_cont"] = int(island.sum())
         res.fitness = fitness_f1(met["overload_mw"], met["n_crit_n0"], met["n_crit_n1"], w_c0, w_c)
@@ -221,7 +225,7 @@ def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], 
             e_i, t_i, l_i = met["worst"]
             res.metrics["worst_branch"] = int(M[e_i])
             res.metrics["worst_t"] = int(t_i)
-            res.metrics["worst_cont"] = int(C[l_i])
+            res.metrics["worst_cont"] = int(C[l_i]) if l_i >= 0 else -1
     return res
 
 

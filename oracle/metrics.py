@@ -8,7 +8,7 @@ import numpy as np
 
 
 def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
-               n1: Optional[np.ndarray] = None, island: Optional[np.ndarray] = None) -> dict:
+               argl: Optional[np.ndarray] = None) -> dict:
     """Fitness function heuristics section: with f^max_e = max over outages of
     |f^(o)_e| and the clip Pi(x) = max(x, 0),
 
@@ -20,7 +20,8 @@ def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
     loading rho = max_{e,t} f^max_e(t) / fbar_e.  The arg-max (e*, t*, l*) is the
     lexicographically smallest index triple attaining max |f^(l)_e(t)| / fbar_e.
 
-    fmax, f0: [|M|, T]; limit: [|M|]; n1: [|C|, |M|, T] (NaN for skipped l).
+    fmax, f0: [|M|, T]; limit: [|M|]; argl: [|M|, T] position in C of the first
+    contingency attaining fmax (-1 if none).
     """
     lim = limit[:, None]
     over = np.maximum(fmax - lim, 0.0)
@@ -32,8 +33,7 @@ def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
     ratio = fmax / lim
     res["max_loading"] = float(ratio.max()) if ratio.size else 0.0
     res["worst"] = None
-    if n1 is not None and ratio.size:
-        # smallest (e, t) attaining the maximum ratio
+    if ratio.size:
         best = res["max_loading"]
         E, T = ratio.shape
         found = None
@@ -45,15 +45,7 @@ def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
             if found is not None:
                 break
         e, t = found
-        col = np.abs(n1[:, e, t])
-        col = np.where(np.isnan(col), -np.inf, col)
-        if island is not None:
-            col = np.where(island, -np.inf, col)
-        l_best = None
-        if np.isfinite(col).any():
-            top = col.max()
-            l_best = int(np.flatnonzero(col == top)[0])
-        res["worst"] = (e, t, l_best if l_best is not None else -1)
+        res["worst"] = (e, t, int(argl[e, t]) if argl is not None else -1)
     return res
 
 

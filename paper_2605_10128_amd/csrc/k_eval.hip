@@ -41,29 +41,6 @@ namespace tto {
 
 __device__ inline unsigned long long ballot64(bool p) { return __ballot(p); }
 
-// U row of branch e: U[q] for the r columns (openings first, then splits).
-template <int KMAX = kMaxRank>
-__device__ inline void u_row(const GridDev& g, int e, int k, int r, const int* s_open,
-                             const int* s_moff, const int* s_mbr, const double* s_msg,
-                             double* U) {
-  const size_t m = g.n_branch;
-#pragma unroll
-  for (int q = 0; q < kMaxRank; ++q) {
-    double v = 0.0;
-    if (q < k) {
-      v = g.HT[(size_t)s_open[q] * m + e];
-    } else if (q < r) {
-      const int j = q - k;
-      for (int p = s_moff[j]; p < s_moff[j + 1]; ++p) {
-        const int b = s_mbr[p];
-        v -= s_msg[p] * g.HT[(size_t)b * m + e];
-        if (b == e) v += s_msg[p];
-      }
-    }
-    U[q] = v;
-  }
-}
-
 // LU solve with the factors in s_M (row swaps in s_piv), in place on x[0..r).
 __device__ inline void lu_solve(const double (*s_M)[kMaxRank], const int* s_piv, int r,
                                 double* x) {
@@ -71,15 +48,16 @@ __device__ inline void lu_solve(const double (*s_M)[kMaxRank], const int* s_piv,
   for (int i = 0; i < kMaxRank; ++i) {
     if (i < r) {
       const int p = s_piv[i];
-      // swap x[i] and x[p] with constant-index selects (p >= i)
+      // swap x[i] and x[p] (p >= i) with selects only: no dynamic indexing
+      const double xi = x[i];
+      double xp = xi;
 #pragma unroll
-      for (int q = 0; q < kMaxRank; ++q) {
-        if (q > i && q == p) {
-          const double t = x[i];
-          x[i] = x[q];
-          x[q] = t;
-        }
-      }
+      for (int q = 0; q < kMaxRank; ++q)
+        if (q > i) xp = (q == p) ? x[q] : xp;
+#pragma unroll
+      for (int q = 0; q < kMaxRank; ++q)
+        if (q > i) x[q] = (q == p) ? xi : x[q];
+      x[i] = xp;
     }
   }
 #pragma unroll
@@ -101,6 +79,46 @@ __device__ inline void lu_solve(const double (*s_M)[kMaxRank], const int* s_piv,
   }
 }
 
+// Compiler barrier: keeps the per-column LDS reads of x(t) inside the column
+// loops instead of hoisting 8 x TT doubles into registers.
+__device__ inline void keep_in_loop() { __asm__ volatile("" ::: "memory"); }
+
+// Shared description of one candidate inside k_setup.
+struct SetupShared {
+  int open[kMaxRank];      // opened branch ids (column q < k)
+  double bK[kMaxRank];     // their susceptances
+  int sslot[kMaxRank];     // genome slot of split j (for the moved injection)
+  int sbus[kMaxRank];      // split buses
+  int moff[kMaxRank + 1];  // moved-branch ranges per split j
+  int mbr[kMaxMoved];      // moved branch ids
+  int mj[kMaxMoved];       // split index of each moved branch
+  double msign[kMaxMoved]; // sg_b = +1 if b leaves the split bus
+  double msg[kMaxMoved];   // sg_b * b_b
+  double inv_s[kMaxRank];  // 1 / sum_b b_b per split
+  double M[kMaxRank][kMaxRank];
+  int piv[kMaxRank];
+  int hdr[4];              // valid, k, ns, islanded
+};
+
+// Column gather for branch e: W[q] = S[K_q][e] (q < k) and
+// W[k + j] = sum_{b in S_j} sg_b b_b S[b][e]; loads issued four at a time.
+// Written to the per-thread row wrow[0..7] (dynamic q), zero beyond r.
+__device__ inline void gather_column(const GridDev& g, const SetupShared& sh, int e, int k,
+                                     int ns, double* wrow) {
+  const size_t m = g.n_branch;
+  const int r = k + ns;
+#pragma unroll 4
+  for (int q = 0; q < k; ++q) wrow[q] = g.S[(size_t)sh.open[q] * m + e];
+  for (int j = 0; j < ns; ++j) {
+    double acc = 0.0;
+    const int p1 = sh.moff[j + 1];
+#pragma unroll 4
+    for (int p = sh.moff[j]; p < p1; ++p) acc += sh.msg[p] * g.S[(size_t)sh.mbr[p] * m + e];
+    wrow[k + j] = acc;
+  }
+  for (int q = r; q < kMaxRank; ++q) wrow[q] = 0.0;
+}
+
 template <typename F, int TT>
 __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs<F> w,
                                                double* __restrict__ base_out) {
@@ -109,16 +127,9 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   const int tid = threadIdx.x;
   const int m = g.n_branch, T = g.T, nM = g.nM, nC = g.nC;
 
-  __shared__ int s_open[kMaxRank], s_sbus[kMaxRank], s_sslot[kMaxRank];
-  __shared__ int s_moff[kMaxRank + 1];
-  __shared__ int s_mbr[kMaxMoved];
-  __shared__ double s_msg[kMaxMoved];
-  __shared__ double s_msign[kMaxMoved];
-  __shared__ double s_inv_s[kMaxRank];
-  __shared__ double s_M[kMaxRank][kMaxRank];
-  __shared__ int s_piv[kMaxRank];
+  __shared__ SetupShared sh;
   __shared__ double s_x[kMaxRank][TT];
-  __shared__ int s_hdr[4];  // valid, k, s, islanded
+  __shared__ double s_w[256][kMaxRank + 1];   // per-thread column gather (padded)
   __shared__ int s_wcnt[4];
   __shared__ int s_base, s_n0, s_nisl;
 
@@ -128,53 +139,55 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
       const int v = bt.open[(size_t)c * bt.no + i];
       if (v == -1) continue;
       if (v < 0 || v >= m) { valid = 0; continue; }
-      for (int q = 0; q < k; ++q) if (s_open[q] == v) valid = 0;
+      for (int q = 0; q < k; ++q) if (sh.open[q] == v) valid = 0;
       if (k >= kMaxRank) { valid = 0; continue; }
-      s_open[k++] = v;
+      sh.bK[k] = g.b[v];
+      sh.open[k++] = v;
     }
     for (int j = 0; j < bt.ns; ++j) {
       const int bus = bt.sbus[(size_t)c * bt.ns + j];
       if (bus == -1) continue;
       if (bus < 0 || bus >= g.n_bus || s >= kMaxRank) { valid = 0; continue; }
-      for (int q = 0; q < s; ++q) if (s_sbus[q] == bus) valid = 0;
+      for (int q = 0; q < s; ++q) if (sh.sbus[q] == bus) valid = 0;
       const int lo = bt.moff[(size_t)c * bt.ns + j], hi = bt.moff[(size_t)c * bt.ns + j + 1];
       // CSR sanity: offsets inside [0, total moved] and increasing
       const int tot = bt.moff[(size_t)bt.B * bt.ns];
       if (lo < 0 || hi > tot || hi <= lo) { valid = 0; continue; }
-      s_moff[s] = nm;
+      sh.moff[s] = nm;
       double ssum = 0.0;
       for (int p = lo; p < hi; ++p) {
         const int e = bt.mbr[p];
         if (e < 0 || e >= m) { valid = 0; continue; }
         const int f = g.from[e], t = g.to[e];
         if (f != bus && t != bus) valid = 0;
-        for (int q = s_moff[s]; q < nm; ++q) if (s_mbr[q] == e) valid = 0;
-        for (int q = 0; q < k; ++q) if (s_open[q] == e) valid = 0;
+        for (int q = sh.moff[s]; q < nm; ++q) if (sh.mbr[q] == e) valid = 0;
+        for (int q = 0; q < k; ++q) if (sh.open[q] == e) valid = 0;
         if (nm >= kMaxMoved) { valid = 0; continue; }
         const double sg = (f == bus) ? 1.0 : -1.0;
-        s_mbr[nm] = e;
-        s_msign[nm] = sg;
-        s_msg[nm] = sg * g.b[e];
+        sh.mbr[nm] = e;
+        sh.mj[nm] = s;
+        sh.msign[nm] = sg;
+        sh.msg[nm] = sg * g.b[e];
         ssum += g.b[e];
         ++nm;
       }
-      s_sbus[s] = bus;
-      s_sslot[s] = j;
-      s_inv_s[s] = ssum > 0.0 ? 1.0 / ssum : 0.0;
+      sh.sbus[s] = bus;
+      sh.sslot[s] = j;
+      sh.inv_s[s] = ssum > 0.0 ? 1.0 / ssum : 0.0;
       ++s;
     }
-    s_moff[s] = nm;
+    sh.moff[s] = nm;
     if (k + s > kMaxRank) valid = 0;
-    s_hdr[0] = valid;
-    s_hdr[1] = k;
-    s_hdr[2] = s;
-    s_hdr[3] = 0;
+    sh.hdr[0] = valid;
+    sh.hdr[1] = k;
+    sh.hdr[2] = s;
+    sh.hdr[3] = 0;
     s_base = 0;
     s_n0 = 0;
     s_nisl = 0;
   }
   __syncthreads();
-  const int valid = s_hdr[0], k = s_hdr[1], ns = s_hdr[2];
+  const int valid = sh.hdr[0], k = sh.hdr[1], ns = sh.hdr[2];
   const int r = k + ns;
   CandInfo* inf = w.info + c;
   if (!valid) {
@@ -186,61 +199,63 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     return;
   }
 
-  // bordered matrix M_c, one entry per thread
+  // bordered matrix M_c, one entry per thread; H_ab = b_a S_ab
   if (tid < r * r) {
     const int i = tid / r, q = tid - (tid / r) * r;
+    const size_t mm = m;
     double v = 0.0;
     if (i < k) {
-      const size_t ki = (size_t)s_open[i] * m;
+      const size_t ki = (size_t)sh.open[i] * mm;
       if (q < k) {
-        v = (i == q ? 1.0 : 0.0) - g.H[ki + s_open[q]];
+        v = (i == q ? 1.0 : 0.0) - sh.bK[i] * g.S[ki + sh.open[q]];
       } else {
         const int j = q - k;
-        for (int p = s_moff[j]; p < s_moff[j + 1]; ++p) v += s_msg[p] * g.H[ki + s_mbr[p]];
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) v += sh.msg[p] * g.S[ki + sh.mbr[p]];
+        v *= sh.bK[i];
       }
     } else {
       const int j = i - k;
       if (q < k) {
-        for (int p = s_moff[j]; p < s_moff[j + 1]; ++p)
-          v += s_msign[p] * g.H[(size_t)s_mbr[p] * m + s_open[q]];
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p)
+          v += sh.msg[p] * g.S[(size_t)sh.mbr[p] * mm + sh.open[q]];
       } else {
         const int j2 = q - k;
-        for (int p = s_moff[j]; p < s_moff[j + 1]; ++p) {
-          const size_t bp = (size_t)s_mbr[p] * m;
-          for (int p2 = s_moff[j2]; p2 < s_moff[j2 + 1]; ++p2) {
-            v -= s_msign[p] * s_msg[p2] * g.H[bp + s_mbr[p2]];
-            if (s_mbr[p] == s_mbr[p2]) v += s_msign[p] * s_msign[p2] * g.b[s_mbr[p]];
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) {
+          const size_t bp = (size_t)sh.mbr[p] * mm;
+          for (int p2 = sh.moff[j2]; p2 < sh.moff[j2 + 1]; ++p2) {
+            v -= sh.msg[p] * sh.msg[p2] * g.S[bp + sh.mbr[p2]];
+            if (sh.mbr[p] == sh.mbr[p2]) v += sh.msign[p] * sh.msign[p2] * g.b[sh.mbr[p]];
           }
         }
       }
-      v *= s_inv_s[j];
+      v *= sh.inv_s[j];
     }
-    s_M[i][q] = v;
+    sh.M[i][q] = v;
   }
   __syncthreads();
   if (tid == 0) {
     double minpiv = DBL_MAX;
     for (int p = 0; p < r; ++p) {
       int best = p;
-      double bv = fabs(s_M[p][p]);
+      double bv = fabs(sh.M[p][p]);
       for (int i = p + 1; i < r; ++i)
-        if (fabs(s_M[i][p]) > bv) { bv = fabs(s_M[i][p]); best = i; }
-      s_piv[p] = best;
+        if (fabs(sh.M[i][p]) > bv) { bv = fabs(sh.M[i][p]); best = i; }
+      sh.piv[p] = best;
       if (best != p)
-        for (int q = 0; q < r; ++q) { const double t = s_M[p][q]; s_M[p][q] = s_M[best][q]; s_M[best][q] = t; }
+        for (int q = 0; q < r; ++q) { const double t = sh.M[p][q]; sh.M[p][q] = sh.M[best][q]; sh.M[best][q] = t; }
       minpiv = fmin(minpiv, bv);
       if (bv > 0.0) {
         for (int i = p + 1; i < r; ++i) {
-          const double f = s_M[i][p] / s_M[p][p];
-          s_M[i][p] = f;
-          for (int q = p + 1; q < r; ++q) s_M[i][q] -= f * s_M[p][q];
+          const double f = sh.M[i][p] / sh.M[p][p];
+          sh.M[i][p] = f;
+          for (int q = p + 1; q < r; ++q) sh.M[i][q] -= f * sh.M[p][q];
         }
       }
     }
-    s_hdr[3] = (r > 0 && minpiv < kTauIsland) ? 1 : 0;
+    sh.hdr[3] = (r > 0 && minpiv < kTauIsland) ? 1 : 0;
   }
   __syncthreads();
-  if (s_hdr[3]) {
+  if (sh.hdr[3]) {
     if (tid == 0) {
       inf->status = TTO_ST_ISLANDED;
       inf->r = r; inf->k = k; inf->n_act = 0; inf->n_act_pad = 0; inf->n_island = 0;
@@ -249,7 +264,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     return;
   }
 
-  // x(t) = M_c^{-1} rhs(t)
+  // x(t) = M_c^{-1} rhs(t), rhs = [f0_K ; (p_j - phi_j) / s_j]
   if (tid < TT) {
     const int t = tid;
     double x[kMaxRank];
@@ -258,31 +273,50 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
       double v = 0.0;
       if (t < T) {
         if (q < k) {
-          v = g.f0[(size_t)s_open[q] * T + t];
+          v = g.f0[(size_t)sh.open[q] * T + t];
         } else if (q < r) {
           const int j = q - k;
           double phi = 0.0;
-          for (int p = s_moff[j]; p < s_moff[j + 1]; ++p) phi += s_msign[p] * g.f0[(size_t)s_mbr[p] * T + t];
-          const double pj = bt.mp ? bt.mp[((size_t)c * bt.ns + s_sslot[j]) * T + t] : 0.0;
-          v = (pj - phi) * s_inv_s[j];
+          for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) phi += sh.msign[p] * g.f0[(size_t)sh.mbr[p] * T + t];
+          const double pj = bt.mp ? bt.mp[((size_t)c * bt.ns + sh.sslot[j]) * T + t] : 0.0;
+          v = (pj - phi) * sh.inv_s[j];
         }
       }
       x[q] = v;
     }
-    if (t < T) lu_solve(s_M, s_piv, r, x);
+    if (t < T) lu_solve(sh.M, sh.piv, r, x);
 #pragma unroll
     for (int q = 0; q < kMaxRank; ++q) s_x[q][t] = (t < T) ? x[q] : 0.0;
   }
   __syncthreads();
 
+  double* wrow = s_w[tid];
+  const int nm = sh.moff[ns];
+  // U row of branch e from its column gather: U_q = b_e W_q (openings),
+  // U_{k+j} = -b_e W_{k+j} + sum_{b in S_j, b = e} sg_b b_b (moved-branch term)
+  auto u_from_w = [&](int e, double be, double* U) {
+#pragma unroll
+    for (int q = 0; q < kMaxRank; ++q) U[q] = (q < k ? be : -be) * wrow[q];
+    for (int p = 0; p < nm; ++p) {
+      if (sh.mbr[p] == e) {
+        const int qq = k + sh.mj[p];
+#pragma unroll
+        for (int q = 0; q < kMaxRank; ++q)
+          if (q == qq) U[q] += sh.msg[p];
+      }
+    }
+  };
+
   // monitored rows: f'_M and U_M
   int n0 = 0;
   for (int ei = tid; ei < nM; ei += 256) {
+    keep_in_loop();
     const int e = g.mon[ei];
     bool opened = false;
-    for (int q = 0; q < k; ++q) opened |= (s_open[q] == e);
+    for (int q = 0; q < k; ++q) opened |= (sh.open[q] == e);
+    gather_column(g, sh, e, k, ns, wrow);
     double U[kMaxRank];
-    u_row(g, e, k, r, s_open, s_moff, s_mbr, s_msg, U);
+    u_from_w(e, g.b[e], U);
     const double lim = g.lim[e];
     F* fo = w.fM + ((size_t)c * nM + ei) * TT;
 #pragma unroll
@@ -305,10 +339,12 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   // optional full post-switch base flows
   if (base_out) {
     for (int e = tid; e < m; e += 256) {
+      keep_in_loop();
       bool opened = false;
-      for (int q = 0; q < k; ++q) opened |= (s_open[q] == e);
+      for (int q = 0; q < k; ++q) opened |= (sh.open[q] == e);
+      gather_column(g, sh, e, k, ns, wrow);
       double U[kMaxRank];
-      u_row(g, e, k, r, s_open, s_moff, s_mbr, s_msg, U);
+      u_from_w(e, g.b[e], U);
       for (int t = 0; t < T; ++t) {
         double fp = 0.0;
         if (!opened) {
@@ -327,41 +363,43 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   int* act = w.act + (size_t)c * (nC + 1);
   int nisl = 0;
   for (int base = 0; base < nC; base += 256) {
+    keep_in_loop();
     const int li = base + tid;
-    bool active = false, island = false;
-    double V[kMaxRank];
-    double phi[TT];
+    bool active = false, island = false, opened = false;
+    int l = 0;
+    double V[kMaxRank], U[kMaxRank];
+    double inv_d = 0.0;
 #pragma unroll
-    for (int q = 0; q < kMaxRank; ++q) V[q] = 0.0;
-#pragma unroll
-    for (int t = 0; t < TT; ++t) phi[t] = 0.0;
+    for (int q = 0; q < kMaxRank; ++q) { V[q] = 0.0; U[q] = 0.0; }
     if (li < nC) {
-      const int l = g.cont[li];
-      bool opened = false;
-      for (int q = 0; q < k; ++q) opened |= (s_open[q] == l);
+      l = g.cont[li];
+      for (int q = 0; q < k; ++q) opened |= (sh.open[q] == l);
       if (opened) {
         active = true;  // already open: the N-0 state (phi = 0)
       } else {
+        gather_column(g, sh, l, k, ns, wrow);
+        const double bl = g.b[l];
+        // right-hand side of the factor column: R_q = b_{K_q} W_q (openings),
+        // R_{k+j} = (ps_j - W_{k+j}) / s_j with ps_j = sg_l if l is moved by j
 #pragma unroll
         for (int q = 0; q < kMaxRank; ++q) {
           double v = 0.0;
-          if (q < k) {
-            v = g.H[(size_t)s_open[q] * m + l];
-          } else if (q < r) {
-            const int j = q - k;
-            double y = 0.0, ps = 0.0;
-            for (int p = s_moff[j]; p < s_moff[j + 1]; ++p) {
-              y += s_msign[p] * g.H[(size_t)s_mbr[p] * m + l];
-              if (s_mbr[p] == l) ps += s_msign[p];
-            }
-            v = (ps - y) * s_inv_s[j];
-          }
+          if (q < k) v = sh.bK[q] * wrow[q];
+          else if (q < r) v = -wrow[q] * sh.inv_s[q - k];
           V[q] = v;
         }
-        lu_solve(s_M, s_piv, r, V);
-        double U[kMaxRank];
-        u_row(g, l, k, r, s_open, s_moff, s_mbr, s_msg, U);
-        double hll = g.H[(size_t)l * m + l];
+        for (int p = 0; p < nm; ++p) {
+          if (sh.mbr[p] == l) {
+            const int qq = k + sh.mj[p];
+            const double add = sh.msign[p] * sh.inv_s[sh.mj[p]];
+#pragma unroll
+            for (int q = 0; q < kMaxRank; ++q)
+              if (q == qq) V[q] += add;
+          }
+        }
+        u_from_w(l, bl, U);
+        lu_solve(sh.M, sh.piv, r, V);
+        double hll = bl * g.S[(size_t)l * m + l];
 #pragma unroll
         for (int q = 0; q < kMaxRank; ++q) hll += U[q] * V[q];
         const double d = 1.0 - hll;
@@ -369,16 +407,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
           island = true;
         } else {
           active = true;
-          const double inv = 1.0 / d;
-#pragma unroll
-          for (int t = 0; t < TT; ++t) {
-            if (t < T) {
-              double fl = g.f0[(size_t)l * T + t];
-#pragma unroll
-              for (int q = 0; q < kMaxRank; ++q) fl += U[q] * s_x[q][t];
-              phi[t] = fl * inv;
-            }
-          }
+          inv_d = 1.0 / d;
         }
       }
     }
@@ -390,9 +419,19 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     for (int q = 0; q < wid; ++q) off += s_wcnt[q];
     off += __popcll(mask & ((1ull << lane) - 1ull));
     if (active) {
+      // phi_l(t) = f'_l(t) / (1 - H'_ll), zero for an already opened l
       F* ro = rec + (size_t)off * RS;
 #pragma unroll
-      for (int t = 0; t < TT; ++t) ro[t] = (F)phi[t];
+      for (int t = 0; t < TT; ++t) {
+        double ph = 0.0;
+        if (t < T && !opened) {
+          double fl = g.f0[(size_t)l * T + t];
+#pragma unroll
+          for (int q = 0; q < kMaxRank; ++q) fl += U[q] * s_x[q][t];
+          ph = fl * inv_d;
+        }
+        ro[t] = (F)ph;
+      }
 #pragma unroll
       for (int q = 0; q < kVSlots; ++q) ro[TT + q] = (F)V[q];
 #pragma unroll
@@ -422,7 +461,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     inf->n_act_pad = n_act + (n_act & 1);
     inf->n_island = s_nisl;
     inf->n_crit_n0 = s_n0;
-    for (int q = 0; q < kMaxRank; ++q) inf->open_br[q] = q < k ? s_open[q] : -1;
+    for (int q = 0; q < kMaxRank; ++q) inf->open_br[q] = q < k ? sh.open[q] : -1;
   }
 }
 
@@ -453,10 +492,16 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   for (int j = 0; j < R; ++j) U[j] = ua[j];
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
+  if (n_act_pad == 0) return;
+  // software pipeline: the H entries of the next pair are in flight while the
+  // current pair is consumed (the last prefetch re-reads an in-range pair)
+  F hn0 = HMC[(size_t)act[0] * nM + ei_c];
+  F hn1 = HMC[(size_t)act[1] * nM + ei_c];
   for (int i = 0; i < n_act_pad; i += 2) {
-    const int l0 = act[i], l1 = act[i + 1];
-    F h0 = HMC[(size_t)l0 * nM + ei_c];
-    F h1 = HMC[(size_t)l1 * nM + ei_c];
+    F h0 = hn0, h1 = hn1;
+    const int nx = (i + 2 < n_act_pad) ? i + 2 : i;
+    hn0 = HMC[(size_t)act[nx] * nM + ei_c];
+    hn1 = HMC[(size_t)act[nx + 1] * nM + ei_c];
     const F* r0 = rec + (size_t)i * RS;
     const F* r1 = r0 + RS;
 #pragma unroll
@@ -473,8 +518,17 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   }
 }
 
+#ifndef TTO_SWEEP_WPE
+#define TTO_SWEEP_WPE 0
+#endif
+#if TTO_SWEEP_WPE > 0
+#define TTO_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(TTO_SWEEP_WPE, 8)))
+#else
+#define TTO_SWEEP_ATTR
+#endif
+
 template <typename F, int TT>
-__global__ __launch_bounds__(256) void k_sweep(GridDev g, SweepBufs<F> w,
+__global__ __launch_bounds__(256) TTO_SWEEP_ATTR void k_sweep(GridDev g, SweepBufs<F> w,
                                                const F* __restrict__ HMC,
                                                double* __restrict__ fmax_out) {
   const int c = blockIdx.y;

@@ -1,5 +1,5 @@
-// Grid-level kernels: H = PTDF * A^T (both layouts), the monitored x contingency
-// block of H, precision conversions, and the base-flow GEMM f0 = PTDF * P on
+// Grid-level kernels: the symmetric sensitivity matrix S = A L^-1 A^T, the
+// monitored x contingency block of H = diag(b) S, precision conversions, and the base-flow GEMM f0 = PTDF * P on
 // MFMA (Importer: PTDF of the pre-optimisation topology; DC-Optimizer: flows
 // are linear in the injections).
 #include "tto_common.h"
@@ -12,40 +12,49 @@ typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
 typedef _Float16 v8f16 __attribute__((ext_vector_type(8)));
 typedef unsigned short v8u16 __attribute__((ext_vector_type(8)));
 
-// H[e][l] = PTDF[e][from(l)] - PTDF[e][to(l)]: flow on e per MW sent from
-// from(l) to to(l).
-__global__ __launch_bounds__(256) void k_build_H(const double* __restrict__ ptdf,
+// S[e][l] = (PTDF[e][from(l)] - PTDF[e][to(l)]) / b_e: with PTDF = diag(b) A L^-1
+// this is (A L^-1 A^T)_el, symmetric in exact arithmetic.
+__global__ __launch_bounds__(256) void k_build_S(const double* __restrict__ ptdf,
                                                  const int* __restrict__ from,
-                                                 const int* __restrict__ to, int m, int n,
-                                                 double* __restrict__ H) {
+                                                 const int* __restrict__ to,
+                                                 const double* __restrict__ b, int m, int n,
+                                                 double* __restrict__ S) {
   const int e = blockIdx.y;
   const int l = blockIdx.x * 256 + threadIdx.x;
   if (l >= m) return;
   const double* row = ptdf + (size_t)e * n;
-  H[(size_t)e * m + l] = row[from[l]] - row[to[l]];
+  S[(size_t)e * m + l] = (row[from[l]] - row[to[l]]) / b[e];
 }
 
-// HT = H^T through a 64x64 LDS tile (coalesced reads and writes).
-__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ H, int m,
-                                                   double* __restrict__ HT) {
-  __shared__ double tile[64][65];
-  const int bx = blockIdx.x * 64, by = blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
+// In-place symmetrisation S <- (S + S^T) / 2 over 64x64 tile pairs (I <= J),
+// so that rows and columns of S are bit-identical.
+__global__ __launch_bounds__(256) void k_symmetrize(double* __restrict__ S, int m) {
+  __shared__ double a[64][65], c[64][65];
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int r = ty; r < 64; r += 4) {
-    const int row = by + r, col = bx + tx;
-    if (row < m && col < m) tile[r][tx] = H[(size_t)row * m + col];
+    const int ra = I * 64 + r, ca = J * 64 + tx;   // tile (I, J)
+    const int rc = J * 64 + r, cc = I * 64 + tx;   // tile (J, I)
+    a[r][tx] = (ra < m && ca < m) ? S[(size_t)ra * m + ca] : 0.0;
+    c[r][tx] = (rc < m && cc < m) ? S[(size_t)rc * m + cc] : 0.0;
   }
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {
-    const int row = bx + r, col = by + tx;   // HT[row=l][col=e] = H[e][l]
-    if (row < m && col < m) HT[(size_t)row * m + col] = tile[tx][r];
+    const int ra = I * 64 + r, ca = J * 64 + tx;
+    const int rc = J * 64 + r, cc = I * 64 + tx;
+    const double va = 0.5 * (a[r][tx] + c[tx][r]);
+    const double vc = 0.5 * (c[r][tx] + a[tx][r]);
+    if (ra < m && ca < m) S[(size_t)ra * m + ca] = va;
+    if (rc < m && cc < m) S[(size_t)rc * m + cc] = vc;
   }
 }
 
-// Contingency-major monitored block: HMC[li][ei] = H[M[ei]][C[li]], with the
+// Contingency-major monitored block: HMC[li][ei] = H[M[ei], C[li]], with the
 // line-outage convention that the outaged branch's own entry is H_ll - 1 so
 // that its post-contingency flow f_l + (H'_ll - 1) f_l / (1 - H'_ll) is zero.
-__global__ __launch_bounds__(256) void k_build_HMC(const double* __restrict__ HT,
+__global__ __launch_bounds__(256) void k_build_HMC(const double* __restrict__ S,
+                                                   const double* __restrict__ b,
                                                    const int* __restrict__ mon,
                                                    const int* __restrict__ cont, int m, int nM,
                                                    float* __restrict__ H32,
@@ -54,7 +63,7 @@ __global__ __launch_bounds__(256) void k_build_HMC(const double* __restrict__ HT
   const int ei = blockIdx.x * 256 + threadIdx.x;
   if (ei >= nM) return;
   const int l = cont[li], e = mon[ei];
-  double v = HT[(size_t)l * m + e];
+  double v = b[e] * S[(size_t)l * m + e];
   if (e == l) v -= 1.0;
   H32[(size_t)li * nM + ei] = (float)v;
   H64[(size_t)li * nM + ei] = v;
@@ -105,8 +114,8 @@ __global__ __launch_bounds__(256) void k_pack_injections(const double* __restric
 // columns (two 16x16 output tiles) over one k-chunk.  The order of the k
 // index inside a chunk is free, so every lane group reads a contiguous run
 // of its row (A) and of its timestep column (PT) and feeds consecutive MFMAs.
-// Output layout of a 16x16 MFMA tile: lane L holds rows 4*(L/16)+v, v<4, of
-// column L%16.
+// Output layout of a 16x16 FP32-accumulating MFMA tile: lane L holds rows
+// 4*(L/16)+v, v<4, of column L%16 (FP64: rows L/16 + 4v).
 template <int PREC>
 __global__ __launch_bounds__(64) void k_gemm_f0(const void* __restrict__ Av,
                                                 const void* __restrict__ PTv, int m, int ld,
@@ -137,9 +146,10 @@ __global__ __launch_bounds__(64) void k_gemm_f0(const void* __restrict__ Av,
       c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.w, b0.w, c0, 0, 0, 0);
       c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.w, b1.w, c1, 0, 0, 0);
     }
+    // the FP64 16x16x4 MFMA interleaves its rows: lane L holds rows L/16 + 4v
     double* out = part64 + (size_t)ks * m * kGemmN;
     for (int v = 0; v < 4; ++v) {
-      const int row = row0 + 4 * lg + v;
+      const int row = row0 + lg + 4 * v;
       if (row < m) {
         if (li < T) out[(size_t)row * kGemmN + li] = c0[v];
         if (16 + li < T) out[(size_t)row * kGemmN + 16 + li] = c1[v];
@@ -219,16 +229,16 @@ __global__ __launch_bounds__(256) void k_reduce_f0(const P* __restrict__ part, i
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-hipError_t launch_build_H(const double* ptdf, const int* from, const int* to, int m, int n,
-                          double* H, double* HT, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_H, dim3(cdiv(m, 256), m), dim3(256), 0, s, ptdf, from, to, m, n, H);
-  hipLaunchKernelGGL(k_transpose, dim3(cdiv(m, 64), cdiv(m, 64)), dim3(256), 0, s, H, m, HT);
+hipError_t launch_build_S(const double* ptdf, const int* from, const int* to, const double* b,
+                          int m, int n, double* S, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_S, dim3(cdiv(m, 256), m), dim3(256), 0, s, ptdf, from, to, b, m, n, S);
+  hipLaunchKernelGGL(k_symmetrize, dim3(cdiv(m, 64), cdiv(m, 64)), dim3(256), 0, s, S, m);
   return hipGetLastError();
 }
 
-hipError_t launch_build_HMC(const double* HT, const int* mon, const int* cont, int m, int nM,
-                            int nC, float* HMC32, double* HMC64, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_HMC, dim3(cdiv(nM, 256), nC), dim3(256), 0, s, HT, mon, cont, m,
+hipError_t launch_build_HMC(const double* S, const double* b, const int* mon, const int* cont,
+                            int m, int nM, int nC, float* HMC32, double* HMC64, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_HMC, dim3(cdiv(nM, 256), nC), dim3(256), 0, s, S, b, mon, cont, m,
                      nM, HMC32, HMC64);
   return hipGetLastError();
 }

@@ -62,7 +62,7 @@ size_t gemm_esize(int prec) {
 
 struct GridLayout {
   int* from; int* to; double* b; double* lim; int* mon; int* cont; double* edges;
-  double* H; double* HT; float* HMC32; double* HMC64; double* f0;
+  double* S; float* HMC32; double* HMC64; double* f0;
   void* A; void* PT; float* part32; double* part64;
   int ksplit;
 };
@@ -78,8 +78,7 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   L.mon = cv.take<int>(d->n_monitored);
   L.cont = cv.take<int>(std::max(d->n_contingency, 1));
   L.edges = cv.take<double>(TTO_MAX_LOAD_BINS);
-  L.H = cv.take<double>(m * m);
-  L.HT = cv.take<double>(m * m);
+  L.S = cv.take<double>(m * m);
   L.HMC32 = cv.take<float>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
   L.HMC64 = cv.take<double>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
   L.f0 = cv.take<double>(m * T);
@@ -243,9 +242,9 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   double edges[31];
   for (int i = 0; i < 31; ++i) edges[i] = 0.25 * pow(256.0, i / 30.0);
   HIP_TRY(hipMemcpyAsync(L.edges, edges, sizeof(edges), hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_build_H(d->ptdf, L.from, L.to, m, n, L.H, L.HT, s));
+  HIP_TRY(launch_build_S(d->ptdf, L.from, L.to, L.b, m, n, L.S, s));
   if (d->n_contingency > 0)
-    HIP_TRY(launch_build_HMC(L.HT, L.mon, L.cont, m, d->n_monitored, d->n_contingency, L.HMC32, L.HMC64, s));
+    HIP_TRY(launch_build_HMC(L.S, L.b, L.mon, L.cont, m, d->n_monitored, d->n_contingency, L.HMC32, L.HMC64, s));
   HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, d->gemm_precision, L.A, s));
   HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -260,7 +259,7 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   g->L = L;
   GridDev& v = g->dev;
   v.n_bus = n; v.n_branch = m; v.slack = d->slack; v.T = g->T; v.TT = g->TT; v.nM = g->nM; v.nC = g->nC;
-  v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.H = L.H; v.HT = L.HT;
+  v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S;
   v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.mon = L.mon; v.cont = L.cont;
   v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
   *out = g;

@@ -36,8 +36,9 @@ struct GridDev {
   const int* to;
   const double* b;
   const double* lim;
-  const double* H;      // [m][m], H[e*m + l]: flow on e per unit transfer across l
-  const double* HT;     // [m][m], HT[l*m + e] = H[e*m + l]
+  // S = A L^-1 A^T, symmetric [m][m]; the flow on e per MW sent across l is
+  // H_el = b_e S_el, so any row or column of H is a contiguous row of S.
+  const double* S;
   const float* HMC32;   // [nC][nM], H[M[ei], C[li]] with -1 where M[ei] == C[li]
   const double* HMC64;  // same in FP64
   const double* f0;     // [m][T] base flows of the unswitched grid
@@ -94,10 +95,10 @@ struct SweepBufs {
 };
 
 // ---- launchers (k_grid.hip) -------------------------------------------------
-hipError_t launch_build_H(const double* ptdf, const int* from, const int* to, int m, int n,
-                          double* H, double* HT, hipStream_t s);
-hipError_t launch_build_HMC(const double* HT, const int* mon, const int* cont, int m, int nM,
-                            int nC, float* HMC32, double* HMC64, hipStream_t s);
+hipError_t launch_build_S(const double* ptdf, const int* from, const int* to, const double* b,
+                          int m, int n, double* S, hipStream_t s);
+hipError_t launch_build_HMC(const double* S, const double* b, const int* mon, const int* cont,
+                            int m, int nM, int nC, float* HMC32, double* HMC64, hipStream_t s);
 hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void* out, hipStream_t s);
 hipError_t launch_pack_injections(const double* p, int n, int T, int prec, void* PT, hipStream_t s);
 hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n, int T,

@@ -331,8 +331,8 @@ def test_metrics_hand_worked_example():
     assert met["max_loading"] == pytest.approx(ex["max_loading"], abs=1e-12)
     fit = o.fitness_f1(met["overload_mw"], met["n_crit_n0"], met["n_crit_n1"])
     assert fit == pytest.approx(ex["fitness_f1"], abs=1e-12)
-    n1 = np.stack([np.zeros_like(fmax), fmax])   # contingency 1 attains fmax
-    met2 = o.n1_metrics(fmax, f0, lim, n1)
+    argl = np.ones(fmax.shape, dtype=int)            # contingency 1 attains fmax
+    met2 = o.n1_metrics(fmax, f0, lim, argl)
     assert met2["worst"] == (ex["worst_e"], ex["worst_t"], 1)
 
 
@@ -372,3 +372,21 @@ def test_archive_strict_and_order_invariant():
     np.testing.assert_array_equal(bi2, bi)
     # islanded / invalid candidates never enter
     assert not np.isin(bi[bi >= 0], np.flatnonzero(~ok)).any()
+
+
+def test_running_argmax_matches_full_tensor():
+    """The arg-max contingency tracked during the loop equals the first
+    maximiser of the stored N-1 tensor at (e*, t*)."""
+    w = gg.build_config(2, B=6, move_frac=0.5)
+    edges = gg.default_load_edges()
+    for c in range(6):
+        cand = o.candidate_from_batch(w.batch, c)
+        r = o.evaluate_candidate(w.grid, w.P, w.M, w.C, cand, edges, keep_n1=True)
+        if r.islanded or not r.valid:
+            continue
+        e = int(np.flatnonzero(w.M == r.metrics["worst_branch"])[0])
+        t_ = r.metrics["worst_t"]
+        col = np.abs(r.n1_flows[:, e, t_])
+        col = np.where(np.isnan(col), -np.inf, col)
+        assert r.metrics["worst_cont"] == int(w.C[int(np.flatnonzero(col == col.max())[0])])
+        np.testing.assert_allclose(r.fmax, np.nanmax(np.abs(r.n1_flows), axis=0))
