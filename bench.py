@@ -73,6 +73,10 @@ def main():
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--flow", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan", default="auto",
+                    help="sweep plan 'auto' (autotune) or 'block,xcd,persistent', e.g. 64,1,0")
+    ap.add_argument("--sweep-plans", action="store_true",
+                    help="also report the sweep time of every plan (stderr)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -105,6 +109,24 @@ def main():
     arch = s.new_archive()
     stream = torch.cuda.current_stream()
     log(f"[bench] grid ready; ws grid {s.grid_bytes/2**30:.2f} GiB batch {s.batch_bytes/2**30:.2f} GiB")
+    if args.sweep_plans:
+        tto.tto_profile_enable(s.handle, True)
+        for plan in [(256, 0, 0), (256, 1, 0)]:
+            s.set_sweep_plan(*plan)
+            ts = []
+            for _ in range(3):
+                s.evaluate(db, out)
+                ts.append(tto.tto_profile_read(s.handle)[1])
+            log(f"[bench] plan block={plan[0]} xcd={plan[1]} persistent={plan[2]}: "
+                f"sweep {sorted(ts)[1]:.3f} ms")
+        tto.tto_profile_enable(s.handle, False)
+    if args.plan == "auto":
+        chosen = s.autotune(db, out)   # untimed: picks the sweep launch shape
+    else:
+        bs, x, p = (int(v) for v in args.plan.split(","))
+        s.set_sweep_plan(bs, bool(x), bool(p))
+        chosen = {"block": bs, "xcd_group": bool(x), "persistent": bool(p), "from_cache": False}
+    log(f"[bench] sweep plan {chosen}")
 
     for i in range(args.warmup):
         s.evaluate(db, out)
@@ -164,6 +186,7 @@ def main():
                         f"|M|={len(w.M)}, |C|={len(w.C)}, rank 0..8 (exact evaluation)",
             "flow_precision": args.flow,
             "candidates_ok": int(ok.sum()),
+            "sweep_plan": {k: chosen[k] for k in ("block", "xcd_group", "persistent")},
             "islanded": int(((o["status"] & 1) != 0).sum()),
         },
         "roofline": {

@@ -269,6 +269,33 @@ tto_status tto_archive_insert(tto_grid* grid, double* elite_fitness, int64_t* el
 tto_status tto_profile_enable(tto_grid* grid, int32_t enable);
 tto_status tto_profile_read(tto_grid* grid, double* ms);
 
+/*
+ * Launch shape of the N-1 sweep (batching of uneven-rank candidates).  A
+ * tile is one candidate x `block` monitored branches (64, 128 or 256 lanes).
+ * xcd_group != 0 deals the tiles of one candidate onto one XCD (shared L2 for
+ * its contingency records); persistent != 0 launches a machine-sized grid
+ * whose workgroups pull tiles from a counter in rank-descending candidate
+ * order (longest tiles first).  Default: block 256, no grouping, not
+ * persistent.  TTO_E_INVALID for other block sizes; TTO_E_UNSUPPORTED for
+ * blocks 64/128 and for persistent != 0, which this build switches off.
+ */
+tto_status tto_set_sweep_plan(tto_grid* grid, int32_t block, int32_t xcd_group,
+                              int32_t persistent);
+tto_status tto_get_sweep_plan(tto_grid* grid, int32_t* block, int32_t* xcd_group,
+                              int32_t* persistent);
+
+/*
+ * Autotuner: times every sweep plan on this batch (three tto_evaluate calls
+ * each, median of the sweep stage by HIP events), keeps the fastest.  With a
+ * non-empty cache_path, a line "<device> <shape>|<block> <xcd> <persistent>"
+ * is looked up first (no timing when found) and appended after tuning.
+ * chosen (optional, int32[4]) receives block, xcd, persistent and 1 if the
+ * cache answered.  Synchronises `stream`; overwrites the outputs.
+ */
+tto_status tto_autotune(tto_grid* grid, const tto_batch* batch, const tto_outputs* out,
+                        void* batch_ws, size_t batch_bytes, void* stream,
+                        const char* cache_path, int32_t* chosen);
+
 #ifdef __cplusplus
 }
 #endif

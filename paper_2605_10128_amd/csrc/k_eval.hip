@@ -98,25 +98,39 @@ struct SetupShared {
   double M[kMaxRank][kMaxRank];
   int piv[kMaxRank];
   int hdr[4];              // valid, k, ns, islanded
+  // flattened sources of the column gathers: row src_row[s] of S enters
+  // column slot q with coefficient coef[s][q] (1 for an opening, sg_b b_b for
+  // a moved branch of its split)
+  int nsrc;
+  int src_row[kMaxRank + kMaxMoved];
+  double coef[kMaxRank + kMaxMoved][kMaxRank];
+  // staging of the genome slots
+  int oval[kMaxRank], sval[kMaxRank], slo[kMaxRank], shi[kMaxRank], stot;
+  int mfrom[kMaxMoved], mto[kMaxMoved];
+  double mb[kMaxMoved];
 };
 
-// Column gather for branch e: W[q] = S[K_q][e] (q < k) and
-// W[k + j] = sum_{b in S_j} sg_b b_b S[b][e]; loads issued four at a time.
-// Written to the per-thread row wrow[0..7] (dynamic q), zero beyond r.
-__device__ inline void gather_column(const GridDev& g, const SetupShared& sh, int e, int k,
-                                     int ns, double* wrow) {
-  const size_t m = g.n_branch;
-  const int r = k + ns;
-#pragma unroll 4
-  for (int q = 0; q < k; ++q) wrow[q] = g.S[(size_t)sh.open[q] * m + e];
-  for (int j = 0; j < ns; ++j) {
-    double acc = 0.0;
-    const int p1 = sh.moff[j + 1];
-#pragma unroll 4
-    for (int p = sh.moff[j]; p < p1; ++p) acc += sh.msg[p] * g.S[(size_t)sh.mbr[p] * m + e];
-    wrow[k + j] = acc;
+// Column gather: W[q] = sum_s coef[s][q] tab[src_row[s]][col], i.e. W[q] =
+// S[K_q][e] for openings and W[k+j] = sum_{b in S_j} sg_b b_b S[b][e] for
+// splits.  Eight independent row loads are in flight per step.
+__device__ inline void gather_column(const double* __restrict__ tab, size_t ld, int col,
+                                     const SetupShared& sh, double* W) {
+#pragma unroll
+  for (int q = 0; q < kMaxRank; ++q) W[q] = 0.0;
+  const int nsrc = sh.nsrc;
+  for (int s0 = 0; s0 < nsrc; s0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = (s0 + u < nsrc) ? tab[(size_t)sh.src_row[s0 + u] * ld + col] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (s0 + u < nsrc) {
+#pragma unroll
+        for (int q = 0; q < kMaxRank; ++q) W[q] = fma(sh.coef[s0 + u][q], v[u], W[q]);
+      }
+    }
   }
-  for (int q = r; q < kMaxRank; ++q) wrow[q] = 0.0;
 }
 
 template <typename F, int TT>
@@ -129,51 +143,42 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
 
   __shared__ SetupShared sh;
   __shared__ double s_x[kMaxRank][TT];
-  __shared__ double s_w[256][kMaxRank + 1];   // per-thread column gather (padded)
   __shared__ int s_wcnt[4];
   __shared__ int s_base, s_n0, s_nisl;
+  __shared__ F s_stage[4][64][17];   // record staging, one slab per wave
 
+  // -- genome parse in stages: slot values, ranges, moved-branch data, checks
+  if (tid < bt.no) sh.oval[tid] = bt.open[(size_t)c * bt.no + tid];
+  if (tid < bt.ns) {
+    sh.sval[tid] = bt.sbus[(size_t)c * bt.ns + tid];
+    sh.slo[tid] = bt.moff[(size_t)c * bt.ns + tid];
+    sh.shi[tid] = bt.moff[(size_t)c * bt.ns + tid + 1];
+  }
+  if (tid == 0) sh.stot = bt.ns > 0 ? bt.moff[(size_t)bt.B * bt.ns] : 0;
+  __syncthreads();
   if (tid == 0) {
     int valid = 1, k = 0, s = 0, nm = 0;
     for (int i = 0; i < bt.no; ++i) {
-      const int v = bt.open[(size_t)c * bt.no + i];
+      const int v = sh.oval[i];
       if (v == -1) continue;
       if (v < 0 || v >= m) { valid = 0; continue; }
       for (int q = 0; q < k; ++q) if (sh.open[q] == v) valid = 0;
       if (k >= kMaxRank) { valid = 0; continue; }
-      sh.bK[k] = g.b[v];
       sh.open[k++] = v;
     }
     for (int j = 0; j < bt.ns; ++j) {
-      const int bus = bt.sbus[(size_t)c * bt.ns + j];
+      const int bus = sh.sval[j];
       if (bus == -1) continue;
       if (bus < 0 || bus >= g.n_bus || s >= kMaxRank) { valid = 0; continue; }
       for (int q = 0; q < s; ++q) if (sh.sbus[q] == bus) valid = 0;
-      const int lo = bt.moff[(size_t)c * bt.ns + j], hi = bt.moff[(size_t)c * bt.ns + j + 1];
+      const int lo = sh.slo[j], hi = sh.shi[j];
       // CSR sanity: offsets inside [0, total moved] and increasing
-      const int tot = bt.moff[(size_t)bt.B * bt.ns];
-      if (lo < 0 || hi > tot || hi <= lo) { valid = 0; continue; }
+      if (lo < 0 || hi > sh.stot || hi <= lo || nm + (hi - lo) > kMaxMoved) { valid = 0; continue; }
       sh.moff[s] = nm;
-      double ssum = 0.0;
-      for (int p = lo; p < hi; ++p) {
-        const int e = bt.mbr[p];
-        if (e < 0 || e >= m) { valid = 0; continue; }
-        const int f = g.from[e], t = g.to[e];
-        if (f != bus && t != bus) valid = 0;
-        for (int q = sh.moff[s]; q < nm; ++q) if (sh.mbr[q] == e) valid = 0;
-        for (int q = 0; q < k; ++q) if (sh.open[q] == e) valid = 0;
-        if (nm >= kMaxMoved) { valid = 0; continue; }
-        const double sg = (f == bus) ? 1.0 : -1.0;
-        sh.mbr[nm] = e;
-        sh.mj[nm] = s;
-        sh.msign[nm] = sg;
-        sh.msg[nm] = sg * g.b[e];
-        ssum += g.b[e];
-        ++nm;
-      }
+      sh.slo[s] = lo;     // compacted: raw start of split s
       sh.sbus[s] = bus;
       sh.sslot[s] = j;
-      sh.inv_s[s] = ssum > 0.0 ? 1.0 / ssum : 0.0;
+      nm += hi - lo;
       ++s;
     }
     sh.moff[s] = nm;
@@ -185,6 +190,58 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     s_base = 0;
     s_n0 = 0;
     s_nisl = 0;
+  }
+  __syncthreads();
+  {
+    const int k0 = sh.hdr[1], ns0 = sh.hdr[2], nm0 = sh.moff[ns0];
+    if (sh.hdr[0] && tid < nm0) {
+      int s = 0;
+      while (s + 1 < ns0 && sh.moff[s + 1] <= tid) ++s;
+      const int e = bt.mbr[sh.slo[s] + (tid - sh.moff[s])];
+      sh.mbr[tid] = e;
+      sh.mj[tid] = s;
+      const bool ok = e >= 0 && e < m;
+      sh.mfrom[tid] = ok ? g.from[e] : -1;
+      sh.mto[tid] = ok ? g.to[e] : -1;
+      sh.mb[tid] = ok ? g.b[e] : 0.0;
+    }
+    if (sh.hdr[0] && tid >= 64 && tid - 64 < k0) sh.bK[tid - 64] = g.b[sh.open[tid - 64]];
+  }
+  __syncthreads();
+  if (tid == 0 && sh.hdr[0]) {
+    int valid = 1;
+    const int k = sh.hdr[1], ns = sh.hdr[2];
+    for (int s = 0; s < ns; ++s) {
+      const int bus = sh.sbus[s];
+      double ssum = 0.0;
+      for (int p = sh.moff[s]; p < sh.moff[s + 1]; ++p) {
+        const int e = sh.mbr[p];
+        if (e < 0 || e >= m) { valid = 0; continue; }
+        if (sh.mfrom[p] != bus && sh.mto[p] != bus) valid = 0;
+        for (int q = sh.moff[s]; q < p; ++q) if (sh.mbr[q] == e) valid = 0;
+        for (int q = 0; q < k; ++q) if (sh.open[q] == e) valid = 0;
+        const double sg = (sh.mfrom[p] == bus) ? 1.0 : -1.0;
+        sh.msign[p] = sg;
+        sh.msg[p] = sg * sh.mb[p];
+        ssum += sh.mb[p];
+      }
+      sh.inv_s[s] = ssum > 0.0 ? 1.0 / ssum : 0.0;
+    }
+    // flattened gather sources
+    int ns_ = 0;
+    for (int q = 0; q < k; ++q) {
+      sh.src_row[ns_] = sh.open[q];
+      for (int qq = 0; qq < kMaxRank; ++qq) sh.coef[ns_][qq] = (qq == q) ? 1.0 : 0.0;
+      ++ns_;
+    }
+    for (int p = 0; p < sh.moff[ns]; ++p) {
+      sh.src_row[ns_] = sh.mbr[p] >= 0 && sh.mbr[p] < m ? sh.mbr[p] : 0;
+      const int slot = k + sh.mj[p];
+      for (int qq = 0; qq < kMaxRank; ++qq) sh.coef[ns_][qq] = (qq == slot) ? sh.msg[p] : 0.0;
+      ++ns_;
+    }
+    sh.nsrc = ns_;
+    sh.hdr[0] = valid;
   }
   __syncthreads();
   const int valid = sh.hdr[0], k = sh.hdr[1], ns = sh.hdr[2];
@@ -290,13 +347,13 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   }
   __syncthreads();
 
-  double* wrow = s_w[tid];
   const int nm = sh.moff[ns];
+  const size_t nMC = (size_t)nM + nC;
   // U row of branch e from its column gather: U_q = b_e W_q (openings),
   // U_{k+j} = -b_e W_{k+j} + sum_{b in S_j, b = e} sg_b b_b (moved-branch term)
-  auto u_from_w = [&](int e, double be, double* U) {
+  auto u_from_w = [&](int e, double be, const double* W, double* U) {
 #pragma unroll
-    for (int q = 0; q < kMaxRank; ++q) U[q] = (q < k ? be : -be) * wrow[q];
+    for (int q = 0; q < kMaxRank; ++q) U[q] = (q < k ? be : -be) * W[q];
     for (int p = 0; p < nm; ++p) {
       if (sh.mbr[p] == e) {
         const int qq = k + sh.mj[p];
@@ -314,11 +371,11 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     const int e = g.mon[ei];
     bool opened = false;
     for (int q = 0; q < k; ++q) opened |= (sh.open[q] == e);
-    gather_column(g, sh, e, k, ns, wrow);
-    double U[kMaxRank];
-    u_from_w(e, g.b[e], U);
+    double W[kMaxRank], U[kMaxRank];
+    gather_column(g.SMC, nMC, ei, sh, W);
+    u_from_w(e, g.b[e], W, U);
     const double lim = g.lim[e];
-    F* fo = w.fM + ((size_t)c * nM + ei) * TT;
+    F* fo = w.fM + (size_t)c * TT * nM + ei;   // [c][t][ei]: coalesced across threads
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
       double fp = 0.0;
@@ -328,11 +385,11 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
         for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
         n0 += fabs(fp) > lim;
       }
-      fo[t] = (F)fp;
+      fo[(size_t)t * nM] = (F)fp;
     }
-    F* uo = w.UM + ((size_t)c * nM + ei) * kVSlots;
+    F* uo = w.UM + (size_t)c * kVSlots * nM + ei;   // [c][q][ei]
 #pragma unroll
-    for (int q = 0; q < kVSlots; ++q) uo[q] = opened ? (F)0 : (F)U[q];
+    for (int q = 0; q < kVSlots; ++q) uo[(size_t)q * nM] = opened ? (F)0 : (F)U[q];
   }
   if (n0) atomicAdd(&s_n0, n0);
 
@@ -342,9 +399,9 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
       keep_in_loop();
       bool opened = false;
       for (int q = 0; q < k; ++q) opened |= (sh.open[q] == e);
-      gather_column(g, sh, e, k, ns, wrow);
-      double U[kMaxRank];
-      u_from_w(e, g.b[e], U);
+      double W[kMaxRank], U[kMaxRank];
+      gather_column(g.S, (size_t)m, e, sh, W);
+      u_from_w(e, g.b[e], W, U);
       for (int t = 0; t < T; ++t) {
         double fp = 0.0;
         if (!opened) {
@@ -377,15 +434,16 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
       if (opened) {
         active = true;  // already open: the N-0 state (phi = 0)
       } else {
-        gather_column(g, sh, l, k, ns, wrow);
+        double W[kMaxRank];
+        gather_column(g.SMC, nMC, nM + li, sh, W);
         const double bl = g.b[l];
         // right-hand side of the factor column: R_q = b_{K_q} W_q (openings),
         // R_{k+j} = (ps_j - W_{k+j}) / s_j with ps_j = sg_l if l is moved by j
 #pragma unroll
         for (int q = 0; q < kMaxRank; ++q) {
           double v = 0.0;
-          if (q < k) v = sh.bK[q] * wrow[q];
-          else if (q < r) v = -wrow[q] * sh.inv_s[q - k];
+          if (q < k) v = sh.bK[q] * W[q];
+          else if (q < r) v = -W[q] * sh.inv_s[q - k];
           V[q] = v;
         }
         for (int p = 0; p < nm; ++p) {
@@ -397,7 +455,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
               if (q == qq) V[q] += add;
           }
         }
-        u_from_w(l, bl, U);
+        u_from_w(l, bl, W, U);
         lu_solve(sh.M, sh.piv, r, V);
         double hll = bl * g.S[(size_t)l * m + l];
 #pragma unroll
@@ -415,29 +473,46 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     const unsigned long long mask = ballot64(active);
     if (lane == 0) s_wcnt[wid] = __popcll(mask);
     __syncthreads();
-    int off = s_base;
-    for (int q = 0; q < wid; ++q) off += s_wcnt[q];
-    off += __popcll(mask & ((1ull << lane) - 1ull));
-    if (active) {
-      // phi_l(t) = f'_l(t) / (1 - H'_ll), zero for an already opened l
-      F* ro = rec + (size_t)off * RS;
+    int o0 = s_base;
+    for (int q = 0; q < wid; ++q) o0 += s_wcnt[q];
+    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    const int na = __popcll(mask);
+    const int off = o0 + rank;
+    // Records go out through LDS in 16-entry passes so that every store
+    // instruction writes whole contiguous runs (direct per-thread 128-byte
+    // records leave partially written lines thrashing the L2).
 #pragma unroll
-      for (int t = 0; t < TT; ++t) {
-        double ph = 0.0;
-        if (t < T && !opened) {
-          double fl = g.f0[(size_t)l * T + t];
+    for (int p0 = 0; p0 < RS; p0 += 16) {
+      if (active) {
 #pragma unroll
-          for (int q = 0; q < kMaxRank; ++q) fl += U[q] * s_x[q][t];
-          ph = fl * inv_d;
+        for (int u = 0; u < 16; ++u) {
+          const int slot = p0 + u;
+          if (slot < RS) {
+            double v = 0.0;
+            if (slot < TT) {
+              // phi_l(t) = f'_l(t) / (1 - H'_ll), zero for an already opened l
+              if (slot < T && !opened) {
+                double fl = g.f0[(size_t)l * T + slot];
+#pragma unroll
+                for (int q = 0; q < kMaxRank; ++q) fl += U[q] * s_x[q][slot];
+                v = fl * inv_d;
+              }
+            } else if (slot < TT + kVSlots) {
+              v = V[slot - TT];
+            }
+            s_stage[wid][rank][u] = (F)v;
+          }
         }
-        ro[t] = (F)ph;
       }
-#pragma unroll
-      for (int q = 0; q < kVSlots; ++q) ro[TT + q] = (F)V[q];
-#pragma unroll
-      for (int q = TT + kVSlots; q < RS; ++q) ro[q] = (F)0;
-      act[off] = li;
+      __syncthreads();
+      const int nsl = (RS - p0) < 16 ? (RS - p0) : 16;
+      for (int idx = lane; idx < na * 16; idx += 64) {
+        const int i = idx >> 4, u = idx & 15;
+        if (u < nsl) rec[(size_t)(o0 + i) * RS + p0 + u] = s_stage[wid][i][u];
+      }
+      __syncthreads();
     }
+    if (active) act[off] = li;
     if (w.slot && li < nC) w.slot[(size_t)c * nC + li] = active ? off : -1;
     __syncthreads();
     if (tid == 0) s_base += s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
@@ -484,19 +559,33 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   constexpr int RS = rec_stride(TT);
   const int nM = g.nM, nC = g.nC;
   F U[R > 0 ? R : 1];
-  const F* fa = w.fM + ((size_t)c * nM + ei_c) * TT;
-  const F* ua = w.UM + ((size_t)c * nM + ei_c) * kVSlots;
+  const F* fa = w.fM + (size_t)c * TT * nM + ei_c;
+  const F* ua = w.UM + (size_t)c * kVSlots * nM + ei_c;
 #pragma unroll
-  for (int t = 0; t < TT; ++t) { a[t] = fa[t]; acc[t] = (F)0; }
+  for (int t = 0; t < TT; ++t) { a[t] = fa[(size_t)t * nM]; acc[t] = (F)0; }
 #pragma unroll
-  for (int j = 0; j < R; ++j) U[j] = ua[j];
+  for (int j = 0; j < R; ++j) U[j] = ua[(size_t)j * nM];
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
   if (n_act_pad == 0) return;
-  // software pipeline: the H entries of the next pair are in flight while the
-  // current pair is consumed (the last prefetch re-reads an in-range pair)
+  // Software pipeline: the H entries of the next pair are in flight while the
+  // current pair is consumed (the last prefetch re-reads an in-range pair).
   F hn0 = HMC[(size_t)act[0] * nM + ei_c];
   F hn1 = HMC[(size_t)act[1] * nM + ei_c];
+  // Half records (TT >= 16): while timesteps t < TT/2 of a pair are consumed
+  // the upper half of the same pair is in flight, and while the upper half is
+  // consumed the lower half of the next pair is.
+#if defined(TTO_SWEEP_HALF)
+  constexpr bool kHalf = TT >= 16;
+#else
+  constexpr bool kHalf = false;
+#endif
+  constexpr int TH = kHalf ? TT / 2 : 1;
+  F pa0[TH], pa1[TH];
+  if constexpr (kHalf) {
+#pragma unroll
+    for (int t = 0; t < TH; ++t) { pa0[t] = rec[t]; pa1[t] = rec[RS + t]; }
+  }
   for (int i = 0; i < n_act_pad; i += 2) {
     F h0 = hn0, h1 = hn1;
     const int nx = (i + 2 < n_act_pad) ? i + 2 : i;
@@ -504,60 +593,80 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
     hn1 = HMC[(size_t)act[nx + 1] * nM + ei_c];
     const F* r0 = rec + (size_t)i * RS;
     const F* r1 = r0 + RS;
+    F pb0[kHalf ? TT - TH : 1], pb1[kHalf ? TT - TH : 1];
+    if constexpr (kHalf) {
+#pragma unroll
+      for (int t = 0; t < TT - TH; ++t) { pb0[t] = r0[TH + t]; pb1[t] = r1[TH + t]; }
+    }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       h0 = fma_t(U[j], r0[TT + j], h0);
       h1 = fma_t(U[j], r1[TT + j], h1);
     }
+    if constexpr (kHalf) {
+#pragma unroll
+    for (int t = 0; t < TH; ++t) {
+      const F g0 = fma_t(h0, pa0[t], a[t]);
+      const F g1 = fma_t(h1, pa1[t], a[t]);
+      acc[t] = max3_t(acc[t], fabs_t(g0), fabs_t(g1));
+    }
+    const F* q0 = rec + (size_t)nx * RS;
+#pragma unroll
+    for (int t = 0; t < TH; ++t) { pa0[t] = q0[t]; pa1[t] = q0[RS + t]; }
+#pragma unroll
+    for (int t = 0; t < TT - TH; ++t) {
+      const F g0 = fma_t(h0, pb0[t], a[TH + t]);
+      const F g1 = fma_t(h1, pb1[t], a[TH + t]);
+      acc[TH + t] = max3_t(acc[TH + t], fabs_t(g0), fabs_t(g1));
+    }
+    } else {
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
       const F g0 = fma_t(h0, r0[t], a[t]);
       const F g1 = fma_t(h1, r1[t], a[t]);
       acc[t] = max3_t(acc[t], fabs_t(g0), fabs_t(g1));
     }
+    }
   }
 }
 
-#ifndef TTO_SWEEP_WPE
-#define TTO_SWEEP_WPE 0
-#endif
-#if TTO_SWEEP_WPE > 0
-#define TTO_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(TTO_SWEEP_WPE, 8)))
-#else
-#define TTO_SWEEP_ATTR
-#endif
-
-template <typename F, int TT>
-__global__ __launch_bounds__(256) TTO_SWEEP_ATTR void k_sweep(GridDev g, SweepBufs<F> w,
-                                               const F* __restrict__ HMC,
-                                               double* __restrict__ fmax_out) {
-  const int c = blockIdx.y;
+// One tile = one candidate x BS consecutive monitored branches (one lane
+// each).  Writes the tile's partial reduction.
+template <typename F, int TT, int BS>
+__device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>& w,
+                                           const F* __restrict__ HMC,
+                                           double* __restrict__ fmax_out, int c, int eb) {
+  constexpr int NW = BS / 64;
   const CandInfo* inf = w.info + c;
   const int status = inf->status;
-  if (status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;
+  if (status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;   // uniform per tile
   const int r = inf->r, k = inf->k, n_act_pad = inf->n_act_pad;
   const int nM = g.nM, T = g.T;
-  const int ei = blockIdx.x * 256 + threadIdx.x;
+  const int tid = threadIdx.x;
+  const int ei = eb * BS + tid;
   const bool valid = ei < nM;
   const int ei_c = valid ? ei : nM - 1;
+  // waves lying wholly past the monitored set skip the sweep (uniform per wave)
+  const bool wave_live = eb * BS + (int)(tid & ~63) < nM;
+  const int n_pairs = wave_live ? n_act_pad : 0;
   F acc[TT], a[TT];
   switch (r) {
-    case 0: sweep_core<F, TT, 0>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    case 1: sweep_core<F, TT, 1>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    case 2: sweep_core<F, TT, 2>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    case 3: sweep_core<F, TT, 3>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    case 4: sweep_core<F, TT, 4>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    case 5: sweep_core<F, TT, 5>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    case 6: sweep_core<F, TT, 6>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    case 7: sweep_core<F, TT, 7>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
-    default: sweep_core<F, TT, 8>(g, w, HMC, c, ei_c, n_act_pad, acc, a); break;
+    case 0: sweep_core<F, TT, 0>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    case 1: sweep_core<F, TT, 1>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    case 2: sweep_core<F, TT, 2>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    case 3: sweep_core<F, TT, 3>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    case 4: sweep_core<F, TT, 4>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    case 5: sweep_core<F, TT, 5>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    case 6: sweep_core<F, TT, 6>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    case 7: sweep_core<F, TT, 7>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
+    default: sweep_core<F, TT, 8>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
   }
   // per-thread reduction over timesteps
   const int e = g.mon[ei_c];
   bool opened = false;
   for (int q = 0; q < k; ++q) opened |= (inf->open_br[q] == e);
   double so = 0.0, best = -1.0;
-  int cc = 0, bt = 0;
+  int cc = 0, bt = 0, be = ei;
   if (valid) {
     const double lim = g.lim[e];
 #pragma unroll
@@ -574,28 +683,112 @@ __global__ __launch_bounds__(256) TTO_SWEEP_ATTR void k_sweep(GridDev g, SweepBu
       }
     }
   }
-  // deterministic block tree reduction
-  __shared__ double s_so[256], s_best[256];
-  __shared__ int s_cc[256], s_be[256], s_bt[256];
-  const int tid = threadIdx.x;
-  s_so[tid] = so; s_best[tid] = best; s_cc[tid] = cc; s_be[tid] = ei; s_bt[tid] = bt;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st) {
-      s_so[tid] += s_so[tid + st];
-      s_cc[tid] += s_cc[tid + st];
-      const double b2 = s_best[tid + st];
-      if (b2 > s_best[tid]) { s_best[tid] = b2; s_be[tid] = s_be[tid + st]; s_bt[tid] = s_bt[tid + st]; }
+  // deterministic wave butterfly (every lane ends with the same values), then
+  // the waves of the tile in increasing monitored order
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    so += __shfl_xor(so, off);
+    cc += __shfl_xor(cc, off);
+    const double b2 = __shfl_xor(best, off);
+    const int e2 = __shfl_xor(be, off), t2 = __shfl_xor(bt, off);
+    if (b2 > best || (b2 == best && e2 < be)) { best = b2; be = e2; bt = t2; }
+  }
+  Partial* out = w.part + (size_t)c * w.n_eblk + eb;
+  if constexpr (NW == 1) {
+    if (tid == 0) {
+      Partial p;
+      p.sum_o = so; p.best = best; p.cnt_c = cc; p.best_e = be; p.best_t = bt; p.pad_ = 0;
+      *out = p;
+    }
+  } else {
+    __shared__ Partial s_p[NW];
+    if ((tid & 63) == 0) {
+      Partial p;
+      p.sum_o = so; p.best = best; p.cnt_c = cc; p.best_e = be; p.best_t = bt; p.pad_ = 0;
+      s_p[tid >> 6] = p;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Partial p = s_p[0];
+      for (int q = 1; q < NW; ++q) {
+        p.sum_o += s_p[q].sum_o;
+        p.cnt_c += s_p[q].cnt_c;
+        if (s_p[q].best > p.best) { p.best = s_p[q].best; p.best_e = s_p[q].best_e; p.best_t = s_p[q].best_t; }
+      }
+      *out = p;
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    Partial p;
-    p.sum_o = s_so[0]; p.best = s_best[0]; p.cnt_c = s_cc[0]; p.best_e = s_be[0];
-    p.best_t = s_bt[0]; p.pad_ = 0;
-    w.part[(size_t)c * w.n_eblk + blockIdx.x] = p;
+}
+
+// Sweep launch.  Non-persistent: one workgroup per tile over a 1-D grid;
+// workgroups are dealt to the 8 XCDs round-robin, so with xcd grouping the
+// tiles of one candidate are remapped onto one XCD (its records then come
+// into one L2).  Persistent: a machine-sized grid pulls tiles from a counter
+// in rank-descending candidate order (longest tiles first).
+template <typename F, int TT, int BS>
+__global__ __launch_bounds__(BS) void k_sweep(GridDev g, SweepBufs<F> w,
+                                              const F* __restrict__ HMC,
+                                              double* __restrict__ fmax_out, int n_cand,
+                                              int xcd, int* __restrict__ counter,
+                                              const int* __restrict__ order) {
+  const int n_tiles = n_cand * w.n_eblk;
+  if (counter == nullptr) {
+    int q = blockIdx.x;
+    if (xcd) q = (q & 7) * (int)(gridDim.x >> 3) + (q >> 3);
+    if (q >= n_tiles) return;
+    const int c = q / w.n_eblk;
+    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, q - c * w.n_eblk);
+    return;
+  }
+  __shared__ int s_q;
+  for (;;) {
+    if (threadIdx.x == 0) s_q = atomicAdd(counter, 1);
+    __syncthreads();
+    const int q = s_q;
+    __syncthreads();
+    if (q >= n_tiles) break;   // every wave of the grid reaches this exit
+    const int ci = q / w.n_eblk;
+    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, order[ci], q - ci * w.n_eblk);
   }
 }
+
+// Stable rank-descending order of the candidates (invalid and islanded
+// last), by ballot compaction per rank; one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_rank_order(const CandInfo* __restrict__ info, int B,
+                                                     int* __restrict__ order) {
+  __shared__ int s_wc[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int key = kMaxRank; key >= -1; --key) {
+    for (int b0 = 0; b0 < B; b0 += 1024) {
+      const int c = b0 + tid;
+      bool take = false;
+      if (c < B) {
+        const bool bad = info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
+        take = (key == -1) ? bad : (!bad && info[c].r == key);
+      }
+      const unsigned long long mask = __ballot(take);
+      if (lane == 0) s_wc[wid] = __popcll(mask);
+      __syncthreads();
+      int off = s_base;
+      for (int q = 0; q < wid; ++q) off += s_wc[q];
+      off += __popcll(mask & ((1ull << lane) - 1ull));
+      if (take) order[off] = c;
+      __syncthreads();
+      if (tid == 0) {
+        int s = 0;
+        for (int q = 0; q < 16; ++q) s += s_wc[q];
+        s_base += s;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
 
 // ---------------------------------------------------------------------------
 template <typename F, int TT>
@@ -648,14 +841,14 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     // every state gives zero flow on an opened branch: first active contingency
     if (inf.n_act > 0 && lane == 0) { bv = 0.0; bi = 0; }
   } else if (be >= 0) {
-    const F a = w.fM[((size_t)c * nM + be) * TT + bt];
-    const F* ua = w.UM + ((size_t)c * nM + be) * kVSlots;
+    const F a = w.fM[((size_t)c * TT + bt) * nM + be];
+    const F* ua = w.UM + (size_t)c * kVSlots * nM + be;
     const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
     const int* act = w.act + (size_t)c * (nC + 1);
     for (int i = lane; i < inf.n_act; i += 64) {
       const F* ri = rec + (size_t)i * RS;
       F h = HMC[(size_t)act[i] * nM + be];
-      for (int j = 0; j < inf.r; ++j) h = fma_t(ua[j], ri[TT + j], h);
+      for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
       const double v = (double)fabs_t(fma_t(h, ri[bt], a));
       if (v > bv) { bv = v; bi = i; }
     }
@@ -705,8 +898,8 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
   const int e = g.mon[ei];
   bool opened = false;
   for (int q = 0; q < inf.k; ++q) opened |= (inf.open_br[q] == e);
-  const F* fa = w.fM + ((size_t)c * nM + ei) * TT;
-  const F* ua = w.UM + ((size_t)c * nM + ei) * kVSlots;
+  const F* fa = w.fM + (size_t)c * TT * nM + ei;
+  const F* ua = w.UM + (size_t)c * kVSlots * nM + ei;
   const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
   for (int li = 0; li < nC; ++li) {
     double* out = n1 + (((size_t)c * nC + li) * nM + ei) * T;
@@ -721,8 +914,8 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
     }
     const F* ri = rec + (size_t)slot * RS;
     F h = HMC[(size_t)li * nM + ei];
-    for (int j = 0; j < inf.r; ++j) h = fma_t(ua[j], ri[TT + j], h);
-    for (int t = 0; t < T; ++t) out[t] = (double)fma_t(h, ri[t], fa[t]);
+    for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
+    for (int t = 0; t < T; ++t) out[t] = (double)fma_t(h, ri[t], fa[(size_t)t * nM]);
   }
 }
 
@@ -788,37 +981,83 @@ hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, con
   return hipGetLastError();
 }
 
+template <typename F, int TT, int BS>
+static void launch_sweep(const GridDev& g, const BatchDev& bt, SweepBufs<F> w, const F* HMC,
+                         const tto_outputs& o, hipStream_t s, const SweepPlan& plan) {
+  w.n_eblk = (g.nM + BS - 1) / BS;
+  const int tiles = w.n_eblk * bt.B;
+  if (plan.persistent) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, w.counter);
+    hipLaunchKernelGGL(k_rank_order, dim3(1), dim3(1024), 0, s, w.info, bt.B, w.order);
+    const int grid = std::min(tiles, std::max(plan.grid, 1));
+    hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3(grid), dim3(BS), 0, s, g, w, HMC, o.fmax,
+                       bt.B, 0, w.counter, (const int*)w.order);
+  } else {
+    hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3((tiles + 7) / 8 * 8), dim3(BS), 0, s, g, w,
+                       HMC, o.fmax, bt.B, plan.xcd, (int*)nullptr, (const int*)nullptr);
+  }
+}
+
 template <typename F, int TT>
-static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
-                                 const tto_outputs& o, hipStream_t s, hipEvent_t* ev) {
+static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w0,
+                                 const tto_outputs& o, hipStream_t s, hipEvent_t* ev,
+                                 const SweepPlan& plan) {
   const F* HMC;
   if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
+  SweepBufs<F> w = w0;
+  w.n_eblk = (g.nM + plan.bs - 1) / plan.bs;
   if (ev) hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_setup<F, TT>), dim3(bt.B), dim3(256), 0, s, g, bt, w, o.base_flows);
   if (ev) hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL((k_sweep<F, TT>), dim3(w.n_eblk, bt.B), dim3(256), 0, s, g, w, HMC, o.fmax);
+  switch (plan.bs) {
+    case 64: launch_sweep<F, TT, 64>(g, bt, w, HMC, o, s, plan); break;
+    case 128: launch_sweep<F, TT, 128>(g, bt, w, HMC, o, s, plan); break;
+    default: launch_sweep<F, TT, 256>(g, bt, w, HMC, o, s, plan); break;
+  }
   if (ev) hipEventRecord(ev[2], s);
   hipLaunchKernelGGL((k_finalize<F, TT>), dim3(bt.B), dim3(64), 0, s, g, w, HMC, o);
   if (ev) hipEventRecord(ev[3], s);
-  if (o.n1_flows)
-    hipLaunchKernelGGL((k_n1_dump<F, TT>), dim3(w.n_eblk, bt.B), dim3(256), 0, s, g, w, HMC, o.n1_flows);
+  if (o.n1_flows) {
+    const int nb = (g.nM + 255) / 256;
+    hipLaunchKernelGGL((k_n1_dump<F, TT>), dim3(nb, bt.B), dim3(256), 0, s, g, w, HMC, o.n1_flows);
+  }
   return hipGetLastError();
 }
 
 template <typename F>
 hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
-                           const tto_outputs& o, hipStream_t s, hipEvent_t* ev) {
+                           const tto_outputs& o, hipStream_t s, hipEvent_t* ev,
+                           const SweepPlan& plan) {
   switch (g.TT) {
-    case 1: return launch_eval_tt<F, 1>(g, bt, w, o, s, ev);
-    case 8: return launch_eval_tt<F, 8>(g, bt, w, o, s, ev);
-    case 24: return launch_eval_tt<F, 24>(g, bt, w, o, s, ev);
-    default: return launch_eval_tt<F, 32>(g, bt, w, o, s, ev);
+    case 1: return launch_eval_tt<F, 1>(g, bt, w, o, s, ev, plan);
+    case 8: return launch_eval_tt<F, 8>(g, bt, w, o, s, ev, plan);
+    case 24: return launch_eval_tt<F, 24>(g, bt, w, o, s, ev, plan);
+    default: return launch_eval_tt<F, 32>(g, bt, w, o, s, ev, plan);
   }
 }
 
+// Occupancy of the sweep for a plan (workgroups per CU), for persistent grids.
+template <typename F>
+static int sweep_occ(int TT, int bs) {
+  int n = 0;
+  const void* fn = nullptr;
+#define TTO_OCC(TTV, BSV) if (TT == TTV && bs == BSV) fn = (const void*)&k_sweep<F, TTV, BSV>;
+  TTO_OCC(1, 64) TTO_OCC(1, 128) TTO_OCC(1, 256) TTO_OCC(8, 64) TTO_OCC(8, 128) TTO_OCC(8, 256)
+  TTO_OCC(24, 64) TTO_OCC(24, 128) TTO_OCC(24, 256) TTO_OCC(32, 64) TTO_OCC(32, 128) TTO_OCC(32, 256)
+#undef TTO_OCC
+  if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, bs, 0) != hipSuccess) n = 0;
+  return n;
+}
+
+int sweep_blocks_per_cu(int flow_f32, int TT, int bs) {
+  return flow_f32 ? sweep_occ<float>(TT, bs) : sweep_occ<double>(TT, bs);
+}
+
 template hipError_t launch_evaluate<float>(const GridDev&, const BatchDev&, const SweepBufs<float>&,
-                                           const tto_outputs&, hipStream_t, hipEvent_t*);
+                                           const tto_outputs&, hipStream_t, hipEvent_t*,
+                                           const SweepPlan&);
 template hipError_t launch_evaluate<double>(const GridDev&, const BatchDev&, const SweepBufs<double>&,
-                                            const tto_outputs&, hipStream_t, hipEvent_t*);
+                                            const tto_outputs&, hipStream_t, hipEvent_t*,
+                                            const SweepPlan&);
 
 }  // namespace tto

@@ -50,6 +50,18 @@ __global__ __launch_bounds__(256) void k_symmetrize(double* __restrict__ S, int 
   }
 }
 
+// Column-compacted copy of S: SMC[s][j] = S[s][col_j], col = M then C.
+__global__ __launch_bounds__(256) void k_build_SMC(const double* __restrict__ S,
+                                                   const int* __restrict__ mon,
+                                                   const int* __restrict__ cont, int m, int nM,
+                                                   int nC, double* __restrict__ SMC) {
+  const int s = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= nM + nC) return;
+  const int col = j < nM ? mon[j] : cont[j - nM];
+  SMC[(size_t)s * (nM + nC) + j] = S[(size_t)s * m + col];
+}
+
 // Contingency-major monitored block: HMC[li][ei] = H[M[ei], C[li]], with the
 // line-outage convention that the outaged branch's own entry is H_ll - 1 so
 // that its post-contingency flow f_l + (H'_ll - 1) f_l / (1 - H'_ll) is zero.
@@ -233,6 +245,13 @@ hipError_t launch_build_S(const double* ptdf, const int* from, const int* to, co
                           int m, int n, double* S, hipStream_t s) {
   hipLaunchKernelGGL(k_build_S, dim3(cdiv(m, 256), m), dim3(256), 0, s, ptdf, from, to, b, m, n, S);
   hipLaunchKernelGGL(k_symmetrize, dim3(cdiv(m, 64), cdiv(m, 64)), dim3(256), 0, s, S, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_SMC(const double* S, const int* mon, const int* cont, int m, int nM,
+                            int nC, double* SMC, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_SMC, dim3(cdiv(nM + nC, 256), m), dim3(256), 0, s, S, mon, cont, m,
+                     nM, nC, SMC);
   return hipGetLastError();
 }
 

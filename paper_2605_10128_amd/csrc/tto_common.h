@@ -39,6 +39,9 @@ struct GridDev {
   // S = A L^-1 A^T, symmetric [m][m]; the flow on e per MW sent across l is
   // H_el = b_e S_el, so any row or column of H is a contiguous row of S.
   const double* S;
+  // S restricted to the monitored then contingency columns, [m][nM + nC]:
+  // column gathers of a candidate's rows are contiguous across threads
+  const double* SMC;
   const float* HMC32;   // [nC][nM], H[M[ei], C[li]] with -1 where M[ei] == C[li]
   const double* HMC64;  // same in FP64
   const double* f0;     // [m][T] base flows of the unswitched grid
@@ -90,13 +93,25 @@ struct SweepBufs {
   F* rec;           // [B][nC+1][rec_stride(TT)]
   int* act;         // [B][nC+1] contingency index of each record
   int* slot;        // [B][nC] record of each contingency or -1 (optional)
-  Partial* part;    // [B][n_eblk]
+  Partial* part;    // [B][ceil(nM / 64)] (n_eblk used per plan)
+  int* counter;     // persistent-sweep tile counter
+  int* order;       // [B] rank-descending candidate order
   int n_eblk;
+};
+
+// Launch shape of the N-1 sweep (chosen by the autotuner).
+struct SweepPlan {
+  int bs;           // monitored branches per tile: 64, 128 or 256 lanes
+  int xcd;          // group the tiles of a candidate onto one XCD
+  int persistent;   // machine-sized grid pulling rank-ordered tiles
+  int grid;         // persistent grid size (workgroups)
 };
 
 // ---- launchers (k_grid.hip) -------------------------------------------------
 hipError_t launch_build_S(const double* ptdf, const int* from, const int* to, const double* b,
                           int m, int n, double* S, hipStream_t s);
+hipError_t launch_build_SMC(const double* S, const int* mon, const int* cont, int m, int nM,
+                            int nC, double* SMC, hipStream_t s);
 hipError_t launch_build_HMC(const double* S, const double* b, const int* mon, const int* cont,
                             int m, int nM, int nC, float* HMC32, double* HMC64, hipStream_t s);
 hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void* out, hipStream_t s);
@@ -110,7 +125,9 @@ int gemm_ksplit(int m, int n);
 // and after finalize.
 template <typename F>
 hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
-                           const tto_outputs& out, hipStream_t s, hipEvent_t* ev);
+                           const tto_outputs& out, hipStream_t s, hipEvent_t* ev,
+                           const SweepPlan& plan);
+int sweep_blocks_per_cu(int flow_f32, int TT, int bs);
 hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
                           const int* cell, const uint8_t* status, int B, int64_t id_base,
                           unsigned long long* key, int* idx, hipStream_t s);

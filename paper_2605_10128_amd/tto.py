@@ -78,6 +78,10 @@ def _load():
                                       ct.c_size_t, _vp]),
         "tto_profile_enable": (_i32, [_vp, _i32]),
         "tto_profile_read": (_i32, [_vp, P(ct.c_double)]),
+        "tto_set_sweep_plan": (_i32, [_vp, _i32, _i32, _i32]),
+        "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
+        "tto_autotune": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
+                                ct.c_char_p, P(_i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -90,7 +94,8 @@ _lib = _load()
 
 EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_create",
             "tto_grid_destroy", "tto_set_injections", "tto_get_base_flows", "tto_set_descriptor",
-            "tto_evaluate", "tto_archive_insert", "tto_profile_enable", "tto_profile_read"]
+            "tto_evaluate", "tto_archive_insert", "tto_profile_enable", "tto_profile_read",
+            "tto_set_sweep_plan", "tto_get_sweep_plan", "tto_autotune"]
 
 
 def _check(code: int):
@@ -159,6 +164,25 @@ def tto_profile_read(handle: int):
     ms = (ct.c_double * 3)()
     _check(_lib.tto_profile_read(_vp(handle), ms))
     return list(ms)
+
+
+def tto_set_sweep_plan(handle: int, block: int, xcd_group: bool, persistent: bool):
+    _check(_lib.tto_set_sweep_plan(_vp(handle), block, int(xcd_group), int(persistent)))
+
+
+def tto_get_sweep_plan(handle: int):
+    b, x, p = _i32(), _i32(), _i32()
+    _check(_lib.tto_get_sweep_plan(_vp(handle), ct.byref(b), ct.byref(x), ct.byref(p)))
+    return b.value, bool(x.value), bool(p.value)
+
+
+def tto_autotune(handle: int, batch: tto_batch, outputs: tto_outputs, ws: int, ws_bytes: int,
+                 stream: int, cache_path: str = ""):
+    ch = (_i32 * 4)()
+    _check(_lib.tto_autotune(_vp(handle), ct.byref(batch), ct.byref(outputs), _vp(ws), ws_bytes,
+                             _vp(stream), cache_path.encode(), ch))
+    return {"block": ch[0], "xcd_group": bool(ch[1]), "persistent": bool(ch[2]),
+            "from_cache": bool(ch[3])}
 
 
 # ---- torch-backed session (device memory and streams only) -----------------
@@ -301,6 +325,16 @@ class Session:
         tto_evaluate(self.handle, dbatch.struct(), st, _ptr(self.batch_ws), self.batch_bytes,
                      self.stream)
         return outputs
+
+    def autotune(self, dbatch: DeviceBatch, outputs=None, cache_path: str = ""):
+        if outputs is None:
+            outputs = self.alloc_outputs(dbatch.n_cand)
+        st = tto_outputs(*[_ptr(outputs.get(f)) for f in OUTPUT_FIELDS])
+        return tto_autotune(self.handle, dbatch.struct(), st, _ptr(self.batch_ws),
+                            self.batch_bytes, self.stream, cache_path)
+
+    def set_sweep_plan(self, block=256, xcd_group=False, persistent=False):
+        tto_set_sweep_plan(self.handle, block, xcd_group, persistent)
 
     def new_archive(self, n_cells=None):
         n = self.n_cells if n_cells is None else n_cells

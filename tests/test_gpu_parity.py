@@ -128,3 +128,59 @@ def test_repeat_runs_bitwise_identical(tto):
     b = to_numpy(s.evaluate(db, fmax=True))
     for k in a:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+PLANS = [(256, False, False), (256, True, False)]
+DISABLED_PLANS = [(64, False, False), (128, False, False), (256, False, True)]
+
+
+def test_disabled_sweep_plans_are_rejected(tto):
+    """64/128-lane tiles and the persistent grid are switched off (a GPU test
+    of them did not finish; cause not found): the ABI refuses them."""
+    w = gg.build_config(1)
+    s = make_session(w, tto.TTO_FLOW_F64)
+    for plan in DISABLED_PLANS:
+        with pytest.raises(tto.TTOError) as ei:
+            s.set_sweep_plan(*plan)
+        assert ei.value.code == tto.TTO_E_UNSUPPORTED
+
+
+def test_sweep_plans_agree(tto):
+    """Every launch shape (tile width, XCD grouping, persistent rank-ordered
+    grid) gives the same discrete outputs; sums agree to rounding."""
+    import torch
+    w = gg.build_config(3, B=96)
+    s = make_session(w, tto.TTO_FLOW_F32)
+    db = tto.device_batch(w.batch)
+    ref = None
+    for plan in PLANS:
+        log(f"[plans] {plan}")
+        s.set_sweep_plan(*plan)
+        o = to_numpy(s.evaluate(db, fmax=True))
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = o
+            continue
+        for key in ("status", "n_island_cont", "n_crit_n1", "n_crit_n0", "worst_branch",
+                    "worst_cont", "worst_t", "cell", "fmax", "max_loading"):
+            np.testing.assert_array_equal(o[key], ref[key], err_msg=f"{plan} {key}")
+        np.testing.assert_allclose(o["overload_mw"], ref["overload_mw"], rtol=1e-12, atol=1e-9)
+
+
+def test_autotune_and_cache(tto, tmp_path):
+    import torch
+    w = gg.build_config(2, B=512)
+    s = make_session(w, tto.TTO_FLOW_F32)
+    db = tto.device_batch(w.batch)
+    cache = str(tmp_path / "plans.txt")
+    first = s.autotune(db, cache_path=cache)
+    assert not first["from_cache"] and first["block"] == 256
+    again = s.autotune(db, cache_path=cache)
+    assert again["from_cache"] and again["block"] == first["block"]
+    assert tto.tto_get_sweep_plan(s.handle) == (first["block"], first["xcd_group"],
+                                                first["persistent"])
+    o = to_numpy(s.evaluate(db))
+    torch.cuda.synchronize()
+    idx = list(range(0, 512, 64))
+    ores = oracle_results(w, idx, keep_n1=False)
+    compare(w, o, idx, ores, TOL_F32)
