@@ -135,7 +135,7 @@ def main():
     log("[bench] warmup done")
 
     tto.tto_profile_enable(s.handle, True)
-    sweep_ms, setup_ms, fin_ms = [], [], []
+    sweep_ms, setup_ms, fin_ms, ref_ms = [], [], [], []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
@@ -143,7 +143,7 @@ def main():
         s.evaluate(db, out)
         s.archive_insert(arch, out, id_base=(args.warmup + i) * B)
         ms = tto.tto_profile_read(s.handle)   # waits for this step's events only
-        setup_ms.append(ms[0]); sweep_ms.append(ms[1]); fin_ms.append(ms[2])
+        setup_ms.append(ms[0]); sweep_ms.append(ms[1]); fin_ms.append(ms[2]); ref_ms.append(ms[3])
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
@@ -151,7 +151,8 @@ def main():
     ms_step = total_ms / args.steps
     value = B * args.steps / (total_ms / 1e3)
     log(f"[bench] {ms_step:.3f} ms/step, {value:,.0f} topologies/s; stage ms "
-        f"setup {np.mean(setup_ms):.3f} sweep {np.mean(sweep_ms):.3f} fin {np.mean(fin_ms):.3f}")
+        f"setup {np.mean(setup_ms):.3f} sweep {np.mean(sweep_ms):.3f} fin {np.mean(fin_ms):.3f} "
+        f"refine {np.mean(ref_ms):.3f}")
 
     o = {k: v.cpu().numpy() for k, v in out.items()}
     ok = (o["status"] & 3) == 0
@@ -188,6 +189,8 @@ def main():
             "candidates_ok": int(ok.sum()),
             "sweep_plan": {k: chosen[k] for k in ("block", "xcd_group", "persistent")},
             "islanded": int(((o["status"] & 1) != 0).sum()),
+            "refined_fp64": int(((o["status"] & 4) != 0).sum()),
+            "refine_skipped": int(((o["status"] & 8) != 0).sum()),
         },
         "roofline": {
             "bound": "alu",
@@ -200,6 +203,7 @@ def main():
             "sweep_ms": float(np.mean(sweep_ms)),
             "setup_ms": float(np.mean(setup_ms)),
             "finalize_ms": float(np.mean(fin_ms)),
+            "refine_ms": float(np.mean(ref_ms)),
         },
         "cpu_baseline": None,
     }

@@ -71,6 +71,8 @@ enum { TTO_GEMM_F64 = 0, TTO_GEMM_F32 = 1, TTO_GEMM_BF16 = 2, TTO_GEMM_F16 = 3 }
 #define TTO_ST_INVALID  0x02u  /* candidate violates the encoding rules */
 #define TTO_ST_REFINED  0x04u  /* FP32 result was near a decision threshold
                                   and was recomputed in FP64 */
+#define TTO_ST_REFINE_SKIPPED 0x08u  /* near a decision threshold but beyond
+                                        the refinement capacity: FP32 result */
 
 typedef struct tto_grid tto_grid;   /* opaque host handle */
 
@@ -260,11 +262,11 @@ tto_status tto_archive_insert(tto_grid* grid, double* elite_fitness, int64_t* el
 
 /*
  * Stage timing of tto_evaluate (tracing aid): when enabled, every
- * tto_evaluate records HIP events on its stream around its three stages
- * (candidate set-up, N-1 sweep, finalize).  tto_profile_read waits for the
- * events of the latest tto_evaluate and writes the stage durations in
- * milliseconds to ms[0..2].  TTO_E_INVALID if profiling is off or nothing was
- * recorded yet.
+ * tto_evaluate records HIP events on its stream around its stages
+ * (candidate set-up, N-1 sweep, finalize, FP64 refinement).
+ * tto_profile_read waits for the events of the latest tto_evaluate and
+ * writes the stage durations in milliseconds to ms[0..3].  TTO_E_INVALID if
+ * profiling is off or nothing was recorded yet.
  */
 tto_status tto_profile_enable(tto_grid* grid, int32_t enable);
 tto_status tto_profile_read(tto_grid* grid, double* ms);
@@ -281,6 +283,19 @@ tto_status tto_profile_read(tto_grid* grid, double* ms);
  */
 tto_status tto_set_sweep_plan(tto_grid* grid, int32_t block, int32_t xcd_group,
                               int32_t persistent);
+
+/*
+ * FP64 refinement of FP32-flow grids (on by default, margin 8e-3 MW): after
+ * the FP32 pass, a candidate whose maximum loading lies within margin_mw /
+ * fbar of a load-bin edge, whose runner-up (branch, timestep) loading is
+ * within margin_mw / min fbar of the maximum, or whose runner-up contingency
+ * flow at the arg-max is within 2 margin_mw, is re-evaluated end to end in
+ * FP64 on the GPU in the same tto_evaluate (status bit REFINED).  Capacity:
+ * max_batch / 8 (at least 64) candidates per call; further flagged
+ * candidates keep FP32 results (status bit REFINE_SKIPPED).  No effect on
+ * FP64 grids.
+ */
+tto_status tto_set_refine(tto_grid* grid, int32_t enable, double margin_mw);
 tto_status tto_get_sweep_plan(tto_grid* grid, int32_t* block, int32_t* xcd_group,
                               int32_t* persistent);
 

@@ -140,6 +140,12 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
   const int m = g.n_branch, T = g.T, nM = g.nM, nC = g.nC;
+  // genome index: refinement passes evaluate map[c] for c < live count
+  int cb = c;
+  if (bt.map) {
+    if (c >= min(*bt.live, bt.B)) return;
+    cb = bt.map[c];
+  }
 
   __shared__ SetupShared sh;
   __shared__ double s_x[kMaxRank][TT];
@@ -148,13 +154,13 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   __shared__ F s_stage[4][64][17];   // record staging, one slab per wave
 
   // -- genome parse in stages: slot values, ranges, moved-branch data, checks
-  if (tid < bt.no) sh.oval[tid] = bt.open[(size_t)c * bt.no + tid];
+  if (tid < bt.no) sh.oval[tid] = bt.open[(size_t)cb * bt.no + tid];
   if (tid < bt.ns) {
-    sh.sval[tid] = bt.sbus[(size_t)c * bt.ns + tid];
-    sh.slo[tid] = bt.moff[(size_t)c * bt.ns + tid];
-    sh.shi[tid] = bt.moff[(size_t)c * bt.ns + tid + 1];
+    sh.sval[tid] = bt.sbus[(size_t)cb * bt.ns + tid];
+    sh.slo[tid] = bt.moff[(size_t)cb * bt.ns + tid];
+    sh.shi[tid] = bt.moff[(size_t)cb * bt.ns + tid + 1];
   }
-  if (tid == 0) sh.stot = bt.ns > 0 ? bt.moff[(size_t)bt.B * bt.ns] : 0;
+  if (tid == 0) sh.stot = bt.ns > 0 ? bt.moff[(size_t)bt.n_genomes * bt.ns] : 0;
   __syncthreads();
   if (tid == 0) {
     int valid = 1, k = 0, s = 0, nm = 0;
@@ -335,7 +341,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
           const int j = q - k;
           double phi = 0.0;
           for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) phi += sh.msign[p] * g.f0[(size_t)sh.mbr[p] * T + t];
-          const double pj = bt.mp ? bt.mp[((size_t)c * bt.ns + sh.sslot[j]) * T + t] : 0.0;
+          const double pj = bt.mp ? bt.mp[((size_t)cb * bt.ns + sh.sslot[j]) * T + t] : 0.0;
           v = (pj - phi) * sh.inv_s[j];
         }
       }
@@ -409,7 +415,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
 #pragma unroll
           for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
         }
-        base_out[((size_t)c * m + e) * T + t] = fp;
+        base_out[((size_t)cb * m + e) * T + t] = fp;
       }
     }
   }
@@ -635,7 +641,8 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
 template <typename F, int TT, int BS>
 __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>& w,
                                            const F* __restrict__ HMC,
-                                           double* __restrict__ fmax_out, int c, int eb) {
+                                           double* __restrict__ fmax_out, int c, int eb,
+                                           int oc) {
   constexpr int NW = BS / 64;
   const CandInfo* inf = w.info + c;
   const int status = inf->status;
@@ -648,7 +655,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
   const int ei_c = valid ? ei : nM - 1;
   // waves lying wholly past the monitored set skip the sweep (uniform per wave)
   const bool wave_live = eb * BS + (int)(tid & ~63) < nM;
-  const int n_pairs = wave_live ? n_act_pad : 0;
+  // wave-uniform by construction; readfirstlane keeps the contingency loop a
+  // scalar loop (its records then load through the scalar cache)
+  const int n_pairs = __builtin_amdgcn_readfirstlane(wave_live ? n_act_pad : 0);
   F acc[TT], a[TT];
   switch (r) {
     case 0: sweep_core<F, TT, 0>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
@@ -665,7 +674,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
   const int e = g.mon[ei_c];
   bool opened = false;
   for (int q = 0; q < k; ++q) opened |= (inf->open_br[q] == e);
-  double so = 0.0, best = -1.0;
+  double so = 0.0, best = -1.0, best2 = -1.0;
   int cc = 0, bt = 0, be = ei;
   if (valid) {
     const double lim = g.lim[e];
@@ -674,37 +683,44 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
       if (t < T) {
         // an opened monitored branch carries no flow in any state
         const double fm = opened ? 0.0 : (double)acc[t];
-        if (fmax_out) fmax_out[((size_t)c * nM + ei) * T + t] = fm;
+        if (fmax_out) fmax_out[((size_t)oc * nM + ei) * T + t] = fm;
         const double ov = fm - lim;
         if (ov > 0.0) so += ov;
         cc += fm > lim;
         const double ratio = fm / lim;
-        if (ratio > best) { best = ratio; bt = t; }
+        if (ratio > best) { best2 = best; best = ratio; bt = t; }
+        else if (ratio > best2) best2 = ratio;
       }
     }
   }
   // deterministic wave butterfly (every lane ends with the same values), then
-  // the waves of the tile in increasing monitored order
+  // the waves of the tile in increasing monitored order; best2 tracks the
+  // runner-up loading for the near-tie test of the FP32 pass
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     so += __shfl_xor(so, off);
     cc += __shfl_xor(cc, off);
-    const double b2 = __shfl_xor(best, off);
+    const double b2 = __shfl_xor(best, off), s2 = __shfl_xor(best2, off);
     const int e2 = __shfl_xor(be, off), t2 = __shfl_xor(bt, off);
-    if (b2 > best || (b2 == best && e2 < be)) { best = b2; be = e2; bt = t2; }
+    const bool take = b2 > best || (b2 == best && e2 < be);
+    const double lo = take ? best : b2;
+    best2 = fmax(fmax(best2, s2), lo);
+    if (take) { best = b2; be = e2; bt = t2; }
   }
   Partial* out = w.part + (size_t)c * w.n_eblk + eb;
   if constexpr (NW == 1) {
     if (tid == 0) {
       Partial p;
-      p.sum_o = so; p.best = best; p.cnt_c = cc; p.best_e = be; p.best_t = bt; p.pad_ = 0;
+      p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
+      p.pad_ = 0;
       *out = p;
     }
   } else {
     __shared__ Partial s_p[NW];
     if ((tid & 63) == 0) {
       Partial p;
-      p.sum_o = so; p.best = best; p.cnt_c = cc; p.best_e = be; p.best_t = bt; p.pad_ = 0;
+      p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
+      p.pad_ = 0;
       s_p[tid >> 6] = p;
     }
     __syncthreads();
@@ -713,7 +729,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
       for (int q = 1; q < NW; ++q) {
         p.sum_o += s_p[q].sum_o;
         p.cnt_c += s_p[q].cnt_c;
-        if (s_p[q].best > p.best) { p.best = s_p[q].best; p.best_e = s_p[q].best_e; p.best_t = s_p[q].best_t; }
+        const bool take = s_p[q].best > p.best;
+        p.best2 = fmax(fmax(p.best2, s_p[q].best2), take ? p.best : s_p[q].best);
+        if (take) { p.best = s_p[q].best; p.best_e = s_p[q].best_e; p.best_t = s_p[q].best_t; }
       }
       *out = p;
     }
@@ -731,14 +749,18 @@ __global__ __launch_bounds__(BS) void k_sweep(GridDev g, SweepBufs<F> w,
                                               const F* __restrict__ HMC,
                                               double* __restrict__ fmax_out, int n_cand,
                                               int xcd, int* __restrict__ counter,
-                                              const int* __restrict__ order) {
-  const int n_tiles = n_cand * w.n_eblk;
+                                              const int* __restrict__ order,
+                                              const int* __restrict__ map,
+                                              const int* __restrict__ live) {
+  int nc = n_cand;
+  if (live) nc = min(*live, n_cand);
+  const int n_tiles = nc * w.n_eblk;
   if (counter == nullptr) {
     int q = blockIdx.x;
     if (xcd) q = (q & 7) * (int)(gridDim.x >> 3) + (q >> 3);
     if (q >= n_tiles) return;
     const int c = q / w.n_eblk;
-    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, q - c * w.n_eblk);
+    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, q - c * w.n_eblk, map ? map[c] : c);
     return;
   }
   __shared__ int s_q;
@@ -749,7 +771,7 @@ __global__ __launch_bounds__(BS) void k_sweep(GridDev g, SweepBufs<F> w,
     __syncthreads();
     if (q >= n_tiles) break;   // every wave of the grid reaches this exit
     const int ci = q / w.n_eblk;
-    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, order[ci], q - ci * w.n_eblk);
+    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, order[ci], q - ci * w.n_eblk, order[ci]);
   }
 }
 
@@ -791,48 +813,63 @@ __global__ __launch_bounds__(1024) void k_rank_order(const CandInfo* __restrict_
 __global__ void k_zero_int(int* p) { *p = 0; }
 
 // ---------------------------------------------------------------------------
+// Finalize one candidate per wave.  Main pass: outputs at index c.  FP64
+// refinement pass (map != NULL): workgroup c < min(*live, cap) finalizes
+// candidate map[c] and marks it REFINED.  With rc.list set (FP32 main pass),
+// candidates whose discrete outputs lie within the flow error margin of a
+// decision (a load-bin edge, a runner-up (e, t) loading, a runner-up
+// contingency at (e*, t*)) are queued for the FP64 pass.
 template <typename F, int TT>
 __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
-                                                 const F* __restrict__ HMC, tto_outputs o) {
+                                                 const F* __restrict__ HMC, tto_outputs o,
+                                                 const int* __restrict__ map,
+                                                 const int* __restrict__ live, int cap,
+                                                 RefineCtl rc) {
   constexpr int RS = rec_stride(TT);
   const int c = blockIdx.x;
+  if (map && c >= min(*live, cap)) return;
+  const int oc = map ? map[c] : c;
   const int lane = threadIdx.x;
   const CandInfo inf = w.info[c];
   const int nM = g.nM, nC = g.nC;
+  const uint8_t refined = map ? (uint8_t)TTO_ST_REFINED : (uint8_t)0;
   if (inf.status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) {
     if (lane == 0) {
       const double nan = __builtin_nan("");
-      if (o.status) o.status[c] = (uint8_t)inf.status;
-      if (o.n_island_cont) o.n_island_cont[c] = 0;
-      if (o.overload_mw) o.overload_mw[c] = nan;
-      if (o.n_crit_n1) o.n_crit_n1[c] = 0;
-      if (o.n_crit_n0) o.n_crit_n0[c] = 0;
-      if (o.max_loading) o.max_loading[c] = nan;
-      if (o.worst_branch) o.worst_branch[c] = -1;
-      if (o.worst_cont) o.worst_cont[c] = -1;
-      if (o.worst_t) o.worst_t[c] = -1;
-      if (o.fitness) o.fitness[c] = -__builtin_inf();
-      if (o.cell) o.cell[c] = -1;
+      if (o.status) o.status[oc] = (uint8_t)inf.status | refined;
+      if (o.n_island_cont) o.n_island_cont[oc] = 0;
+      if (o.overload_mw) o.overload_mw[oc] = nan;
+      if (o.n_crit_n1) o.n_crit_n1[oc] = 0;
+      if (o.n_crit_n0) o.n_crit_n0[oc] = 0;
+      if (o.max_loading) o.max_loading[oc] = nan;
+      if (o.worst_branch) o.worst_branch[oc] = -1;
+      if (o.worst_cont) o.worst_cont[oc] = -1;
+      if (o.worst_t) o.worst_t[oc] = -1;
+      if (o.fitness) o.fitness[oc] = -__builtin_inf();
+      if (o.cell) o.cell[oc] = -1;
     }
     return;
   }
-  __shared__ double s_sum, s_best;
+  __shared__ double s_sum, s_best, s_best2;
   __shared__ int s_cc, s_be, s_bt;
   if (lane == 0) {
-    double so = 0.0, best = -1.0;
+    double so = 0.0, best = -1.0, best2 = -1.0;
     int cc = 0, be = -1, bt = 0;
     const Partial* p = w.part + (size_t)c * w.n_eblk;
     for (int b = 0; b < w.n_eblk; ++b) {
       so += p[b].sum_o;
       cc += p[b].cnt_c;
-      if (p[b].best > best) { best = p[b].best; be = p[b].best_e; bt = p[b].best_t; }
+      const bool take = p[b].best > best;
+      best2 = fmax(fmax(best2, p[b].best2), take ? best : p[b].best);
+      if (take) { best = p[b].best; be = p[b].best_e; bt = p[b].best_t; }
     }
-    s_sum = so; s_best = best; s_cc = cc; s_be = be; s_bt = bt;
+    s_sum = so; s_best = best; s_best2 = best2; s_cc = cc; s_be = be; s_bt = bt;
   }
   __syncthreads();
   const int be = s_be, bt = s_bt;
-  // arg-max contingency at (e*, t*), same arithmetic as the sweep
-  double bv = -1.0;
+  // arg-max contingency at (e*, t*), same arithmetic as the sweep; v2 keeps
+  // the runner-up value for the near-tie test
+  double bv = -1.0, v2 = -1.0;
   int bi = INT_MAX;
   bool be_open = false;
   if (be >= 0)
@@ -850,13 +887,16 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
       F h = HMC[(size_t)act[i] * nM + be];
       for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
       const double v = (double)fabs_t(fma_t(h, ri[bt], a));
-      if (v > bv) { bv = v; bi = i; }
+      if (v > bv) { v2 = bv; bv = v; bi = i; }
+      else if (v > v2) v2 = v;
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(bv, off);
+    const double ov = __shfl_xor(bv, off), o2 = __shfl_xor(v2, off);
     const int oi = __shfl_xor(bi, off);
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    const bool take = ov > bv || (ov == bv && oi < bi);
+    v2 = fmax(fmax(v2, o2), take ? bv : ov);
+    if (take) { bv = ov; bi = oi; }
   }
   if (lane == 0) {
     const double so = s_sum, best = s_best;
@@ -867,17 +907,30 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     for (int q = 0; q < g.n_load_bins - 1; ++q) bin += (g.edges[q] <= best) ? 1 : 0;
     const int cnt = inf.r < g.n_count_bins - 1 ? inf.r : g.n_count_bins - 1;
     const int* act = w.act + (size_t)c * (nC + 1);
-    if (o.status) o.status[c] = (uint8_t)inf.status;
-    if (o.n_island_cont) o.n_island_cont[c] = inf.n_island;
-    if (o.overload_mw) o.overload_mw[c] = so;
-    if (o.n_crit_n1) o.n_crit_n1[c] = cc;
-    if (o.n_crit_n0) o.n_crit_n0[c] = n0;
-    if (o.max_loading) o.max_loading[c] = best < 0.0 ? 0.0 : best;
-    if (o.worst_branch) o.worst_branch[c] = be >= 0 ? g.mon[be] : -1;
-    if (o.worst_t) o.worst_t[c] = be >= 0 ? bt : -1;
-    if (o.worst_cont) o.worst_cont[c] = (bi != INT_MAX) ? g.cont[act[bi]] : -1;
-    if (o.fitness) o.fitness[c] = fit;
-    if (o.cell) o.cell[c] = cnt * g.n_load_bins + bin;
+    uint8_t st = (uint8_t)inf.status | refined;
+    if (rc.list && be >= 0) {
+      const double lim_e = g.lim[g.mon[be]];
+      bool near = (best - s_best2) * g.lim_min <= rc.margin;          // runner-up (e, t)
+      near |= (inf.n_act > 1 && bv - v2 <= 2.0 * rc.margin);           // runner-up l
+      for (int q = 0; q < g.n_load_bins - 1; ++q)                      // load-bin edge
+        near |= fabs(best - g.edges[q]) * lim_e <= rc.margin;
+      if (near) {
+        const int slot = atomicAdd(rc.count, 1);
+        if (slot < rc.cap) rc.list[slot] = c;
+        else st |= (uint8_t)TTO_ST_REFINE_SKIPPED;
+      }
+    }
+    if (o.status) o.status[oc] = st;
+    if (o.n_island_cont) o.n_island_cont[oc] = inf.n_island;
+    if (o.overload_mw) o.overload_mw[oc] = so;
+    if (o.n_crit_n1) o.n_crit_n1[oc] = cc;
+    if (o.n_crit_n0) o.n_crit_n0[oc] = n0;
+    if (o.max_loading) o.max_loading[oc] = best < 0.0 ? 0.0 : best;
+    if (o.worst_branch) o.worst_branch[oc] = be >= 0 ? g.mon[be] : -1;
+    if (o.worst_t) o.worst_t[oc] = be >= 0 ? bt : -1;
+    if (o.worst_cont) o.worst_cont[oc] = (bi != INT_MAX) ? g.cont[act[bi]] : -1;
+    if (o.fitness) o.fitness[oc] = fit;
+    if (o.cell) o.cell[oc] = cnt * g.n_load_bins + bin;
   }
 }
 
@@ -983,56 +1036,91 @@ hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, con
 
 template <typename F, int TT, int BS>
 static void launch_sweep(const GridDev& g, const BatchDev& bt, SweepBufs<F> w, const F* HMC,
-                         const tto_outputs& o, hipStream_t s, const SweepPlan& plan) {
+                         double* fmax_out, hipStream_t s, const SweepPlan& plan) {
   w.n_eblk = (g.nM + BS - 1) / BS;
   const int tiles = w.n_eblk * bt.B;
   if (plan.persistent) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, w.counter);
     hipLaunchKernelGGL(k_rank_order, dim3(1), dim3(1024), 0, s, w.info, bt.B, w.order);
     const int grid = std::min(tiles, std::max(plan.grid, 1));
-    hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3(grid), dim3(BS), 0, s, g, w, HMC, o.fmax,
-                       bt.B, 0, w.counter, (const int*)w.order);
+    hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3(grid), dim3(BS), 0, s, g, w, HMC, fmax_out,
+                       bt.B, 0, w.counter, (const int*)w.order, bt.map, bt.live);
   } else {
     hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3((tiles + 7) / 8 * 8), dim3(BS), 0, s, g, w,
-                       HMC, o.fmax, bt.B, plan.xcd, (int*)nullptr, (const int*)nullptr);
+                       HMC, fmax_out, bt.B, plan.xcd, (int*)nullptr, (const int*)nullptr,
+                       bt.map, bt.live);
   }
 }
 
 template <typename F, int TT>
-static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w0,
-                                 const tto_outputs& o, hipStream_t s, hipEvent_t* ev,
-                                 const SweepPlan& plan) {
+static void launch_pass(const GridDev& g, const BatchDev& bt, SweepBufs<F> w,
+                        const tto_outputs& o, hipStream_t s, hipEvent_t* ev,
+                        const SweepPlan& plan, const RefineCtl& rc) {
   const F* HMC;
   if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
-  SweepBufs<F> w = w0;
   w.n_eblk = (g.nM + plan.bs - 1) / plan.bs;
   if (ev) hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_setup<F, TT>), dim3(bt.B), dim3(256), 0, s, g, bt, w, o.base_flows);
   if (ev) hipEventRecord(ev[1], s);
   switch (plan.bs) {
-    case 64: launch_sweep<F, TT, 64>(g, bt, w, HMC, o, s, plan); break;
-    case 128: launch_sweep<F, TT, 128>(g, bt, w, HMC, o, s, plan); break;
-    default: launch_sweep<F, TT, 256>(g, bt, w, HMC, o, s, plan); break;
+    case 64: launch_sweep<F, TT, 64>(g, bt, w, HMC, o.fmax, s, plan); break;
+    case 128: launch_sweep<F, TT, 128>(g, bt, w, HMC, o.fmax, s, plan); break;
+    default: launch_sweep<F, TT, 256>(g, bt, w, HMC, o.fmax, s, plan); break;
   }
   if (ev) hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL((k_finalize<F, TT>), dim3(bt.B), dim3(64), 0, s, g, w, HMC, o);
+  hipLaunchKernelGGL((k_finalize<F, TT>), dim3(bt.B), dim3(64), 0, s, g, w, HMC, o, bt.map,
+                     bt.live, bt.B, rc);
   if (ev) hipEventRecord(ev[3], s);
+}
+
+template <typename F, int TT>
+static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                                 const tto_outputs& o, hipStream_t s, hipEvent_t* ev,
+                                 const SweepPlan& plan, const SweepBufs<double>* rw,
+                                 const RefineCtl& rc) {
+  const bool refine = (sizeof(F) == 4) && rw && rc.cap > 0;
+  RefineCtl main_rc = rc;
+  if (!refine) main_rc.list = nullptr;
+  if (refine) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, rc.count);
+  launch_pass<F, TT>(g, bt, w, o, s, ev, plan, main_rc);
   if (o.n1_flows) {
+    const F* HMC;
+    if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
     const int nb = (g.nM + 255) / 256;
     hipLaunchKernelGGL((k_n1_dump<F, TT>), dim3(nb, bt.B), dim3(256), 0, s, g, w, HMC, o.n1_flows);
   }
+  if (refine) {
+    // FP64 re-evaluation of the queued candidates (no host synchronisation:
+    // grids are sized for the capacity and idle workgroups exit at once)
+    BatchDev rb = bt;
+    rb.B = rc.cap;
+    rb.map = rc.list;
+    rb.live = rc.count;
+    tto_outputs ro = o;
+    ro.base_flows = nullptr;
+    ro.n1_flows = nullptr;
+    RefineCtl none = rc;
+    none.list = nullptr;
+    SweepPlan rp = plan;
+    rp.persistent = 0;
+    GridDev gh = g;
+    gh.f0 = g.f0_hi;   // FP64-GEMM base flows
+    launch_pass<double, TT>(gh, rb, *rw, ro, s, nullptr, rp, none);
+  }
+  if (ev) hipEventRecord(ev[4], s);
   return hipGetLastError();
 }
 
 template <typename F>
 hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
                            const tto_outputs& o, hipStream_t s, hipEvent_t* ev,
-                           const SweepPlan& plan) {
+                           const SweepPlan& plan, const SweepBufs<double>* rw,
+                           const RefineCtl& rc) {
   switch (g.TT) {
-    case 1: return launch_eval_tt<F, 1>(g, bt, w, o, s, ev, plan);
-    case 8: return launch_eval_tt<F, 8>(g, bt, w, o, s, ev, plan);
-    case 24: return launch_eval_tt<F, 24>(g, bt, w, o, s, ev, plan);
-    default: return launch_eval_tt<F, 32>(g, bt, w, o, s, ev, plan);
+    case 1: return launch_eval_tt<F, 1>(g, bt, w, o, s, ev, plan, rw, rc);
+    case 8: return launch_eval_tt<F, 8>(g, bt, w, o, s, ev, plan, rw, rc);
+    case 24: return launch_eval_tt<F, 24>(g, bt, w, o, s, ev, plan, rw, rc);
+    default: return launch_eval_tt<F, 32>(g, bt, w, o, s, ev, plan, rw, rc);
   }
 }
 
@@ -1055,9 +1143,11 @@ int sweep_blocks_per_cu(int flow_f32, int TT, int bs) {
 
 template hipError_t launch_evaluate<float>(const GridDev&, const BatchDev&, const SweepBufs<float>&,
                                            const tto_outputs&, hipStream_t, hipEvent_t*,
-                                           const SweepPlan&);
+                                           const SweepPlan&, const SweepBufs<double>*,
+                                           const RefineCtl&);
 template hipError_t launch_evaluate<double>(const GridDev&, const BatchDev&, const SweepBufs<double>&,
                                             const tto_outputs&, hipStream_t, hipEvent_t*,
-                                            const SweepPlan&);
+                                            const SweepPlan&, const SweepBufs<double>*,
+                                            const RefineCtl&);
 
 }  // namespace tto

@@ -65,6 +65,8 @@ struct GridLayout {
   double* S; double* SMC; float* HMC32; double* HMC64; double* f0;
   void* A; void* PT; float* part32; double* part64;
   int ksplit;
+  // FP64 copy of the base-flow product for the refinement of FP32 grids
+  double* f0_hi; void* A64; void* PT64; double* part_hi;
 };
 
 GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
@@ -95,6 +97,14 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
     L.part32 = cv.take<float>((size_t)L.ksplit * m * kGemmN);
     L.part64 = nullptr;
   }
+  if (d->gemm_precision == TTO_GEMM_F64 || d->flow_precision == TTO_FLOW_F64) {
+    L.f0_hi = nullptr; L.A64 = nullptr; L.PT64 = nullptr; L.part_hi = nullptr;
+  } else {
+    L.f0_hi = cv.take<double>(m * T);
+    L.A64 = cv.take<double>(mp * ld);
+    L.PT64 = cv.take<double>((size_t)kGemmN * ld);
+    L.part_hi = cv.take<double>((size_t)L.ksplit * m * kGemmN);
+  }
   (void)n;
   *bytes = cv.off;
   return L;
@@ -118,14 +128,36 @@ SweepBufs<F> carve_batch(int B, int nM, int nC, int TT, void* ws, size_t* bytes)
   return w;
 }
 
-size_t batch_bytes_for(const tto_grid_desc* d) {
-  size_t bytes = 0;
-  const int TT = tile_T(d->n_timesteps);
-  if (d->flow_precision == TTO_FLOW_F32)
-    carve_batch<float>(d->max_batch, d->n_monitored, d->n_contingency, TT, nullptr, &bytes);
+// FP64 refinement capacity of an FP32 grid: an eighth of the batch, >= 64.
+int refine_cap(int max_batch) { return std::min(max_batch, std::max(64, (max_batch + 7) / 8)); }
+
+struct BatchLayout {
+  size_t main_bytes;     // main-pass buffers
+  size_t refine_off;     // start of the refinement region (FP32 grids)
+  size_t bytes;          // total
+};
+
+BatchLayout batch_layout(int flow_prec, int B, int max_batch, int nM, int nC, int TT) {
+  BatchLayout L;
+  if (flow_prec == TTO_FLOW_F32)
+    carve_batch<float>(B, nM, nC, TT, nullptr, &L.main_bytes);
   else
-    carve_batch<double>(d->max_batch, d->n_monitored, d->n_contingency, TT, nullptr, &bytes);
-  return std::max(bytes, (size_t)16 * 4096);   // archive scratch for up to 4096 cells
+    carve_batch<double>(B, nM, nC, TT, nullptr, &L.main_bytes);
+  L.refine_off = (L.main_bytes + 255) & ~(size_t)255;
+  L.bytes = L.main_bytes;
+  if (flow_prec == TTO_FLOW_F32) {
+    size_t rb = 0;
+    carve_batch<double>(refine_cap(max_batch), nM, nC, TT, nullptr, &rb);
+    L.bytes = L.refine_off + rb + 2 * 256 + sizeof(int) * (size_t)refine_cap(max_batch);
+  }
+  return L;
+}
+
+size_t batch_bytes_for(const tto_grid_desc* d) {
+  const int TT = tile_T(d->n_timesteps);
+  BatchLayout L = batch_layout(d->flow_precision, d->max_batch, d->max_batch, d->n_monitored,
+                               d->n_contingency, TT);
+  return std::max(L.bytes, (size_t)16 * 4096);   // archive scratch for up to 4096 cells
 }
 
 tto_status check_desc(const tto_grid_desc* d) {
@@ -165,9 +197,11 @@ struct tto_grid {
   GridDev dev;
   bool profile = false;
   bool recorded = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   SweepPlan plan = {256, 0, 0, 0};
   int n_cu = 0;
+  int refine = 1;              // FP64 refinement of near-decision candidates (FP32 flows)
+  double refine_margin = 8e-3; // MW
 };
 
 extern "C" {
@@ -252,6 +286,7 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   if (d->n_contingency > 0)
     HIP_TRY(launch_build_HMC(L.S, L.b, L.mon, L.cont, m, d->n_monitored, d->n_contingency, L.HMC32, L.HMC64, s));
   HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, d->gemm_precision, L.A, s));
+  if (L.A64) HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, TTO_GEMM_F64, L.A64, s));
   HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
   HIP_TRY(hipStreamSynchronize(s));
 
@@ -267,8 +302,10 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   GridDev& v = g->dev;
   v.n_bus = n; v.n_branch = m; v.slack = d->slack; v.T = g->T; v.TT = g->TT; v.nM = g->nM; v.nC = g->nC;
   v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S; v.SMC = L.SMC;
-  v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.mon = L.mon; v.cont = L.cont;
+  v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.f0_hi = L.f0_hi ? L.f0_hi : L.f0; v.mon = L.mon; v.cont = L.cont;
   v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
+  v.lim_min = 1e300;
+  for (int i = 0; i < d->n_monitored; ++i) v.lim_min = std::min(v.lim_min, d->limit_mw[d->monitored[i]]);
   *out = g;
   return ok();
 }
@@ -292,8 +329,8 @@ tto_status tto_profile_enable(tto_grid* g, int32_t enable) {
 tto_status tto_profile_read(tto_grid* g, double* ms) {
   if (!g || !ms) return fail(TTO_E_INVALID, "grid or ms is NULL");
   if (!g->profile || !g->recorded) return fail(TTO_E_INVALID, "profiling off or nothing recorded");
-  HIP_TRY(hipEventSynchronize(g->ev[3]));
-  for (int i = 0; i < 3; ++i) {
+  HIP_TRY(hipEventSynchronize(g->ev[4]));
+  for (int i = 0; i < 4; ++i) {
     float t = 0.f;
     HIP_TRY(hipEventElapsedTime(&t, g->ev[i], g->ev[i + 1]));
     ms[i] = t;
@@ -307,6 +344,11 @@ tto_status tto_set_injections(tto_grid* g, const double* p_mw, void* stream) {
   HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, g->gemm_prec, g->L.PT, s));
   HIP_TRY(launch_gemm_f0(g->gemm_prec, g->L.A, g->L.PT, g->m, g->n_bus, g->T, g->L.ksplit,
                          g->L.part32, g->L.part64, g->L.f0, s));
+  if (g->L.f0_hi) {
+    HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, TTO_GEMM_F64, g->L.PT64, s));
+    HIP_TRY(launch_gemm_f0(TTO_GEMM_F64, g->L.A64, g->L.PT64, g->m, g->n_bus, g->T, g->L.ksplit,
+                           nullptr, g->L.part_hi, g->L.f0_hi, s));
+  }
   return ok();
 }
 
@@ -358,20 +400,50 @@ tto_status tto_evaluate(tto_grid* g, const tto_batch* bt, const tto_outputs* out
   if (g->nC == 0 && out->n1_flows) return fail(TTO_E_INVALID, "n1_flows requested with no contingencies");
   BatchDev b;
   b.B = bt->n_cand; b.no = bt->n_open_slots; b.ns = bt->n_split_slots;
+  b.n_genomes = bt->n_cand;
   b.open = bt->open; b.sbus = bt->split_bus; b.moff = bt->moved_off; b.mbr = bt->moved_br;
   b.mp = bt->moved_p_mw;
+  b.map = nullptr;
+  b.live = nullptr;
   hipStream_t s = (hipStream_t)stream;
   size_t used = 0;
+  RefineCtl rc;
+  rc.list = nullptr; rc.count = nullptr; rc.cap = 0; rc.margin = g->refine_margin;
   if (g->flow_prec == TTO_FLOW_F32) {
     SweepBufs<float> w = carve_batch<float>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
     if (!out->n1_flows) w.slot = nullptr;
-    HIP_TRY(launch_evaluate<float>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr, g->plan));
+    SweepBufs<double> rw;
+    const SweepBufs<double>* rwp = nullptr;
+    if (g->refine) {
+      BatchLayout BL = batch_layout(g->flow_prec, bt->n_cand, g->max_batch, g->nM, g->nC, g->TT);
+      char* base = (char*)batch_ws + BL.refine_off;
+      size_t rb = 0;
+      const int cap = refine_cap(g->max_batch);
+      rw = carve_batch<double>(cap, g->nM, g->nC, g->TT, base, &rb);
+      rw.slot = nullptr;
+      char* tail = base + ((rb + 255) & ~(size_t)255);
+      rc.count = (int*)tail;
+      rc.list = (int*)(tail + 256);
+      rc.cap = cap;
+      rwp = &rw;
+    }
+    HIP_TRY(launch_evaluate<float>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr, g->plan,
+                                   rwp, rc));
   } else {
     SweepBufs<double> w = carve_batch<double>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
     if (!out->n1_flows) w.slot = nullptr;
-    HIP_TRY(launch_evaluate<double>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr, g->plan));
+    HIP_TRY(launch_evaluate<double>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr, g->plan,
+                                    nullptr, rc));
   }
   if (g->profile) g->recorded = true;
+  return ok();
+}
+
+tto_status tto_set_refine(tto_grid* g, int32_t enable, double margin_mw) {
+  if (!g) return fail(TTO_E_INVALID, "grid is NULL");
+  if (!(margin_mw >= 0.0) || !isfinite(margin_mw)) return fail(TTO_E_INVALID, "margin must be finite and >= 0");
+  g->refine = enable ? 1 : 0;
+  g->refine_margin = margin_mw;
   return ok();
 }
 
@@ -451,7 +523,7 @@ tto_status tto_autotune(tto_grid* g, const tto_batch* bt, const tto_outputs* out
     for (int rep = 0; rep < 3; ++rep) {
       st = tto_evaluate(g, bt, out, batch_ws, batch_bytes, stream);
       if (st != TTO_OK) return st;
-      double ms[3];
+      double ms[4];
       st = tto_profile_read(g, ms);
       if (st != TTO_OK) return st;
       t[rep] = ms[1];

@@ -44,21 +44,35 @@ struct GridDev {
   const double* SMC;
   const float* HMC32;   // [nC][nM], H[M[ei], C[li]] with -1 where M[ei] == C[li]
   const double* HMC64;  // same in FP64
-  const double* f0;     // [m][T] base flows of the unswitched grid
+  const double* f0;     // [m][T] base flows of the unswitched grid (GEMM precision)
+  const double* f0_hi;  // [m][T] the same from the FP64 GEMM (refinement pass)
   const int* mon;       // [nM]
   const int* cont;      // [nC]
   const double* edges;  // [n_load_bins - 1]
+  double lim_min;       // smallest monitored limit
   int n_count_bins, n_load_bins;
   double w_c0, w_c;
 };
 
 struct BatchDev {
   int B, no, ns;
+  int n_genomes;      // rows of the genome arrays (B of the caller's batch)
   const int* open;
   const int* sbus;
   const int* moff;
   const int* mbr;
   const double* mp;
+  // refinement pass: workgroup c < min(*live, B) evaluates genome map[c]
+  const int* map;
+  const int* live;
+};
+
+// FP32 pass -> FP64 refinement hand-over.
+struct RefineCtl {
+  int* list;        // [cap] candidates to re-evaluate in FP64
+  int* count;       // number flagged (may exceed cap)
+  int cap;
+  double margin;    // flow error margin in MW
 };
 
 // Per-candidate summary written by the set-up kernel.
@@ -78,6 +92,7 @@ struct CandInfo {
 struct Partial {
   double sum_o;     // sum of max(fmax - lim, 0)
   double best;      // max loading in this block
+  double best2;     // second largest loading (another (e, t)) in this block
   int cnt_c;        // fmax > lim count
   int best_e;       // monitored index of the max (smallest on ties)
   int best_t;
@@ -121,12 +136,14 @@ hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n,
 int gemm_ksplit(int m, int n);
 
 // ---- launchers (k_eval.hip) -------------------------------------------------
-// ev: NULL or 4 events recorded before set-up, after set-up, after the sweep
-// and after finalize.
+// ev: NULL or 5 events recorded before set-up, after set-up, after the sweep,
+// after finalize and after the FP64 refinement pass.  rw/rc: refinement
+// buffers and control (FP32 flows only; rc.cap == 0 disables).
 template <typename F>
 hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
                            const tto_outputs& out, hipStream_t s, hipEvent_t* ev,
-                           const SweepPlan& plan);
+                           const SweepPlan& plan, const SweepBufs<double>* rw,
+                           const RefineCtl& rc);
 int sweep_blocks_per_cu(int flow_f32, int TT, int bs);
 hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
                           const int* cell, const uint8_t* status, int B, int64_t id_base,

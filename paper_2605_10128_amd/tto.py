@@ -18,7 +18,7 @@ TTO_OK = 0
 TTO_E_INVALID, TTO_E_GRID, TTO_E_RANK, TTO_E_WORKSPACE, TTO_E_HIP, TTO_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 TTO_FLOW_F64, TTO_FLOW_F32 = 0, 1
 TTO_GEMM_F64, TTO_GEMM_F32, TTO_GEMM_BF16, TTO_GEMM_F16 = 0, 1, 2, 3
-TTO_ST_ISLANDED, TTO_ST_INVALID, TTO_ST_REFINED = 1, 2, 4
+TTO_ST_ISLANDED, TTO_ST_INVALID, TTO_ST_REFINED, TTO_ST_REFINE_SKIPPED = 1, 2, 4, 8
 TTO_MAX_RANK, TTO_MAX_T, TTO_MAX_MOVED, TTO_MAX_LOAD_BINS = 8, 32, 64, 64
 
 _vp = ct.c_void_p
@@ -79,6 +79,7 @@ def _load():
         "tto_profile_enable": (_i32, [_vp, _i32]),
         "tto_profile_read": (_i32, [_vp, P(ct.c_double)]),
         "tto_set_sweep_plan": (_i32, [_vp, _i32, _i32, _i32]),
+        "tto_set_refine": (_i32, [_vp, _i32, ct.c_double]),
         "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
         "tto_autotune": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                 ct.c_char_p, P(_i32)]),
@@ -95,7 +96,7 @@ _lib = _load()
 EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_create",
             "tto_grid_destroy", "tto_set_injections", "tto_get_base_flows", "tto_set_descriptor",
             "tto_evaluate", "tto_archive_insert", "tto_profile_enable", "tto_profile_read",
-            "tto_set_sweep_plan", "tto_get_sweep_plan", "tto_autotune"]
+            "tto_set_sweep_plan", "tto_get_sweep_plan", "tto_autotune", "tto_set_refine"]
 
 
 def _check(code: int):
@@ -161,13 +162,17 @@ def tto_profile_enable(handle: int, enable: bool):
 
 
 def tto_profile_read(handle: int):
-    ms = (ct.c_double * 3)()
+    ms = (ct.c_double * 4)()
     _check(_lib.tto_profile_read(_vp(handle), ms))
     return list(ms)
 
 
 def tto_set_sweep_plan(handle: int, block: int, xcd_group: bool, persistent: bool):
     _check(_lib.tto_set_sweep_plan(_vp(handle), block, int(xcd_group), int(persistent)))
+
+
+def tto_set_refine(handle: int, enable: bool, margin_mw: float = 8e-3):
+    _check(_lib.tto_set_refine(_vp(handle), 1 if enable else 0, float(margin_mw)))
 
 
 def tto_get_sweep_plan(handle: int):
