@@ -73,6 +73,7 @@ class Batch:
     moved_off: np.ndarray
     moved_br: np.ndarray
     moved_p: Optional[np.ndarray] = None
+    split_action: Optional[np.ndarray] = None   # [B, n_split_slots] action-table id or EMPTY
 
     @property
     def n_cand(self) -> int:
@@ -83,24 +84,22 @@ class Batch:
         return self.moved_br[self.moved_off[s]:self.moved_off[s + 1]]
 
     def subset(self, idx) -> "Batch":
+        """Candidates idx (repeats allowed) as a new batch."""
         idx = np.asarray(idx, dtype=np.int64)
         ns = self.split_bus.shape[1]
-        offs = [0]
-        br = []
-        mp = [] if self.moved_p is not None else None
-        for c in idx.tolist():
-            for j in range(ns):
-                m = self.moved(c, j)
-                br.extend(m.tolist())
-                offs.append(offs[-1] + len(m))
-                if mp is not None:
-                    mp.append(self.moved_p[c * ns + j])
+        slots = (idx[:, None] * ns + np.arange(ns)[None, :]).ravel()
+        lo = self.moved_off[:-1][slots].astype(np.int64)
+        lens = (self.moved_off[1:][slots] - self.moved_off[:-1][slots]).astype(np.int64)
+        offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+        rep = np.repeat(lo - offs[:-1], lens)
+        br = self.moved_br[np.arange(int(offs[-1])) + rep] if offs[-1] else np.zeros(0, np.int32)
         return Batch(
             open=self.open[idx].copy(),
             split_bus=self.split_bus[idx].copy(),
-            moved_off=np.asarray(offs, dtype=np.int32),
+            moved_off=offs,
             moved_br=np.asarray(br, dtype=np.int32),
-            moved_p=None if mp is None else np.asarray(mp, dtype=np.float64).reshape(len(idx) * ns, -1),
+            moved_p=None if self.moved_p is None else self.moved_p[slots].copy(),
+            split_action=None if self.split_action is None else self.split_action[idx].copy(),
         )
 
 
@@ -250,7 +249,7 @@ def make_split_table(grid: Grid, size: int, seed: int, min_degree: int = 3):
     return table
 
 
-def _pack(opens, splits, n_open_slots, n_split_slots, T, moved_p_list):
+def _pack(opens, splits, n_open_slots, n_split_slots, T, moved_p_list, actions=None):
     B = len(opens)
     op = np.full((B, n_open_slots), EMPTY, dtype=np.int32)
     sb = np.full((B, n_split_slots), EMPTY, dtype=np.int32)
@@ -272,8 +271,14 @@ def _pack(opens, splits, n_open_slots, n_split_slots, T, moved_p_list):
                     mp[c * n_split_slots + j] = moved_p_list[c][j]
             else:
                 offs.append(offs[-1])
+    sa = None
+    if actions is not None:
+        sa = np.full((B, n_split_slots), EMPTY, dtype=np.int32)
+        for c in range(B):
+            for j, a in enumerate(actions[c]):
+                sa[c, j] = a
     return Batch(open=op, split_bus=sb, moved_off=np.asarray(offs, dtype=np.int32),
-                 moved_br=np.asarray(br, dtype=np.int32), moved_p=mp)
+                 moved_br=np.asarray(br, dtype=np.int32), moved_p=mp, split_action=sa)
 
 
 def _shuffle_slots(rng, batch: Batch) -> Batch:
@@ -285,6 +290,7 @@ def _shuffle_slots(rng, batch: Batch) -> Batch:
         op[c] = op[c][rng.permutation(no)]
     perm_s = [rng.permutation(ns) for _ in range(B)]
     sb = np.full_like(batch.split_bus, EMPTY)
+    sa = None if batch.split_action is None else np.full_like(batch.split_action, EMPTY)
     offs = [0]
     br = []
     mp = None if batch.moved_p is None else np.zeros_like(batch.moved_p)
@@ -292,13 +298,15 @@ def _shuffle_slots(rng, batch: Batch) -> Batch:
         for j in range(ns):
             src = int(perm_s[c][j])
             sb[c, j] = batch.split_bus[c, src]
+            if sa is not None:
+                sa[c, j] = batch.split_action[c, src]
             mv = batch.moved(c, src)
             br.extend(mv.tolist())
             offs.append(offs[-1] + len(mv))
             if mp is not None:
                 mp[c * ns + j] = batch.moved_p[c * ns + src]
     return Batch(open=op, split_bus=sb, moved_off=np.asarray(offs, dtype=np.int32),
-                 moved_br=np.asarray(br, dtype=np.int32), moved_p=mp)
+                 moved_br=np.asarray(br, dtype=np.int32), moved_p=mp, split_action=sa)
 
 
 def _moved_injection(rng, P_bus_row, move_frac):
@@ -356,34 +364,97 @@ def make_candidates_ranked(grid: Grid, B: int, seed: int, split_table, P=None,
                            move_frac: float = 0.0, n_open_slots: int = 8,
                            n_split_slots: int = 8) -> Batch:
     """Uneven-rank candidates: r ~ U{rank_range}, splits ~ Binomial(r, split_prob)
-    drawn from the split-action table at distinct buses, the rest non-bridge openings."""
+    drawn from the split-action table at distinct buses, the rest distinct
+    non-bridge openings that are not moved by the candidate's own splits.
+    Rows violating a rule are redrawn whole (vectorised rejection)."""
     rng = np.random.default_rng(seed)
     nb = bridges(grid.n_bus, grid.from_bus, grid.to_bus)
-    D = np.flatnonzero(~nb)
+    D = np.flatnonzero(~nb).astype(np.int64)
     T = 1 if P is None else P.shape[1]
-    opens, splits, mps = [], [], []
-    for _ in range(B):
-        r = int(rng.integers(rank_range[0], rank_range[1] + 1))
-        s = int(rng.binomial(r, split_prob))
-        s = min(s, n_split_slots)
-        k = min(r - s, n_open_slots)
-        sp, mp, used, moved_all = [], [], set(), set()
-        tries = 0
-        while len(sp) < s and tries < 1000:
-            tries += 1
-            bus, mv = split_table[int(rng.integers(0, len(split_table)))]
-            if bus in used:
-                continue
-            used.add(bus)
-            sp.append((bus, list(mv)))
-            moved_all.update(mv)
-            mp.append(None if P is None else _moved_injection(rng, P[bus], move_frac))
-        pool = np.asarray([e for e in D.tolist() if e not in moved_all])
-        opens.append(rng.choice(pool, size=k, replace=False).tolist())
-        splits.append(sp)
-        mps.append(mp)
-    batch = _pack(opens, splits, n_open_slots, n_split_slots, T, mps if P is not None else None)
-    return _shuffle_slots(rng, batch)
+    m = grid.n_branch
+    n_tab = len(split_table)
+    tab_bus = np.asarray([b for b, _ in split_table], dtype=np.int64)
+    tab_len = np.asarray([len(mv) for _, mv in split_table], dtype=np.int64)
+    tab_off = np.concatenate([[0], np.cumsum(tab_len)])
+    tab_flat = np.asarray([e for _, mv in split_table for e in mv], dtype=np.int64)
+    moved_keys = np.sort(np.repeat(np.arange(n_tab, dtype=np.int64), tab_len) * m + tab_flat)
+
+    r = rng.integers(rank_range[0], rank_range[1] + 1, size=B)
+    s = np.minimum(rng.binomial(r, split_prob), n_split_slots)
+    k = np.minimum(r - s, n_open_slots)
+    S = max(1, n_split_slots)
+    K = max(1, n_open_slots)
+    act = np.full((B, S), EMPTY, dtype=np.int64)
+    opn = np.full((B, K), EMPTY, dtype=np.int64)
+    sm = np.arange(S)[None, :] < s[:, None]
+    km = np.arange(K)[None, :] < k[:, None]
+    todo = np.arange(B)
+    while todo.size:
+        a = rng.integers(0, max(n_tab, 1), size=(todo.size, S))
+        o = D[rng.integers(0, len(D), size=(todo.size, K))]
+        a = np.where(sm[todo], a, EMPTY)
+        o = np.where(km[todo], o, EMPTY)
+        bad = np.zeros(todo.size, dtype=bool)
+        bus = np.where(a >= 0, tab_bus[np.maximum(a, 0)], -1)
+        for j in range(S):
+            for j2 in range(j):
+                bad |= (bus[:, j] >= 0) & (bus[:, j] == bus[:, j2])
+        for i in range(K):
+            for i2 in range(i):
+                bad |= (o[:, i] >= 0) & (o[:, i] == o[:, i2])
+            for j in range(S):
+                key = a[:, j] * m + o[:, i]
+                hit = (a[:, j] >= 0) & (o[:, i] >= 0)
+                pos = np.searchsorted(moved_keys, key)
+                pos = np.minimum(pos, len(moved_keys) - 1)
+                bad |= hit & (moved_keys[pos] == key)
+        ok = ~bad
+        act[todo[ok]] = a[ok]
+        opn[todo[ok]] = o[ok]
+        todo = todo[bad]
+    # scatter the filled slots over random slot positions
+    act = np.take_along_axis(act, np.argsort(rng.random((B, S)), axis=1), axis=1)[:, :n_split_slots]
+    opn = np.take_along_axis(opn, np.argsort(rng.random((B, K)), axis=1), axis=1)[:, :n_open_slots]
+    sb = np.where(act >= 0, tab_bus[np.maximum(act, 0)], EMPTY)
+    lens = np.where(act >= 0, tab_len[np.maximum(act, 0)], 0).ravel()
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    starts = np.where(act >= 0, tab_off[np.maximum(act, 0)], 0).ravel()
+    rep = np.repeat(starts - offs[:-1], lens)
+    br = tab_flat[np.arange(int(offs[-1])) + rep] if offs[-1] else np.zeros(0, np.int64)
+    mp = None
+    if P is not None and move_frac > 0.0:
+        flat_bus = sb.ravel()
+        take = (flat_bus >= 0) & (rng.random(flat_bus.size) < move_frac)
+        share = rng.uniform(0.1, 0.9, size=flat_bus.size)
+        mp = np.zeros((flat_bus.size, T), dtype=np.float64)
+        mp[take] = share[take, None] * np.asarray(P, dtype=np.float64)[flat_bus[take]]
+        if not take.any():
+            mp = None
+    return Batch(open=opn.astype(np.int32), split_bus=sb.astype(np.int32), moved_off=offs,
+                 moved_br=br.astype(np.int32), moved_p=mp,
+                 split_action=act.astype(np.int32))
+
+
+def action_bits(grid: Grid, batch: Batch, table_size: int):
+    """Feature bitmask of each candidate as CSR (offsets, ids): bit d for the
+    opening of the d-th base non-bridge branch, bit |D| + a for split action a
+    of the action table.  Ids are sorted and distinct within a row.
+    Returns (off [B+1], ids, n_bits)."""
+    nb = bridges(grid.n_bus, grid.from_bus, grid.to_bus)
+    D = np.flatnonzero(~nb)
+    pos = -np.ones(grid.n_branch + 1, dtype=np.int64)
+    pos[D] = np.arange(len(D))
+    op = batch.open.astype(np.int64)
+    cols = [np.where(op >= 0, pos[np.where(op >= 0, op, grid.n_branch)], -1)]
+    if batch.split_action is not None:
+        sa = batch.split_action.astype(np.int64)
+        cols.append(np.where(sa >= 0, len(D) + sa, -1))
+    ids = np.concatenate(cols, axis=1)
+    big = np.iinfo(np.int64).max
+    ids = np.sort(np.where(ids >= 0, ids, big), axis=1)
+    valid = ids != big
+    off = np.concatenate([[0], np.cumsum(valid.sum(axis=1))]).astype(np.int32)
+    return off, ids[valid].astype(np.int32), len(D) + table_size
 
 
 def make_candidates(kind: str, grid: Grid, B: int, seed: int, **kw) -> Batch:

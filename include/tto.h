@@ -311,6 +311,80 @@ tto_status tto_autotune(tto_grid* grid, const tto_batch* batch, const tto_output
                         void* batch_ws, size_t batch_bytes, void* stream,
                         const char* cache_path, int32_t* chosen);
 
+/*
+ * Gather candidates idx[0..k) of `src` into the caller's device arrays
+ * (dst_open [k][n_open_slots], dst_split [k][n_split_slots], dst_moved_off
+ * [k*n_split_slots+1], dst_moved_br (capacity dst_moved_cap), dst_moved_p
+ * [k*n_split_slots][T] or NULL) and fill *dst as a batch over them: used to
+ * evaluate a screened subset exactly.  Indices must lie in [0, src->n_cand)
+ * (checked on the device; a bad index yields an empty, INVALID-to-be
+ * candidate).  If the gathered moved lists exceed dst_moved_cap the tail
+ * candidates get empty split slots with a -2 bus (INVALID).  Asynchronous.
+ */
+tto_status tto_batch_gather(const tto_batch* src, const int32_t* idx, int32_t k,
+                            int32_t n_timesteps, int32_t* dst_open, int32_t* dst_split,
+                            int32_t* dst_moved_off, int32_t* dst_moved_br,
+                            int32_t dst_moved_cap, double* dst_moved_p, tto_batch* dst,
+                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned pre-screen (surrogate).  Not in the paper (its DC-Optimizer scores
+ * every candidate exactly); added so that a generation can be screened
+ * before exact evaluation.  A 4-layer perceptron:
+ *   z1 = sum_{i in bits} W1b[i] + dense W1d + b1, h1 = relu(z1),
+ *   h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 + b3), y = h3 W4 + b4 (2 outputs),
+ * input = the candidate's action bitmask (CSR list of set bit ids) and a
+ * dense summary (e.g. per-timestep injection totals); outputs trained on the
+ * exact evaluator's (maximum loading, log overload).  W1b, W1d, W2, W3 are
+ * used in BF16 (MFMA, FP32 accumulation); activations are BF16; biases, W4
+ * and the Adam master weights are FP32.  Loss 1/(2B) sum (y - t)^2.
+ * Parameters are one flat FP32 array in the order W1b [d_bits][width],
+ * W1d [d_dense][width], b1, W2 [width][width], b2, W3, b3, W4 [width][2], b4.
+ */
+typedef struct tto_mlp tto_mlp;
+
+typedef struct {
+  int32_t d_bits;            /* bitmask width (action vocabulary), >= 1 */
+  int32_t d_dense;           /* dense inputs, 0..64 */
+  int32_t width;             /* hidden width: multiple of 64 in 64..2048 */
+  int32_t max_batch;         /* largest forward batch */
+  int32_t max_train_batch;   /* largest training / gradient batch */
+} tto_mlp_desc;
+
+/* Device workspace sizes: parameters + Adam state (persistent) and batch
+ * scratch (per call).  Host only. */
+tto_status tto_mlp_workspace_bytes(const tto_mlp_desc* desc, size_t* param_bytes,
+                                   size_t* batch_bytes);
+/* Bind a network to param_ws (256-byte aligned, param_bytes long).  Weights
+ * are zero until tto_mlp_set_params.  Host only. */
+tto_status tto_mlp_create(const tto_mlp_desc* desc, void* param_ws, size_t param_bytes,
+                          tto_mlp** out);
+void tto_mlp_destroy(tto_mlp* mlp);
+tto_status tto_mlp_n_params(tto_mlp* mlp, int64_t* n);
+/* Copy flat FP32 parameters (device) in / out; set also clears Adam. */
+tto_status tto_mlp_set_params(tto_mlp* mlp, const float* params, void* stream);
+tto_status tto_mlp_get_params(tto_mlp* mlp, float* params, void* stream);
+/* y[B][2] for B candidates: bits_off [B+1] and bits_idx (device CSR; the
+ * offsets must be non-decreasing and index inside bits_idx, which is the
+ * caller's duty; ids distinct within a row; ids outside [0, d_bits) are
+ * ignored), dense [B][d_dense] (device, may be NULL iff d_dense == 0). */
+tto_status tto_mlp_forward(tto_mlp* mlp, const int32_t* bits_off, const int32_t* bits_idx,
+                           const float* dense, int32_t n, float* y, void* batch_ws,
+                           size_t batch_bytes, void* stream);
+/* Loss (device scalar) and flat gradients (device, n_params) for targets
+ * t[B][2]; B <= max_train_batch. */
+tto_status tto_mlp_gradients(tto_mlp* mlp, const int32_t* bits_off, const int32_t* bits_idx,
+                             const float* dense, const float* target, int32_t n, float* grad,
+                             float* loss, void* batch_ws, size_t batch_bytes, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the loss of this batch. */
+tto_status tto_mlp_train_step(tto_mlp* mlp, const int32_t* bits_off, const int32_t* bits_idx,
+                              const float* dense, const float* target, int32_t n, float lr,
+                              float* loss, void* batch_ws, size_t batch_bytes, void* stream);
+/* Indices of the k smallest score[i * stride] (device), i < n, in index
+ * order among equals; deterministic.  n <= 2^24, 0 <= k <= n. */
+tto_status tto_topk_smallest(const float* score, int32_t n, int32_t stride, int32_t k,
+                             int32_t* idx_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

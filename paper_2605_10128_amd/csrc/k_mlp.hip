@@ -1,0 +1,509 @@
+// Learned pre-screen: a 4-layer perceptron over a candidate's action bitmask
+// and an injection summary, predicting (maximum loading, log-overload).
+// Forward and backward on the GPU: embedding-bag first layer, BF16 MFMA GEMMs
+// with FP32 accumulation for the hidden layers (fused bias + ReLU, or ReLU
+// mask in the backward pass), VALU output layer, Adam on FP32 master weights,
+// and a deterministic single-workgroup radix top-k for the screen.
+#include "tto_common.h"
+#include "tto_mlp.h"
+
+#include <limits.h>
+
+namespace tto {
+
+typedef float v4f32m __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf16m __attribute__((ext_vector_type(8)));
+typedef unsigned short v8u16m __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// ---------------------------------------------------------------------------
+// C[M x N] = op(A) op(B), BF16 operands, FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  A_COL: A stored [K][M] (else [M][K]); B_COL: B
+// stored [N][K] (else [K][N]).  Workgroup of 256 threads = 64 x 64 tile, each
+// wave a 32 x 32 quarter (2 x 2 MFMA tiles); K in steps of 32 through LDS,
+// both operands staged k-contiguous so every lane reads 16-byte fragments.
+// Epilogue EPI: 0 = FP32 store, 1 = + bias, ReLU, BF16 store, 2 = times the
+// ReLU mask (mask[i][j] > 0) and BF16 store.
+template <bool A_COL, bool B_COL, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(const unsigned short* __restrict__ A,
+                                                   const unsigned short* __restrict__ Bm,
+                                                   int M, int N, int K,
+                                                   float* __restrict__ Cf,
+                                                   unsigned short* __restrict__ Cb,
+                                                   const float* __restrict__ bias,
+                                                   const unsigned short* __restrict__ mask) {
+  constexpr int PAD = 8;
+  __shared__ unsigned short As[64][32 + PAD];
+  __shared__ unsigned short Bs[64][32 + PAD];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
+  v4f32m acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f32m{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    // ---- stage A tile (64 x 32) as As[m][k]
+    if constexpr (!A_COL) {
+      const int r = tid >> 2, kc = (tid & 3) * 8;
+      const int gm = m0 + r;
+      for (int u = 0; u < 8; ++u) {
+        const int gk = k0 + kc + u;
+        As[r][kc + u] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : (unsigned short)0;
+      }
+    } else {
+      const int kr = tid >> 3, mc = (tid & 7) * 8;   // 32 k-rows x 64 m
+      const int gk = k0 + kr;
+      for (int u = 0; u < 8; ++u) {
+        const int gm = m0 + mc + u;
+        As[mc + u][kr] = (gm < M && gk < K) ? A[(size_t)gk * M + gm] : (unsigned short)0;
+      }
+    }
+    // ---- stage B tile (32 x 64) as Bs[n][k]
+    if constexpr (B_COL) {
+      const int r = tid >> 2, kc = (tid & 3) * 8;
+      const int gn = n0 + r;
+      for (int u = 0; u < 8; ++u) {
+        const int gk = k0 + kc + u;
+        Bs[r][kc + u] = (gn < N && gk < K) ? Bm[(size_t)gn * K + gk] : (unsigned short)0;
+      }
+    } else {
+      const int kr = tid >> 3, nc = (tid & 7) * 8;
+      const int gk = k0 + kr;
+      for (int u = 0; u < 8; ++u) {
+        const int gn = n0 + nc + u;
+        Bs[nc + u][kr] = (gn < N && gk < K) ? Bm[(size_t)gk * N + gn] : (unsigned short)0;
+      }
+    }
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      v8u16m a;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = As[wm + i * 16 + fr][fk + u];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        v8u16m b;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = Bs[wn + j * 16 + fr][fk + u];
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16m, a),
+                                                            __builtin_bit_cast(v8bf16m, b),
+                                                            acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- epilogue: lane holds rows 4*(lane/16)+v of column lane%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          float x = acc[i][j][v];
+          const size_t o = (size_t)row * N + col;
+          if constexpr (EPI == 0) {
+            Cf[o] = x;
+          } else if constexpr (EPI == 1) {
+            x += bias[col];
+            x = x > 0.f ? x : 0.f;
+            Cb[o] = bf16_rne(x);
+            if (Cf) Cf[o] = x;
+          } else {
+            x = (mask[o] != 0) ? x : 0.f;   // bf16 activation > 0 <=> nonzero bits
+            Cb[o] = bf16_rne(x);
+          }
+        }
+      }
+}
+
+// First layer (embedding bag): z1[b][j] = b1[j] + sum_d dense[b][d] W1d[d][j]
+// + sum_{i in bits(b)} W1b[i][j] (BF16 weights, FP32 sum); h1 = relu(z1).
+__global__ __launch_bounds__(256) void k_mlp_l1(const int* __restrict__ off,
+                                                const int* __restrict__ idx,
+                                                const float* __restrict__ dense, int d_dense,
+                                                int d_bits,
+                                                const unsigned short* __restrict__ W1b,
+                                                const unsigned short* __restrict__ W1d,
+                                                const float* __restrict__ b1, int H,
+                                                unsigned short* __restrict__ h1) {
+  const int b = blockIdx.x;
+  const int lo = off[b], hi = off[b + 1];
+  for (int j = threadIdx.x; j < H; j += 256) {
+    float z = b1[j];
+    for (int d = 0; d < d_dense; ++d) z += dense[(size_t)b * d_dense + d] * bf16_to_f(W1d[(size_t)d * H + j]);
+    for (int p = lo; p < hi; ++p) {
+      const int i = idx[p];
+      if (i >= 0 && i < d_bits) z += bf16_to_f(W1b[(size_t)i * H + j]);   // others ignored
+    }
+    h1[(size_t)b * H + j] = bf16_rne(z > 0.f ? z : 0.f);
+  }
+}
+
+// Output layer y[b][k] = b4[k] + sum_j h3[b][j] W4[j][k], one wave per sample.
+__global__ __launch_bounds__(64) void k_mlp_out(const unsigned short* __restrict__ h3,
+                                                const float* __restrict__ W4,
+                                                const float* __restrict__ b4, int H,
+                                                float* __restrict__ y) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  float s0 = 0.f, s1 = 0.f;
+  for (int j = lane; j < H; j += 64) {
+    const float h = bf16_to_f(h3[(size_t)b * H + j]);
+    s0 += h * W4[j * 2];
+    s1 += h * W4[j * 2 + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o);
+    s1 += __shfl_xor(s1, o);
+  }
+  if (lane == 0) {
+    y[b * 2] = s0 + b4[0];
+    y[b * 2 + 1] = s1 + b4[1];
+  }
+}
+
+// dy = (y - t) / B; per-sample loss terms (summed in fixed order later).
+__global__ __launch_bounds__(256) void k_mlp_dy(const float* __restrict__ y,
+                                                const float* __restrict__ t, int B,
+                                                float* __restrict__ dy,
+                                                float* __restrict__ lterm) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const float e0 = y[b * 2] - t[b * 2], e1 = y[b * 2 + 1] - t[b * 2 + 1];
+  dy[b * 2] = e0 / (float)B;
+  dy[b * 2 + 1] = e1 / (float)B;
+  lterm[b] = 0.5f * (e0 * e0 + e1 * e1);
+}
+
+// Output-layer backward: gW4[j][k] = sum_b h3[b][j] dy[b][k], gb4 = sum_b dy,
+// and dz3[b][j] = (dy[b] . W4[j]) where h3 > 0 (BF16).  Fixed-order sums.
+__global__ __launch_bounds__(256) void k_mlp_out_bwd_w(const unsigned short* __restrict__ h3,
+                                                       const float* __restrict__ dy, int B,
+                                                       int H, float* __restrict__ gW4) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= H) return;
+  float s0 = 0.f, s1 = 0.f;
+  for (int b = 0; b < B; ++b) {
+    const float h = bf16_to_f(h3[(size_t)b * H + j]);
+    s0 += h * dy[b * 2];
+    s1 += h * dy[b * 2 + 1];
+  }
+  gW4[j * 2] = s0;
+  gW4[j * 2 + 1] = s1;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_out_bwd_x(const unsigned short* __restrict__ h3,
+                                                       const float* __restrict__ dy,
+                                                       const float* __restrict__ W4, int B,
+                                                       int H, unsigned short* __restrict__ dz3) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)B * H) return;
+  const int b = (int)(i / H), j = (int)(i - (size_t)b * H);
+  const float g = dy[b * 2] * W4[j * 2] + dy[b * 2 + 1] * W4[j * 2 + 1];
+  dz3[i] = h3[i] != 0 ? bf16_rne(g) : (unsigned short)0;
+}
+
+// Column sums over the batch of a [B][n] matrix (BF16 or FP32), fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_colsum(const T* __restrict__ x, int B, int n,
+                                                float* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) {
+    if constexpr (sizeof(T) == 2) s += bf16_to_f(x[(size_t)b * n + j]);
+    else s += x[(size_t)b * n + j];
+  }
+  out[j] = s;
+}
+
+// Dense views for the first-layer gradients: X[b][i] = 1 for i in bits(b)
+// (BF16 0/1, exact) and the dense inputs in BF16.
+__global__ __launch_bounds__(256) void k_bits_dense(const int* __restrict__ off,
+                                                    const int* __restrict__ idx, int B, int d_bits,
+                                                    unsigned short* __restrict__ X) {
+  const int b = blockIdx.x;
+  for (int i = threadIdx.x; i < d_bits; i += 256) X[(size_t)b * d_bits + i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int p = off[b]; p < off[b + 1]; ++p) {
+      const int i = idx[p];
+      if (i >= 0 && i < d_bits) X[(size_t)b * d_bits + i] = 0x3F80;   // 1.0
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ x, size_t n,
+                                                 unsigned short* __restrict__ y) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = bf16_rne(x[i]);
+}
+
+// Adam (bias-corrected moments) on FP32 master weights; refreshes the BF16 copy.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, float* __restrict__ m,
+                                              float* __restrict__ v,
+                                              const float* __restrict__ g, size_t n, float lr,
+                                              float b1, float b2, float c1, float c2, float eps,
+                                              unsigned short* __restrict__ wb) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = bf16_rne(wi);
+}
+
+// Fixed-order sum of per-sample loss terms (single wave).
+__global__ __launch_bounds__(64) void k_sum(const float* __restrict__ x, int n,
+                                            float* __restrict__ out) {
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n; i += 64) s += x[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// k smallest scores, deterministically: radix select of the k-th smallest
+// key over 4 digits of 8 bits in one workgroup, then an ordered compaction
+// (all keys below the threshold, then threshold ties in index order).
+__device__ inline unsigned int key_of(float f) {
+  const unsigned int u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // ascending order of floats
+}
+
+__global__ __launch_bounds__(1024) void k_topk_smallest(const float* __restrict__ score, int n,
+                                                        int stride, int k,
+                                                        int* __restrict__ out) {
+  __shared__ unsigned int hist[256];
+  __shared__ unsigned int s_prefix, s_mask, s_need;
+  __shared__ int s_wc[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) { s_prefix = 0; s_mask = 0; s_need = (unsigned)k; }
+  __syncthreads();
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += 1024) hist[i] = 0;
+    __syncthreads();
+    const unsigned int pre = s_prefix, msk = s_mask;
+    for (int i = tid; i < n; i += 1024) {
+      const unsigned int key = key_of(score[(size_t)i * stride]);
+      if ((key & msk) == pre) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned int need = s_need, d = 0;
+      while (d < 255 && hist[d] < need) { need -= hist[d]; ++d; }
+      s_prefix = pre | (d << shift);
+      s_mask = msk | (255u << shift);
+      s_need = need;   // how many of the keys equal to the threshold to take
+    }
+    __syncthreads();
+  }
+  const unsigned int thr = s_prefix;
+  const int ties = (int)s_need;
+  // pass 1: keys strictly below the threshold; pass 2: first `ties` equal keys
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i0 = 0; i0 < n; i0 += 1024) {
+      const int i = i0 + tid;
+      bool take = false;
+      if (i < n) {
+        const unsigned int key = key_of(score[(size_t)i * stride]);
+        take = pass == 0 ? key < thr : key == thr;
+      }
+      const unsigned long long msk64 = __ballot(take);
+      if (lane == 0) s_wc[wid] = __popcll(msk64);
+      __syncthreads();
+      int pos = s_base;
+      for (int q = 0; q < wid; ++q) pos += s_wc[q];
+      pos += __popcll(msk64 & ((1ull << lane) - 1ull));
+      const int limit = pass == 0 ? k : (k - ties) + ties;
+      if (take && pos < limit) out[pos] = i;
+      __syncthreads();
+      if (tid == 0) {
+        int s = 0;
+        for (int q = 0; q < 16; ++q) s += s_wc[q];
+        s_base += s;
+      }
+      __syncthreads();
+    }
+    if (pass == 0) {
+      if (tid == 0) s_base = k - ties;
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batch gather: copy the genomes idx[0..k) into a compact batch.  One
+// workgroup; moved-list offsets by an ordered block scan over the gathered
+// split slots.
+__global__ __launch_bounds__(1024) void k_batch_gather(
+    const int* __restrict__ open, const int* __restrict__ sbus, const int* __restrict__ moff,
+    const int* __restrict__ mbr, const double* __restrict__ mp, int n_src, int no, int ns, int T,
+    const int* __restrict__ idx, int k, int* __restrict__ d_open, int* __restrict__ d_sbus,
+    int* __restrict__ d_moff, int* __restrict__ d_mbr, int cap, double* __restrict__ d_mp) {
+  __shared__ int s_wsum[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) { s_base = 0; d_moff[0] = 0; }
+  __syncthreads();
+  const int slots = k * ns;
+  for (int s0 = 0; s0 < slots || (ns == 0 && s0 == 0); s0 += 1024) {
+    const int sl = s0 + tid;
+    int len = 0, src = 0, c = 0, j = 0;
+    bool okc = false;
+    if (sl < slots) {
+      c = sl / ns;
+      j = sl - c * ns;
+      src = idx[c];
+      okc = src >= 0 && src < n_src;
+      if (okc) len = moff[(size_t)src * ns + j + 1] - moff[(size_t)src * ns + j];
+      if (len < 0) len = 0;
+    }
+    // inclusive wave scan of len, then across waves in order
+    int v = len;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o);
+      if (lane >= o) v += u;
+    }
+    if (lane == 63) s_wsum[wid] = v;
+    __syncthreads();
+    int pre = s_base;
+    for (int q = 0; q < wid; ++q) pre += s_wsum[q];
+    const int start = pre + v - len;
+    if (sl < slots) {
+      const bool fits = start + len <= cap;
+      d_sbus[sl] = okc ? (fits ? sbus[(size_t)src * ns + j] : (sbus[(size_t)src * ns + j] == -1 ? -1 : -2)) : -2;
+      const int ln = fits ? len : 0;
+      for (int q = 0; q < ln; ++q) d_mbr[start + q] = mbr[moff[(size_t)src * ns + j] + q];
+      // clipped end: monotone and inside [0, cap] even past the first overflow
+      d_moff[sl + 1] = min(start + len, cap);
+      if (d_mp) {
+        for (int t = 0; t < T; ++t)
+          d_mp[(size_t)sl * T + t] = (okc && mp) ? mp[((size_t)src * ns + j) * T + t] : 0.0;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int sum = 0;
+      for (int q = 0; q < 16; ++q) sum += s_wsum[q];
+      s_base += sum;
+    }
+    __syncthreads();
+    if (ns == 0) break;
+  }
+  for (int i = tid; i < k * no; i += 1024) {
+    const int c = i / no, q = i - c * no;
+    const int src = idx[c];
+    d_open[i] = (src >= 0 && src < n_src) ? open[(size_t)src * no + q] : -2;
+  }
+}
+
+void batch_gather(const int* open, const int* sbus, const int* moff, const int* mbr,
+                  const double* mp, int n_src, int no, int ns, int T, const int* idx, int k,
+                  int* d_open, int* d_sbus, int* d_moff, int* d_mbr, int cap, double* d_mp,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_gather, dim3(1), dim3(1024), 0, s, open, sbus, moff, mbr, mp, n_src,
+                     no, ns, T, idx, k, d_open, d_sbus, d_moff, d_mbr, cap, d_mp);
+}
+
+static inline int cdiv_m(long a, int b) { return (int)((a + b - 1) / b); }
+
+template <bool AC, bool BC, int EPI>
+static void gemm(const unsigned short* A, const unsigned short* B, int M, int N, int K, float* Cf,
+                 unsigned short* Cb, const float* bias, const unsigned short* mask, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_bf16<AC, BC, EPI>), dim3(cdiv_m(N, 64), cdiv_m(M, 64)), dim3(256), 0,
+                     s, A, B, M, N, K, Cf, Cb, bias, mask);
+}
+
+// ---------------------------------------------------------------------------
+void mlp_forward(const MlpDev& p, const MlpBatch& wb, const int* off, const int* idx,
+                 const float* dense, int B, float* y, hipStream_t s) {
+  const int H = p.H;
+  hipLaunchKernelGGL(k_mlp_l1, dim3(B), dim3(256), 0, s, off, idx, dense, p.d_dense, p.d_bits,
+                     p.W1b_h,
+                     p.W1d_h, p.b1, H, wb.h1);
+  gemm<false, false, 1>(wb.h1, p.W2_h, B, H, H, nullptr, wb.h2, p.b2, nullptr, s);
+  gemm<false, false, 1>(wb.h2, p.W3_h, B, H, H, nullptr, wb.h3, p.b3, nullptr, s);
+  hipLaunchKernelGGL(k_mlp_out, dim3(B), dim3(64), 0, s, wb.h3, p.W4, p.b4, H, y);
+}
+
+void mlp_gradients(const MlpDev& p, const MlpBatch& wb, const int* off, const int* idx,
+                   const float* dense, const float* target, int B, float* grad, float* loss,
+                   hipStream_t s) {
+  const int H = p.H, db = p.d_bits, dd = p.d_dense;
+  mlp_forward(p, wb, off, idx, dense, B, wb.y, s);
+  hipLaunchKernelGGL(k_mlp_dy, dim3(cdiv_m(B, 256)), dim3(256), 0, s, wb.y, target, B, wb.dy,
+                     wb.lterm);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, wb.lterm, B, loss);
+  MlpGrad g = mlp_grad_view(p, grad);
+  // output layer
+  hipLaunchKernelGGL(k_mlp_out_bwd_w, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.h3, wb.dy, B, H,
+                     g.W4);
+  hipLaunchKernelGGL(k_colsum<float>, dim3(1), dim3(256), 0, s, wb.dy, B, 2, g.b4);
+  hipLaunchKernelGGL(k_mlp_out_bwd_x, dim3(cdiv_m((long)B * H, 256)), dim3(256), 0, s, wb.h3,
+                     wb.dy, p.W4, B, H, wb.dz3);
+  // layer 3: gW3 = h2^T dz3, gb3 = colsum dz3, dz2 = (dz3 W3^T) * [h2 > 0]
+  gemm<true, false, 0>(wb.h2, wb.dz3, H, H, B, g.W3, nullptr, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_colsum<unsigned short>, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.dz3, B,
+                     H, g.b3);
+  gemm<false, true, 2>(wb.dz3, p.W3_h, B, H, H, nullptr, wb.dz2, nullptr, wb.h2, s);
+  // layer 2
+  gemm<true, false, 0>(wb.h1, wb.dz2, H, H, B, g.W2, nullptr, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_colsum<unsigned short>, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.dz2, B,
+                     H, g.b2);
+  gemm<false, true, 2>(wb.dz2, p.W2_h, B, H, H, nullptr, wb.dz1, nullptr, wb.h1, s);
+  // layer 1: gW1b = X^T dz1 over the 0/1 bitmask, gW1d = dense^T dz1
+  hipLaunchKernelGGL(k_colsum<unsigned short>, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.dz1, B,
+                     H, g.b1);
+  hipLaunchKernelGGL(k_bits_dense, dim3(B), dim3(256), 0, s, off, idx, B, db, wb.X);
+  gemm<true, false, 0>(wb.X, wb.dz1, db, H, B, g.W1b, nullptr, nullptr, nullptr, s);
+  if (dd > 0) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)B * dd, 256)), dim3(256), 0, s, dense,
+                       (size_t)B * dd, wb.Xd);
+    gemm<true, false, 0>(wb.Xd, wb.dz1, dd, H, B, g.W1d, nullptr, nullptr, nullptr, s);
+  }
+}
+
+void mlp_adam(const MlpDev& p, const float* grad, float lr, int step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  const size_t n = p.n_params;
+  hipLaunchKernelGGL(k_adam, dim3(cdiv_m((long)n, 256)), dim3(256), 0, s, p.master, p.m, p.v,
+                     grad, n, lr, b1, b2, c1, c2, eps, (unsigned short*)nullptr);
+  mlp_refresh_bf16(p, s);
+}
+
+void mlp_refresh_bf16(const MlpDev& p, hipStream_t s) {
+  const size_t H = p.H;
+  MlpGrad w = mlp_grad_view(p, p.master);
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(p.d_bits * H), 256)), dim3(256), 0, s, w.W1b,
+                     (size_t)p.d_bits * H, p.W1b_h);
+  if (p.d_dense > 0)
+    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(p.d_dense * H), 256)), dim3(256), 0, s,
+                       w.W1d, (size_t)p.d_dense * H, p.W1d_h);
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(H * H), 256)), dim3(256), 0, s, w.W2, H * H,
+                     p.W2_h);
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(H * H), 256)), dim3(256), 0, s, w.W3, H * H,
+                     p.W3_h);
+}
+
+void topk_smallest(const float* score, int n, int stride, int k, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_topk_smallest, dim3(1), dim3(1024), 0, s, score, n, stride, k, out);
+}
+
+}  // namespace tto

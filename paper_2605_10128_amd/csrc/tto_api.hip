@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/tto.h: argument validation,
 // workspace carving, device table construction and kernel launch order.
 #include "tto_common.h"
+#include "tto_mlp.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -560,6 +561,224 @@ tto_status tto_archive_insert(tto_grid* g, double* elite_fitness, int64_t* elite
   int* idx = (int*)((char*)batch_ws + 8 * (size_t)n_cells);
   HIP_TRY(launch_archive(elite_fitness, elite_id, n_cells, fitness, cell, status, n_cand, id_base,
                          key, idx, (hipStream_t)stream));
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Learned pre-screen
+}  // extern "C"
+
+struct tto_mlp {
+  tto_mlp_desc d;
+  MlpDev p;
+  size_t param_bytes;
+  int step = 0;
+};
+
+namespace {
+
+MlpDev carve_mlp_params(const tto_mlp_desc* d, void* ws, size_t* bytes) {
+  Carver cv(ws);
+  MlpDev p;
+  p.d_bits = d->d_bits; p.d_dense = d->d_dense; p.H = d->width;
+  p.n_params = mlp_param_count(d->d_bits, d->d_dense, d->width);
+  p.master = cv.take<float>(p.n_params);
+  p.m = cv.take<float>(p.n_params);
+  p.v = cv.take<float>(p.n_params);
+  p.grad = cv.take<float>(p.n_params);
+  const size_t H = d->width;
+  p.W1b_h = cv.take<unsigned short>((size_t)d->d_bits * H);
+  p.W1d_h = cv.take<unsigned short>(std::max((size_t)d->d_dense * H, (size_t)1));
+  p.W2_h = cv.take<unsigned short>(H * H);
+  p.W3_h = cv.take<unsigned short>(H * H);
+  if (p.master) {
+    MlpGrad w = mlp_grad_view(p, p.master);
+    p.b1 = w.b1; p.b2 = w.b2; p.b3 = w.b3; p.W4 = w.W4; p.b4 = w.b4;
+  } else {
+    p.b1 = p.b2 = p.b3 = p.W4 = p.b4 = nullptr;
+  }
+  *bytes = cv.off;
+  return p;
+}
+
+MlpBatch carve_mlp_batch(const tto_mlp_desc* d, void* ws, size_t* bytes) {
+  Carver cv(ws);
+  MlpBatch b;
+  const size_t H = d->width, Bf = d->max_batch, Bt = d->max_train_batch;
+  const size_t Ba = std::max(Bf, Bt);
+  b.h1 = cv.take<unsigned short>(Ba * H);
+  b.h2 = cv.take<unsigned short>(Ba * H);
+  b.h3 = cv.take<unsigned short>(Ba * H);
+  b.dz1 = cv.take<unsigned short>(Bt * H);
+  b.dz2 = cv.take<unsigned short>(Bt * H);
+  b.dz3 = cv.take<unsigned short>(Bt * H);
+  b.X = cv.take<unsigned short>(Bt * (size_t)d->d_bits);
+  b.Xd = cv.take<unsigned short>(std::max(Bt * (size_t)d->d_dense, (size_t)1));
+  b.y = cv.take<float>(Ba * 2);
+  b.dy = cv.take<float>(Bt * 2);
+  b.lterm = cv.take<float>(Bt);
+  *bytes = cv.off;
+  return b;
+}
+
+tto_status check_mlp_desc(const tto_mlp_desc* d) {
+  if (!d) return fail(TTO_E_INVALID, "desc is NULL");
+  if (d->d_bits < 1) return fail(TTO_E_INVALID, "d_bits must be >= 1");
+  if (d->d_dense < 0 || d->d_dense > 64) return fail(TTO_E_INVALID, "d_dense must be in 0..64");
+  if (d->width < 64 || d->width > 2048 || d->width % 64) return fail(TTO_E_INVALID, "width must be a multiple of 64 in 64..2048");
+  if (d->max_batch < 1 || d->max_train_batch < 1) return fail(TTO_E_INVALID, "batch sizes must be >= 1");
+  return TTO_OK;
+}
+
+tto_status check_mlp_call(tto_mlp* m, const int32_t* off, const int32_t* idx, const float* dense,
+                          int32_t n, int32_t limit, void* ws, size_t bytes) {
+  if (!m) return fail(TTO_E_INVALID, "mlp is NULL");
+  if (!off || !idx) return fail(TTO_E_INVALID, "bits arrays are NULL");
+  if (m->d.d_dense > 0 && !dense) return fail(TTO_E_INVALID, "dense is NULL");
+  if (n < 1 || n > limit) return fail(TTO_E_INVALID, "batch %d not in 1..%d", n, limit);
+  size_t need = 0;
+  carve_mlp_batch(&m->d, nullptr, &need);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(TTO_E_WORKSPACE, "batch_ws NULL or misaligned");
+  if (bytes < need) return fail(TTO_E_WORKSPACE, "batch_ws has %zu bytes, needs %zu", bytes, need);
+  return TTO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tto_status tto_mlp_workspace_bytes(const tto_mlp_desc* d, size_t* param_bytes, size_t* batch_bytes) {
+  tto_status st = check_mlp_desc(d);
+  if (st != TTO_OK) return st;
+  if (!param_bytes || !batch_bytes) return fail(TTO_E_INVALID, "NULL output pointer");
+  carve_mlp_params(d, nullptr, param_bytes);
+  carve_mlp_batch(d, nullptr, batch_bytes);
+  return ok();
+}
+
+tto_status tto_mlp_create(const tto_mlp_desc* d, void* ws, size_t bytes, tto_mlp** out) {
+  tto_status st = check_mlp_desc(d);
+  if (st != TTO_OK) return st;
+  if (!out) return fail(TTO_E_INVALID, "out is NULL");
+  size_t need = 0;
+  carve_mlp_params(d, nullptr, &need);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(TTO_E_WORKSPACE, "param_ws NULL or misaligned");
+  if (bytes < need) return fail(TTO_E_WORKSPACE, "param_ws has %zu bytes, needs %zu", bytes, need);
+  tto_mlp* m = new tto_mlp();
+  m->d = *d;
+  m->p = carve_mlp_params(d, ws, &m->param_bytes);
+  *out = m;
+  return ok();
+}
+
+void tto_mlp_destroy(tto_mlp* m) { delete m; }
+
+tto_status tto_mlp_n_params(tto_mlp* m, int64_t* n) {
+  if (!m || !n) return fail(TTO_E_INVALID, "NULL argument");
+  *n = (int64_t)m->p.n_params;
+  return ok();
+}
+
+tto_status tto_mlp_set_params(tto_mlp* m, const float* params, void* stream) {
+  if (!m || !params) return fail(TTO_E_INVALID, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = m->p.n_params * sizeof(float);
+  HIP_TRY(hipMemcpyAsync(m->p.master, params, n, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemsetAsync(m->p.m, 0, n, s));
+  HIP_TRY(hipMemsetAsync(m->p.v, 0, n, s));
+  mlp_refresh_bf16(m->p, s);
+  HIP_TRY(hipGetLastError());
+  m->step = 0;
+  return ok();
+}
+
+tto_status tto_mlp_get_params(tto_mlp* m, float* params, void* stream) {
+  if (!m || !params) return fail(TTO_E_INVALID, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(params, m->p.master, m->p.n_params * sizeof(float),
+                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return ok();
+}
+
+tto_status tto_mlp_forward(tto_mlp* m, const int32_t* off, const int32_t* idx, const float* dense,
+                           int32_t n, float* y, void* ws, size_t bytes, void* stream) {
+  tto_status st = check_mlp_call(m, off, idx, dense, n, m ? m->d.max_batch : 0, ws, bytes);
+  if (st != TTO_OK) return st;
+  if (!y) return fail(TTO_E_INVALID, "y is NULL");
+  size_t used = 0;
+  MlpBatch b = carve_mlp_batch(&m->d, ws, &used);
+  mlp_forward(m->p, b, off, idx, dense, n, y, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return ok();
+}
+
+tto_status tto_mlp_gradients(tto_mlp* m, const int32_t* off, const int32_t* idx, const float* dense,
+                             const float* target, int32_t n, float* grad, float* loss, void* ws,
+                             size_t bytes, void* stream) {
+  tto_status st = check_mlp_call(m, off, idx, dense, n, m ? m->d.max_train_batch : 0, ws, bytes);
+  if (st != TTO_OK) return st;
+  if (!target || !grad || !loss) return fail(TTO_E_INVALID, "target, grad or loss is NULL");
+  size_t used = 0;
+  MlpBatch b = carve_mlp_batch(&m->d, ws, &used);
+  mlp_gradients(m->p, b, off, idx, dense, target, n, grad, loss, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return ok();
+}
+
+tto_status tto_mlp_train_step(tto_mlp* m, const int32_t* off, const int32_t* idx, const float* dense,
+                              const float* target, int32_t n, float lr, float* loss, void* ws,
+                              size_t bytes, void* stream) {
+  tto_status st = check_mlp_call(m, off, idx, dense, n, m ? m->d.max_train_batch : 0, ws, bytes);
+  if (st != TTO_OK) return st;
+  if (!target || !loss) return fail(TTO_E_INVALID, "target or loss is NULL");
+  if (!(lr >= 0.f) || !isfinite(lr)) return fail(TTO_E_INVALID, "lr must be finite and >= 0");
+  size_t used = 0;
+  MlpBatch b = carve_mlp_batch(&m->d, ws, &used);
+  hipStream_t s = (hipStream_t)stream;
+  mlp_gradients(m->p, b, off, idx, dense, target, n, m->p.grad, loss, s);
+  m->step += 1;
+  mlp_adam(m->p, m->p.grad, lr, m->step, s);
+  HIP_TRY(hipGetLastError());
+  return ok();
+}
+
+tto_status tto_batch_gather(const tto_batch* src, const int32_t* idx, int32_t k, int32_t T,
+                            int32_t* d_open, int32_t* d_split, int32_t* d_moff, int32_t* d_mbr,
+                            int32_t cap, double* d_mp, tto_batch* dst, void* stream) {
+  if (!src || !idx || !dst) return fail(TTO_E_INVALID, "NULL argument");
+  if (k < 1 || k > src->n_cand) return fail(TTO_E_INVALID, "k must be in 1..src->n_cand");
+  if (src->n_open_slots < 0 || src->n_open_slots > TTO_MAX_RANK || src->n_split_slots < 0 ||
+      src->n_split_slots > TTO_MAX_RANK)
+    return fail(TTO_E_RANK, "slot counts out of range");
+  if (src->n_open_slots > 0 && (!src->open || !d_open)) return fail(TTO_E_INVALID, "open arrays NULL");
+  if (!d_moff) return fail(TTO_E_INVALID, "dst_moved_off is NULL");
+  if (src->n_split_slots > 0 && (!src->split_bus || !src->moved_off || !src->moved_br || !d_split || !d_mbr))
+    return fail(TTO_E_INVALID, "split arrays NULL");
+  if (cap < 0) return fail(TTO_E_INVALID, "dst_moved_cap must be >= 0");
+  if (src->moved_p_mw && !d_mp) return fail(TTO_E_INVALID, "dst_moved_p is NULL");
+  if (src->moved_p_mw && (T < 1 || T > TTO_MAX_T)) return fail(TTO_E_INVALID, "n_timesteps out of range");
+  batch_gather(src->open, src->split_bus, src->moved_off, src->moved_br, src->moved_p_mw, src->n_cand,
+               src->n_open_slots, src->n_split_slots, src->moved_p_mw ? T : 0, idx, k, d_open,
+               d_split, d_moff, d_mbr, cap, src->moved_p_mw ? d_mp : nullptr, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  dst->n_cand = k;
+  dst->n_open_slots = src->n_open_slots;
+  dst->n_split_slots = src->n_split_slots;
+  dst->open = d_open;
+  dst->split_bus = d_split;
+  dst->moved_off = d_moff;
+  dst->moved_br = d_mbr;
+  dst->moved_p_mw = src->moved_p_mw ? d_mp : nullptr;
+  return ok();
+}
+
+tto_status tto_topk_smallest(const float* score, int32_t n, int32_t stride, int32_t k,
+                             int32_t* idx_out, void* stream) {
+  if (!score || !idx_out) return fail(TTO_E_INVALID, "NULL argument");
+  if (n < 1 || n > (1 << 24)) return fail(TTO_E_INVALID, "n must be in 1..2^24");
+  if (k < 0 || k > n) return fail(TTO_E_INVALID, "k must be in 0..n");
+  if (stride < 1) return fail(TTO_E_INVALID, "stride must be >= 1");
+  topk_smallest(score, n, stride, k, idx_out, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
   return ok();
 }
 

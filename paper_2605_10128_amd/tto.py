@@ -53,6 +53,11 @@ class tto_outputs(ct.Structure):
     _fields_ = [(f, _vp) for f in OUTPUT_FIELDS]
 
 
+class tto_mlp_desc(ct.Structure):
+    _fields_ = [("d_bits", _i32), ("d_dense", _i32), ("width", _i32), ("max_batch", _i32),
+                ("max_train_batch", _i32)]
+
+
 class TTOError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"tto error {code}: {msg}")
@@ -80,6 +85,20 @@ def _load():
         "tto_profile_read": (_i32, [_vp, P(ct.c_double)]),
         "tto_set_sweep_plan": (_i32, [_vp, _i32, _i32, _i32]),
         "tto_set_refine": (_i32, [_vp, _i32, ct.c_double]),
+        "tto_batch_gather": (_i32, [P(tto_batch), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp,
+                                    P(tto_batch), _vp]),
+        "tto_mlp_workspace_bytes": (_i32, [P(tto_mlp_desc), P(ct.c_size_t), P(ct.c_size_t)]),
+        "tto_mlp_create": (_i32, [P(tto_mlp_desc), _vp, ct.c_size_t, P(_vp)]),
+        "tto_mlp_destroy": (None, [_vp]),
+        "tto_mlp_n_params": (_i32, [_vp, P(ct.c_int64)]),
+        "tto_mlp_set_params": (_i32, [_vp, _vp, _vp]),
+        "tto_mlp_get_params": (_i32, [_vp, _vp, _vp]),
+        "tto_mlp_forward": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, ct.c_size_t, _vp]),
+        "tto_mlp_gradients": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, ct.c_size_t,
+                                     _vp]),
+        "tto_mlp_train_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, ct.c_float, _vp, _vp,
+                                      ct.c_size_t, _vp]),
+        "tto_topk_smallest": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp]),
         "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
         "tto_autotune": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                 ct.c_char_p, P(_i32)]),
@@ -96,7 +115,10 @@ _lib = _load()
 EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_create",
             "tto_grid_destroy", "tto_set_injections", "tto_get_base_flows", "tto_set_descriptor",
             "tto_evaluate", "tto_archive_insert", "tto_profile_enable", "tto_profile_read",
-            "tto_set_sweep_plan", "tto_get_sweep_plan", "tto_autotune", "tto_set_refine"]
+            "tto_set_sweep_plan", "tto_get_sweep_plan", "tto_autotune", "tto_set_refine",
+            "tto_batch_gather", "tto_mlp_workspace_bytes", "tto_mlp_create", "tto_mlp_destroy",
+            "tto_mlp_n_params", "tto_mlp_set_params", "tto_mlp_get_params", "tto_mlp_forward",
+            "tto_mlp_gradients", "tto_mlp_train_step", "tto_topk_smallest"]
 
 
 def _check(code: int):
@@ -188,6 +210,148 @@ def tto_autotune(handle: int, batch: tto_batch, outputs: tto_outputs, ws: int, w
                              _vp(stream), cache_path.encode(), ch))
     return {"block": ch[0], "xcd_group": bool(ch[1]), "persistent": bool(ch[2]),
             "from_cache": bool(ch[3])}
+
+
+def tto_topk_smallest(score: int, n: int, stride: int, k: int, idx_out: int, stream: int):
+    _check(_lib.tto_topk_smallest(_vp(score), n, stride, k, _vp(idx_out), _vp(stream)))
+
+
+def tto_batch_gather(src: tto_batch, idx: int, k: int, T: int, d_open: int, d_split: int,
+                     d_moff: int, d_mbr: int, cap: int, d_mp: int, stream: int) -> tto_batch:
+    dst = tto_batch()
+    _check(_lib.tto_batch_gather(ct.byref(src), _vp(idx), k, T, _vp(d_open), _vp(d_split),
+                                 _vp(d_moff), _vp(d_mbr), cap, _vp(d_mp), ct.byref(dst),
+                                 _vp(stream)))
+    return dst
+
+
+def tto_mlp_workspace_bytes(desc: tto_mlp_desc):
+    a, b = ct.c_size_t(), ct.c_size_t()
+    _check(_lib.tto_mlp_workspace_bytes(ct.byref(desc), ct.byref(a), ct.byref(b)))
+    return a.value, b.value
+
+
+def tto_mlp_create(desc: tto_mlp_desc, ws: int, nbytes: int) -> int:
+    h = _vp()
+    _check(_lib.tto_mlp_create(ct.byref(desc), _vp(ws), nbytes, ct.byref(h)))
+    return h.value
+
+
+def tto_mlp_destroy(handle: int):
+    _lib.tto_mlp_destroy(_vp(handle))
+
+
+def tto_mlp_n_params(handle: int) -> int:
+    n = ct.c_int64()
+    _check(_lib.tto_mlp_n_params(_vp(handle), ct.byref(n)))
+    return n.value
+
+
+def tto_mlp_set_params(handle: int, params: int, stream: int):
+    _check(_lib.tto_mlp_set_params(_vp(handle), _vp(params), _vp(stream)))
+
+
+def tto_mlp_get_params(handle: int, params: int, stream: int):
+    _check(_lib.tto_mlp_get_params(_vp(handle), _vp(params), _vp(stream)))
+
+
+def tto_mlp_forward(handle, off, idx, dense, n, y, ws, nbytes, stream):
+    _check(_lib.tto_mlp_forward(_vp(handle), _vp(off), _vp(idx), _vp(dense), n, _vp(y), _vp(ws),
+                                nbytes, _vp(stream)))
+
+
+def tto_mlp_gradients(handle, off, idx, dense, target, n, grad, loss, ws, nbytes, stream):
+    _check(_lib.tto_mlp_gradients(_vp(handle), _vp(off), _vp(idx), _vp(dense), _vp(target), n,
+                                  _vp(grad), _vp(loss), _vp(ws), nbytes, _vp(stream)))
+
+
+def tto_mlp_train_step(handle, off, idx, dense, target, n, lr, loss, ws, nbytes, stream):
+    _check(_lib.tto_mlp_train_step(_vp(handle), _vp(off), _vp(idx), _vp(dense), _vp(target), n,
+                                   float(lr), _vp(loss), _vp(ws), nbytes, _vp(stream)))
+
+
+class Surrogate:
+    """Torch-allocated workspaces around the tto_mlp_* entry points."""
+
+    def __init__(self, d_bits, d_dense, width=512, max_batch=65536, max_train_batch=4096,
+                 device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.desc = tto_mlp_desc(int(d_bits), int(d_dense), int(width), int(max_batch),
+                                 int(max_train_batch))
+        self.pbytes, self.bbytes = tto_mlp_workspace_bytes(self.desc)
+        self.pws = torch.empty(self.pbytes, dtype=torch.uint8, device=self.device)
+        self.bws = torch.empty(self.bbytes, dtype=torch.uint8, device=self.device)
+        self.handle = tto_mlp_create(self.desc, _ptr(self.pws), self.pbytes)
+        self.n_params = tto_mlp_n_params(self.handle)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    @property
+    def stream(self) -> int:
+        return int(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                tto_mlp_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        t = self.torch.as_tensor(np.ascontiguousarray(flat, dtype=np.float32), device=self.device)
+        tto_mlp_set_params(self.handle, _ptr(t), self.stream)
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def get_params(self):
+        out = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.device)
+        tto_mlp_get_params(self.handle, _ptr(out), self.stream)
+        return out
+
+    def forward(self, off, idx, dense, n, y=None):
+        if y is None:
+            y = self.torch.empty((n, 2), dtype=self.torch.float32, device=self.device)
+        tto_mlp_forward(self.handle, _ptr(off), _ptr(idx), _ptr(dense), n, _ptr(y),
+                        _ptr(self.bws), self.bbytes, self.stream)
+        return y
+
+    def gradients(self, off, idx, dense, target, n):
+        g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.device)
+        tto_mlp_gradients(self.handle, _ptr(off), _ptr(idx), _ptr(dense), _ptr(target), n,
+                          _ptr(g), _ptr(self.loss), _ptr(self.bws), self.bbytes, self.stream)
+        return g, self.loss
+
+    def train_step(self, off, idx, dense, target, n, lr):
+        tto_mlp_train_step(self.handle, _ptr(off), _ptr(idx), _ptr(dense), _ptr(target), n, lr,
+                           _ptr(self.loss), _ptr(self.bws), self.bbytes, self.stream)
+        return self.loss
+
+
+def he_init(d_bits, d_dense, width, seed=0):
+    """He-normal weights, zero biases, flat in the tto_mlp parameter order."""
+    rng = np.random.default_rng(seed)
+    H = width
+    parts = [
+        rng.normal(0, np.sqrt(2.0 / 8.0), (d_bits, H)),          # ~8 set bits per sample
+        rng.normal(0, np.sqrt(2.0 / max(d_dense, 1)), (d_dense, H)),
+        np.zeros(H), rng.normal(0, np.sqrt(2.0 / H), (H, H)), np.zeros(H),
+        rng.normal(0, np.sqrt(2.0 / H), (H, H)), np.zeros(H),
+        rng.normal(0, np.sqrt(1.0 / H), (H, 2)), np.zeros(2),
+    ]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def split_params(flat, d_bits, d_dense, width):
+    H = width
+    shapes = [("W1b", (d_bits, H)), ("W1d", (d_dense, H)), ("b1", (H,)), ("W2", (H, H)),
+              ("b2", (H,)), ("W3", (H, H)), ("b3", (H,)), ("W4", (H, 2)), ("b4", (2,))]
+    out, o = {}, 0
+    for name, shp in shapes:
+        n = int(np.prod(shp))
+        out[name] = np.asarray(flat[o:o + n]).reshape(shp)
+        o += n
+    return out
 
 
 # ---- torch-backed session (device memory and streams only) -----------------
