@@ -385,6 +385,35 @@ tto_status tto_mlp_train_step(tto_mlp* mlp, const int32_t* bits_off, const int32
 tto_status tto_topk_smallest(const float* score, int32_t n, int32_t stride, int32_t k,
                              int32_t* idx_out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Graph capture and replay.  A generation's launches (evaluate, archive
+ * insertion, or the whole screened pipeline) are recorded once and replayed
+ * with one call, so that many small launches cost one submission.
+ *
+ * tto_graph_begin creates a private stream in capture mode and returns it in
+ * *capture_stream; pass that stream to the asynchronous tto_* calls to be
+ * recorded, then call tto_graph_end.  Every pointer and size is fixed at
+ * capture: a replay re-reads the current contents of the same buffers.
+ * Calls that synchronise, allocate or clear memory refuse to run while their
+ * stream is captured (tto_autotune, tto_mlp_set_params, tto_mlp_train_step
+ * return TTO_E_UNSUPPORTED).  With profiling on, tto_evaluate records its
+ * stage events into the graph.  Host only, except tto_graph_launch, which is
+ * asynchronous on `stream`.  tto_graph_destroy ends an open capture.
+ */
+typedef struct tto_graph tto_graph;
+tto_status tto_graph_begin(tto_graph** out, void** capture_stream);
+tto_status tto_graph_end(tto_graph* graph);
+tto_status tto_graph_launch(tto_graph* graph, void* stream);
+void tto_graph_destroy(tto_graph* graph);
+
+/* One-call form: tto_evaluate on this batch followed, when elite_fitness is
+ * not NULL, by tto_archive_insert of its results (ids id_base + i), captured
+ * into *graph. */
+tto_status tto_evaluate_capture(tto_grid* grid, const tto_batch* batch, const tto_outputs* out,
+                                void* batch_ws, size_t batch_bytes, double* elite_fitness,
+                                int64_t* elite_id, int32_t n_cells, int64_t id_base,
+                                tto_graph** graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -189,6 +189,14 @@ int uf_find(std::vector<int>& p, int a) {
 
 }  // namespace
 
+// True when `s` is being captured into a graph (calls that synchronise,
+// allocate or clear memory with hipMemsetAsync refuse to run then).
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
 struct tto_grid {
   int device;
   int n_bus, m, slack, T, TT, nM, nC;
@@ -486,6 +494,7 @@ tto_status tto_autotune(tto_grid* g, const tto_batch* bt, const tto_outputs* out
                         size_t batch_bytes, void* stream, const char* cache_path,
                         int32_t* chosen) {
   if (!g || !bt || !out) return fail(TTO_E_INVALID, "grid, batch or outputs is NULL");
+  if (capturing((hipStream_t)stream)) return fail(TTO_E_UNSUPPORTED, "autotune cannot be captured");
   char key[256];
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, g->device));
@@ -682,6 +691,7 @@ tto_status tto_mlp_n_params(tto_mlp* m, int64_t* n) {
 tto_status tto_mlp_set_params(tto_mlp* m, const float* params, void* stream) {
   if (!m || !params) return fail(TTO_E_INVALID, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
+  if (capturing(s)) return fail(TTO_E_UNSUPPORTED, "set_params cannot be captured");
   const size_t n = m->p.n_params * sizeof(float);
   HIP_TRY(hipMemcpyAsync(m->p.master, params, n, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemsetAsync(m->p.m, 0, n, s));
@@ -731,6 +741,8 @@ tto_status tto_mlp_train_step(tto_mlp* m, const int32_t* off, const int32_t* idx
   if (st != TTO_OK) return st;
   if (!target || !loss) return fail(TTO_E_INVALID, "target or loss is NULL");
   if (!(lr >= 0.f) || !isfinite(lr)) return fail(TTO_E_INVALID, "lr must be finite and >= 0");
+  if (capturing((hipStream_t)stream))
+    return fail(TTO_E_UNSUPPORTED, "train_step cannot be captured (its Adam step count is host state)");
   size_t used = 0;
   MlpBatch b = carve_mlp_batch(&m->d, ws, &used);
   hipStream_t s = (hipStream_t)stream;
@@ -779,6 +791,90 @@ tto_status tto_topk_smallest(const float* score, int32_t n, int32_t stride, int3
   if (stride < 1) return fail(TTO_E_INVALID, "stride must be >= 1");
   topk_smallest(score, n, stride, k, idx_out, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Graph capture and replay
+struct tto_graph {
+  int device = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool open = false;
+};
+
+tto_status tto_graph_begin(tto_graph** out, void** capture_stream) {
+  if (!out || !capture_stream) return fail(TTO_E_INVALID, "NULL output pointer");
+  tto_graph* gr = new tto_graph();
+  hipError_t e = hipGetDevice(&gr->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&gr->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(gr->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    if (gr->cap) (void)hipStreamDestroy(gr->cap);
+    delete gr;
+    return fail(TTO_E_HIP, "graph begin: %s", hipGetErrorString(e));
+  }
+  gr->open = true;
+  *out = gr;
+  *capture_stream = gr->cap;
+  return ok();
+}
+
+tto_status tto_graph_end(tto_graph* gr) {
+  if (!gr || !gr->open) return fail(TTO_E_INVALID, "graph is NULL or not capturing");
+  gr->open = false;
+  hipError_t e = hipStreamEndCapture(gr->cap, &gr->graph);
+  if (e != hipSuccess) return fail(TTO_E_HIP, "end capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail(TTO_E_HIP, "instantiate: %s", hipGetErrorString(e));
+  return ok();
+}
+
+tto_status tto_graph_launch(tto_graph* gr, void* stream) {
+  if (!gr || !gr->exec) return fail(TTO_E_INVALID, "graph is NULL or not instantiated");
+  HIP_TRY(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+  return ok();
+}
+
+void tto_graph_destroy(tto_graph* gr) {
+  if (!gr) return;
+  if (gr->open) {
+    hipGraph_t tmp = nullptr;
+    if (hipStreamEndCapture(gr->cap, &tmp) == hipSuccess && tmp) (void)hipGraphDestroy(tmp);
+  }
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  if (gr->cap) (void)hipStreamDestroy(gr->cap);
+  delete gr;
+}
+
+tto_status tto_evaluate_capture(tto_grid* g, const tto_batch* bt, const tto_outputs* out,
+                                void* batch_ws, size_t batch_bytes, double* elite_fitness,
+                                int64_t* elite_id, int32_t n_cells, int64_t id_base,
+                                tto_graph** graph) {
+  if (!graph) return fail(TTO_E_INVALID, "graph is NULL");
+  *graph = nullptr;
+  tto_graph* gr = nullptr;
+  void* cs = nullptr;
+  tto_status st = tto_graph_begin(&gr, &cs);
+  if (st != TTO_OK) return st;
+  st = tto_evaluate(g, bt, out, batch_ws, batch_bytes, cs);
+  if (st == TTO_OK && elite_fitness)
+    st = tto_archive_insert(g, elite_fitness, elite_id, n_cells, out->fitness, out->cell,
+                            out->status, bt->n_cand, id_base, batch_ws, batch_bytes, cs);
+  if (st != TTO_OK) {
+    std::string msg = g_err;
+    tto_graph_destroy(gr);
+    return fail(st, "%s", msg.c_str());
+  }
+  st = tto_graph_end(gr);
+  if (st != TTO_OK) {
+    std::string msg = g_err;
+    tto_graph_destroy(gr);
+    return fail(st, "%s", msg.c_str());
+  }
+  *graph = gr;
   return ok();
 }
 

@@ -99,6 +99,12 @@ def _load():
         "tto_mlp_train_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, ct.c_float, _vp, _vp,
                                       ct.c_size_t, _vp]),
         "tto_topk_smallest": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp]),
+        "tto_graph_begin": (_i32, [P(_vp), P(_vp)]),
+        "tto_graph_end": (_i32, [_vp]),
+        "tto_graph_launch": (_i32, [_vp, _vp]),
+        "tto_graph_destroy": (None, [_vp]),
+        "tto_evaluate_capture": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
+                                        _vp, _i32, ct.c_int64, P(_vp)]),
         "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
         "tto_autotune": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                 ct.c_char_p, P(_i32)]),
@@ -118,7 +124,9 @@ EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_cr
             "tto_set_sweep_plan", "tto_get_sweep_plan", "tto_autotune", "tto_set_refine",
             "tto_batch_gather", "tto_mlp_workspace_bytes", "tto_mlp_create", "tto_mlp_destroy",
             "tto_mlp_n_params", "tto_mlp_set_params", "tto_mlp_get_params", "tto_mlp_forward",
-            "tto_mlp_gradients", "tto_mlp_train_step", "tto_topk_smallest"]
+            "tto_mlp_gradients", "tto_mlp_train_step", "tto_topk_smallest",
+            "tto_graph_begin", "tto_graph_end", "tto_graph_launch", "tto_graph_destroy",
+            "tto_evaluate_capture"]
 
 
 def _check(code: int):
@@ -268,6 +276,81 @@ def tto_mlp_gradients(handle, off, idx, dense, target, n, grad, loss, ws, nbytes
 def tto_mlp_train_step(handle, off, idx, dense, target, n, lr, loss, ws, nbytes, stream):
     _check(_lib.tto_mlp_train_step(_vp(handle), _vp(off), _vp(idx), _vp(dense), _vp(target), n,
                                    float(lr), _vp(loss), _vp(ws), nbytes, _vp(stream)))
+
+
+def tto_graph_begin():
+    g, cs = _vp(), _vp()
+    _check(_lib.tto_graph_begin(ct.byref(g), ct.byref(cs)))
+    return g.value, cs.value or 0
+
+
+def tto_graph_end(graph: int):
+    _check(_lib.tto_graph_end(_vp(graph)))
+
+
+def tto_graph_launch(graph: int, stream: int):
+    _check(_lib.tto_graph_launch(_vp(graph), _vp(stream)))
+
+
+def tto_graph_destroy(graph: int):
+    _lib.tto_graph_destroy(_vp(graph))
+
+
+def tto_evaluate_capture(handle, batch: "tto_batch", outputs: "tto_outputs", ws, ws_bytes,
+                         elite_fit, elite_id, n_cells, id_base) -> int:
+    g = _vp()
+    _check(_lib.tto_evaluate_capture(_vp(handle), ct.byref(batch), ct.byref(outputs), _vp(ws),
+                                     ws_bytes, _vp(elite_fit), _vp(elite_id), int(n_cells),
+                                     int(id_base), ct.byref(g)))
+    return g.value
+
+
+class Graph:
+    """A captured sequence of library calls, replayed with launch().
+
+    Use as a context manager: inside the `with` block torch's current stream
+    is the capture stream, so Session / Surrogate / Screener calls made there
+    are recorded (their buffers must already be allocated)."""
+
+    def __init__(self, handle: int = 0):
+        self.handle = handle
+        self._ctx = None
+
+    def __enter__(self):
+        import torch
+        self.handle, cs = tto_graph_begin()
+        self._ctx = torch.cuda.stream(torch.cuda.ExternalStream(cs))
+        self._ctx.__enter__()
+        return self
+
+    def __exit__(self, et, ev, tb):
+        self._ctx.__exit__(et, ev, tb)
+        self._ctx = None
+        if et is None:
+            try:
+                tto_graph_end(self.handle)
+            except Exception:
+                self.close()
+                raise
+        else:
+            self.close()          # ends the open capture before anything else runs
+        return False
+
+    def launch(self, stream: Optional[int] = None):
+        import torch
+        s = int(torch.cuda.current_stream().cuda_stream) if stream is None else stream
+        tto_graph_launch(self.handle, s)
+
+    def close(self):
+        if self.handle:
+            tto_graph_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Surrogate:
@@ -501,6 +584,15 @@ class Session:
         st = tto_outputs(*[_ptr(outputs.get(f)) for f in OUTPUT_FIELDS])
         return tto_autotune(self.handle, dbatch.struct(), st, _ptr(self.batch_ws),
                             self.batch_bytes, self.stream, cache_path)
+
+    def capture_evaluate(self, dbatch: DeviceBatch, outputs, archive=None, id_base=0) -> Graph:
+        """Graph of evaluate (+ archive insertion) on these buffers."""
+        st = tto_outputs(*[_ptr(outputs.get(f)) for f in OUTPUT_FIELDS])
+        fit, ids = archive if archive is not None else (None, None)
+        h = tto_evaluate_capture(self.handle, dbatch.struct(), st, _ptr(self.batch_ws),
+                                 self.batch_bytes, _ptr(fit), _ptr(ids),
+                                 int(fit.shape[0]) if fit is not None else 0, id_base)
+        return Graph(h)
 
     def set_sweep_plan(self, block=256, xcd_group=False, persistent=False):
         tto_set_sweep_plan(self.handle, block, xcd_group, persistent)
