@@ -8,10 +8,10 @@ offered to the archive.  The network is trained on exact evaluations the DC
 evaluator itself produces.  Every numerical step runs in the library's
 kernels; this module only moves arrays and chains the calls.
 
-The paper scores every mutated candidate exactly (Section 4, DC-Optimizer);
+The paper scores every mutated candidate exactly (DC-Optimizer section);
 the screen is an addition for large generations.  Feature encoding: one bit
 per base non-bridge opening and one per split action of the action table
-(the paper's set of station reconfigurations, Section 3.2), plus the
+(the paper's reconfiguration action set, Importer section), plus the
 per-timestep total positive injection, standardised.  Targets: maximum
 loading and log1p(overload / 100 MW).
 """
