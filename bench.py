@@ -1,11 +1,20 @@
 """Throughput of the batched DC N-1 topology screen on one MI355X.
 
 One step = one tto_evaluate over the whole candidate batch (set-up, N-1 sweep
-with fused reductions, finalize) plus the archive update, inputs resident in
-HBM.  Default workload: 2000-bus / 3200-branch grid, 24 timesteps, 16384
-candidates of rank 0..8, 1200 monitored x 1600 contingencies, FP32 flows.
+with fused reductions, finalize, FP64 refinement) plus the archive update,
+replayed as one captured graph, inputs resident in HBM.  Default workload:
+2000-bus / 3200-branch grid, 24 timesteps, 16384 candidates of rank 0..8,
+1200 monitored x 1600 contingencies, FP32 flows.
 
-Prints one JSON line (see the design notes for the roofline definition).
+A second leg measures the learned pre-screen on the same grid: the network is
+trained on exact evaluations over 8 injection scenarios, then a generation of
+65536 candidates of an unseen scenario is screened (forward, top 10%, gather)
+and the survivors evaluated exactly and archived, again as one captured graph;
+it reports the screened rate next to the exact one, the surrogate's error and
+the agreement of the screened archive with the exact-only archive.
+
+Prints one JSON line.  `python bench.py --copy-calibration` instead runs a
+plain 1 GiB device copy, the reference for scaling HBM byte counters.
 """
 from __future__ import annotations
 
@@ -64,6 +73,177 @@ def cpu_baseline(w, seconds_target=20.0):
                       f"{cores} processes, {dt:.1f} s wall; scaled by (n_cont+1)/(|C|+1)"}
 
 
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy (reference for HBM byte counters)."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copied {a.numel() * 4} bytes")
+
+
+def surrogate_leg(s, w, args, exact_rate):
+    """Train the pre-screen on exact evaluations, then time screened generations."""
+    import numpy as np
+    import torch
+    import gridgen as gg
+    from paper_2605_10128_amd import tto, screen
+    grid, T, B = w.grid, w.P.shape[1], s.max_batch
+    n_scen = 8
+    per = max(B, (args.train_samples // n_scen) // B * B)
+    n_gen = args.screen
+    keep = max(1, int(round(args.keep_frac * n_gen)))
+    if keep > B:
+        raise SystemExit(f"keep {keep} exceeds the evaluation batch {B}")
+    nb = gg.bridges(grid.n_bus, grid.from_bus, grid.to_bus)
+    d_bits = int((~nb).sum()) + len(w.split_table)
+    scen = [gg.make_injections(grid, T, 0x7000 + i) for i in range(n_scen + 1)]
+    scale = screen.FeatureScale.fit([screen.injection_summary(P) for P in scen[:n_scen]])
+    out = s.alloc_outputs(B)
+    parts, t_eval, t0 = [], 0.0, time.perf_counter()
+    for i in range(n_scen):
+        s.set_injections(scen[i])
+        b = gg.make_candidates_ranked(grid, per, 0x8000 + i, w.split_table, P=scen[i])
+        off, ids, _ = gg.action_bits(grid, b, len(w.split_table))
+        tg, ok = [], []
+        for c0 in range(0, per, B):
+            db = tto.device_batch(b.subset(np.arange(c0, c0 + B)))
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            s.evaluate(db, out)
+            torch.cuda.synchronize()
+            t_eval += time.perf_counter() - te
+            t_, ok_ = screen.targets_from_outputs(out)
+            tg.append(t_)
+            ok.append(ok_)
+        parts.append((off, ids, scale.apply(screen.injection_summary(scen[i])),
+                      np.concatenate(tg), np.concatenate(ok)))
+    data = screen.Dataset.assemble(parts, seed=1)
+    log(f"[bench] surrogate data: {n_scen * per} exact evaluations ({data.n} usable) in "
+        f"{time.perf_counter() - t0:.1f} s ({t_eval:.1f} s on the GPU)")
+    sc = screen.Screener(s, d_bits, T, width=512, max_screen=n_gen, max_keep=keep)
+    t0 = time.perf_counter()
+    losses = sc.train(data, epochs=args.epochs, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[bench] surrogate trained: losses {['%.4f' % x for x in losses]} in {t_train:.1f} s")
+
+    # unseen scenario, one generation
+    P = scen[-1]
+    s.set_injections(P)
+    gen = gg.make_candidates_ranked(grid, n_gen, 0x9999, w.split_table, P=P)
+    off, ids, _ = gg.action_bits(grid, gen, len(w.split_table))
+    exact = {}
+    for c0 in range(0, n_gen, B):
+        n = min(B, n_gen - c0)
+        o = s.evaluate(tto.device_batch(gen.subset(np.arange(c0, c0 + n))))
+        for k, v in o.items():
+            exact.setdefault(k, []).append(v.cpu().numpy())
+    exact = {k: np.concatenate(v) for k, v in exact.items()}
+    dev = s.device
+    db = tto.device_batch(gen)
+    off_d, ids_d = torch.as_tensor(off, device=dev), torch.as_tensor(ids, device=dev)
+    dense_d = sc.dense_rows(scale, P, n_gen)
+    so = s.alloc_outputs(keep)
+    arch = s.new_archive()
+    sc.screen_and_evaluate(db, off_d, ids_d, dense_d, keep, outputs=so)   # eager warm-up
+    launch = "eager"
+    graph = None
+    try:
+        with tto.Graph() as graph:
+            sc.screen_and_evaluate(db, off_d, ids_d, dense_d, keep, outputs=so)
+            s.archive_insert(arch, so)
+        launch = "hipGraph replay"
+    except tto.TTOError as e:
+        log(f"[bench] screened graph capture unavailable ({e}); eager launches")
+        graph = None
+
+    def one():
+        if graph is not None:
+            graph.launch()
+        else:
+            sc.screen_and_evaluate(db, off_d, ids_d, dense_d, keep, outputs=so)
+            s.archive_insert(arch, so)
+    for _ in range(2):
+        one()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.screen_steps):
+        one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_gen = e0.elapsed_time(e1) / args.screen_steps
+    if graph is not None:
+        graph.close()
+    # stage split of one eager generation (events on the launch stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ev[0].record(stream)
+    sc.predict(off_d, ids_d, dense_d, n_gen)
+    ev[1].record(stream)
+    sc.select(n_gen, keep)
+    ev[2].record(stream)
+    gb = sc.gather(db, keep)
+    ev[3].record(stream)
+    s.evaluate(gb, so)
+    s.archive_insert(arch, so)
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    stage = [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+
+    idx = sc.idx[:keep].cpu().numpy()
+    y = sc.y[:n_gen].cpu().numpy()
+    valid = (exact["status"] & 3) == 0
+    fit = np.where(valid, exact["fitness"], -np.inf)
+    best = np.argsort(-fit, kind="stable")[:keep]
+    recall = len(np.intersect1d(best, idx)) / keep
+    t1 = np.log1p(exact["overload_mw"][valid] / screen.OVERLOAD_SCALE_MW)
+
+    def archive(cands):
+        a = {}
+        for c in cands:
+            if valid[c]:
+                cell = int(exact["cell"][c])
+                e = a.get(cell)
+                if e is None or fit[c] > fit[e] or (fit[c] == fit[e] and c < e):
+                    a[cell] = c
+        return a
+    a_all, a_scr = archive(range(n_gen)), archive(idx.tolist())
+    kept = sum(1 for c, e in a_all.items() if a_scr.get(c) == e)
+    scr_rate = n_gen / (ms_gen / 1e3)
+    res = {
+        "value": scr_rate,
+        "unit": "screened topologies/s",
+        "ms_per_generation": ms_gen,
+        "launch": launch,
+        "generation": n_gen,
+        "exactly_evaluated": keep,
+        "vs_exact_only": scr_rate / exact_rate,
+        "stage_ms": {"mlp_forward": stage[0], "top_k": stage[1], "gather": stage[2],
+                     "exact_and_archive": stage[3]},
+        "train": {"exact_evaluations": n_scen * per, "usable": int(data.n),
+                  "scenarios": n_scen, "epochs": args.epochs, "final_loss": losses[-1],
+                  "train_s": t_train, "gpu_eval_s": t_eval, "width": 512,
+                  "bits": d_bits, "dense": T},
+        "error_unseen_scenario": {
+            "max_loading_mae": float(np.abs(y[valid, 0] - exact["max_loading"][valid]).mean()),
+            "log_overload_mae": float(np.abs(y[valid, 1] - t1).mean()),
+            "log_overload_corr": float(np.corrcoef(y[valid, 1], t1)[0, 1]),
+        },
+        "recall_top10pct_fitness": recall,
+        "archive": {"exact_only_cells": len(a_all), "screened_cells": len(a_scr),
+                    "identical_elites": kept},
+    }
+    log(f"[bench] screened: {scr_rate:,.0f} topologies/s ({ms_gen:.2f} ms per {n_gen}), "
+        f"stages {['%.3f' % x for x in stage]} ms, recall {recall:.3f}, "
+        f"archive {kept}/{len(a_all)} identical")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +257,18 @@ def main():
                     help="sweep plan 'auto' (autotune) or 'block,xcd,persistent', e.g. 64,1,0")
     ap.add_argument("--sweep-plans", action="store_true",
                     help="also report the sweep time of every plan (stderr)")
+    ap.add_argument("--no-graph", action="store_true", help="eager launches instead of replay")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the screened leg")
+    ap.add_argument("--train-samples", type=int, default=1 << 20)
+    ap.add_argument("--epochs", type=int, default=2)
+    ap.add_argument("--screen", type=int, default=65536)
+    ap.add_argument("--keep-frac", type=float, default=0.1)
+    ap.add_argument("--screen-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(candidates shard along the batch; see the design notes)"}))
@@ -135,13 +326,26 @@ def main():
     log("[bench] warmup done")
 
     tto.tto_profile_enable(s.handle, True)
+    graph, launch = None, "eager"
+    if not args.no_graph:
+        try:
+            graph = s.capture_evaluate(db, out, arch, id_base=args.warmup * B)
+            launch = "hipGraph replay"
+            graph.launch()
+            torch.cuda.synchronize()
+        except tto.TTOError as e:
+            log(f"[bench] graph capture unavailable ({e}); timing eager launches")
+            graph = None
     sweep_ms, setup_ms, fin_ms, ref_ms = [], [], [], []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
     for i in range(args.steps):
-        s.evaluate(db, out)
-        s.archive_insert(arch, out, id_base=(args.warmup + i) * B)
+        if graph is not None:
+            graph.launch()
+        else:
+            s.evaluate(db, out)
+            s.archive_insert(arch, out, id_base=(args.warmup + i) * B)
         ms = tto.tto_profile_read(s.handle)   # waits for this step's events only
         setup_ms.append(ms[0]); sweep_ms.append(ms[1]); fin_ms.append(ms[2]); ref_ms.append(ms[3])
     ev1.record(stream)
@@ -188,6 +392,7 @@ def main():
             "flow_precision": args.flow,
             "candidates_ok": int(ok.sum()),
             "sweep_plan": {k: chosen[k] for k in ("block", "xcd_group", "persistent")},
+            "launch": launch,
             "islanded": int(((o["status"] & 1) != 0).sum()),
             "refined_fp64": int(((o["status"] & 4) != 0).sum()),
             "refine_skipped": int(((o["status"] & 8) != 0).sum()),
@@ -206,7 +411,12 @@ def main():
             "refine_ms": float(np.mean(ref_ms)),
         },
         "cpu_baseline": None,
+        "surrogate_screened": None,
     }
+    if graph is not None:
+        graph.close()
+    if not args.no_surrogate:
+        result["surrogate_screened"] = surrogate_leg(s, w, args, value)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         result["cpu_baseline"] = cpu_baseline(w)
