@@ -62,9 +62,15 @@ enum {
  * mode. */
 enum { TTO_FLOW_F64 = 0, TTO_FLOW_F32 = 1 };
 
-/* Arithmetic of the base-flow product f0 = PTDF * P (MFMA); FP32 accumulate
- * for F32/BF16/F16, FP64 accumulate for F64.  f0 is kept in FP64. */
-enum { TTO_GEMM_F64 = 0, TTO_GEMM_F32 = 1, TTO_GEMM_BF16 = 2, TTO_GEMM_F16 = 3 };
+/* Arithmetic of the base-flow product f0 = PTDF * P (MFMA); FP64 accumulate
+ * for F64, FP32 accumulate otherwise.  f0 is kept in FP64.  BF16X3 and F16X3
+ * split both operands into hi + lo 16-bit parts and sum the three products
+ * hi*hi + hi*lo + lo*hi on the 16-bit MFMA (about 16 and 22 significant bits).
+ * F16 and F16X3 need |injections| below 65504 MW. */
+enum {
+  TTO_GEMM_F64 = 0, TTO_GEMM_F32 = 1, TTO_GEMM_BF16 = 2, TTO_GEMM_F16 = 3,
+  TTO_GEMM_BF16X3 = 4, TTO_GEMM_F16X3 = 5
+};
 
 /* Per-candidate status bits. */
 #define TTO_ST_ISLANDED 0x01u  /* post-switch grid is not connected */

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   __shared__ SetupShared sh;
   __shared__ double s_x[kMaxRank][TT];
   __shared__ int s_wcnt[4];
-  __shared__ int s_base, s_n0, s_nisl;
+  __shared__ int s_base, s_n0, s_nisl, s_near0;
   __shared__ F s_stage[4][64][17];   // record staging, one slab per wave
 
   // -- genome parse in stages: slot values, ranges, moved-branch data, checks
@@ -196,6 +196,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     s_base = 0;
     s_n0 = 0;
     s_nisl = 0;
+    s_near0 = 0;
   }
   __syncthreads();
   {
@@ -371,7 +372,8 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   };
 
   // monitored rows: f'_M and U_M
-  int n0 = 0;
+  int n0 = 0, near0 = 0;
+  const double mg = decision_margin(g);
   for (int ei = tid; ei < nM; ei += 256) {
     keep_in_loop();
     const int e = g.mon[ei];
@@ -390,6 +392,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
 #pragma unroll
         for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
         n0 += fabs(fp) > lim;
+        near0 |= fabs(fabs(fp) - lim) <= mg;
       }
       fo[(size_t)t * nM] = (F)fp;
     }
@@ -398,6 +401,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     for (int q = 0; q < kVSlots; ++q) uo[(size_t)q * nM] = opened ? (F)0 : (F)U[q];
   }
   if (n0) atomicAdd(&s_n0, n0);
+  if (near0) atomicOr(&s_near0, 1);
 
   // optional full post-switch base flows
   if (base_out) {
@@ -542,6 +546,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     inf->n_act_pad = n_act + (n_act & 1);
     inf->n_island = s_nisl;
     inf->n_crit_n0 = s_n0;
+    inf->near0 = s_near0;
     for (int q = 0; q < kMaxRank; ++q) inf->open_br[q] = q < k ? sh.open[q] : -1;
   }
 }
@@ -675,9 +680,10 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
   bool opened = false;
   for (int q = 0; q < k; ++q) opened |= (inf->open_br[q] == e);
   double so = 0.0, best = -1.0, best2 = -1.0;
-  int cc = 0, bt = 0, be = ei;
+  int cc = 0, bt = 0, be = ei, near = 0;
   if (valid) {
     const double lim = g.lim[e];
+    const double mg = decision_margin(g);
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
       if (t < T) {
@@ -687,6 +693,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
         const double ov = fm - lim;
         if (ov > 0.0) so += ov;
         cc += fm > lim;
+        near |= fabs(fm - lim) <= mg;
         const double ratio = fm / lim;
         if (ratio > best) { best2 = best; best = ratio; bt = t; }
         else if (ratio > best2) best2 = ratio;
@@ -700,6 +707,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
   for (int off = 32; off > 0; off >>= 1) {
     so += __shfl_xor(so, off);
     cc += __shfl_xor(cc, off);
+    near |= __shfl_xor(near, off);
     const double b2 = __shfl_xor(best, off), s2 = __shfl_xor(best2, off);
     const int e2 = __shfl_xor(be, off), t2 = __shfl_xor(bt, off);
     const bool take = b2 > best || (b2 == best && e2 < be);
@@ -712,7 +720,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
     if (tid == 0) {
       Partial p;
       p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
-      p.pad_ = 0;
+      p.near = near;
       *out = p;
     }
   } else {
@@ -720,7 +728,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
     if ((tid & 63) == 0) {
       Partial p;
       p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
-      p.pad_ = 0;
+      p.near = near;
       s_p[tid >> 6] = p;
     }
     __syncthreads();
@@ -729,6 +737,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
       for (int q = 1; q < NW; ++q) {
         p.sum_o += s_p[q].sum_o;
         p.cnt_c += s_p[q].cnt_c;
+        p.near |= s_p[q].near;
         const bool take = s_p[q].best > p.best;
         p.best2 = fmax(fmax(p.best2, s_p[q].best2), take ? p.best : s_p[q].best);
         if (take) { p.best = s_p[q].best; p.best_e = s_p[q].best_e; p.best_t = s_p[q].best_t; }
@@ -851,19 +860,20 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     return;
   }
   __shared__ double s_sum, s_best, s_best2;
-  __shared__ int s_cc, s_be, s_bt;
+  __shared__ int s_cc, s_be, s_bt, s_near;
   if (lane == 0) {
     double so = 0.0, best = -1.0, best2 = -1.0;
-    int cc = 0, be = -1, bt = 0;
+    int cc = 0, be = -1, bt = 0, nr = 0;
     const Partial* p = w.part + (size_t)c * w.n_eblk;
     for (int b = 0; b < w.n_eblk; ++b) {
       so += p[b].sum_o;
       cc += p[b].cnt_c;
+      nr |= p[b].near;
       const bool take = p[b].best > best;
       best2 = fmax(fmax(best2, p[b].best2), take ? best : p[b].best);
       if (take) { best = p[b].best; be = p[b].best_e; bt = p[b].best_t; }
     }
-    s_sum = so; s_best = best; s_best2 = best2; s_cc = cc; s_be = be; s_bt = bt;
+    s_sum = so; s_best = best; s_best2 = best2; s_cc = cc; s_be = be; s_bt = bt; s_near = nr;
   }
   __syncthreads();
   const int be = s_be, bt = s_bt;
@@ -909,11 +919,13 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     const int* act = w.act + (size_t)c * (nC + 1);
     uint8_t st = (uint8_t)inf.status | refined;
     if (rc.list && be >= 0) {
+      const double mg = decision_margin(g);
       const double lim_e = g.lim[g.mon[be]];
-      bool near = (best - s_best2) * g.lim_min <= rc.margin;          // runner-up (e, t)
-      near |= (inf.n_act > 1 && bv - v2 <= 2.0 * rc.margin);           // runner-up l
+      bool near = (best - s_best2) * g.lim_min <= mg;                  // runner-up (e, t)
+      near |= (inf.n_act > 1 && bv - v2 <= 2.0 * mg);                  // runner-up l
       for (int q = 0; q < g.n_load_bins - 1; ++q)                      // load-bin edge
-        near |= fabs(best - g.edges[q]) * lim_e <= rc.margin;
+        near |= fabs(best - g.edges[q]) * lim_e <= mg;
+      near |= s_near != 0 || inf.near0 != 0;                           // a limit (lambda_c, lambda_c0)
       if (near) {
         const int slot = atomicAdd(rc.count, 1);
         if (slot < rc.cap) rc.list[slot] = c;
@@ -1082,7 +1094,9 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
   RefineCtl main_rc = rc;
   if (!refine) main_rc.list = nullptr;
   if (refine) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, rc.count);
-  launch_pass<F, TT>(g, bt, w, o, s, ev, plan, main_rc);
+  GridDev gm = g;
+  gm.near_margin = refine ? rc.margin : -1.0;
+  launch_pass<F, TT>(gm, bt, w, o, s, ev, plan, main_rc);
   if (o.n1_flows) {
     const F* HMC;
     if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
@@ -1105,6 +1119,7 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     rp.persistent = 0;
     GridDev gh = g;
     gh.f0 = g.f0_hi;   // FP64-GEMM base flows
+    gh.near_margin = -1.0;
     launch_pass<double, TT>(gh, rb, *rw, ro, s, nullptr, rp, none);
   }
   if (ev) hipEventRecord(ev[4], s);

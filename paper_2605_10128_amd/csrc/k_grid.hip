@@ -87,38 +87,54 @@ __device__ inline unsigned short f32_to_bf16_rne(float f) {
   return (unsigned short)(u >> 16);
 }
 
+__device__ inline float bf16_bits_to_f32(unsigned short h) {
+  return __uint_as_float((unsigned int)h << 16);
+}
+
+// Element i of a padded operand in the GEMM precision.  The split modes keep
+// two planes of 16-bit values, hi = round(v) and lo = round(v - hi), the lo
+// plane `plane` elements after the hi plane.
 template <int PREC>
-__device__ inline void store_prec(void* out, size_t i, double v) {
+__device__ inline void store_prec(void* out, size_t i, double v, size_t plane) {
   if constexpr (PREC == TTO_GEMM_F64) {
     ((double*)out)[i] = v;
   } else if constexpr (PREC == TTO_GEMM_F32) {
     ((float*)out)[i] = (float)v;
   } else if constexpr (PREC == TTO_GEMM_BF16) {
     ((unsigned short*)out)[i] = f32_to_bf16_rne((float)v);
-  } else {
+  } else if constexpr (PREC == TTO_GEMM_F16) {
     ((_Float16*)out)[i] = (_Float16)(float)v;
+  } else if constexpr (PREC == TTO_GEMM_BF16X3) {
+    const unsigned short hi = f32_to_bf16_rne((float)v);
+    const double rest = v - (double)bf16_bits_to_f32(hi);
+    ((unsigned short*)out)[i] = hi;
+    ((unsigned short*)out)[plane + i] = f32_to_bf16_rne((float)rest);
+  } else {
+    const _Float16 hi = (_Float16)(float)v;
+    ((_Float16*)out)[i] = hi;
+    ((_Float16*)out)[plane + i] = (_Float16)(float)(v - (double)(float)hi);
   }
 }
 
 // Padded copy of the PTDF in the GEMM precision: [m_pad][ld], zeros outside.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_convert_ptdf(const double* __restrict__ ptdf, int m,
-                                                      int n, int ld, void* out) {
+                                                      int n, int ld, void* out, size_t plane) {
   const int row = blockIdx.y;
   for (int k = blockIdx.x * 256 + threadIdx.x; k < ld; k += gridDim.x * 256) {
     const double v = (row < m && k < n) ? ptdf[(size_t)row * n + k] : 0.0;
-    store_prec<PREC>(out, (size_t)row * ld + k, v);
+    store_prec<PREC>(out, (size_t)row * ld + k, v, plane);
   }
 }
 
 // Injections transposed and padded: PT[t][k] for t < kGemmN, k < ld.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_pack_injections(const double* __restrict__ p, int n,
-                                                         int T, int ld, void* out) {
+                                                         int T, int ld, void* out, size_t plane) {
   const int t = blockIdx.y;
   for (int k = blockIdx.x * 256 + threadIdx.x; k < ld; k += gridDim.x * 256) {
     const double v = (t < T && k < n) ? p[(size_t)k * T + t] : 0.0;
-    store_prec<PREC>(out, (size_t)t * ld + k, v);
+    store_prec<PREC>(out, (size_t)t * ld + k, v, plane);
   }
 }
 
@@ -132,7 +148,8 @@ template <int PREC>
 __global__ __launch_bounds__(64) void k_gemm_f0(const void* __restrict__ Av,
                                                 const void* __restrict__ PTv, int m, int ld,
                                                 int T, int kchunk, float* __restrict__ part32,
-                                                double* __restrict__ part64) {
+                                                double* __restrict__ part64, size_t a_plane,
+                                                size_t p_plane) {
   const int lane = threadIdx.x;
   const int li = lane & 15, lg = lane >> 4;
   const int row0 = blockIdx.x * 16;
@@ -184,6 +201,35 @@ __global__ __launch_bounds__(64) void k_gemm_f0(const void* __restrict__ Av,
         c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b1.z, c1, 0, 0, 0);
         c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b0.w, c0, 0, 0, 0);
         c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b1.w, c1, 0, 0, 0);
+      }
+    } else if constexpr (PREC == TTO_GEMM_BF16X3 || PREC == TTO_GEMM_F16X3) {
+      // (A_hi + A_lo)(P_hi + P_lo) without the lo*lo term: three products
+      const unsigned short* A = (const unsigned short*)Av;
+      const unsigned short* PT = (const unsigned short*)PTv;
+      for (int k = k0 + 8 * lg; k < k1; k += 32) {
+        const v8u16 ah = *(const v8u16*)(A + arow + k);
+        const v8u16 al = *(const v8u16*)(A + a_plane + arow + k);
+        const v8u16 ph = *(const v8u16*)(PT + b0row + k);
+        const v8u16 pl = *(const v8u16*)(PT + p_plane + b0row + k);
+        const v8u16 qh = *(const v8u16*)(PT + b1row + k);
+        const v8u16 ql = *(const v8u16*)(PT + p_plane + b1row + k);
+        if constexpr (PREC == TTO_GEMM_BF16X3) {
+          const v8bf16 AH = __builtin_bit_cast(v8bf16, ah), AL = __builtin_bit_cast(v8bf16, al);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, __builtin_bit_cast(v8bf16, ph), c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, __builtin_bit_cast(v8bf16, qh), c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, __builtin_bit_cast(v8bf16, pl), c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, __builtin_bit_cast(v8bf16, ql), c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, __builtin_bit_cast(v8bf16, ph), c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, __builtin_bit_cast(v8bf16, qh), c1, 0, 0, 0);
+        } else {
+          const v8f16 AH = __builtin_bit_cast(v8f16, ah), AL = __builtin_bit_cast(v8f16, al);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(AL, __builtin_bit_cast(v8f16, ph), c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(AL, __builtin_bit_cast(v8f16, qh), c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(AH, __builtin_bit_cast(v8f16, pl), c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(AH, __builtin_bit_cast(v8f16, ql), c1, 0, 0, 0);
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(AH, __builtin_bit_cast(v8f16, ph), c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(AH, __builtin_bit_cast(v8f16, qh), c1, 0, 0, 0);
+        }
       }
     } else {
       const unsigned short* A = (const unsigned short*)Av;
@@ -239,6 +285,29 @@ __global__ __launch_bounds__(256) void k_reduce_f0(const P* __restrict__ part, i
   f0[i] = s;
 }
 
+// out = max_i |a_i - b_i| (one workgroup; max is order independent).
+__global__ __launch_bounds__(1024) void k_max_abs_diff(const double* __restrict__ a,
+                                                       const double* __restrict__ b, size_t n,
+                                                       double* __restrict__ out) {
+  __shared__ double s_w[16];
+  double v = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += 1024) v = fmax(v, fabs(a[i] - b[i]));
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int q = 0; q < 16; ++q) m = fmax(m, s_w[q]);
+    *out = m;
+  }
+}
+
+hipError_t launch_max_abs_diff(const double* a, const double* b, size_t n, double* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_max_abs_diff, dim3(1), dim3(1024), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 hipError_t launch_build_S(const double* ptdf, const int* from, const int* to, const double* b,
@@ -269,11 +338,14 @@ hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void*
                                hipStream_t s) {
   const int ld = gemm_ld(n), mp = gemm_mpad(m);
   const dim3 grid(std::min(cdiv(ld, 256), 64), mp);
+  const size_t plane = (size_t)mp * ld;
   switch (prec) {
-    case TTO_GEMM_F64: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_F64>, grid, dim3(256), 0, s, ptdf, m, n, ld, out); break;
-    case TTO_GEMM_F32: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_F32>, grid, dim3(256), 0, s, ptdf, m, n, ld, out); break;
-    case TTO_GEMM_BF16: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_BF16>, grid, dim3(256), 0, s, ptdf, m, n, ld, out); break;
-    default: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_F16>, grid, dim3(256), 0, s, ptdf, m, n, ld, out); break;
+    case TTO_GEMM_F64: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_F64>, grid, dim3(256), 0, s, ptdf, m, n, ld, out, plane); break;
+    case TTO_GEMM_F32: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_F32>, grid, dim3(256), 0, s, ptdf, m, n, ld, out, plane); break;
+    case TTO_GEMM_BF16: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_BF16>, grid, dim3(256), 0, s, ptdf, m, n, ld, out, plane); break;
+    case TTO_GEMM_F16: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_F16>, grid, dim3(256), 0, s, ptdf, m, n, ld, out, plane); break;
+    case TTO_GEMM_BF16X3: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_BF16X3>, grid, dim3(256), 0, s, ptdf, m, n, ld, out, plane); break;
+    default: hipLaunchKernelGGL(k_convert_ptdf<TTO_GEMM_F16X3>, grid, dim3(256), 0, s, ptdf, m, n, ld, out, plane); break;
   }
   return hipGetLastError();
 }
@@ -282,11 +354,14 @@ hipError_t launch_pack_injections(const double* p, int n, int T, int prec, void*
                                   hipStream_t s) {
   const int ld = gemm_ld(n);
   const dim3 grid(std::min(cdiv(ld, 256), 64), kGemmN);
+  const size_t plane = (size_t)kGemmN * ld;
   switch (prec) {
-    case TTO_GEMM_F64: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_F64>, grid, dim3(256), 0, s, p, n, T, ld, PT); break;
-    case TTO_GEMM_F32: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_F32>, grid, dim3(256), 0, s, p, n, T, ld, PT); break;
-    case TTO_GEMM_BF16: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_BF16>, grid, dim3(256), 0, s, p, n, T, ld, PT); break;
-    default: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_F16>, grid, dim3(256), 0, s, p, n, T, ld, PT); break;
+    case TTO_GEMM_F64: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_F64>, grid, dim3(256), 0, s, p, n, T, ld, PT, plane); break;
+    case TTO_GEMM_F32: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_F32>, grid, dim3(256), 0, s, p, n, T, ld, PT, plane); break;
+    case TTO_GEMM_BF16: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_BF16>, grid, dim3(256), 0, s, p, n, T, ld, PT, plane); break;
+    case TTO_GEMM_F16: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_F16>, grid, dim3(256), 0, s, p, n, T, ld, PT, plane); break;
+    case TTO_GEMM_BF16X3: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_BF16X3>, grid, dim3(256), 0, s, p, n, T, ld, PT, plane); break;
+    default: hipLaunchKernelGGL(k_pack_injections<TTO_GEMM_F16X3>, grid, dim3(256), 0, s, p, n, T, ld, PT, plane); break;
   }
   return hipGetLastError();
 }
@@ -306,11 +381,14 @@ hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n,
   const int ld = gemm_ld(n);
   int kchunk = cdiv(cdiv(ld, ksplit), 64) * 64;
   const dim3 grid(gemm_mpad(m) / 16, ksplit);
+  const size_t ap = (size_t)gemm_mpad(m) * ld, pp = (size_t)kGemmN * ld;
   switch (prec) {
-    case TTO_GEMM_F64: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_F64>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64); break;
-    case TTO_GEMM_F32: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_F32>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64); break;
-    case TTO_GEMM_BF16: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_BF16>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64); break;
-    default: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_F16>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64); break;
+    case TTO_GEMM_F64: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_F64>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64, ap, pp); break;
+    case TTO_GEMM_F32: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_F32>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64, ap, pp); break;
+    case TTO_GEMM_BF16: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_BF16>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64, ap, pp); break;
+    case TTO_GEMM_F16: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_F16>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64, ap, pp); break;
+    case TTO_GEMM_BF16X3: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_BF16X3>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64, ap, pp); break;
+    default: hipLaunchKernelGGL(k_gemm_f0<TTO_GEMM_F16X3>, grid, dim3(64), 0, s, A, PT, m, ld, T, kchunk, part32, part64, ap, pp); break;
   }
   if (prec == TTO_GEMM_F64)
     hipLaunchKernelGGL(k_reduce_f0<double>, dim3(cdiv(m * T, 256)), dim3(256), 0, s, part64, m, T, ksplit, f0);

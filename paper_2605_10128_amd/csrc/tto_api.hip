@@ -57,8 +57,10 @@ struct Carver {
 
 int gemm_ld(int n) { return ((n + 63) / 64) * 64; }
 int gemm_mpad(int m) { return ((m + 15) / 16) * 16; }
+// Bytes per operand element (the split modes hold a hi and a lo plane).
 size_t gemm_esize(int prec) {
-  return prec == TTO_GEMM_F64 ? 8 : prec == TTO_GEMM_F32 ? 4 : 2;
+  return prec == TTO_GEMM_F64 ? 8 : (prec == TTO_GEMM_F32 || prec == TTO_GEMM_BF16X3 ||
+                                     prec == TTO_GEMM_F16X3) ? 4 : 2;
 }
 
 struct GridLayout {
@@ -66,8 +68,9 @@ struct GridLayout {
   double* S; double* SMC; float* HMC32; double* HMC64; double* f0;
   void* A; void* PT; float* part32; double* part64;
   int ksplit;
-  // FP64 copy of the base-flow product for the refinement of FP32 grids
-  double* f0_hi; void* A64; void* PT64; double* part_hi;
+  // FP64 copy of the base-flow product for the refinement of FP32 grids, and
+  // max |f0 - f0_hi| (device scalar)
+  double* f0_hi; void* A64; void* PT64; double* part_hi; double* gemm_err;
 };
 
 GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
@@ -100,11 +103,13 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   }
   if (d->gemm_precision == TTO_GEMM_F64 || d->flow_precision == TTO_FLOW_F64) {
     L.f0_hi = nullptr; L.A64 = nullptr; L.PT64 = nullptr; L.part_hi = nullptr;
+    L.gemm_err = nullptr;
   } else {
     L.f0_hi = cv.take<double>(m * T);
     L.A64 = cv.take<double>(mp * ld);
     L.PT64 = cv.take<double>((size_t)kGemmN * ld);
     L.part_hi = cv.take<double>((size_t)L.ksplit * m * kGemmN);
+    L.gemm_err = cv.take<double>(1);
   }
   (void)n;
   *bytes = cv.off;
@@ -173,7 +178,7 @@ tto_status check_desc(const tto_grid_desc* d) {
     return fail(TTO_E_INVALID, "n_contingency %d not in 0..n_branch", d->n_contingency);
   if (d->flow_precision != TTO_FLOW_F64 && d->flow_precision != TTO_FLOW_F32)
     return fail(TTO_E_INVALID, "flow_precision %d unknown", d->flow_precision);
-  if (d->gemm_precision < TTO_GEMM_F64 || d->gemm_precision > TTO_GEMM_F16)
+  if (d->gemm_precision < TTO_GEMM_F64 || d->gemm_precision > TTO_GEMM_F16X3)
     return fail(TTO_E_INVALID, "gemm_precision %d unknown", d->gemm_precision);
   if (d->max_batch < 1 || d->max_batch > 65535)
     return fail(TTO_E_INVALID, "max_batch %d not in 1..65535", d->max_batch);
@@ -297,6 +302,10 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, d->gemm_precision, L.A, s));
   if (L.A64) HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, TTO_GEMM_F64, L.A64, s));
   HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
+  if (L.f0_hi) {
+    HIP_TRY(hipMemsetAsync(L.f0_hi, 0, sizeof(double) * m * d->n_timesteps, s));
+    HIP_TRY(hipMemsetAsync(L.gemm_err, 0, sizeof(double), s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
 
   tto_grid* g = new tto_grid();
@@ -313,6 +322,8 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S; v.SMC = L.SMC;
   v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.f0_hi = L.f0_hi ? L.f0_hi : L.f0; v.mon = L.mon; v.cont = L.cont;
   v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
+  v.near_margin = -1.0;
+  v.gemm_err = L.gemm_err;
   v.lim_min = 1e300;
   for (int i = 0; i < d->n_monitored; ++i) v.lim_min = std::min(v.lim_min, d->limit_mw[d->monitored[i]]);
   *out = g;
@@ -357,6 +368,7 @@ tto_status tto_set_injections(tto_grid* g, const double* p_mw, void* stream) {
     HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, TTO_GEMM_F64, g->L.PT64, s));
     HIP_TRY(launch_gemm_f0(TTO_GEMM_F64, g->L.A64, g->L.PT64, g->m, g->n_bus, g->T, g->L.ksplit,
                            nullptr, g->L.part_hi, g->L.f0_hi, s));
+    HIP_TRY(launch_max_abs_diff(g->L.f0, g->L.f0_hi, (size_t)g->m * g->T, g->L.gemm_err, s));
   }
   return ok();
 }

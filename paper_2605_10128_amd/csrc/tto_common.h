@@ -52,7 +52,18 @@ struct GridDev {
   double lim_min;       // smallest monitored limit
   int n_count_bins, n_load_bins;
   double w_c0, w_c;
+  // Decision margin of an FP32 pass that queues FP64 refinement (< 0: none):
+  // near_margin + 4 max|f0 - f0_hi| MW, the second term read from gemm_err
+  // (device scalar written with the base flows; NULL when f0 is FP64).
+  double near_margin;
+  const double* gemm_err;
 };
+
+// Decision margin in MW of the current pass (negative: no refinement).
+__device__ inline double decision_margin(const GridDev& g) {
+  if (g.near_margin < 0.0) return -1.0;
+  return g.near_margin + (g.gemm_err ? 4.0 * *g.gemm_err : 0.0);
+}
 
 struct BatchDev {
   int B, no, ns;
@@ -84,7 +95,7 @@ struct CandInfo {
   int n_act_pad;   // n_act rounded up to even (duplicate of the last record)
   int n_island;    // islanding contingencies
   int n_crit_n0;   // lambda_c0 from the FP64 post-switch flows
-  int pad_;
+  int near0;       // some |f'| lies within the decision margin of its limit
   int open_br[kMaxRank];
 };
 
@@ -96,7 +107,7 @@ struct Partial {
   int cnt_c;        // fmax > lim count
   int best_e;       // monitored index of the max (smallest on ties)
   int best_t;
-  int pad_;
+  int near;         // some fmax lies within the decision margin of its limit
 };
 
 // Batch workspace views (carved from the caller's batch workspace).
@@ -133,6 +144,8 @@ hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void*
 hipError_t launch_pack_injections(const double* p, int n, int T, int prec, void* PT, hipStream_t s);
 hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n, int T,
                           int ksplit, float* part32, double* part64, double* f0, hipStream_t s);
+hipError_t launch_max_abs_diff(const double* a, const double* b, size_t n, double* out,
+                               hipStream_t s);
 int gemm_ksplit(int m, int n);
 
 // ---- launchers (k_eval.hip) -------------------------------------------------

@@ -18,6 +18,7 @@ TTO_OK = 0
 TTO_E_INVALID, TTO_E_GRID, TTO_E_RANK, TTO_E_WORKSPACE, TTO_E_HIP, TTO_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 TTO_FLOW_F64, TTO_FLOW_F32 = 0, 1
 TTO_GEMM_F64, TTO_GEMM_F32, TTO_GEMM_BF16, TTO_GEMM_F16 = 0, 1, 2, 3
+TTO_GEMM_BF16X3, TTO_GEMM_F16X3 = 4, 5
 TTO_ST_ISLANDED, TTO_ST_INVALID, TTO_ST_REFINED, TTO_ST_REFINE_SKIPPED = 1, 2, 4, 8
 TTO_MAX_RANK, TTO_MAX_T, TTO_MAX_MOVED, TTO_MAX_LOAD_BINS = 8, 32, 64, 64
 

@@ -37,6 +37,7 @@ def test_base_flows_all_gemm_precisions(tto):
         ref = oracle.solve_flows(w.grid.n_bus, w.grid.from_bus, w.grid.to_bus, b,
                                  np.ones(w.grid.n_branch, bool), w.P, 0)
         for gemm, tol in ((tto.TTO_GEMM_F64, 1e-8), (tto.TTO_GEMM_F32, 5e-2),
+                          (tto.TTO_GEMM_BF16X3, 1.0), (tto.TTO_GEMM_F16X3, 1.0),
                           (tto.TTO_GEMM_F16, 10.0), (tto.TTO_GEMM_BF16, 100.0)):
             log(f"[base flows] cfg{cfg} gemm={gemm}")
             s = make_session(w, tto.TTO_FLOW_F64, gemm)

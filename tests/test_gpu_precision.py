@@ -1,0 +1,126 @@
+"""Precision of the GPU path on the 6000-bus / 9500-branch, 24-step grid
+(2000 monitored x 3000 contingencies), through the C ABI.
+
+Base flows in every GEMM mode against the oracle's from-scratch N-0 solve;
+sampled N-1 flows of a few candidates against oracle re-solves at full size;
+and, per GEMM mode with FP32 flows, the N-1 maxima and discrete outputs of a
+candidate batch against the FP64 path.  Errors are reported in MW (max, p99).
+"""
+import numpy as np
+import pytest
+
+import gridgen as gg
+from parity_util import TOL_F32, TOL_F64, log, make_session, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+TARGET_MW = 1.0      # stated flow error target of the reduced-precision modes
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_10128_amd import tto
+    log("[precision] building the 6000-bus workload")
+    w = gg.build_config(4, B=512)
+    import oracle
+    b = 1.0 / w.grid.x_pu
+    f0_ref = oracle.solve_flows(w.grid.n_bus, w.grid.from_bus, w.grid.to_bus, b,
+                                np.ones(w.grid.n_branch, bool), w.P, 0)
+    return tto, w, f0_ref
+
+
+def _modes(tto):
+    return [("f32", tto.TTO_GEMM_F32, TARGET_MW), ("bf16x3", tto.TTO_GEMM_BF16X3, TARGET_MW),
+            ("f16x3", tto.TTO_GEMM_F16X3, TARGET_MW), ("bf16", tto.TTO_GEMM_BF16, None),
+            ("f16", tto.TTO_GEMM_F16, None)]
+
+
+def test_base_flows_6000_bus_every_mode(env):
+    import torch
+    tto, w, f0_ref = env
+    for name, gemm, tol in [("f64", tto.TTO_GEMM_F64, TOL_F64)] + _modes(tto):
+        s = make_session(w, tto.TTO_FLOW_F64 if gemm == tto.TTO_GEMM_F64 else tto.TTO_FLOW_F32,
+                         gemm, max_batch=8)
+        f0 = s.base_flows().cpu().numpy()
+        torch.cuda.synchronize()
+        d = np.abs(f0 - f0_ref)
+        log(f"[precision] base flows {name}: max {d.max():.3e} MW, p99 {np.quantile(d, 0.99):.3e} MW")
+        if tol is not None:
+            assert d.max() <= tol, name
+        s.close()
+
+
+def test_sampled_n1_flows_against_oracle_6000_bus(env):
+    """Four candidates with splits and openings: N-0 flows and the N-1 flows of
+    12 contingencies each, FP64 and FP32 paths against oracle re-solves."""
+    import torch
+    import oracle
+    tto, w, _ = env
+    r = (w.batch.open >= 0).sum(1) + (w.batch.split_bus >= 0).sum(1)
+    ns = (w.batch.split_bus >= 0).sum(1)
+    pick = [int(c) for c in np.flatnonzero((r >= 4) & (ns >= 1))[:4]]
+    sub = w.batch.subset(pick)
+    ws = gg.Workload(cfg=4, grid=w.grid, P=w.P, M=w.M, C=w.C, batch=sub,
+                     split_table=w.split_table)
+    rng = np.random.default_rng(7)
+    positions = sorted(rng.choice(len(w.C), size=12, replace=False).tolist())
+    cands = [oracle.candidate_from_batch(sub, i) for i in range(len(pick))]
+    edges = gg.default_load_edges()
+    ores = [oracle.evaluate_candidate(w.grid, w.P, w.M, w.C, cd, edges, keep_n1=True,
+                                      cont_subset=positions) for cd in cands]
+    for flow, tol in ((tto.TTO_FLOW_F64, TOL_F64), (tto.TTO_FLOW_F32, TOL_F32)):
+        s = make_session(ws, flow, max_batch=len(pick))
+        out = to_numpy(s.evaluate(tto.device_batch(sub), base_flows=True, n1=True))
+        torch.cuda.synchronize()
+        worst0 = worst1 = 0.0
+        for i, res in enumerate(ores):
+            if res.islanded:
+                assert out["status"][i] & 1
+                continue
+            assert out["status"][i] & 3 == 0
+            d0 = np.abs(out["base_flows"][i] - res.base_flows).max()
+            worst0 = max(worst0, d0)
+            for li in positions:
+                a, b = out["n1_flows"][i][li], res.n1_flows[li]
+                assert np.array_equal(np.isnan(a), np.isnan(b))
+                if not np.isnan(b).any():
+                    worst1 = max(worst1, np.abs(a - b).max())
+        log(f"[precision] sampled oracle, flow={'f64' if flow == 0 else 'f32'}: "
+            f"N-0 max {worst0:.3e} MW, N-1 max {worst1:.3e} MW over {len(positions)} contingencies")
+        assert worst0 <= tol and worst1 <= tol
+        s.close()
+
+
+def test_modes_against_fp64_path_6000_bus(env):
+    """512 candidates: f^max error per GEMM mode (FP32 flows) against the FP64
+    path, refinement counts, and discrete outputs for refined/unflagged
+    candidates."""
+    import torch
+    tto, w, _ = env
+    db = tto.device_batch(w.batch)
+    s64 = make_session(w, tto.TTO_FLOW_F64, tto.TTO_GEMM_F64)
+    ref = to_numpy(s64.evaluate(db, fmax=True))
+    torch.cuda.synchronize()
+    s64.close()
+    ok = (ref["status"] & 3) == 0
+    for name, gemm, tol in [("f32", tto.TTO_GEMM_F32, TARGET_MW)] + _modes(tto)[1:]:
+        s = make_session(w, tto.TTO_FLOW_F32, gemm)
+        out = to_numpy(s.evaluate(db, fmax=True))
+        torch.cuda.synchronize()
+        s.close()
+        assert np.array_equal(out["status"] & 3, ref["status"] & 3), name
+        d = np.abs(out["fmax"][ok] - ref["fmax"][ok])
+        refined = int(((out["status"] & 4) != 0).sum())
+        skipped = (out["status"] & 8) != 0
+        trust = ok & ~skipped
+        mism = {k: int((out[k][trust] != ref[k][trust]).sum())
+                for k in ("cell", "worst_branch", "worst_t", "n_crit_n1", "n_crit_n0")}
+        log(f"[precision] {name}: fmax max {d.max():.3e} MW p99 {np.quantile(d, 0.99):.3e} MW; "
+            f"refined {refined}, skipped {int(skipped.sum())} of {int(ok.sum())}; "
+            f"discrete mismatches outside skipped {mism}")
+        if tol is not None:
+            assert d.max() <= tol, name
+            assert all(v == 0 for v in mism.values()), (name, mism)
