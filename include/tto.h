@@ -354,8 +354,11 @@ typedef struct {
   int32_t d_dense;           /* dense inputs, 0..64 */
   int32_t width;             /* hidden width: multiple of 64 in 64..2048 */
   int32_t max_batch;         /* largest forward batch */
-  int32_t max_train_batch;   /* largest training / gradient batch */
+  int32_t max_train_batch;   /* largest training / gradient batch, 1..TTO_MLP_MAX_TRAIN */
 } tto_mlp_desc;
+
+#define TTO_MLP_MAX_ROW_BITS 64   /* entries read per bitmask row */
+#define TTO_MLP_MAX_TRAIN 4096
 
 /* Device workspace sizes: parameters + Adam state (persistent) and batch
  * scratch (per call).  Host only. */
@@ -372,8 +375,9 @@ tto_status tto_mlp_set_params(tto_mlp* mlp, const float* params, void* stream);
 tto_status tto_mlp_get_params(tto_mlp* mlp, float* params, void* stream);
 /* y[B][2] for B candidates: bits_off [B+1] and bits_idx (device CSR; the
  * offsets must be non-decreasing and index inside bits_idx, which is the
- * caller's duty; ids distinct within a row; ids outside [0, d_bits) are
- * ignored), dense [B][d_dense] (device, may be NULL iff d_dense == 0). */
+ * caller's duty).  A row's bit set is the distinct ids in [0, d_bits) among
+ * its first TTO_MLP_MAX_ROW_BITS entries (repeats and other ids are
+ * ignored).  dense [B][d_dense] (device, may be NULL iff d_dense == 0). */
 tto_status tto_mlp_forward(tto_mlp* mlp, const int32_t* bits_off, const int32_t* bits_idx,
                            const float* dense, int32_t n, float* y, void* batch_ws,
                            size_t batch_bytes, void* stream);

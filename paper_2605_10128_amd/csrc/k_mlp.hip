@@ -9,6 +9,8 @@
 
 #include <limits.h>
 
+#include <algorithm>
+
 namespace tto {
 
 typedef float v4f32m __attribute__((ext_vector_type(4)));
@@ -126,6 +128,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const unsigned short* __restr
       }
 }
 
+// A row's bit set: the distinct ids in [0, d_bits) among its first
+// kMlpRowBits entries (repeats and out-of-range ids are ignored).
+__device__ inline bool row_bit_ok(const int* __restrict__ idx, int lo, int p, int i, int d_bits) {
+  if (i < 0 || i >= d_bits) return false;
+  for (int q = lo; q < p; ++q)
+    if (idx[q] == i) return false;
+  return true;
+}
+
 // First layer (embedding bag): z1[b][j] = b1[j] + sum_d dense[b][d] W1d[d][j]
 // + sum_{i in bits(b)} W1b[i][j] (BF16 weights, FP32 sum); h1 = relu(z1).
 __global__ __launch_bounds__(256) void k_mlp_l1(const int* __restrict__ off,
@@ -141,9 +152,10 @@ __global__ __launch_bounds__(256) void k_mlp_l1(const int* __restrict__ off,
   for (int j = threadIdx.x; j < H; j += 256) {
     float z = b1[j];
     for (int d = 0; d < d_dense; ++d) z += dense[(size_t)b * d_dense + d] * bf16_to_f(W1d[(size_t)d * H + j]);
-    for (int p = lo; p < hi; ++p) {
+    const int end = min(hi, lo + kMlpRowBits);
+    for (int p = lo; p < end; ++p) {
       const int i = idx[p];
-      if (i >= 0 && i < d_bits) z += bf16_to_f(W1b[(size_t)i * H + j]);   // others ignored
+      if (row_bit_ok(idx, lo, p, i, d_bits)) z += bf16_to_f(W1b[(size_t)i * H + j]);
     }
     h1[(size_t)b * H + j] = bf16_rne(z > 0.f ? z : 0.f);
   }
@@ -226,19 +238,86 @@ __global__ __launch_bounds__(256) void k_colsum(const T* __restrict__ x, int B, 
   out[j] = s;
 }
 
-// Dense views for the first-layer gradients: X[b][i] = 1 for i in bits(b)
-// (BF16 0/1, exact) and the dense inputs in BF16.
-__global__ __launch_bounds__(256) void k_bits_dense(const int* __restrict__ off,
-                                                    const int* __restrict__ idx, int B, int d_bits,
-                                                    unsigned short* __restrict__ X) {
-  const int b = blockIdx.x;
-  for (int i = threadIdx.x; i < d_bits; i += 256) X[(size_t)b * d_bits + i] = 0;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int p = off[b]; p < off[b + 1]; ++p) {
+// First-layer weight gradient gW1b[i] = sum of dz1[b] over the samples b
+// whose bit set holds i.  The (bit, sample) pairs are bucketed by bit
+// (count, exclusive scan, fill); each bit's bucket is then put in sample
+// order in LDS and summed in that order, so the result is deterministic.
+__global__ __launch_bounds__(256) void k_zero_i32(int* __restrict__ p, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_bits_bucket(const int* __restrict__ off,
+                                                     const int* __restrict__ idx, int B,
+                                                     int d_bits, int* __restrict__ cnt,
+                                                     int* __restrict__ list) {
+  for (int b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
+    const int lo = off[b], end = min(off[b + 1], lo + kMlpRowBits);
+    for (int p = lo; p < end; ++p) {
       const int i = idx[p];
-      if (i >= 0 && i < d_bits) X[(size_t)b * d_bits + i] = 0x3F80;   // 1.0
+      if (!row_bit_ok(idx, lo, p, i, d_bits)) continue;
+      const int pos = atomicAdd(&cnt[i], 1);
+      if constexpr (FILL) list[pos] = b;
     }
+  }
+}
+
+// Exclusive scan of cnt[0..n) into start[0..n] and cursor[0..n) (one workgroup).
+__global__ __launch_bounds__(1024) void k_scan_counts(const int* __restrict__ cnt, int n,
+                                                      int* __restrict__ start,
+                                                      int* __restrict__ cursor) {
+  __shared__ int s_w[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < n; i0 += 1024) {
+    const int i = i0 + tid;
+    const int v = i < n ? cnt[i] : 0;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(x, o);
+      if (lane >= o) x += u;
+    }
+    if (lane == 63) s_w[wid] = x;
+    __syncthreads();
+    int pre = s_base;
+    for (int q = 0; q < wid; ++q) pre += s_w[q];
+    if (i < n) { start[i] = pre + x - v; cursor[i] = pre + x - v; }
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int q = 0; q < 16; ++q) t += s_w[q];
+      s_base += t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) start[n] = s_base;
+}
+
+__global__ __launch_bounds__(256) void k_w1b_grad(const int* __restrict__ start,
+                                                  const int* __restrict__ list,
+                                                  const unsigned short* __restrict__ dz1, int H,
+                                                  float* __restrict__ g) {
+  __shared__ int s_in[kMlpMaxTrain];
+  __shared__ int s_sorted[kMlpMaxTrain];
+  const int i = blockIdx.x;
+  const int lo = start[i], L = min(start[i + 1] - lo, kMlpMaxTrain);
+  for (int q = threadIdx.x; q < L; q += 256) s_in[q] = list[lo + q];
+  __syncthreads();
+  // rank of each entry among the bucket by sample id (sample ids are distinct)
+  for (int q = threadIdx.x; q < L; q += 256) {
+    const int v = s_in[q];
+    int rank = 0;
+    for (int u = 0; u < L; ++u) rank += s_in[u] < v;
+    s_sorted[rank] = v;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < H; j += 256) {
+    float acc = 0.f;
+    for (int q = 0; q < L; ++q) acc += bf16_to_f(dz1[(size_t)s_sorted[q] * H + j]);
+    g[(size_t)i * H + j] = acc;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ x, size_t n,
@@ -470,8 +549,14 @@ void mlp_gradients(const MlpDev& p, const MlpBatch& wb, const int* off, const in
   // layer 1: gW1b = X^T dz1 over the 0/1 bitmask, gW1d = dense^T dz1
   hipLaunchKernelGGL(k_colsum<unsigned short>, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.dz1, B,
                      H, g.b1);
-  hipLaunchKernelGGL(k_bits_dense, dim3(B), dim3(256), 0, s, off, idx, B, db, wb.X);
-  gemm<true, false, 0>(wb.X, wb.dz1, db, H, B, g.W1b, nullptr, nullptr, nullptr, s);
+  const int nb = std::min(cdiv_m(B, 256), 1024);
+  hipLaunchKernelGGL(k_zero_i32, dim3(std::min(cdiv_m(db, 256), 1024)), dim3(256), 0, s, wb.cnt, db);
+  hipLaunchKernelGGL((k_bits_bucket<false>), dim3(nb), dim3(256), 0, s, off, idx, B, db, wb.cnt,
+                     (int*)nullptr);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, wb.cnt, db, wb.start, wb.cursor);
+  hipLaunchKernelGGL((k_bits_bucket<true>), dim3(nb), dim3(256), 0, s, off, idx, B, db,
+                     wb.cursor, wb.list);
+  hipLaunchKernelGGL(k_w1b_grad, dim3(db), dim3(256), 0, s, wb.start, wb.list, wb.dz1, H, g.W1b);
   if (dd > 0) {
     hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)B * dd, 256)), dim3(256), 0, s, dense,
                        (size_t)B * dd, wb.Xd);

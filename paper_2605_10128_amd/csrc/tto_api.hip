@@ -633,7 +633,10 @@ MlpBatch carve_mlp_batch(const tto_mlp_desc* d, void* ws, size_t* bytes) {
   b.dz1 = cv.take<unsigned short>(Bt * H);
   b.dz2 = cv.take<unsigned short>(Bt * H);
   b.dz3 = cv.take<unsigned short>(Bt * H);
-  b.X = cv.take<unsigned short>(Bt * (size_t)d->d_bits);
+  b.cnt = cv.take<int>((size_t)d->d_bits);
+  b.start = cv.take<int>((size_t)d->d_bits + 1);
+  b.cursor = cv.take<int>((size_t)d->d_bits);
+  b.list = cv.take<int>(Bt * (size_t)kMlpRowBits);
   b.Xd = cv.take<unsigned short>(std::max(Bt * (size_t)d->d_dense, (size_t)1));
   b.y = cv.take<float>(Ba * 2);
   b.dy = cv.take<float>(Bt * 2);
@@ -648,6 +651,8 @@ tto_status check_mlp_desc(const tto_mlp_desc* d) {
   if (d->d_dense < 0 || d->d_dense > 64) return fail(TTO_E_INVALID, "d_dense must be in 0..64");
   if (d->width < 64 || d->width > 2048 || d->width % 64) return fail(TTO_E_INVALID, "width must be a multiple of 64 in 64..2048");
   if (d->max_batch < 1 || d->max_train_batch < 1) return fail(TTO_E_INVALID, "batch sizes must be >= 1");
+  if (d->max_train_batch > kMlpMaxTrain)
+    return fail(TTO_E_INVALID, "max_train_batch must be <= %d", kMlpMaxTrain);
   return TTO_OK;
 }
 

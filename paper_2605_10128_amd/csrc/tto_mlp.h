@@ -6,6 +6,9 @@
 
 namespace tto {
 
+constexpr int kMlpRowBits = 64;      // bits read per row (TTO_MLP_MAX_ROW_BITS)
+constexpr int kMlpMaxTrain = 4096;   // largest training batch (TTO_MLP_MAX_TRAIN)
+
 // Parameters: FP32 master copy (flat: W1b, W1d, b1, W2, b2, W3, b3, W4, b4),
 // Adam moments, BF16 copies of the matrices used as MFMA / gather operands.
 struct MlpDev {
@@ -56,7 +59,10 @@ inline size_t mlp_param_count(int d_bits, int d_dense, int H) {
 struct MlpBatch {
   unsigned short *h1, *h2, *h3;      // [B][H] BF16 activations
   unsigned short *dz1, *dz2, *dz3;   // [B][H] BF16 back-propagated pre-activation grads
-  unsigned short* X;                 // [B][d_bits] 0/1 bitmask
+  int* cnt;                          // [d_bits] bucket sizes of the first-layer gradient
+  int* start;                        // [d_bits + 1] bucket offsets
+  int* cursor;                       // [d_bits] fill cursors
+  int* list;                         // [B * kMlpRowBits] samples per bit
   unsigned short* Xd;                // [B][d_dense] BF16 dense inputs
   float* y;                          // [B][2]
   float* dy;                         // [B][2]
