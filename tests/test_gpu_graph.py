@@ -54,8 +54,8 @@ def test_evaluate_graph_replays_match_eager(flow):
             torch.cuda.synchronize()
             got = _np(out)
             for k in ref:
-                assert np.array_equal(got[k], ref[k]), (rep, k)
-                assert np.array_equal(eager[k], ref[k]), (rep, k)
+                assert np.array_equal(got[k], ref[k], equal_nan=True), (rep, k)
+                assert np.array_equal(eager[k], ref[k], equal_nan=True), (rep, k)
             assert np.array_equal(arc[0].cpu().numpy(), a_ref[0]), rep
             assert np.array_equal(arc[1].cpu().numpy(), a_ref[1]), rep
     finally:
@@ -130,7 +130,7 @@ def test_screen_pipeline_graph_matches_eager():
             assert np.array_equal(sc.y[:n].cpu().numpy(), y_ref), rep
             got = _np(o2)
             for name in ref:
-                assert np.array_equal(got[name], ref[name]), (rep, name)
+                assert np.array_equal(got[name], ref[name], equal_nan=True), (rep, name)
     finally:
         g.close()
     log("  3 replays of forward + top-k + gather + evaluate identical to eager")

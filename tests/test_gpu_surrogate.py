@@ -229,7 +229,7 @@ def test_batch_gather_matches_host_subset_and_evaluation():
             gs = g_split.cpu().numpy()
             assert np.array_equal(gs[ok_rows], sub.split_bus[ok_rows])
         for name in full:
-            assert np.array_equal(got[name][ok_rows], full[name][idx][ok_rows]), name
+            assert np.array_equal(got[name][ok_rows], full[name][idx][ok_rows], equal_nan=True), name
         log(f"  cap={cap}: {ok_rows.sum()} of {k} rows identical to the full evaluation")
 
 
@@ -298,7 +298,7 @@ def test_surrogate_trains_and_screens_a_generation():
     # the survivors' exact results are those of the full exact pass
     same = ((got["status"] | exact["status"][idx]) & 8) == 0
     for name in ("status", "cell", "fitness", "overload_mw", "max_loading", "worst_branch"):
-        assert np.array_equal(got[name][same], exact[name][idx][same]), name
+        assert np.array_equal(got[name][same], exact[name][idx][same], equal_nan=True), name
     # prediction error on the unseen scenario
     y = sc.y[:n_gen].cpu().numpy()
     valid = (exact["status"] & 3) == 0
