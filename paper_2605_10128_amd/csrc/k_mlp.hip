@@ -25,6 +25,44 @@ __device__ inline unsigned short bf16_rne(float f) {
 __device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // ---------------------------------------------------------------------------
+// Stage a 64 x 32 operand tile into LDS as T[r][k] (k contiguous, row stride
+// 40 halfwords so every 8-element fragment is one aligned 16-byte access).
+// ROWK: the operand is stored [rows][ld] with k contiguous (global row r0+i,
+// column k0+j); otherwise [k][ld] with the rows contiguous.  `vec` selects
+// 16-byte global loads (requires the contiguous extent to be a multiple of 8).
+template <bool ROWK>
+__device__ inline void stage_tile(const unsigned short* __restrict__ X, int rows, int K, int r0,
+                                  int k0, bool vec, unsigned short (*T)[40], int tid) {
+  if constexpr (ROWK) {
+    const int r = tid >> 2, kc = (tid & 3) * 8;
+    const int gr = r0 + r, gk = k0 + kc;
+    v8u16m v;
+    if (vec) {
+      if (gr < rows && gk < K) v = *(const v8u16m*)(X + (size_t)gr * K + gk);
+      else v = v8u16m{0, 0, 0, 0, 0, 0, 0, 0};
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = (gr < rows && gk + u < K) ? X[(size_t)gr * K + gk + u] : (unsigned short)0;
+    }
+    *(v8u16m*)&T[r][kc] = v;
+  } else {
+    const int kr = tid >> 3, rc = (tid & 7) * 8;
+    const int gk = k0 + kr, gr = r0 + rc;
+    v8u16m v;
+    if (vec) {
+      if (gk < K && gr < rows) v = *(const v8u16m*)(X + (size_t)gk * rows + gr);
+      else v = v8u16m{0, 0, 0, 0, 0, 0, 0, 0};
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = (gk < K && gr + u < rows) ? X[(size_t)gk * rows + gr + u] : (unsigned short)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) T[rc + u][kr] = v[u];
+  }
+}
+
 // C[M x N] = op(A) op(B), BF16 operands, FP32 accumulation on
 // v_mfma_f32_16x16x32_bf16.  A_COL: A stored [K][M] (else [M][K]); B_COL: B
 // stored [N][K] (else [K][N]).  Workgroup of 256 threads = 64 x 64 tile, each
@@ -40,60 +78,28 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const unsigned short* __restr
                                                    unsigned short* __restrict__ Cb,
                                                    const float* __restrict__ bias,
                                                    const unsigned short* __restrict__ mask) {
-  constexpr int PAD = 8;
-  __shared__ unsigned short As[64][32 + PAD];
-  __shared__ unsigned short Bs[64][32 + PAD];
+  __shared__ __attribute__((aligned(16))) unsigned short As[64][40];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[64][40];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
+  // contiguous extents: A_COL -> M, else K; B_COL -> K, else N
+  const bool vec_a = ((A_COL ? M : K) & 7) == 0;
+  const bool vec_b = ((B_COL ? K : N) & 7) == 0;
   v4f32m acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f32m{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += 32) {
-    // ---- stage A tile (64 x 32) as As[m][k]
-    if constexpr (!A_COL) {
-      const int r = tid >> 2, kc = (tid & 3) * 8;
-      const int gm = m0 + r;
-      for (int u = 0; u < 8; ++u) {
-        const int gk = k0 + kc + u;
-        As[r][kc + u] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : (unsigned short)0;
-      }
-    } else {
-      const int kr = tid >> 3, mc = (tid & 7) * 8;   // 32 k-rows x 64 m
-      const int gk = k0 + kr;
-      for (int u = 0; u < 8; ++u) {
-        const int gm = m0 + mc + u;
-        As[mc + u][kr] = (gm < M && gk < K) ? A[(size_t)gk * M + gm] : (unsigned short)0;
-      }
-    }
-    // ---- stage B tile (32 x 64) as Bs[n][k]
-    if constexpr (B_COL) {
-      const int r = tid >> 2, kc = (tid & 3) * 8;
-      const int gn = n0 + r;
-      for (int u = 0; u < 8; ++u) {
-        const int gk = k0 + kc + u;
-        Bs[r][kc + u] = (gn < N && gk < K) ? Bm[(size_t)gn * K + gk] : (unsigned short)0;
-      }
-    } else {
-      const int kr = tid >> 3, nc = (tid & 7) * 8;
-      const int gk = k0 + kr;
-      for (int u = 0; u < 8; ++u) {
-        const int gn = n0 + nc + u;
-        Bs[nc + u][kr] = (gn < N && gk < K) ? Bm[(size_t)gk * N + gn] : (unsigned short)0;
-      }
-    }
-    __syncthreads();
+    stage_tile<!A_COL>(A, M, K, m0, k0, vec_a, As, tid);
+    stage_tile<B_COL>(Bm, N, K, n0, k0, vec_b, Bs, tid);
+  __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      v8u16m a;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = As[wm + i * 16 + fr][fk + u];
+      const v8u16m a = *(const v8u16m*)&As[wm + i * 16 + fr][fk];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        v8u16m b;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = Bs[wn + j * 16 + fr][fk + u];
+        const v8u16m b = *(const v8u16m*)&Bs[wn + j * 16 + fr][fk];
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16m, a),
                                                             __builtin_bit_cast(v8bf16m, b),
                                                             acc[i][j], 0, 0, 0);
