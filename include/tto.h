@@ -406,9 +406,9 @@ tto_status tto_topk_smallest(const float* score, int32_t n, int32_t stride, int3
  * capture: a replay re-reads the current contents of the same buffers.
  * Calls that synchronise, allocate or clear memory refuse to run while their
  * stream is captured (tto_autotune, tto_mlp_set_params, tto_mlp_train_step
- * return TTO_E_UNSUPPORTED).  With profiling on, tto_evaluate records its
- * stage events into the graph.  Host only, except tto_graph_launch, which is
- * asynchronous on `stream`.  tto_graph_destroy ends an open capture.
+ * return TTO_E_UNSUPPORTED).  Stage events (tto_profile_*) are recorded by
+ * eager calls only, never into a graph.  Host only, except tto_graph_launch,
+ * which is asynchronous on `stream`.  tto_graph_destroy ends an open capture.
  */
 typedef struct tto_graph tto_graph;
 tto_status tto_graph_begin(tto_graph** out, void** capture_stream);

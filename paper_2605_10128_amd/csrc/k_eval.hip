@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   __shared__ SetupShared sh;
   __shared__ double s_x[kMaxRank][TT];
   __shared__ int s_wcnt[4];
-  __shared__ int s_base, s_n0, s_nisl, s_near0;
+  __shared__ int s_base, s_n0, s_nisl;
   __shared__ F s_stage[4][64][17];   // record staging, one slab per wave
 
   // -- genome parse in stages: slot values, ranges, moved-branch data, checks
@@ -196,7 +196,6 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     s_base = 0;
     s_n0 = 0;
     s_nisl = 0;
-    s_near0 = 0;
   }
   __syncthreads();
   {
@@ -372,8 +371,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   };
 
   // monitored rows: f'_M and U_M
-  int n0 = 0, near0 = 0;
-  const double mg = decision_margin(g);
+  int n0 = 0;
   for (int ei = tid; ei < nM; ei += 256) {
     keep_in_loop();
     const int e = g.mon[ei];
@@ -392,7 +390,6 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
 #pragma unroll
         for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
         n0 += fabs(fp) > lim;
-        near0 |= fabs(fabs(fp) - lim) <= mg;
       }
       fo[(size_t)t * nM] = (F)fp;
     }
@@ -401,7 +398,6 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     for (int q = 0; q < kVSlots; ++q) uo[(size_t)q * nM] = opened ? (F)0 : (F)U[q];
   }
   if (n0) atomicAdd(&s_n0, n0);
-  if (near0) atomicOr(&s_near0, 1);
 
   // optional full post-switch base flows
   if (base_out) {
@@ -546,7 +542,6 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     inf->n_act_pad = n_act + (n_act & 1);
     inf->n_island = s_nisl;
     inf->n_crit_n0 = s_n0;
-    inf->near0 = s_near0;
     for (int q = 0; q < kMaxRank; ++q) inf->open_br[q] = q < k ? sh.open[q] : -1;
   }
 }
@@ -649,6 +644,11 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
                                            double* __restrict__ fmax_out, int c, int eb,
                                            int oc) {
   constexpr int NW = BS / 64;
+  // The tile's candidate is uniform by construction on every launch path;
+  // stating it keeps the per-candidate pointers in scalar registers.
+  c = __builtin_amdgcn_readfirstlane(c);
+  eb = __builtin_amdgcn_readfirstlane(eb);
+  oc = __builtin_amdgcn_readfirstlane(oc);
   const CandInfo* inf = w.info + c;
   const int status = inf->status;
   if (status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;   // uniform per tile
@@ -680,10 +680,9 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
   bool opened = false;
   for (int q = 0; q < k; ++q) opened |= (inf->open_br[q] == e);
   double so = 0.0, best = -1.0, best2 = -1.0;
-  int cc = 0, bt = 0, be = ei, near = 0;
+  int cc = 0, bt = 0, be = ei;
   if (valid) {
     const double lim = g.lim[e];
-    const double mg = decision_margin(g);
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
       if (t < T) {
@@ -693,7 +692,6 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
         const double ov = fm - lim;
         if (ov > 0.0) so += ov;
         cc += fm > lim;
-        near |= fabs(fm - lim) <= mg;
         const double ratio = fm / lim;
         if (ratio > best) { best2 = best; best = ratio; bt = t; }
         else if (ratio > best2) best2 = ratio;
@@ -707,7 +705,6 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
   for (int off = 32; off > 0; off >>= 1) {
     so += __shfl_xor(so, off);
     cc += __shfl_xor(cc, off);
-    near |= __shfl_xor(near, off);
     const double b2 = __shfl_xor(best, off), s2 = __shfl_xor(best2, off);
     const int e2 = __shfl_xor(be, off), t2 = __shfl_xor(bt, off);
     const bool take = b2 > best || (b2 == best && e2 < be);
@@ -720,7 +717,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
     if (tid == 0) {
       Partial p;
       p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
-      p.near = near;
+      p.pad_ = 0;
       *out = p;
     }
   } else {
@@ -728,7 +725,7 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
     if ((tid & 63) == 0) {
       Partial p;
       p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
-      p.near = near;
+      p.pad_ = 0;
       s_p[tid >> 6] = p;
     }
     __syncthreads();
@@ -737,7 +734,6 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
       for (int q = 1; q < NW; ++q) {
         p.sum_o += s_p[q].sum_o;
         p.cnt_c += s_p[q].cnt_c;
-        p.near |= s_p[q].near;
         const bool take = s_p[q].best > p.best;
         p.best2 = fmax(fmax(p.best2, s_p[q].best2), take ? p.best : s_p[q].best);
         if (take) { p.best = s_p[q].best; p.best_e = s_p[q].best_e; p.best_t = s_p[q].best_t; }
@@ -756,22 +752,28 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
 template <typename F, int TT, int BS>
 __global__ __launch_bounds__(BS) void k_sweep(GridDev g, SweepBufs<F> w,
                                               const F* __restrict__ HMC,
-                                              double* __restrict__ fmax_out, int n_cand,
-                                              int xcd, int* __restrict__ counter,
-                                              const int* __restrict__ order,
+                                              double* __restrict__ fmax_out, int n_cand, int xcd,
                                               const int* __restrict__ map,
                                               const int* __restrict__ live) {
   int nc = n_cand;
   if (live) nc = min(*live, n_cand);
   const int n_tiles = nc * w.n_eblk;
-  if (counter == nullptr) {
-    int q = blockIdx.x;
-    if (xcd) q = (q & 7) * (int)(gridDim.x >> 3) + (q >> 3);
-    if (q >= n_tiles) return;
-    const int c = q / w.n_eblk;
-    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, q - c * w.n_eblk, map ? map[c] : c);
-    return;
-  }
+  int q = blockIdx.x;
+  if (xcd) q = (q & 7) * (int)(gridDim.x >> 3) + (q >> 3);
+  if (q >= n_tiles) return;
+  const int c = q / w.n_eblk;
+  sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, q - c * w.n_eblk, map ? map[c] : c);
+}
+
+// Persistent variant: a machine-sized grid pulls rank-ordered tiles from a
+// counter until none are left (every wave reaches the exit).
+template <typename F, int TT, int BS>
+__global__ __launch_bounds__(BS) void k_sweep_persistent(GridDev g, SweepBufs<F> w,
+                                                         const F* __restrict__ HMC,
+                                                         double* __restrict__ fmax_out,
+                                                         int n_cand, int* __restrict__ counter,
+                                                         const int* __restrict__ order) {
+  const int n_tiles = n_cand * w.n_eblk;
   __shared__ int s_q;
   for (;;) {
     if (threadIdx.x == 0) s_q = atomicAdd(counter, 1);
@@ -845,6 +847,7 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
   if (inf.status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) {
     if (lane == 0) {
       const double nan = __builtin_nan("");
+      if (rc.flags) rc.flags[c] = 0;
       if (o.status) o.status[oc] = (uint8_t)inf.status | refined;
       if (o.n_island_cont) o.n_island_cont[oc] = 0;
       if (o.overload_mw) o.overload_mw[oc] = nan;
@@ -860,20 +863,19 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     return;
   }
   __shared__ double s_sum, s_best, s_best2;
-  __shared__ int s_cc, s_be, s_bt, s_near;
+  __shared__ int s_cc, s_be, s_bt;
   if (lane == 0) {
     double so = 0.0, best = -1.0, best2 = -1.0;
-    int cc = 0, be = -1, bt = 0, nr = 0;
+    int cc = 0, be = -1, bt = 0;
     const Partial* p = w.part + (size_t)c * w.n_eblk;
     for (int b = 0; b < w.n_eblk; ++b) {
       so += p[b].sum_o;
       cc += p[b].cnt_c;
-      nr |= p[b].near;
       const bool take = p[b].best > best;
       best2 = fmax(fmax(best2, p[b].best2), take ? best : p[b].best);
       if (take) { best = p[b].best; be = p[b].best_e; bt = p[b].best_t; }
     }
-    s_sum = so; s_best = best; s_best2 = best2; s_cc = cc; s_be = be; s_bt = bt; s_near = nr;
+    s_sum = so; s_best = best; s_best2 = best2; s_cc = cc; s_be = be; s_bt = bt;
   }
   __syncthreads();
   const int be = s_be, bt = s_bt;
@@ -918,19 +920,17 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     const int cnt = inf.r < g.n_count_bins - 1 ? inf.r : g.n_count_bins - 1;
     const int* act = w.act + (size_t)c * (nC + 1);
     uint8_t st = (uint8_t)inf.status | refined;
-    if (rc.list && be >= 0) {
-      const double mg = decision_margin(g);
-      const double lim_e = g.lim[g.mon[be]];
-      bool near = (best - s_best2) * g.lim_min <= mg;                  // runner-up (e, t)
-      near |= (inf.n_act > 1 && bv - v2 <= 2.0 * mg);                  // runner-up l
-      for (int q = 0; q < g.n_load_bins - 1; ++q)                      // load-bin edge
-        near |= fabs(best - g.edges[q]) * lim_e <= mg;
-      near |= s_near != 0 || inf.near0 != 0;                           // a limit (lambda_c, lambda_c0)
-      if (near) {
-        const int slot = atomicAdd(rc.count, 1);
-        if (slot < rc.cap) rc.list[slot] = c;
-        else st |= (uint8_t)TTO_ST_REFINE_SKIPPED;
+    if (rc.flags) {
+      int near = 0;
+      if (be >= 0) {
+        const double mg = decision_margin(g);
+        const double lim_e = g.lim[g.mon[be]];
+        near = (best - s_best2) * g.lim_min <= mg;                     // runner-up (e, t)
+        near |= (inf.n_act > 1 && bv - v2 <= 2.0 * mg);                // runner-up l
+        for (int q = 0; q < g.n_load_bins - 1; ++q)                    // load-bin edge
+          near |= fabs(best - g.edges[q]) * lim_e <= mg;
       }
+      rc.flags[c] = near;
     }
     if (o.status) o.status[oc] = st;
     if (o.n_island_cont) o.n_island_cont[oc] = inf.n_island;
@@ -1055,13 +1055,48 @@ static void launch_sweep(const GridDev& g, const BatchDev& bt, SweepBufs<F> w, c
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, w.counter);
     hipLaunchKernelGGL(k_rank_order, dim3(1), dim3(1024), 0, s, w.info, bt.B, w.order);
     const int grid = std::min(tiles, std::max(plan.grid, 1));
-    hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3(grid), dim3(BS), 0, s, g, w, HMC, fmax_out,
-                       bt.B, 0, w.counter, (const int*)w.order, bt.map, bt.live);
+    hipLaunchKernelGGL((k_sweep_persistent<F, TT, BS>), dim3(grid), dim3(BS), 0, s, g, w, HMC,
+                       fmax_out, bt.B, w.counter, (const int*)w.order);
   } else {
     hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3((tiles + 7) / 8 * 8), dim3(BS), 0, s, g, w,
-                       HMC, fmax_out, bt.B, plan.xcd, (int*)nullptr, (const int*)nullptr,
-                       bt.map, bt.live);
+                       HMC, fmax_out, bt.B, plan.xcd, bt.map, bt.live);
   }
+}
+
+// Refinement queue: the flagged candidates in index order, the first `cap`
+// of them queued for the FP64 pass, the rest marked REFINE_SKIPPED; one
+// workgroup, ordered scan, so the choice does not depend on scheduling.
+__global__ __launch_bounds__(1024) void k_refine_queue(const int* __restrict__ flags, int B,
+                                                       int cap, int* __restrict__ list,
+                                                       int* __restrict__ count,
+                                                       uint8_t* __restrict__ status) {
+  __shared__ int s_w[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < B; i0 += 1024) {
+    const int i = i0 + tid;
+    const bool f = i < B && flags[i] != 0;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) s_w[wid] = __popcll(m);
+    __syncthreads();
+    int pos = s_base;
+    for (int q = 0; q < wid; ++q) pos += s_w[q];
+    pos += __popcll(m & ((1ull << lane) - 1ull));
+    if (f) {
+      if (pos < cap) list[pos] = i;
+      else if (status) status[i] |= (uint8_t)TTO_ST_REFINE_SKIPPED;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int q = 0; q < 16; ++q) t += s_w[q];
+      s_base += t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *count = s_base;
 }
 
 template <typename F, int TT>
@@ -1092,11 +1127,13 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
                                  const RefineCtl& rc) {
   const bool refine = (sizeof(F) == 4) && rw && rc.cap > 0;
   RefineCtl main_rc = rc;
-  if (!refine) main_rc.list = nullptr;
-  if (refine) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, rc.count);
+  if (!refine) { main_rc.list = nullptr; main_rc.flags = nullptr; }
   GridDev gm = g;
   gm.near_margin = refine ? rc.margin : -1.0;
   launch_pass<F, TT>(gm, bt, w, o, s, ev, plan, main_rc);
+  if (refine)
+    hipLaunchKernelGGL(k_refine_queue, dim3(1), dim3(1024), 0, s, (const int*)rc.flags, bt.B,
+                       rc.cap, rc.list, rc.count, o.status);
   if (o.n1_flows) {
     const F* HMC;
     if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
@@ -1115,6 +1152,7 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     ro.n1_flows = nullptr;
     RefineCtl none = rc;
     none.list = nullptr;
+    none.flags = nullptr;
     SweepPlan rp = plan;
     rp.persistent = 0;
     GridDev gh = g;
@@ -1144,7 +1182,7 @@ template <typename F>
 static int sweep_occ(int TT, int bs) {
   int n = 0;
   const void* fn = nullptr;
-#define TTO_OCC(TTV, BSV) if (TT == TTV && bs == BSV) fn = (const void*)&k_sweep<F, TTV, BSV>;
+#define TTO_OCC(TTV, BSV) if (TT == TTV && bs == BSV) fn = (const void*)&k_sweep_persistent<F, TTV, BSV>;
   TTO_OCC(1, 64) TTO_OCC(1, 128) TTO_OCC(1, 256) TTO_OCC(8, 64) TTO_OCC(8, 128) TTO_OCC(8, 256)
   TTO_OCC(24, 64) TTO_OCC(24, 128) TTO_OCC(24, 256) TTO_OCC(32, 64) TTO_OCC(32, 128) TTO_OCC(32, 256)
 #undef TTO_OCC

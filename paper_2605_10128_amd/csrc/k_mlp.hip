@@ -189,7 +189,8 @@ __global__ __launch_bounds__(64) void k_mlp_out(const unsigned short* __restrict
   }
 }
 
-// dy = (y - t) / B; per-sample loss terms (summed in fixed order later).
+// dy = (y - t) / B; per-sample terms of the loss 1/(2B) sum (y - t)^2
+// (summed in a fixed order later).
 __global__ __launch_bounds__(256) void k_mlp_dy(const float* __restrict__ y,
                                                 const float* __restrict__ t, int B,
                                                 float* __restrict__ dy,
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void k_mlp_dy(const float* __restrict__ y,
   const float e0 = y[b * 2] - t[b * 2], e1 = y[b * 2 + 1] - t[b * 2 + 1];
   dy[b * 2] = e0 / (float)B;
   dy[b * 2 + 1] = e1 / (float)B;
-  lterm[b] = 0.5f * (e0 * e0 + e1 * e1);
+  lterm[b] = 0.5f * (e0 * e0 + e1 * e1) / (float)B;
 }
 
 // Output-layer backward: gW4[j][k] = sum_b h3[b][j] dy[b][k], gb4 = sum_b dy,

@@ -135,6 +135,8 @@ SweepBufs<F> carve_batch(int B, int nM, int nC, int TT, void* ws, size_t* bytes)
 }
 
 // FP64 refinement capacity of an FP32 grid: an eighth of the batch, >= 64.
+static inline size_t round256(size_t v) { return (v + 255) & ~(size_t)255; }
+
 int refine_cap(int max_batch) { return std::min(max_batch, std::max(64, (max_batch + 7) / 8)); }
 
 struct BatchLayout {
@@ -154,7 +156,10 @@ BatchLayout batch_layout(int flow_prec, int B, int max_batch, int nM, int nC, in
   if (flow_prec == TTO_FLOW_F32) {
     size_t rb = 0;
     carve_batch<double>(refine_cap(max_batch), nM, nC, TT, nullptr, &rb);
-    L.bytes = L.refine_off + rb + 2 * 256 + sizeof(int) * (size_t)refine_cap(max_batch);
+    // FP64 buffers, then count (256 B), list [cap], flags [max_batch]
+    L.bytes = L.refine_off + round256(rb) + 256 +
+              round256(sizeof(int) * (size_t)refine_cap(max_batch)) +
+              sizeof(int) * (size_t)max_batch + 256;
   }
   return L;
 }
@@ -427,9 +432,12 @@ tto_status tto_evaluate(tto_grid* g, const tto_batch* bt, const tto_outputs* out
   b.map = nullptr;
   b.live = nullptr;
   hipStream_t s = (hipStream_t)stream;
+  // stage events are recorded on eager calls only (not into a captured graph)
+  const bool prof = g->profile && !capturing(s);
   size_t used = 0;
   RefineCtl rc;
-  rc.list = nullptr; rc.count = nullptr; rc.cap = 0; rc.margin = g->refine_margin;
+  rc.list = nullptr; rc.count = nullptr; rc.flags = nullptr; rc.cap = 0;
+  rc.margin = g->refine_margin;
   if (g->flow_prec == TTO_FLOW_F32) {
     SweepBufs<float> w = carve_batch<float>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
     if (!out->n1_flows) w.slot = nullptr;
@@ -442,21 +450,22 @@ tto_status tto_evaluate(tto_grid* g, const tto_batch* bt, const tto_outputs* out
       const int cap = refine_cap(g->max_batch);
       rw = carve_batch<double>(cap, g->nM, g->nC, g->TT, base, &rb);
       rw.slot = nullptr;
-      char* tail = base + ((rb + 255) & ~(size_t)255);
+      char* tail = base + round256(rb);
       rc.count = (int*)tail;
       rc.list = (int*)(tail + 256);
+      rc.flags = (int*)(tail + 256 + round256(sizeof(int) * (size_t)cap));
       rc.cap = cap;
       rwp = &rw;
     }
-    HIP_TRY(launch_evaluate<float>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr, g->plan,
+    HIP_TRY(launch_evaluate<float>(g->dev, b, w, *out, s, prof ? g->ev : nullptr, g->plan,
                                    rwp, rc));
   } else {
     SweepBufs<double> w = carve_batch<double>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
     if (!out->n1_flows) w.slot = nullptr;
-    HIP_TRY(launch_evaluate<double>(g->dev, b, w, *out, s, g->profile ? g->ev : nullptr, g->plan,
+    HIP_TRY(launch_evaluate<double>(g->dev, b, w, *out, s, prof ? g->ev : nullptr, g->plan,
                                     nullptr, rc));
   }
-  if (g->profile) g->recorded = true;
+  if (prof) g->recorded = true;
   return ok();
 }
 

@@ -80,8 +80,9 @@ struct BatchDev {
 
 // FP32 pass -> FP64 refinement hand-over.
 struct RefineCtl {
-  int* list;        // [cap] candidates to re-evaluate in FP64
+  int* list;        // [cap] candidates to re-evaluate in FP64, in index order
   int* count;       // number flagged (may exceed cap)
+  int* flags;       // [B] 1 if the candidate's FP32 decisions are near a threshold
   int cap;
   double margin;    // flow error margin in MW
 };
@@ -95,7 +96,7 @@ struct CandInfo {
   int n_act_pad;   // n_act rounded up to even (duplicate of the last record)
   int n_island;    // islanding contingencies
   int n_crit_n0;   // lambda_c0 from the FP64 post-switch flows
-  int near0;       // some |f'| lies within the decision margin of its limit
+  int pad_;
   int open_br[kMaxRank];
 };
 
@@ -107,7 +108,7 @@ struct Partial {
   int cnt_c;        // fmax > lim count
   int best_e;       // monitored index of the max (smallest on ties)
   int best_t;
-  int near;         // some fmax lies within the decision margin of its limit
+  int pad_;
 };
 
 // Batch workspace views (carved from the caller's batch workspace).

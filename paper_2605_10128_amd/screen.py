@@ -13,7 +13,9 @@ the screen is an addition for large generations.  Feature encoding: one bit
 per base non-bridge opening and one per split action of the action table
 (the paper's reconfiguration action set, Importer section), plus the
 per-timestep total positive injection, standardised.  Targets: maximum
-loading and log1p(overload / 100 MW).
+loading and log1p(overload / 100 MW), each taken relative to the unswitched
+grid under the same injections (what the actions change, which is all a
+screen within one generation needs) and standardised over the training set.
 """
 from __future__ import annotations
 
@@ -47,14 +49,55 @@ class FeatureScale:
         return ((np.asarray(summary, dtype=np.float64) - self.mu) / self.sd).astype(np.float32)
 
 
-def targets_from_outputs(out: dict):
-    """(targets [B][2] float32, usable mask) from tto_evaluate outputs."""
+def raw_targets(rho, overload_mw):
+    """(maximum loading, log1p(overload / 100 MW)) as float64 columns."""
+    rho = np.asarray(rho, dtype=np.float64)
+    lam = np.maximum(np.asarray(overload_mw, dtype=np.float64), 0.0)
+    return np.stack([rho, np.log1p(lam / OVERLOAD_SCALE_MW)], axis=-1)
+
+
+def unswitched_reference(session: tto.Session):
+    """Raw targets of the unswitched grid under the session's current
+    injections (one exact evaluation of the empty candidate)."""
+    torch = session.torch
+    d = session.device
+    empty = tto.DeviceBatch(1, torch.full((1, 1), -1, dtype=torch.int32, device=d),
+                            torch.full((1, 1), -1, dtype=torch.int32, device=d),
+                            torch.zeros(2, dtype=torch.int32, device=d),
+                            torch.zeros(1, dtype=torch.int32, device=d), None)
+    o = session.evaluate(empty)
+    if int(o["status"][0].item()) & 3:
+        raise RuntimeError("the unswitched grid is islanded or invalid")
+    return raw_targets(o["max_loading"].cpu().numpy(), o["overload_mw"].cpu().numpy())[0]
+
+
+def targets_from_outputs(out: dict, reference=None):
+    """(targets [B][2] float32, usable mask) from tto_evaluate outputs,
+    relative to `reference` (raw targets of the unswitched grid) if given."""
     st = out["status"].cpu().numpy()
-    rho = out["max_loading"].cpu().numpy()
-    lam = out["overload_mw"].cpu().numpy()
+    t = raw_targets(out["max_loading"].cpu().numpy(), out["overload_mw"].cpu().numpy())
+    if reference is not None:
+        t = t - np.asarray(reference, dtype=np.float64)[None, :]
     ok = (st & 3) == 0
-    t = np.stack([rho, np.log1p(np.maximum(lam, 0.0) / OVERLOAD_SCALE_MW)], axis=1)
-    return t.astype(np.float32), ok
+    return np.where(ok[:, None], t, 0.0).astype(np.float32), ok
+
+
+@dataclass
+class TargetScale:
+    """Per-column mean and deviation of the training targets."""
+    mu: np.ndarray
+    sd: np.ndarray
+
+    @staticmethod
+    def fit(targets, mask) -> "TargetScale":
+        t = np.asarray(targets, dtype=np.float64)[np.asarray(mask, bool)]
+        return TargetScale(t.mean(axis=0), np.maximum(t.std(axis=0), 1e-9))
+
+    def apply(self, t) -> np.ndarray:
+        return ((np.asarray(t, dtype=np.float64) - self.mu) / self.sd).astype(np.float32)
+
+    def invert(self, y) -> np.ndarray:
+        return np.asarray(y, dtype=np.float64) * self.sd + self.mu
 
 
 class Dataset:
