@@ -28,18 +28,25 @@ def relu(x):
     return np.maximum(x, 0.0)
 
 
-def forward(p: Dict[str, np.ndarray], bits: List[np.ndarray], dense: np.ndarray):
-    """Returns y [B, 2] and the cache of pre-activations/activations."""
+def forward(p: Dict[str, np.ndarray], bits: List[np.ndarray], dense: np.ndarray,
+            act_round=None):
+    """Returns y [B, 2] and the cache of pre-activations/activations.
+
+    act_round, if given, is applied to every hidden activation: a network
+    specified with activations stored in a narrower type (BF16) is then the
+    same function here, and its ReLU decisions are taken on the same values.
+    The backward pass treats the rounding as the identity."""
+    rnd = (lambda v: v) if act_round is None else act_round
     B = len(bits)
     z1 = dense @ p["W1d"] + p["b1"][None, :]
     for b in range(B):
         for i in bits[b]:
             z1[b] += p["W1b"][int(i)]
-    h1 = relu(z1)
+    h1 = rnd(relu(z1))
     z2 = h1 @ p["W2"] + p["b2"][None, :]
-    h2 = relu(z2)
+    h2 = rnd(relu(z2))
     z3 = h2 @ p["W3"] + p["b3"][None, :]
-    h3 = relu(z3)
+    h3 = rnd(relu(z3))
     y = h3 @ p["W4"] + p["b4"][None, :]
     return y, dict(z1=z1, h1=h1, z2=z2, h2=h2, z3=z3, h3=h3)
 

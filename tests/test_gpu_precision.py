@@ -102,13 +102,13 @@ def test_modes_against_fp64_path_6000_bus(env):
     tto, w, _ = env
     db = tto.device_batch(w.batch)
     s64 = make_session(w, tto.TTO_FLOW_F64, tto.TTO_GEMM_F64)
-    ref = to_numpy(s64.evaluate(db, fmax=True))
+    ref = to_numpy(s64.evaluate(db, fmax=True, base_flows=True))
     torch.cuda.synchronize()
     s64.close()
     ok = (ref["status"] & 3) == 0
     for name, gemm, tol in [("f32", tto.TTO_GEMM_F32, TARGET_MW)] + _modes(tto)[1:]:
         s = make_session(w, tto.TTO_FLOW_F32, gemm)
-        out = to_numpy(s.evaluate(db, fmax=True))
+        out = to_numpy(s.evaluate(db, fmax=True, base_flows=True))
         torch.cuda.synchronize()
         s.close()
         assert np.array_equal(out["status"] & 3, ref["status"] & 3), name
@@ -117,10 +117,21 @@ def test_modes_against_fp64_path_6000_bus(env):
         skipped = (out["status"] & 8) != 0
         trust = ok & ~skipped
         mism = {k: int((out[k][trust] != ref[k][trust]).sum())
-                for k in ("cell", "worst_branch", "worst_t", "n_crit_n1", "n_crit_n0")}
+                for k in ("cell", "worst_branch", "worst_t")}
+        # the critical counts are FP32 decisions: they may differ from FP64
+        # only by elements lying within this mode's flow error of their limit
+        lim = w.grid.limit_mw[w.M][None, :, None]
+        near1 = (np.abs(ref["fmax"] - lim) <= d.max()).sum(axis=(1, 2))
+        d0 = np.abs(out["base_flows"][ok] - ref["base_flows"][ok]).max()
+        near0 = (np.abs(np.abs(ref["base_flows"][:, w.M, :]) - lim) <= d0).sum(axis=(1, 2))
+        dn1 = np.abs(out["n_crit_n1"] - ref["n_crit_n1"])
+        dn0 = np.abs(out["n_crit_n0"] - ref["n_crit_n0"])
+        mism["n_crit_n1_beyond_error"] = int((dn1[ok] > near1[ok]).sum())
+        mism["n_crit_n0_beyond_error"] = int((dn0[ok] > near0[ok]).sum())
+        mism["n_crit_differ"] = int(((dn1 + dn0)[ok] > 0).sum())
         log(f"[precision] {name}: fmax max {d.max():.3e} MW p99 {np.quantile(d, 0.99):.3e} MW; "
             f"refined {refined}, skipped {int(skipped.sum())} of {int(ok.sum())}; "
             f"discrete mismatches outside skipped {mism}")
         if tol is not None:
             assert d.max() <= tol, name
-            assert all(v == 0 for v in mism.values()), (name, mism)
+            assert all(v == 0 for k, v in mism.items() if k != "n_crit_differ"), (name, mism)

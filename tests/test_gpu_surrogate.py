@@ -63,12 +63,14 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
 
 
-# BF16 unit roundoff is 2^-9.  The forward rounds h1, h2, h3 to BF16 (three
-# roundings on the path to y); the backward adds dz3, dz2, dz1 (six).  A
-# relative-L2 error of at most (roundings) * 2^-9 with a factor 2 of margin for
-# ReLU masks that flip near zero gives 1.2e-2 (forward) and 2.4e-2 (gradients).
+# BF16 unit roundoff is 2^-9.  With the activations rounded alike on both
+# sides, the forward differs only by FP32 against FP64 sums of the same
+# values; the backward rounds dz3, dz2, dz1 to BF16 (three roundings on the
+# path to the first layer).  A relative-L2 error of at most (roundings) * 2^-9
+# with a factor 2 of margin gives 1.2e-2 for both; the forward keeps the
+# looser of the two bounds.
 TOL_FWD = 1.2e-2
-TOL_GRAD = 2.4e-2
+TOL_GRAD = 1.2e-2
 
 
 @pytest.mark.parametrize("d_bits,d_dense,H,B", [(700, 24, 128, 100), (131, 0, 64, 37)])
@@ -87,7 +89,10 @@ def test_mlp_forward_and_gradients_match_oracle(d_bits, d_dense, H, B):
     y = net.forward(off_d, ids_d, dense_d, B).cpu().numpy().astype(np.float64)
 
     q = _oracle_params(flat, d_bits, d_dense, H)
-    y_ref, cache = om.forward(q, rows, dense.astype(np.float64).reshape(B, d_dense))
+    # the network keeps its hidden activations in BF16: the reference applies
+    # the same rounding, so both take their ReLU decisions on the same values
+    y_ref, cache = om.forward(q, rows, dense.astype(np.float64).reshape(B, d_dense),
+                              act_round=bf16_round)
     log(f"  forward rel err {_rel(y, y_ref):.2e}")
     assert _rel(y, y_ref) <= TOL_FWD
 
@@ -311,16 +316,16 @@ def test_surrogate_trains_and_screens_a_generation():
     # prediction error on the unseen scenario
     y = tscale.invert(sc.y[:n_gen].cpu().numpy()) + ref_h[None, :]
     valid = (exact["status"] & 3) == 0
-    truth = screen.raw_targets(exact["max_loading"], exact["overload_mw"])
+    truth = screen.raw_targets(exact["max_loading"], exact["fitness"])
     mae_rho = np.abs(y[valid, 0] - truth[valid, 0]).mean()
     corr = np.corrcoef(y[valid, 1], truth[valid, 1])[0, 1]
     # gain: the screened tenth against the best tenth by exact fitness
     fit = np.where(valid, exact["fitness"], -np.inf)
     best = np.argsort(-fit, kind="stable")[:keep]
     recall = len(np.intersect1d(best, idx)) / keep
-    # overload change against the unswitched grid: screened tenth, all, and
-    # the tenth with the lowest exact overload (the best any screen can do)
-    d_lam = exact["overload_mw"] - np.expm1(ref_h[1]) * screen.OVERLOAD_SCALE_MW
+    # penalised-overload change against the unswitched grid: screened tenth,
+    # all, and the tenth with the lowest exact value (the best any screen can do)
+    d_lam = -exact["fitness"] - np.expm1(ref_h[1]) * screen.OVERLOAD_SCALE_MW
     mean_all = d_lam[valid].mean()
     mean_scr = d_lam[idx][valid[idx]].mean()
     lam_v = np.where(valid, d_lam, np.inf)
@@ -340,7 +345,7 @@ def test_surrogate_trains_and_screens_a_generation():
     a_all, a_scr = archive(range(n_gen)), archive(idx.tolist())
     kept = sum(1 for c, e in a_all.items() if a_scr.get(c) == e)
     log(f"  rho MAE {mae_rho:.4f}, overload corr {corr:.3f}, recall@10% {recall:.3f} "
-        f"(random 0.100), overload change screened {mean_scr:.1f} vs all {mean_all:.1f} vs "
+        f"(random 0.100), penalised overload change screened {mean_scr:.1f} vs all {mean_all:.1f} vs "
         f"best tenth {mean_best:.1f} MW (screen efficiency {efficiency:.2f}), "
         f"archive: {kept}/{len(a_all)} exact-only elites kept, {len(a_scr)} cells filled "
         f"of {cells}")
