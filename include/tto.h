@@ -280,11 +280,15 @@ tto_status tto_profile_read(tto_grid* grid, double* ms);
 /*
  * Launch shape of the N-1 sweep (batching of uneven-rank candidates).  A
  * tile is one candidate x `block` monitored branches (64, 128 or 256 lanes).
- * xcd_group != 0 deals the tiles of one candidate onto one XCD (shared L2 for
- * its contingency records); persistent != 0 launches a machine-sized grid
+ * xcd_group 1 deals the tiles of one candidate onto one XCD (shared L2 for
+ * its contingency records); xcd_group 2 deals each XCD a contiguous range of
+ * the monitored-block-major tile order (each XCD then streams one or two
+ * column blocks of H[M, C] for many candidates); 0 uses the hardware's
+ * round-robin order.  persistent != 0 launches a machine-sized grid
  * whose workgroups pull tiles from a counter in rank-descending candidate
  * order (longest tiles first).  Default: block 256, no grouping, not
- * persistent.  TTO_E_INVALID for other block sizes; TTO_E_UNSUPPORTED for
+ * persistent.  TTO_E_INVALID for other block sizes or xcd_group values;
+ * TTO_E_UNSUPPORTED for
  * blocks 64/128 and for persistent != 0, which this build switches off.
  */
 tto_status tto_set_sweep_plan(tto_grid* grid, int32_t block, int32_t xcd_group,

@@ -758,11 +758,18 @@ __global__ __launch_bounds__(BS) void k_sweep(GridDev g, SweepBufs<F> w,
   int nc = n_cand;
   if (live) nc = min(*live, n_cand);
   const int n_tiles = nc * w.n_eblk;
+  // Workgroup w runs on XCD w % 8.  xcd != 0: the 8 XCDs take contiguous
+  // ranges of the tile order.  xcd == 1 orders tiles candidate-major (the
+  // tiles of a candidate share its records in one L2); xcd == 2 orders them
+  // monitored-block-major (each XCD streams at most two column blocks of
+  // H[M, C] across many candidates, which then stay in its L2).
   int q = blockIdx.x;
   if (xcd) q = (q & 7) * (int)(gridDim.x >> 3) + (q >> 3);
   if (q >= n_tiles) return;
-  const int c = q / w.n_eblk;
-  sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, q - c * w.n_eblk, map ? map[c] : c);
+  int c, eb;
+  if (xcd == 2) { eb = q / nc; c = q - eb * nc; }
+  else { c = q / w.n_eblk; eb = q - c * w.n_eblk; }
+  sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, eb, map ? map[c] : c);
 }
 
 // Persistent variant: a machine-sized grid pulls rank-ordered tiles from a

@@ -204,20 +204,25 @@ __global__ __launch_bounds__(256) void k_mlp_dy(const float* __restrict__ y,
 }
 
 // Output-layer backward: gW4[j][k] = sum_b h3[b][j] dy[b][k], gb4 = sum_b dy,
-// and dz3[b][j] = (dy[b] . W4[j]) where h3 > 0 (BF16).  Fixed-order sums.
-__global__ __launch_bounds__(256) void k_mlp_out_bwd_w(const unsigned short* __restrict__ h3,
-                                                       const float* __restrict__ dy, int B,
-                                                       int H, float* __restrict__ gW4) {
+// and dz3[b][j] = (dy[b] . W4[j]) where h3 > 0 (BF16).  Batch sums in two
+// fixed-order stages: per chunk of kRowChunk rows, then over the chunks.
+constexpr int kRowChunk = 64;
+
+__global__ __launch_bounds__(256) void k_mlp_out_bwd_w_part(const unsigned short* __restrict__ h3,
+                                                            const float* __restrict__ dy, int B,
+                                                            int H, float* __restrict__ part) {
   const int j = blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y;
   if (j >= H) return;
+  const int b0 = r * kRowChunk, b1 = min(B, b0 + kRowChunk);
   float s0 = 0.f, s1 = 0.f;
-  for (int b = 0; b < B; ++b) {
+  for (int b = b0; b < b1; ++b) {
     const float h = bf16_to_f(h3[(size_t)b * H + j]);
     s0 += h * dy[b * 2];
     s1 += h * dy[b * 2 + 1];
   }
-  gW4[j * 2] = s0;
-  gW4[j * 2 + 1] = s1;
+  part[((size_t)r * H + j) * 2] = s0;
+  part[((size_t)r * H + j) * 2 + 1] = s1;
 }
 
 __global__ __launch_bounds__(256) void k_mlp_out_bwd_x(const unsigned short* __restrict__ h3,
@@ -231,17 +236,30 @@ __global__ __launch_bounds__(256) void k_mlp_out_bwd_x(const unsigned short* __r
   dz3[i] = h3[i] != 0 ? bf16_rne(g) : (unsigned short)0;
 }
 
-// Column sums over the batch of a [B][n] matrix (BF16 or FP32), fixed order.
+// Column sums over the batch of a [B][n] matrix (BF16 or FP32): per chunk of
+// kRowChunk rows into part[chunk][n], then k_chunk_sum over the chunks.
 template <typename T>
-__global__ __launch_bounds__(256) void k_colsum(const T* __restrict__ x, int B, int n,
-                                                float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_colsum_part(const T* __restrict__ x, int B, int n,
+                                                     float* __restrict__ part) {
   const int j = blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.y;
   if (j >= n) return;
+  const int b0 = r * kRowChunk, b1 = min(B, b0 + kRowChunk);
   float s = 0.f;
-  for (int b = 0; b < B; ++b) {
+  for (int b = b0; b < b1; ++b) {
     if constexpr (sizeof(T) == 2) s += bf16_to_f(x[(size_t)b * n + j]);
     else s += x[(size_t)b * n + j];
   }
+  part[(size_t)r * n + j] = s;
+}
+
+// out[j] = sum over chunks r (in order) of part[r][j].
+__global__ __launch_bounds__(256) void k_chunk_sum(const float* __restrict__ part, int R, int n,
+                                                   float* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.f;
+  for (int r = 0; r < R; ++r) s += part[(size_t)r * n + j];
   out[j] = s;
 }
 
@@ -516,6 +534,13 @@ static void gemm(const unsigned short* A, const unsigned short* B, int M, int N,
                      s, A, B, M, N, K, Cf, Cb, bias, mask);
 }
 
+template <typename T>
+static void colsum(const T* x, int B, int n, float* part, float* out, hipStream_t s) {
+  const int R = cdiv_m(B, kRowChunk);
+  hipLaunchKernelGGL((k_colsum_part<T>), dim3(cdiv_m(n, 256), R), dim3(256), 0, s, x, B, n, part);
+  hipLaunchKernelGGL(k_chunk_sum, dim3(cdiv_m(n, 256)), dim3(256), 0, s, part, R, n, out);
+}
+
 // ---------------------------------------------------------------------------
 void mlp_forward(const MlpDev& p, const MlpBatch& wb, const int* off, const int* idx,
                  const float* dense, int B, float* y, hipStream_t s) {
@@ -538,24 +563,24 @@ void mlp_gradients(const MlpDev& p, const MlpBatch& wb, const int* off, const in
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, wb.lterm, B, loss);
   MlpGrad g = mlp_grad_view(p, grad);
   // output layer
-  hipLaunchKernelGGL(k_mlp_out_bwd_w, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.h3, wb.dy, B, H,
+  const int R = cdiv_m(B, kRowChunk);
+  hipLaunchKernelGGL(k_mlp_out_bwd_w_part, dim3(cdiv_m(H, 256), R), dim3(256), 0, s, wb.h3,
+                     wb.dy, B, H, wb.part);
+  hipLaunchKernelGGL(k_chunk_sum, dim3(cdiv_m(2 * H, 256)), dim3(256), 0, s, wb.part, R, 2 * H,
                      g.W4);
-  hipLaunchKernelGGL(k_colsum<float>, dim3(1), dim3(256), 0, s, wb.dy, B, 2, g.b4);
+  colsum<float>(wb.dy, B, 2, wb.part, g.b4, s);
   hipLaunchKernelGGL(k_mlp_out_bwd_x, dim3(cdiv_m((long)B * H, 256)), dim3(256), 0, s, wb.h3,
                      wb.dy, p.W4, B, H, wb.dz3);
   // layer 3: gW3 = h2^T dz3, gb3 = colsum dz3, dz2 = (dz3 W3^T) * [h2 > 0]
   gemm<true, false, 0>(wb.h2, wb.dz3, H, H, B, g.W3, nullptr, nullptr, nullptr, s);
-  hipLaunchKernelGGL(k_colsum<unsigned short>, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.dz3, B,
-                     H, g.b3);
+  colsum<unsigned short>(wb.dz3, B, H, wb.part, g.b3, s);
   gemm<false, true, 2>(wb.dz3, p.W3_h, B, H, H, nullptr, wb.dz2, nullptr, wb.h2, s);
   // layer 2
   gemm<true, false, 0>(wb.h1, wb.dz2, H, H, B, g.W2, nullptr, nullptr, nullptr, s);
-  hipLaunchKernelGGL(k_colsum<unsigned short>, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.dz2, B,
-                     H, g.b2);
+  colsum<unsigned short>(wb.dz2, B, H, wb.part, g.b2, s);
   gemm<false, true, 2>(wb.dz2, p.W2_h, B, H, H, nullptr, wb.dz1, nullptr, wb.h1, s);
   // layer 1: gW1b = X^T dz1 over the 0/1 bitmask, gW1d = dense^T dz1
-  hipLaunchKernelGGL(k_colsum<unsigned short>, dim3(cdiv_m(H, 256)), dim3(256), 0, s, wb.dz1, B,
-                     H, g.b1);
+  colsum<unsigned short>(wb.dz1, B, H, wb.part, g.b1, s);
   const int nb = std::min(cdiv_m(B, 256), 1024);
   hipLaunchKernelGGL(k_zero_i32, dim3(std::min(cdiv_m(db, 256), 1024)), dim3(256), 0, s, wb.cnt, db);
   hipLaunchKernelGGL((k_bits_bucket<false>), dim3(nb), dim3(256), 0, s, off, idx, B, db, wb.cnt,

@@ -486,7 +486,8 @@ static tto_status apply_plan(tto_grid* g, int bs, int xcd, int persistent) {
                 bs, persistent);
   SweepPlan p;
   p.bs = bs;
-  p.xcd = xcd ? 1 : 0;
+  if (xcd < 0 || xcd > 2) return fail(TTO_E_INVALID, "xcd_group must be 0, 1 or 2");
+  p.xcd = xcd;
   p.persistent = persistent ? 1 : 0;
   p.grid = 0;
   if (p.persistent) {
@@ -541,7 +542,7 @@ tto_status tto_autotune(tto_grid* g, const tto_batch* bt, const tto_outputs* out
       fclose(f);
     }
   }
-  const int cands[][3] = {{256, 0, 0}, {256, 1, 0}};
+  const int cands[][3] = {{256, 0, 0}, {256, 1, 0}, {256, 2, 0}};
   const bool prof0 = g->profile;
   tto_status st = tto_profile_enable(g, 1);
   if (st != TTO_OK) return st;
@@ -650,6 +651,7 @@ MlpBatch carve_mlp_batch(const tto_mlp_desc* d, void* ws, size_t* bytes) {
   b.y = cv.take<float>(Ba * 2);
   b.dy = cv.take<float>(Bt * 2);
   b.lterm = cv.take<float>(Bt);
+  b.part = cv.take<float>(((Bt + 63) / 64) * 2 * H);
   *bytes = cv.off;
   return b;
 }

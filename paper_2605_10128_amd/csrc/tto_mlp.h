@@ -67,6 +67,7 @@ struct MlpBatch {
   float* y;                          // [B][2]
   float* dy;                         // [B][2]
   float* lterm;                      // [B]
+  float* part;                       // [ceil(B / 64)][2 H] chunk partial sums
 };
 
 void mlp_forward(const MlpDev& p, const MlpBatch& wb, const int* off, const int* idx,

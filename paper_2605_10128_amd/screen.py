@@ -13,12 +13,11 @@ the screen is an addition for large generations.  Feature encoding: one bit
 per base non-bridge opening and one per split action of the action table
 (the paper's reconfiguration action set, Importer section), plus the
 per-timestep total positive injection, standardised.  Targets: maximum
-loading (it places a candidate in its descriptor cell) and log1p(penalised
-overload / 100 MW), the penalised overload being the overload energy plus
-the critical-branch penalties of the fitness, -lambda_f1 (it decides the
-elite within a cell); each taken relative to the unswitched grid under the
-same injections (what the actions change, which is all a screen within one
-generation needs) and standardised over the training set.
+loading (it places a candidate in its descriptor cell) and log1p(overload
+energy / 100 MW) (the dominant term of the fitness), each taken relative to
+the unswitched grid under the same injections (what the actions change,
+which is all a screen within one generation needs) and standardised over the
+training set.
 """
 from __future__ import annotations
 
@@ -52,11 +51,11 @@ class FeatureScale:
         return ((np.asarray(summary, dtype=np.float64) - self.mu) / self.sd).astype(np.float32)
 
 
-def raw_targets(rho, fitness):
-    """(maximum loading, log1p(-fitness / 100 MW)) as float64 columns."""
+def raw_targets(rho, overload_mw):
+    """(maximum loading, log1p(overload / 100 MW)) as float64 columns."""
     rho = np.asarray(rho, dtype=np.float64)
-    pen = np.maximum(-np.asarray(fitness, dtype=np.float64), 0.0)
-    return np.stack([rho, np.log1p(pen / OVERLOAD_SCALE_MW)], axis=-1)
+    lam = np.maximum(np.asarray(overload_mw, dtype=np.float64), 0.0)
+    return np.stack([rho, np.log1p(lam / OVERLOAD_SCALE_MW)], axis=-1)
 
 
 def unswitched_reference(session: tto.Session):
@@ -71,14 +70,14 @@ def unswitched_reference(session: tto.Session):
     o = session.evaluate(empty)
     if int(o["status"][0].item()) & 3:
         raise RuntimeError("the unswitched grid is islanded or invalid")
-    return raw_targets(o["max_loading"].cpu().numpy(), o["fitness"].cpu().numpy())[0]
+    return raw_targets(o["max_loading"].cpu().numpy(), o["overload_mw"].cpu().numpy())[0]
 
 
 def targets_from_outputs(out: dict, reference=None):
     """(targets [B][2] float32, usable mask) from tto_evaluate outputs,
     relative to `reference` (raw targets of the unswitched grid) if given."""
     st = out["status"].cpu().numpy()
-    t = raw_targets(out["max_loading"].cpu().numpy(), out["fitness"].cpu().numpy())
+    t = raw_targets(out["max_loading"].cpu().numpy(), out["overload_mw"].cpu().numpy())
     if reference is not None:
         t = t - np.asarray(reference, dtype=np.float64)[None, :]
     ok = (st & 3) == 0
@@ -199,7 +198,7 @@ class Screener:
         return self.net.forward(off_d, ids_d, dense_d, n, y=self.y)
 
     def select(self, n, k):
-        """Indices (device int32 [k]) of the k lowest predicted penalised overloads."""
+        """Indices (device int32 [k]) of the k lowest predicted overloads."""
         if k > self.max_keep:
             raise ValueError(f"k={k} exceeds max_keep={self.max_keep}")
         y1 = int(self.y.data_ptr()) + 4   # column 1, stride 2 floats

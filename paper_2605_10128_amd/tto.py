@@ -198,7 +198,7 @@ def tto_profile_read(handle: int):
     return list(ms)
 
 
-def tto_set_sweep_plan(handle: int, block: int, xcd_group: bool, persistent: bool):
+def tto_set_sweep_plan(handle: int, block: int, xcd_group: int, persistent: bool):
     _check(_lib.tto_set_sweep_plan(_vp(handle), block, int(xcd_group), int(persistent)))
 
 
@@ -209,7 +209,7 @@ def tto_set_refine(handle: int, enable: bool, margin_mw: float = 8e-3):
 def tto_get_sweep_plan(handle: int):
     b, x, p = _i32(), _i32(), _i32()
     _check(_lib.tto_get_sweep_plan(_vp(handle), ct.byref(b), ct.byref(x), ct.byref(p)))
-    return b.value, bool(x.value), bool(p.value)
+    return b.value, int(x.value), bool(p.value)
 
 
 def tto_autotune(handle: int, batch: tto_batch, outputs: tto_outputs, ws: int, ws_bytes: int,
@@ -217,7 +217,7 @@ def tto_autotune(handle: int, batch: tto_batch, outputs: tto_outputs, ws: int, w
     ch = (_i32 * 4)()
     _check(_lib.tto_autotune(_vp(handle), ct.byref(batch), ct.byref(outputs), _vp(ws), ws_bytes,
                              _vp(stream), cache_path.encode(), ch))
-    return {"block": ch[0], "xcd_group": bool(ch[1]), "persistent": bool(ch[2]),
+    return {"block": ch[0], "xcd_group": int(ch[1]), "persistent": bool(ch[2]),
             "from_cache": bool(ch[3])}
 
 
@@ -595,7 +595,7 @@ class Session:
                                  int(fit.shape[0]) if fit is not None else 0, id_base)
         return Graph(h)
 
-    def set_sweep_plan(self, block=256, xcd_group=False, persistent=False):
+    def set_sweep_plan(self, block=256, xcd_group=0, persistent=False):
         tto_set_sweep_plan(self.handle, block, xcd_group, persistent)
 
     def new_archive(self, n_cells=None):

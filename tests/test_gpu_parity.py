@@ -131,8 +131,8 @@ def test_repeat_runs_bitwise_identical(tto):
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
 
 
-PLANS = [(256, False, False), (256, True, False)]
-DISABLED_PLANS = [(64, False, False), (128, False, False), (256, False, True)]
+PLANS = [(256, 0, False), (256, 1, False), (256, 2, False)]
+DISABLED_PLANS = [(64, 0, False), (128, 0, False), (256, 0, True)]
 
 
 def test_disabled_sweep_plans_are_rejected(tto):
