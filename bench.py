@@ -325,7 +325,7 @@ def main():
     log(f"[bench] grid ready; ws grid {s.grid_bytes/2**30:.2f} GiB batch {s.batch_bytes/2**30:.2f} GiB")
     if args.sweep_plans:
         tto.tto_profile_enable(s.handle, True)
-        for plan in [(256, 0, 0), (256, 1, 0)]:
+        for plan in [(256, 0, 0), (256, 1, 0), (256, 2, 0)]:
             s.set_sweep_plan(*plan)
             ts = []
             for _ in range(3):
