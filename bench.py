@@ -61,8 +61,8 @@ def cpu_baseline(w, seconds_target=20.0):
     import oracle
     cores = min(16, os.cpu_count() or 1)
     nC = len(w.C)
-    # one candidate per worker, a slice of its contingencies (a few seconds each)
-    n_cont = max(8, min(nC, int(nC * 0.25)))
+    # one candidate per worker, a slice of its contingencies (about 30 s in all)
+    n_cont = max(8, min(nC, nC // 16))
     idx = list(range(cores))
     subset = list(range(n_cont))
     t0 = time.perf_counter()
