@@ -370,11 +370,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     }
   };
 
-  // x(t) for the sweep, which rebuilds f'_M = f0_M + U_M x from it
-  for (int i = tid; i < kMaxRank * TT; i += 256)
-    w.xs[(size_t)c * kMaxRank * TT + i] = s_x[i / TT][i % TT];
-
-  // monitored rows: U_M, and lambda_c0 from the FP64 post-switch flows
+  // monitored rows: f'_M and U_M
   int n0 = 0;
   for (int ei = tid; ei < nM; ei += 256) {
     keep_in_loop();
@@ -385,16 +381,17 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     gather_column(g.SMC, nMC, ei, sh, W);
     u_from_w(e, g.b[e], W, U);
     const double lim = g.lim[e];
-    if (!opened) {
+    F* fo = w.fM + (size_t)c * TT * nM + ei;   // [c][t][ei]: coalesced across threads
 #pragma unroll
-      for (int t = 0; t < TT; ++t) {
-        if (t < T) {
-          double fp = g.f0[(size_t)e * T + t];
+    for (int t = 0; t < TT; ++t) {
+      double fp = 0.0;
+      if (t < T && !opened) {
+        fp = g.f0[(size_t)e * T + t];
 #pragma unroll
-          for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
-          n0 += fabs(fp) > lim;
-        }
+        for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
+        n0 += fabs(fp) > lim;
       }
+      fo[(size_t)t * nM] = (F)fp;
     }
     F* uo = w.UM + (size_t)c * kVSlots * nM + ei;   // [c][q][ei]
 #pragma unroll
@@ -561,18 +558,6 @@ __device__ inline double fma_t(double a, double b, double c) { return __builtin_
 __device__ inline float max3_t(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
 __device__ inline double max3_t(double a, double b, double c) { return fmax(a, fmax(b, c)); }
 
-// Post-switch flow of monitored branch ei at timestep t, rebuilt from the
-// unswitched flows and the candidate's rank-r solution: f0_M(t) + U_M x(t),
-// accumulated in FP64 in a fixed order from the stored U (F precision).  The
-// sweep, finalize and the N-1 dump use this same expression.
-template <typename F, int TT>
-__device__ inline F post_flow(const GridDev& g, const double* __restrict__ xs, const F* U, int R,
-                              int ei, int t) {
-  double v = g.f0M[(size_t)t * g.nM + ei];
-  for (int j = 0; j < R; ++j) v = fma_t((double)U[j], xs[j * TT + t], v);
-  return (F)v;
-}
-
 template <typename F, int TT, int R>
 __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>& w,
                                            const F* __restrict__ HMC, int c, int ei_c,
@@ -580,18 +565,12 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   constexpr int RS = rec_stride(TT);
   const int nM = g.nM, nC = g.nC;
   F U[R > 0 ? R : 1];
+  const F* fa = w.fM + (size_t)c * TT * nM + ei_c;
   const F* ua = w.UM + (size_t)c * kVSlots * nM + ei_c;
 #pragma unroll
+  for (int t = 0; t < TT; ++t) { a[t] = fa[(size_t)t * nM]; acc[t] = (F)0; }
+#pragma unroll
   for (int j = 0; j < R; ++j) U[j] = ua[(size_t)j * nM];
-  const double* __restrict__ xs = w.xs + (size_t)c * kMaxRank * TT;
-#pragma unroll
-  for (int t = 0; t < TT; ++t) {
-    double v = g.f0M[(size_t)t * nM + ei_c];
-#pragma unroll
-    for (int j = 0; j < R; ++j) v = fma_t((double)U[j], xs[j * TT + t], v);
-    a[t] = (F)v;
-    acc[t] = (F)0;
-  }
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
   if (n_act_pad == 0) return;
@@ -918,10 +897,8 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     // every state gives zero flow on an opened branch: first active contingency
     if (inf.n_act > 0 && lane == 0) { bv = 0.0; bi = 0; }
   } else if (be >= 0) {
+    const F a = w.fM[((size_t)c * TT + bt) * nM + be];
     const F* ua = w.UM + (size_t)c * kVSlots * nM + be;
-    F Ub[kMaxRank];
-    for (int j = 0; j < kMaxRank; ++j) Ub[j] = j < inf.r ? ua[(size_t)j * nM] : (F)0;
-    const F a = post_flow<F, TT>(g, w.xs + (size_t)c * kMaxRank * TT, Ub, inf.r, be, bt);
     const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
     const int* act = w.act + (size_t)c * (nC + 1);
     for (int i = lane; i < inf.n_act; i += 64) {
@@ -993,10 +970,8 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
   const int e = g.mon[ei];
   bool opened = false;
   for (int q = 0; q < inf.k; ++q) opened |= (inf.open_br[q] == e);
+  const F* fa = w.fM + (size_t)c * TT * nM + ei;
   const F* ua = w.UM + (size_t)c * kVSlots * nM + ei;
-  F Ue[kMaxRank];
-  for (int j = 0; j < kMaxRank; ++j) Ue[j] = j < inf.r ? ua[(size_t)j * nM] : (F)0;
-  const double* xs = w.xs + (size_t)c * kMaxRank * TT;
   const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
   for (int li = 0; li < nC; ++li) {
     double* out = n1 + (((size_t)c * nC + li) * nM + ei) * T;
@@ -1012,8 +987,7 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
     const F* ri = rec + (size_t)slot * RS;
     F h = HMC[(size_t)li * nM + ei];
     for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
-    for (int t = 0; t < T; ++t)
-      out[t] = (double)fma_t(h, ri[t], post_flow<F, TT>(g, xs, Ue, inf.r, ei, t));
+    for (int t = 0; t < T; ++t) out[t] = (double)fma_t(h, ri[t], fa[(size_t)t * nM]);
   }
 }
 
@@ -1190,7 +1164,6 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     rp.persistent = 0;
     GridDev gh = g;
     gh.f0 = g.f0_hi;   // FP64-GEMM base flows
-    gh.f0M = g.f0M_hi;
     gh.near_margin = -1.0;
     launch_pass<double, TT>(gh, rb, *rw, ro, s, nullptr, rp, none);
   }

@@ -285,23 +285,6 @@ __global__ __launch_bounds__(256) void k_reduce_f0(const P* __restrict__ part, i
   f0[i] = s;
 }
 
-// Monitored base flows, time-major and padded: out[t][ei] = f0[mon[ei]][t]
-// for t < T, 0 for T <= t < TT.
-__global__ __launch_bounds__(256) void k_gather_f0M(const double* __restrict__ f0,
-                                                    const int* __restrict__ mon, int nM, int T,
-                                                    double* __restrict__ out) {
-  const int ei = blockIdx.x * 256 + threadIdx.x, t = blockIdx.y;
-  if (ei >= nM) return;
-  out[(size_t)t * nM + ei] = t < T ? f0[(size_t)mon[ei] * T + t] : 0.0;
-}
-
-hipError_t launch_gather_f0M(const double* f0, const int* mon, int nM, int T, int TT, double* out,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_f0M, dim3((nM + 255) / 256, TT), dim3(256), 0, s, f0, mon, nM, T,
-                     out);
-  return hipGetLastError();
-}
-
 // out = max_i |a_i - b_i| (one workgroup; max is order independent).
 __global__ __launch_bounds__(1024) void k_max_abs_diff(const double* __restrict__ a,
                                                        const double* __restrict__ b, size_t n,

@@ -71,7 +71,6 @@ struct GridLayout {
   // FP64 copy of the base-flow product for the refinement of FP32 grids, and
   // max |f0 - f0_hi| (device scalar)
   double* f0_hi; void* A64; void* PT64; double* part_hi; double* gemm_err;
-  double* f0M; double* f0M_hi;   // monitored base flows [TT][nM]
 };
 
 GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
@@ -90,8 +89,6 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   L.HMC32 = cv.take<float>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
   L.HMC64 = cv.take<double>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
   L.f0 = cv.take<double>(m * T);
-  const size_t TTp = (size_t)tile_T(d->n_timesteps);
-  L.f0M = cv.take<double>(TTp * d->n_monitored);
   const size_t ld = gemm_ld(d->n_bus), mp = gemm_mpad(d->n_branch);
   const size_t es = gemm_esize(d->gemm_precision);
   L.A = cv.take<char>(mp * ld * es);
@@ -106,14 +103,13 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   }
   if (d->gemm_precision == TTO_GEMM_F64 || d->flow_precision == TTO_FLOW_F64) {
     L.f0_hi = nullptr; L.A64 = nullptr; L.PT64 = nullptr; L.part_hi = nullptr;
-    L.gemm_err = nullptr; L.f0M_hi = nullptr;
+    L.gemm_err = nullptr;
   } else {
     L.f0_hi = cv.take<double>(m * T);
     L.A64 = cv.take<double>(mp * ld);
     L.PT64 = cv.take<double>((size_t)kGemmN * ld);
     L.part_hi = cv.take<double>((size_t)L.ksplit * m * kGemmN);
     L.gemm_err = cv.take<double>(1);
-    L.f0M_hi = cv.take<double>(TTp * d->n_monitored);
   }
   (void)n;
   *bytes = cv.off;
@@ -126,7 +122,7 @@ SweepBufs<F> carve_batch(int B, int nM, int nC, int TT, void* ws, size_t* bytes)
   SweepBufs<F> w;
   w.n_eblk = (nM + 63) / 64;
   w.info = cv.take<CandInfo>(B);
-  w.xs = cv.take<double>((size_t)B * kMaxRank * TT);
+  w.fM = cv.take<F>((size_t)B * nM * TT);
   w.UM = cv.take<F>((size_t)B * nM * kVSlots);
   w.rec = cv.take<F>((size_t)B * (nC + 1) * rec_stride(TT));
   w.act = cv.take<int>((size_t)B * (nC + 1));
@@ -311,9 +307,6 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, d->gemm_precision, L.A, s));
   if (L.A64) HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, TTO_GEMM_F64, L.A64, s));
   HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
-  HIP_TRY(hipMemsetAsync(L.f0M, 0, sizeof(double) * tile_T(d->n_timesteps) * d->n_monitored, s));
-  if (L.f0M_hi)
-    HIP_TRY(hipMemsetAsync(L.f0M_hi, 0, sizeof(double) * tile_T(d->n_timesteps) * d->n_monitored, s));
   if (L.f0_hi) {
     HIP_TRY(hipMemsetAsync(L.f0_hi, 0, sizeof(double) * m * d->n_timesteps, s));
     HIP_TRY(hipMemsetAsync(L.gemm_err, 0, sizeof(double), s));
@@ -333,7 +326,6 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   v.n_bus = n; v.n_branch = m; v.slack = d->slack; v.T = g->T; v.TT = g->TT; v.nM = g->nM; v.nC = g->nC;
   v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S; v.SMC = L.SMC;
   v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.f0_hi = L.f0_hi ? L.f0_hi : L.f0; v.mon = L.mon; v.cont = L.cont;
-  v.f0M = L.f0M; v.f0M_hi = L.f0M_hi ? L.f0M_hi : L.f0M;
   v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
   v.near_margin = -1.0;
   v.gemm_err = L.gemm_err;
@@ -377,13 +369,11 @@ tto_status tto_set_injections(tto_grid* g, const double* p_mw, void* stream) {
   HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, g->gemm_prec, g->L.PT, s));
   HIP_TRY(launch_gemm_f0(g->gemm_prec, g->L.A, g->L.PT, g->m, g->n_bus, g->T, g->L.ksplit,
                          g->L.part32, g->L.part64, g->L.f0, s));
-  HIP_TRY(launch_gather_f0M(g->L.f0, g->L.mon, g->nM, g->T, g->TT, g->L.f0M, s));
   if (g->L.f0_hi) {
     HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, TTO_GEMM_F64, g->L.PT64, s));
     HIP_TRY(launch_gemm_f0(TTO_GEMM_F64, g->L.A64, g->L.PT64, g->m, g->n_bus, g->T, g->L.ksplit,
                            nullptr, g->L.part_hi, g->L.f0_hi, s));
     HIP_TRY(launch_max_abs_diff(g->L.f0, g->L.f0_hi, (size_t)g->m * g->T, g->L.gemm_err, s));
-    HIP_TRY(launch_gather_f0M(g->L.f0_hi, g->L.mon, g->nM, g->T, g->TT, g->L.f0M_hi, s));
   }
   return ok();
 }

@@ -46,8 +46,6 @@ struct GridDev {
   const double* HMC64;  // same in FP64
   const double* f0;     // [m][T] base flows of the unswitched grid (GEMM precision)
   const double* f0_hi;  // [m][T] the same from the FP64 GEMM (refinement pass)
-  const double* f0M;    // [TT][nM] f0 of the monitored branches, time-major
-  const double* f0M_hi; // [TT][nM] the same from f0_hi
   const int* mon;       // [nM]
   const int* cont;      // [nC]
   const double* edges;  // [n_load_bins - 1]
@@ -117,7 +115,7 @@ struct Partial {
 template <typename F>
 struct SweepBufs {
   CandInfo* info;   // [B]
-  double* xs;       // [B][8][TT] solution x_q(t) of the candidate's bordered system
+  F* fM;            // [B][nM][TT]
   F* UM;            // [B][nM][8]
   F* rec;           // [B][nC+1][rec_stride(TT)]
   int* act;         // [B][nC+1] contingency index of each record
@@ -147,8 +145,6 @@ hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void*
 hipError_t launch_pack_injections(const double* p, int n, int T, int prec, void* PT, hipStream_t s);
 hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n, int T,
                           int ksplit, float* part32, double* part64, double* f0, hipStream_t s);
-hipError_t launch_gather_f0M(const double* f0, const int* mon, int nM, int T, int TT, double* out,
-                             hipStream_t s);
 hipError_t launch_max_abs_diff(const double* a, const double* b, size_t n, double* out,
                                hipStream_t s);
 int gemm_ksplit(int m, int n);
