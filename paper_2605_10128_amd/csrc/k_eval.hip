@@ -561,7 +561,7 @@ __device__ inline double max3_t(double a, double b, double c) { return fmax(a, f
 template <typename F, int TT, int R>
 __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>& w,
                                            const F* __restrict__ HMC, int c, int ei_c,
-                                           int n_act_pad, F* acc, F* a) {
+                                           int i0, int n_act_pad, F* acc, F* a) {
   constexpr int RS = rec_stride(TT);
   const int nM = g.nM, nC = g.nC;
   F U[R > 0 ? R : 1];
@@ -573,11 +573,11 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   for (int j = 0; j < R; ++j) U[j] = ua[(size_t)j * nM];
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
-  if (n_act_pad == 0) return;
+  if (n_act_pad <= i0) return;
   // Software pipeline: the H entries of the next pair are in flight while the
   // current pair is consumed (the last prefetch re-reads an in-range pair).
-  F hn0 = HMC[(size_t)act[0] * nM + ei_c];
-  F hn1 = HMC[(size_t)act[1] * nM + ei_c];
+  F hn0 = HMC[(size_t)act[i0] * nM + ei_c];
+  F hn1 = HMC[(size_t)act[i0 + 1] * nM + ei_c];
   // Half records (TT >= 16): while timesteps t < TT/2 of a pair are consumed
   // the upper half of the same pair is in flight, and while the upper half is
   // consumed the lower half of the next pair is.
@@ -592,7 +592,7 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
 #pragma unroll
     for (int t = 0; t < TH; ++t) { pa0[t] = rec[t]; pa1[t] = rec[RS + t]; }
   }
-  for (int i = 0; i < n_act_pad; i += 2) {
+  for (int i = i0; i < n_act_pad; i += 2) {
     F h0 = hn0, h1 = hn1;
     const int nx = (i + 2 < n_act_pad) ? i + 2 : i;
     hn0 = HMC[(size_t)act[nx] * nM + ei_c];
@@ -636,46 +636,20 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   }
 }
 
-// One tile = one candidate x BS consecutive monitored branches (one lane
-// each).  Writes the tile's partial reduction.
+// Per-thread reduction over timesteps of a tile's f^max and the tile's
+// partial (sums, counts, top-2 loading, arg-max), shared by both sweeps.
 template <typename F, int TT, int BS>
-__device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>& w,
-                                           const F* __restrict__ HMC,
-                                           double* __restrict__ fmax_out, int c, int eb,
-                                           int oc) {
+__device__ __forceinline__ void tile_epilogue(const GridDev& g, const SweepBufs<F>& w,
+                                              double* __restrict__ fmax_out, int c, int eb,
+                                              int oc, const F* acc) {
   constexpr int NW = BS / 64;
-  // The tile's candidate is uniform by construction on every launch path;
-  // stating it keeps the per-candidate pointers in scalar registers.
-  c = __builtin_amdgcn_readfirstlane(c);
-  eb = __builtin_amdgcn_readfirstlane(eb);
-  oc = __builtin_amdgcn_readfirstlane(oc);
   const CandInfo* inf = w.info + c;
-  const int status = inf->status;
-  if (status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;   // uniform per tile
-  const int r = inf->r, k = inf->k, n_act_pad = inf->n_act_pad;
+  const int k = inf->k;
   const int nM = g.nM, T = g.T;
   const int tid = threadIdx.x;
   const int ei = eb * BS + tid;
   const bool valid = ei < nM;
   const int ei_c = valid ? ei : nM - 1;
-  // waves lying wholly past the monitored set skip the sweep (uniform per wave)
-  const bool wave_live = eb * BS + (int)(tid & ~63) < nM;
-  // wave-uniform by construction; readfirstlane keeps the contingency loop a
-  // scalar loop (its records then load through the scalar cache)
-  const int n_pairs = __builtin_amdgcn_readfirstlane(wave_live ? n_act_pad : 0);
-  F acc[TT], a[TT];
-  switch (r) {
-    case 0: sweep_core<F, TT, 0>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    case 1: sweep_core<F, TT, 1>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    case 2: sweep_core<F, TT, 2>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    case 3: sweep_core<F, TT, 3>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    case 4: sweep_core<F, TT, 4>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    case 5: sweep_core<F, TT, 5>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    case 6: sweep_core<F, TT, 6>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    case 7: sweep_core<F, TT, 7>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-    default: sweep_core<F, TT, 8>(g, w, HMC, c, ei_c, n_pairs, acc, a); break;
-  }
-  // per-thread reduction over timesteps
   const int e = g.mon[ei_c];
   bool opened = false;
   for (int q = 0; q < k; ++q) opened |= (inf->open_br[q] == e);
@@ -749,6 +723,48 @@ __device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>&
 // tiles of one candidate are remapped onto one XCD (its records then come
 // into one L2).  Persistent: a machine-sized grid pulls tiles from a counter
 // in rank-descending candidate order (longest tiles first).
+// One tile = one candidate x BS consecutive monitored branches (one lane
+// each).  Writes the tile's partial reduction.
+template <typename F, int TT, int BS>
+__device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>& w,
+                                           const F* __restrict__ HMC,
+                                           double* __restrict__ fmax_out, int c, int eb,
+                                           int oc) {
+  constexpr int NW = BS / 64;
+  // The tile's candidate is uniform by construction on every launch path;
+  // stating it keeps the per-candidate pointers in scalar registers.
+  c = __builtin_amdgcn_readfirstlane(c);
+  eb = __builtin_amdgcn_readfirstlane(eb);
+  oc = __builtin_amdgcn_readfirstlane(oc);
+  const CandInfo* inf = w.info + c;
+  const int status = inf->status;
+  if (status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;   // uniform per tile
+  const int r = inf->r, k = inf->k, n_act_pad = inf->n_act_pad;
+  const int nM = g.nM, T = g.T;
+  const int tid = threadIdx.x;
+  const int ei = eb * BS + tid;
+  const bool valid = ei < nM;
+  const int ei_c = valid ? ei : nM - 1;
+  // waves lying wholly past the monitored set skip the sweep (uniform per wave)
+  const bool wave_live = eb * BS + (int)(tid & ~63) < nM;
+  // wave-uniform by construction; readfirstlane keeps the contingency loop a
+  // scalar loop (its records then load through the scalar cache)
+  const int n_pairs = __builtin_amdgcn_readfirstlane(wave_live ? n_act_pad : 0);
+  F acc[TT], a[TT];
+  switch (r) {
+    case 0: sweep_core<F, TT, 0>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    case 1: sweep_core<F, TT, 1>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    case 2: sweep_core<F, TT, 2>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    case 3: sweep_core<F, TT, 3>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    case 4: sweep_core<F, TT, 4>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    case 5: sweep_core<F, TT, 5>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    case 6: sweep_core<F, TT, 6>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    case 7: sweep_core<F, TT, 7>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+    default: sweep_core<F, TT, 8>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+  }
+  tile_epilogue<F, TT, BS>(g, w, fmax_out, c, eb, oc, acc);
+}
+
 template <typename F, int TT, int BS>
 __global__ __launch_bounds__(BS) void k_sweep(GridDev g, SweepBufs<F> w,
                                               const F* __restrict__ HMC,
@@ -1053,6 +1069,87 @@ hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, con
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// FP64 refinement sweep, split over contingency ranges so that a handful of
+// queued candidates still fill the machine: workgroup (candidate, monitored
+// block, range s of S) merges the f^max of its range into fbuf by an atomic
+// max on the bit patterns (the values are >= 0, so the integer order is the
+// numeric order: order-free and exact); k_sweep_split_epi then runs the usual
+// tile epilogue on the merged maxima.
+__global__ __launch_bounds__(256) void k_zero_live_u64(unsigned long long* __restrict__ p,
+                                                       const int* __restrict__ live, int cap,
+                                                       size_t per) {
+  const size_t n = (size_t)min(*live, cap) * per;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    p[i] = 0ull;
+}
+
+template <int TT, int BS>
+__global__ __launch_bounds__(BS) void k_sweep_split(GridDev g, SweepBufs<double> w,
+                                                    const double* __restrict__ HMC, int n_cand,
+                                                    int S, const int* __restrict__ live,
+                                                    unsigned long long* __restrict__ fbuf) {
+  const int nc = min(*live, n_cand);
+  int q = blockIdx.x;
+  if (q >= nc * w.n_eblk * S) return;
+  const int sr = __builtin_amdgcn_readfirstlane(q % S);
+  q /= S;
+  const int c = __builtin_amdgcn_readfirstlane(q / w.n_eblk);
+  const int eb = __builtin_amdgcn_readfirstlane(q - c * w.n_eblk);
+  const CandInfo* inf = w.info + c;
+  if (inf->status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;
+  const int r = inf->r, n_act_pad = inf->n_act_pad, nM = g.nM;
+  const int per = ((n_act_pad >> 1) + S - 1) / S;       // pairs per range
+  const int i0 = 2 * sr * per;
+  const int i1 = min(n_act_pad, 2 * (sr + 1) * per);
+  const int tid = threadIdx.x;
+  const int ei = eb * BS + tid;
+  const bool valid = ei < nM;
+  const int ei_c = valid ? ei : nM - 1;
+  const bool wave_live = eb * BS + (int)(tid & ~63) < nM;
+  const int end = __builtin_amdgcn_readfirstlane(wave_live ? i1 : 0);
+  double acc[TT], a[TT];
+  switch (r) {
+    case 0: sweep_core<double, TT, 0>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    case 1: sweep_core<double, TT, 1>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    case 2: sweep_core<double, TT, 2>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    case 3: sweep_core<double, TT, 3>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    case 4: sweep_core<double, TT, 4>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    case 5: sweep_core<double, TT, 5>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    case 6: sweep_core<double, TT, 6>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    case 7: sweep_core<double, TT, 7>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+    default: sweep_core<double, TT, 8>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
+  }
+  if (valid && i0 < i1) {
+    unsigned long long* out = fbuf + (size_t)c * TT * nM + ei;
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+      atomicMax(out + (size_t)t * nM, (unsigned long long)__double_as_longlong(acc[t]));
+  }
+}
+
+template <int TT, int BS>
+__global__ __launch_bounds__(BS) void k_sweep_split_epi(GridDev g, SweepBufs<double> w,
+                                                        double* __restrict__ fmax_out,
+                                                        int n_cand, const int* __restrict__ map,
+                                                        const int* __restrict__ live,
+                                                        const unsigned long long* __restrict__ fbuf) {
+  const int nc = min(*live, n_cand);
+  const int q = blockIdx.x;
+  if (q >= nc * w.n_eblk) return;
+  const int c = __builtin_amdgcn_readfirstlane(q / w.n_eblk);
+  const int eb = __builtin_amdgcn_readfirstlane(q - c * w.n_eblk);
+  const int oc = __builtin_amdgcn_readfirstlane(map[c]);
+  if (w.info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;
+  const int nM = g.nM;
+  const int ei_c = min(eb * BS + (int)threadIdx.x, nM - 1);
+  const unsigned long long* in = fbuf + (size_t)c * TT * nM + ei_c;
+  double acc[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) acc[t] = __longlong_as_double((long long)in[(size_t)t * nM]);
+  tile_epilogue<double, TT, BS>(g, w, fmax_out, c, eb, oc, acc);
+}
+
 template <typename F, int TT, int BS>
 static void launch_sweep(const GridDev& g, const BatchDev& bt, SweepBufs<F> w, const F* HMC,
                          double* fmax_out, hipStream_t s, const SweepPlan& plan) {
@@ -1165,7 +1262,22 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     GridDev gh = g;
     gh.f0 = g.f0_hi;   // FP64-GEMM base flows
     gh.near_margin = -1.0;
-    launch_pass<double, TT>(gh, rb, *rw, ro, s, nullptr, rp, none);
+    SweepBufs<double> w64 = *rw;
+    w64.n_eblk = (g.nM + 255) / 256;
+    constexpr int kSplit = 8;
+    hipLaunchKernelGGL((k_setup<double, TT>), dim3(rb.B), dim3(256), 0, s, gh, rb, w64,
+                       (double*)nullptr);
+    hipLaunchKernelGGL(k_zero_live_u64, dim3(1024), dim3(256), 0, s, rc.fbuf,
+                       (const int*)rc.count, rc.cap, (size_t)TT * g.nM);
+    hipLaunchKernelGGL((k_sweep_split<TT, 256>), dim3(rb.B * w64.n_eblk * kSplit), dim3(256), 0,
+                       s, gh, w64, (const double*)g.HMC64, rb.B, kSplit, (const int*)rc.count,
+                       rc.fbuf);
+    hipLaunchKernelGGL((k_sweep_split_epi<TT, 256>), dim3(rb.B * w64.n_eblk), dim3(256), 0, s,
+                       gh, w64, ro.fmax, rb.B, (const int*)rc.list, (const int*)rc.count,
+                       (const unsigned long long*)rc.fbuf);
+    hipLaunchKernelGGL((k_finalize<double, TT>), dim3(rb.B), dim3(64), 0, s, gh, w64,
+                       (const double*)g.HMC64, ro, rb.map, rb.live, rb.B, none);
+    (void)rp;
   }
   if (ev) hipEventRecord(ev[4], s);
   return hipGetLastError();

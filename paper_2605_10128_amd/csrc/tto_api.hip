@@ -156,10 +156,12 @@ BatchLayout batch_layout(int flow_prec, int B, int max_batch, int nM, int nC, in
   if (flow_prec == TTO_FLOW_F32) {
     size_t rb = 0;
     carve_batch<double>(refine_cap(max_batch), nM, nC, TT, nullptr, &rb);
-    // FP64 buffers, then count (256 B), list [cap], flags [max_batch]
+    // FP64 buffers, then count (256 B), list [cap], flags [max_batch],
+    // f^max bit patterns [cap][TT][nM] of the split FP64 sweep
     L.bytes = L.refine_off + round256(rb) + 256 +
               round256(sizeof(int) * (size_t)refine_cap(max_batch)) +
-              sizeof(int) * (size_t)max_batch + 256;
+              round256(sizeof(int) * (size_t)max_batch) +
+              sizeof(unsigned long long) * (size_t)refine_cap(max_batch) * TT * nM + 256;
   }
   return L;
 }
@@ -436,7 +438,7 @@ tto_status tto_evaluate(tto_grid* g, const tto_batch* bt, const tto_outputs* out
   const bool prof = g->profile && !capturing(s);
   size_t used = 0;
   RefineCtl rc;
-  rc.list = nullptr; rc.count = nullptr; rc.flags = nullptr; rc.cap = 0;
+  rc.list = nullptr; rc.count = nullptr; rc.flags = nullptr; rc.fbuf = nullptr; rc.cap = 0;
   rc.margin = g->refine_margin;
   if (g->flow_prec == TTO_FLOW_F32) {
     SweepBufs<float> w = carve_batch<float>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
@@ -454,6 +456,8 @@ tto_status tto_evaluate(tto_grid* g, const tto_batch* bt, const tto_outputs* out
       rc.count = (int*)tail;
       rc.list = (int*)(tail + 256);
       rc.flags = (int*)(tail + 256 + round256(sizeof(int) * (size_t)cap));
+      rc.fbuf = (unsigned long long*)((char*)rc.flags +
+                                      round256(sizeof(int) * (size_t)g->max_batch));
       rc.cap = cap;
       rwp = &rw;
     }

@@ -83,6 +83,7 @@ struct RefineCtl {
   int* list;        // [cap] candidates to re-evaluate in FP64, in index order
   int* count;       // number flagged (may exceed cap)
   int* flags;       // [B] 1 if the candidate's FP32 decisions are near a threshold
+  unsigned long long* fbuf;   // [cap][TT][nM] f^max bit patterns of the FP64 pass
   int cap;
   double margin;    // flow error margin in MW
 };
