@@ -578,20 +578,6 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   // current pair is consumed (the last prefetch re-reads an in-range pair).
   F hn0 = HMC[(size_t)act[i0] * nM + ei_c];
   F hn1 = HMC[(size_t)act[i0 + 1] * nM + ei_c];
-  // Half records (TT >= 16): while timesteps t < TT/2 of a pair are consumed
-  // the upper half of the same pair is in flight, and while the upper half is
-  // consumed the lower half of the next pair is.
-#if defined(TTO_SWEEP_HALF)
-  constexpr bool kHalf = TT >= 16;
-#else
-  constexpr bool kHalf = false;
-#endif
-  constexpr int TH = kHalf ? TT / 2 : 1;
-  F pa0[TH], pa1[TH];
-  if constexpr (kHalf) {
-#pragma unroll
-    for (int t = 0; t < TH; ++t) { pa0[t] = rec[t]; pa1[t] = rec[RS + t]; }
-  }
   for (int i = i0; i < n_act_pad; i += 2) {
     F h0 = hn0, h1 = hn1;
     const int nx = (i + 2 < n_act_pad) ? i + 2 : i;
@@ -599,39 +585,16 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
     hn1 = HMC[(size_t)act[nx + 1] * nM + ei_c];
     const F* r0 = rec + (size_t)i * RS;
     const F* r1 = r0 + RS;
-    F pb0[kHalf ? TT - TH : 1], pb1[kHalf ? TT - TH : 1];
-    if constexpr (kHalf) {
-#pragma unroll
-      for (int t = 0; t < TT - TH; ++t) { pb0[t] = r0[TH + t]; pb1[t] = r1[TH + t]; }
-    }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       h0 = fma_t(U[j], r0[TT + j], h0);
       h1 = fma_t(U[j], r1[TT + j], h1);
     }
-    if constexpr (kHalf) {
-#pragma unroll
-    for (int t = 0; t < TH; ++t) {
-      const F g0 = fma_t(h0, pa0[t], a[t]);
-      const F g1 = fma_t(h1, pa1[t], a[t]);
-      acc[t] = max3_t(acc[t], fabs_t(g0), fabs_t(g1));
-    }
-    const F* q0 = rec + (size_t)nx * RS;
-#pragma unroll
-    for (int t = 0; t < TH; ++t) { pa0[t] = q0[t]; pa1[t] = q0[RS + t]; }
-#pragma unroll
-    for (int t = 0; t < TT - TH; ++t) {
-      const F g0 = fma_t(h0, pb0[t], a[TH + t]);
-      const F g1 = fma_t(h1, pb1[t], a[TH + t]);
-      acc[TH + t] = max3_t(acc[TH + t], fabs_t(g0), fabs_t(g1));
-    }
-    } else {
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
       const F g0 = fma_t(h0, r0[t], a[t]);
       const F g1 = fma_t(h1, r1[t], a[t]);
       acc[t] = max3_t(acc[t], fabs_t(g0), fabs_t(g1));
-    }
     }
   }
 }
