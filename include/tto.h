@@ -346,8 +346,9 @@ tto_status tto_batch_gather(const tto_batch* src, const int32_t* idx, int32_t k,
  * input = the candidate's action bitmask (CSR list of set bit ids) and a
  * dense summary (e.g. per-timestep injection totals); outputs trained on the
  * exact evaluator's (maximum loading, log overload).  W1b, W1d, W2, W3 are
- * used in BF16 (MFMA, FP32 accumulation); activations are BF16; biases, W4
- * and the Adam master weights are FP32.  Loss 1/(2B) sum (y - t)^2.
+ * used in BF16 (MFMA, FP32 accumulation); the dense inputs and the hidden
+ * activations are BF16; biases, W4 and the Adam master weights are FP32.
+ * Loss 1/(2B) sum (y - t)^2.
  * Parameters are one flat FP32 array in the order W1b [d_bits][width],
  * W1d [d_dense][width], b1, W2 [width][width], b2, W3, b3, W4 [width][2], b4.
  */

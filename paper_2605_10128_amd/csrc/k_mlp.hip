@@ -143,21 +143,20 @@ __device__ inline bool row_bit_ok(const int* __restrict__ idx, int lo, int p, in
   return true;
 }
 
-// First layer (embedding bag): z1[b][j] = b1[j] + sum_d dense[b][d] W1d[d][j]
-// + sum_{i in bits(b)} W1b[i][j] (BF16 weights, FP32 sum); h1 = relu(z1).
+// First layer (embedding bag): z1[b][j] = b1[j] + (dense W1d)[b][j] + sum over
+// the row's bit set of W1b[i][j] (BF16 weights, FP32 sum); h1 = relu(z1).  The
+// dense product comes from the BF16 MFMA GEMM (zd, FP32) or is absent.
 __global__ __launch_bounds__(256) void k_mlp_l1(const int* __restrict__ off,
                                                 const int* __restrict__ idx,
-                                                const float* __restrict__ dense, int d_dense,
-                                                int d_bits,
+                                                const float* __restrict__ zd, int d_bits,
                                                 const unsigned short* __restrict__ W1b,
-                                                const unsigned short* __restrict__ W1d,
                                                 const float* __restrict__ b1, int H,
                                                 unsigned short* __restrict__ h1) {
   const int b = blockIdx.x;
   const int lo = off[b], hi = off[b + 1];
   for (int j = threadIdx.x; j < H; j += 256) {
     float z = b1[j];
-    for (int d = 0; d < d_dense; ++d) z += dense[(size_t)b * d_dense + d] * bf16_to_f(W1d[(size_t)d * H + j]);
+    if (zd) z += zd[(size_t)b * H + j];   // dense part, from the MFMA GEMM
     const int end = min(hi, lo + kMlpRowBits);
     for (int p = lo; p < end; ++p) {
       const int i = idx[p];
@@ -453,25 +452,25 @@ __global__ __launch_bounds__(1024) void k_topk_smallest(const float* __restrict_
 
 // ---------------------------------------------------------------------------
 // Batch gather: copy the genomes idx[0..k) into a compact batch.  One
-// workgroup; moved-list offsets by an ordered block scan over the gathered
-// split slots.
-__global__ __launch_bounds__(1024) void k_batch_gather(
-    const int* __restrict__ open, const int* __restrict__ sbus, const int* __restrict__ moff,
-    const int* __restrict__ mbr, const double* __restrict__ mp, int n_src, int no, int ns, int T,
-    const int* __restrict__ idx, int k, int* __restrict__ d_open, int* __restrict__ d_sbus,
-    int* __restrict__ d_moff, int* __restrict__ d_mbr, int cap, double* __restrict__ d_mp) {
+// workgroup scans the gathered split slots in order (moved-list offsets and
+// split buses); a second, machine-wide kernel copies the openings, moved
+// lists and moved injections.
+__global__ __launch_bounds__(1024) void k_gather_scan(
+    const int* __restrict__ sbus, const int* __restrict__ moff, int n_src, int ns,
+    const int* __restrict__ idx, int k, int* __restrict__ d_sbus, int* __restrict__ d_moff,
+    int cap) {
   __shared__ int s_wsum[16];
   __shared__ int s_base;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) { s_base = 0; d_moff[0] = 0; }
   __syncthreads();
   const int slots = k * ns;
-  for (int s0 = 0; s0 < slots || (ns == 0 && s0 == 0); s0 += 1024) {
+  for (int s0 = 0; s0 < slots; s0 += 1024) {
     const int sl = s0 + tid;
-    int len = 0, src = 0, c = 0, j = 0;
+    int len = 0, src = 0, j = 0;
     bool okc = false;
     if (sl < slots) {
-      c = sl / ns;
+      const int c = sl / ns;
       j = sl - c * ns;
       src = idx[c];
       okc = src >= 0 && src < n_src;
@@ -491,15 +490,10 @@ __global__ __launch_bounds__(1024) void k_batch_gather(
     const int start = pre + v - len;
     if (sl < slots) {
       const bool fits = start + len <= cap;
-      d_sbus[sl] = okc ? (fits ? sbus[(size_t)src * ns + j] : (sbus[(size_t)src * ns + j] == -1 ? -1 : -2)) : -2;
-      const int ln = fits ? len : 0;
-      for (int q = 0; q < ln; ++q) d_mbr[start + q] = mbr[moff[(size_t)src * ns + j] + q];
+      const int bus = okc ? sbus[(size_t)src * ns + j] : -2;
+      d_sbus[sl] = fits ? bus : (bus == -1 ? -1 : -2);
       // clipped end: monotone and inside [0, cap] even past the first overflow
       d_moff[sl + 1] = min(start + len, cap);
-      if (d_mp) {
-        for (int t = 0; t < T; ++t)
-          d_mp[(size_t)sl * T + t] = (okc && mp) ? mp[((size_t)src * ns + j) * T + t] : 0.0;
-      }
     }
     __syncthreads();
     if (tid == 0) {
@@ -508,9 +502,33 @@ __global__ __launch_bounds__(1024) void k_batch_gather(
       s_base += sum;
     }
     __syncthreads();
-    if (ns == 0) break;
   }
-  for (int i = tid; i < k * no; i += 1024) {
+}
+
+// One thread per gathered split slot and per gathered opening slot.  A slot's
+// moved list is copied when its range got its full length (it fitted).
+__global__ __launch_bounds__(256) void k_gather_copy(
+    const int* __restrict__ open, const int* __restrict__ moff, const int* __restrict__ mbr,
+    const double* __restrict__ mp, int n_src, int no, int ns, int T,
+    const int* __restrict__ idx, int k, int* __restrict__ d_open,
+    const int* __restrict__ d_moff, int* __restrict__ d_mbr, double* __restrict__ d_mp) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < k * ns) {
+    const int c = i / ns, j = i - c * ns;
+    const int src = idx[c];
+    const bool okc = src >= 0 && src < n_src;
+    if (okc) {
+      const int lo = moff[(size_t)src * ns + j];
+      const int len = moff[(size_t)src * ns + j + 1] - lo;
+      const int dlo = d_moff[i], dhi = d_moff[i + 1];
+      if (len > 0 && dhi - dlo == len)
+        for (int q = 0; q < len; ++q) d_mbr[dlo + q] = mbr[lo + q];
+    }
+    if (d_mp)
+      for (int t = 0; t < T; ++t)
+        d_mp[(size_t)i * T + t] = (okc && mp) ? mp[((size_t)src * ns + j) * T + t] : 0.0;
+  }
+  if (i < k * no) {
     const int c = i / no, q = i - c * no;
     const int src = idx[c];
     d_open[i] = (src >= 0 && src < n_src) ? open[(size_t)src * no + q] : -2;
@@ -521,8 +539,12 @@ void batch_gather(const int* open, const int* sbus, const int* moff, const int* 
                   const double* mp, int n_src, int no, int ns, int T, const int* idx, int k,
                   int* d_open, int* d_sbus, int* d_moff, int* d_mbr, int cap, double* d_mp,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_gather, dim3(1), dim3(1024), 0, s, open, sbus, moff, mbr, mp, n_src,
-                     no, ns, T, idx, k, d_open, d_sbus, d_moff, d_mbr, cap, d_mp);
+  hipLaunchKernelGGL(k_gather_scan, dim3(1), dim3(1024), 0, s, sbus, moff, n_src, ns, idx, k,
+                     d_sbus, d_moff, cap);
+  const int n = k * (ns > no ? ns : no);
+  if (n > 0)
+    hipLaunchKernelGGL(k_gather_copy, dim3((n + 255) / 256), dim3(256), 0, s, open, moff, mbr, mp,
+                       n_src, no, ns, T, idx, k, d_open, (const int*)d_moff, d_mbr, d_mp);
 }
 
 static inline int cdiv_m(long a, int b) { return (int)((a + b - 1) / b); }
@@ -544,10 +566,15 @@ static void colsum(const T* x, int B, int n, float* part, float* out, hipStream_
 // ---------------------------------------------------------------------------
 void mlp_forward(const MlpDev& p, const MlpBatch& wb, const int* off, const int* idx,
                  const float* dense, int B, float* y, hipStream_t s) {
-  const int H = p.H;
-  hipLaunchKernelGGL(k_mlp_l1, dim3(B), dim3(256), 0, s, off, idx, dense, p.d_dense, p.d_bits,
-                     p.W1b_h,
-                     p.W1d_h, p.b1, H, wb.h1);
+  const int H = p.H, dd = p.d_dense;
+  if (dd > 0) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)B * dd, 256)), dim3(256), 0, s, dense,
+                       (size_t)B * dd, wb.Xd);
+    gemm<false, false, 0>(wb.Xd, p.W1d_h, B, H, dd, wb.zd, nullptr, nullptr, nullptr, s);
+  }
+  hipLaunchKernelGGL(k_mlp_l1, dim3(B), dim3(256), 0, s, off, idx,
+                     dd > 0 ? (const float*)wb.zd : (const float*)nullptr, p.d_bits, p.W1b_h,
+                     p.b1, H, wb.h1);
   gemm<false, false, 1>(wb.h1, p.W2_h, B, H, H, nullptr, wb.h2, p.b2, nullptr, s);
   gemm<false, false, 1>(wb.h2, p.W3_h, B, H, H, nullptr, wb.h3, p.b3, nullptr, s);
   hipLaunchKernelGGL(k_mlp_out, dim3(B), dim3(64), 0, s, wb.h3, p.W4, p.b4, H, y);
@@ -589,11 +616,8 @@ void mlp_gradients(const MlpDev& p, const MlpBatch& wb, const int* off, const in
   hipLaunchKernelGGL((k_bits_bucket<true>), dim3(nb), dim3(256), 0, s, off, idx, B, db,
                      wb.cursor, wb.list);
   hipLaunchKernelGGL(k_w1b_grad, dim3(db), dim3(256), 0, s, wb.start, wb.list, wb.dz1, H, g.W1b);
-  if (dd > 0) {
-    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)B * dd, 256)), dim3(256), 0, s, dense,
-                       (size_t)B * dd, wb.Xd);
+  if (dd > 0)   // wb.Xd holds the BF16 dense inputs from the forward pass
     gemm<true, false, 0>(wb.Xd, wb.dz1, dd, H, B, g.W1d, nullptr, nullptr, nullptr, s);
-  }
 }
 
 void mlp_adam(const MlpDev& p, const float* grad, float lr, int step, hipStream_t s) {

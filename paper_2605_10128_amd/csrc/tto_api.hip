@@ -651,7 +651,8 @@ MlpBatch carve_mlp_batch(const tto_mlp_desc* d, void* ws, size_t* bytes) {
   b.start = cv.take<int>((size_t)d->d_bits + 1);
   b.cursor = cv.take<int>((size_t)d->d_bits);
   b.list = cv.take<int>(Bt * (size_t)kMlpRowBits);
-  b.Xd = cv.take<unsigned short>(std::max(Bt * (size_t)d->d_dense, (size_t)1));
+  b.Xd = cv.take<unsigned short>(std::max(Ba * (size_t)d->d_dense, (size_t)1));
+  b.zd = cv.take<float>(d->d_dense > 0 ? Ba * H : (size_t)1);
   b.y = cv.take<float>(Ba * 2);
   b.dy = cv.take<float>(Bt * 2);
   b.lterm = cv.take<float>(Bt);

@@ -64,6 +64,7 @@ struct MlpBatch {
   int* cursor;                       // [d_bits] fill cursors
   int* list;                         // [B * kMlpRowBits] samples per bit
   unsigned short* Xd;                // [B][d_dense] BF16 dense inputs
+  float* zd;                         // [B][H] dense inputs times W1d (FP32)
   float* y;                          // [B][2]
   float* dy;                         // [B][2]
   float* lterm;                      // [B]
