@@ -429,6 +429,139 @@ tto_status tto_evaluate_capture(tto_grid* grid, const tto_batch* batch, const tt
                                 int64_t* elite_id, int32_t n_cells, int64_t id_base,
                                 tto_graph** graph);
 
+/* ------------------------------------------------------------------------
+ * MapElites generation on the device (DC-Optimizer: Repertoire design,
+ * Mutation Alg. 1, Crossover Alg. 2, High-level loop Alg. 3): parents are
+ * drawn from the repertoire, varied, expanded into a tto_batch, scored by
+ * tto_evaluate and inserted, with no host synchronisation, so that a
+ * generation can be captured once and replayed for a whole epoch.
+ *
+ * Genome: int32 [N_a action slots | N_d disconnection slots].  An action slot
+ * holds an id into the split-action set A (each action splits one substation,
+ * i.e. one bus, and names the branches it moves to busbar B), a disconnection
+ * slot an index into the disconnectable-branch set D; -1 is the empty slot.
+ *
+ * Random numbers are Philox4x32-10 words addressed by (seed, generation,
+ * child, draw position), so a generation's children depend only on the seed,
+ * the generation counter and the repertoire.  Operator rules where the paper
+ * leaves the sampling open:
+ *   - Action Add: a uniform action outside every substation the individual
+ *     splits, into a uniform empty slot; action Change: a uniform other action
+ *     of a split substation, into that substation's slot; Remove: a uniform
+ *     filled slot.  Disconnection Add / Change draw from D minus the current
+ *     entries.  Operations are drawn with the integer weights over those that
+ *     are feasible; N_mut = clip(Poisson(mut_mean), 1, N_a); the
+ *     disconnection step takes Add when the individual (after its action
+ *     steps) holds nothing.
+ *   - Crossover: each child slot picks parent 1 with probability p_c1 (the
+ *     other parent when one has nothing left), then a uniform remaining entry
+ *     of that parent, empty entries included; the value also leaves the other
+ *     parent once; an action at a substation the child already splits becomes
+ *     empty.
+ *   - Generation: b_mc uniform on 0..n_child; children [0, b_mc) are
+ *     mutations, the rest crossovers; parents uniform over the occupied cells
+ *     (the empty individual while none is occupied).  Parent genomes are
+ *     first made feasible: out-of-range entries, actions at a substation an
+ *     earlier slot splits and repeated disconnections read as empty.
+ * Children may still be INVALID for tto_evaluate (a disconnected branch that
+ * an action moves, more than TTO_MAX_MOVED moved branches); such children
+ * never enter the repertoire.
+ */
+#define TTO_MAX_CELLS 4096
+
+typedef struct tto_genome_space tto_genome_space;  /* opaque host handle */
+
+typedef struct {
+  int32_t n_action_slots;           /* N_a, 0..TTO_MAX_RANK */
+  int32_t n_disc_slots;             /* N_d, 0..TTO_MAX_RANK */
+  int32_t n_actions;                /* |A| >= 0 */
+  const int32_t* action_bus;        /* host [n_actions] substation (bus) of each action */
+  const int32_t* action_moved_off;  /* host [n_actions + 1] CSR offsets */
+  const int32_t* action_moved_br;   /* host, distinct branches incident to the bus,
+                                       at most TTO_MAX_MOVED per action */
+  int32_t n_disc;                   /* |D| >= 0 */
+  const int32_t* disc_branch;       /* host [n_disc] distinct branch ids */
+  double mut_mean;                  /* N_mutmean >= 0 (paper: 2) */
+  int32_t w_action[4];              /* Add, Remove, Change, Identity weights >= 0
+                                       (paper: 20 20 50 10) */
+  int32_t w_disc[4];                /* (paper: 25 25 50 0) */
+  double p_c1;                      /* crossover bias toward parent 1, 0..1 */
+} tto_genome_desc;
+
+/* Device bytes of the genome tables (host only). */
+tto_status tto_genome_space_bytes(const tto_genome_desc* desc, size_t* bytes);
+
+/*
+ * Validate the tables against the grid (ids in range, moved lists non-empty,
+ * distinct and incident to their bus, D distinct) and upload them into ws
+ * (device, 256-byte aligned, tto_genome_space_bytes long; caller-owned, kept
+ * untouched until tto_genome_space_destroy).  Synchronises `stream`.
+ * TTO_E_GRID for a table that does not fit the grid, TTO_E_RANK for slot
+ * counts beyond TTO_MAX_RANK.
+ */
+tto_status tto_genome_space_create(const tto_grid* grid, const tto_genome_desc* desc, void* ws,
+                                   size_t bytes, void* stream, tto_genome_space** out);
+
+void tto_genome_space_destroy(tto_genome_space* gs);
+
+/* Upper bound of moved branches per expanded candidate (N_a x longest action). */
+tto_status tto_genome_max_moved(const tto_genome_space* gs, int32_t* per_candidate);
+
+/*
+ * Variation step of one generation (Alg. 3 with Alg. 1 and 2): children
+ * [n_child][N_a + N_d] (device out) from the repertoire's occupied cells
+ * (elite_id [n_cells] device, -1 = empty; elite_genome [n_cells][N_a + N_d]
+ * device) for generation *generation (device int64, read only).  b_mc
+ * (device int32, may be NULL) receives the number of mutated children.
+ * n_cells 1..TTO_MAX_CELLS.
+ */
+tto_status tto_vary(const tto_genome_space* gs, const int64_t* elite_id,
+                    const int32_t* elite_genome, int32_t n_cells, uint64_t seed,
+                    const int64_t* generation, int32_t n_child, int32_t* children,
+                    int32_t* b_mc, void* stream);
+
+/*
+ * Genomes [n][N_a + N_d] (device) -> tto_batch arrays (device, caller-owned):
+ * open [n][N_d] (D index -> branch id), split_bus [n][N_a] (action -> bus),
+ * moved_off [n*N_a + 1] and moved_br (the action's list).  Empty slots give
+ * -1, out-of-range ids -2 (an INVALID candidate).  moved_cap (entries of
+ * moved_br) must be at least n * tto_genome_max_moved; split_bus, moved_off
+ * and moved_br may be NULL iff N_a == 0, open iff N_d == 0.
+ */
+tto_status tto_genome_expand(const tto_genome_space* gs, const int32_t* genomes, int32_t n,
+                             int32_t* open, int32_t* split_bus, int32_t* moved_off,
+                             int32_t* moved_br, int64_t moved_cap, void* stream);
+
+/* Repertoire in device memory (caller-owned).  Empty cells have id -1. */
+typedef struct {
+  int32_t n_cells;          /* 1..TTO_MAX_CELLS, = the descriptor's cell count */
+  double* fitness;          /* [n_cells] */
+  int64_t* id;              /* [n_cells] generation * n_child + child index */
+  int32_t* genome;          /* [n_cells][N_a + N_d] */
+  int64_t* generation;      /* [1] generations completed so far */
+} tto_repertoire;
+
+/* Bytes of gen_ws for tto_generation with n_child children (host only). */
+tto_status tto_generation_bytes(const tto_grid* grid, const tto_genome_space* gs,
+                                int32_t n_child, size_t* bytes);
+
+/*
+ * One generation of Alg. 3 on `stream`: tto_vary, tto_genome_expand,
+ * tto_evaluate (batch_ws as for tto_evaluate), insertion into the repertoire
+ * (one elite per cell, ties to the lowest child index, strictly better
+ * replaces; the genome is copied with the fitness and id), then
+ * *generation += 1.  gen_ws (device, 256-byte aligned) holds the children
+ * [n_child][N_a + N_d] int32 at offset 0, the int32 b_mc at byte offset
+ * round_up(4 n_child (N_a + N_d), 256), and the expanded batch and the
+ * status / fitness / cell outputs after it.  `out` may be NULL; otherwise its
+ * non-NULL fields receive the outputs as from tto_evaluate.  No host
+ * synchronisation: a generation can be captured between tto_graph_begin and
+ * tto_graph_end and replayed; each replay advances the counter.
+ */
+tto_status tto_generation(tto_grid* grid, const tto_genome_space* gs, const tto_repertoire* rep,
+                          uint64_t seed, int32_t n_child, const tto_outputs* out, void* gen_ws,
+                          size_t gen_bytes, void* batch_ws, size_t batch_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,9 @@ What it follows (DC-Optimizer section of the paper):
   - High-level loop (Alg. 3): per generation a mutation/crossover split
     b_mc ~ U{0..b}; parents uniform over the occupied cells (the empty
     individual while the repertoire is empty); evaluation; one elite per
-    cell, strictly-better replacement.
+    cell, strictly-better replacement.  A parent is first made feasible:
+    out-of-range entries, actions at a substation an earlier slot already
+    splits and repeated disconnections read as empty.
 
 Random numbers.  The method draws random numbers whose count depends on the
 state (feasible operations, pool sizes), so they cannot be handed in as an
@@ -330,6 +332,19 @@ def crossover(gs: GenomeSpace, g1: Sequence[int], g2: Sequence[int],
 
 
 # ---------------------------------------------------------------- Alg. 3
+def feasible_parent(gs: GenomeSpace, genome: Sequence[int]) -> List[int]:
+    a, d = [], []
+    for v in (int(x) for x in genome[: gs.n_a]):
+        if not 0 <= v < gs.n_actions or gs.bus(v) in {gs.bus(u) for u in a if u != -1}:
+            v = -1
+        a.append(v)
+    for v in (int(x) for x in genome[gs.n_a: gs.n_a + gs.n_d]):
+        if not 0 <= v < gs.n_disc or v in d:
+            v = -1
+        d.append(v)
+    return a + d
+
+
 def vary(gs: GenomeSpace, elite_id: np.ndarray, elite_genome: np.ndarray, seed: int, gen: int,
          n_child: int) -> Tuple[np.ndarray, int]:
     """Children genomes [n_child][N_a + N_d] and b_mc of generation `gen`."""
@@ -345,7 +360,7 @@ def vary(gs: GenomeSpace, elite_id: np.ndarray, elite_genome: np.ndarray, seed: 
         def pick(j):
             if not occ:
                 return empty
-            return [int(v) for v in elite_genome[occ[uniform_index(rnd(j), len(occ))]]]
+            return feasible_parent(gs, elite_genome[occ[uniform_index(rnd(j), len(occ))]])
 
         if i < b_mc:
             out[i] = mutate(gs, pick(0), rnd)
@@ -354,9 +369,20 @@ def vary(gs: GenomeSpace, elite_id: np.ndarray, elite_genome: np.ndarray, seed: 
     return out, b_mc
 
 
+def _canonical(vals: Sequence[int], n: int, site) -> List[int]:
+    """Slots in canonical order: valid ids ascending by (site, id), then
+    out-of-range ids (in slot order), then empty slots."""
+    valid = sorted((v for v in vals if 0 <= v < n), key=lambda v: (int(site[v]), v))
+    bad = [v for v in vals if v != -1 and not 0 <= v < n]
+    return valid + bad + [-1] * (len(vals) - len(valid) - len(bad))
+
+
 def expand(gs: GenomeSpace, genomes: np.ndarray):
     """Genomes -> (open [n][N_d] branch ids, split_bus [n][N_a], moved lists
-    per (candidate, slot)).  Out-of-range ids become -2 (an invalid slot)."""
+    per (candidate, slot)), slots in canonical order (actions by bus,
+    disconnections by branch id, then invalid entries, then empty slots), so
+    that a candidate's evaluation does not depend on its slot order.
+    Out-of-range ids become -2 (an invalid slot)."""
     genomes = np.asarray(genomes)
     n = genomes.shape[0]
     na, nd = gs.n_a, gs.n_d
@@ -364,8 +390,8 @@ def expand(gs: GenomeSpace, genomes: np.ndarray):
     sbus = np.full((n, na), -1, dtype=np.int32)
     moved: List[List[int]] = []
     for c in range(n):
-        for j in range(na):
-            v = int(genomes[c, j])
+        acts = _canonical([int(v) for v in genomes[c, :na]], gs.n_actions, gs.action_bus)
+        for j, v in enumerate(acts):
             if v == -1:
                 moved.append([])
             elif 0 <= v < gs.n_actions:
@@ -374,8 +400,8 @@ def expand(gs: GenomeSpace, genomes: np.ndarray):
             else:
                 sbus[c, j] = -2
                 moved.append([])
-        for j in range(nd):
-            v = int(genomes[c, na + j])
+        discs = _canonical([int(v) for v in genomes[c, na:na + nd]], gs.n_disc, gs.disc_branch)
+        for j, v in enumerate(discs):
             if v == -1:
                 continue
             opens[c, j] = int(gs.disc_branch[v]) if 0 <= v < gs.n_disc else -2

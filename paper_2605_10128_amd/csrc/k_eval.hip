@@ -13,7 +13,7 @@
 //   k_finalize deterministic combination of the block partials, arg-max
 //              contingency, fitness lambda_f1 and the descriptor cell.
 //   k_n1_dump  full N-1 flow tensor for small debugging batches.
-//   k_arch_*   one-elite-per-cell repertoire update.
+//   (The repertoire update lives in k_archive.hip.)
 //
 // Algebra of a candidate (standard DC sensitivities; the paper cites, but does
 // not print, its low-rank formulas).  H = PTDF A^T, H_el = flow on e per MW
@@ -968,68 +968,6 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
     for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
     for (int t = 0; t < T; ++t) out[t] = (double)fma_t(h, ri[t], fa[(size_t)t * nM]);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Archive: per-cell best of the batch by an order-free 64-bit atomic max of a
-// monotone key, then the lowest index among exact ties, then the strict
-// replacement test against the stored elite.
-__device__ inline unsigned long long order_key(double d) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(d);
-  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-}
-
-__global__ __launch_bounds__(256) void k_arch_init(unsigned long long* key, int* idx, int n) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) { key[i] = 0ull; idx[i] = INT_MAX; }
-}
-
-__global__ __launch_bounds__(256) void k_arch_key(const double* fit, const int* cell,
-                                                  const uint8_t* st, int B, int n_cells,
-                                                  unsigned long long* key) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= B) return;
-  const int cl = cell[i];
-  if ((st[i] & (TTO_ST_ISLANDED | TTO_ST_INVALID)) || cl < 0 || cl >= n_cells) return;
-  atomicMax(key + cl, order_key(fit[i]));
-}
-
-__global__ __launch_bounds__(256) void k_arch_idx(const double* fit, const int* cell,
-                                                  const uint8_t* st, int B, int n_cells,
-                                                  const unsigned long long* key, int* idx) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= B) return;
-  const int cl = cell[i];
-  if ((st[i] & (TTO_ST_ISLANDED | TTO_ST_INVALID)) || cl < 0 || cl >= n_cells) return;
-  if (order_key(fit[i]) == key[cl]) atomicMin(idx + cl, i);
-}
-
-__global__ __launch_bounds__(256) void k_arch_apply(const double* fit, const int* idx,
-                                                    int n_cells, int64_t id_base,
-                                                    double* elite_fit, int64_t* elite_id) {
-  const int cl = blockIdx.x * 256 + threadIdx.x;
-  if (cl >= n_cells) return;
-  const int i = idx[cl];
-  if (i == INT_MAX) return;
-  const double f = fit[i];
-  if (elite_id[cl] == -1 || f > elite_fit[cl]) {
-    elite_fit[cl] = f;
-    elite_id[cl] = id_base + i;
-  }
-}
-
-static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
-
-hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
-                          const int* cell, const uint8_t* status, int B, int64_t id_base,
-                          unsigned long long* key, int* idx, hipStream_t s) {
-  hipLaunchKernelGGL(k_arch_init, dim3(cdiv(n_cells, 256)), dim3(256), 0, s, key, idx, n_cells);
-  if (B > 0) {
-    hipLaunchKernelGGL(k_arch_key, dim3(cdiv(B, 256)), dim3(256), 0, s, fit, cell, status, B, n_cells, key);
-    hipLaunchKernelGGL(k_arch_idx, dim3(cdiv(B, 256)), dim3(256), 0, s, fit, cell, status, B, n_cells, key, idx);
-  }
-  hipLaunchKernelGGL(k_arch_apply, dim3(cdiv(n_cells, 256)), dim3(256), 0, s, fit, idx, n_cells, id_base, elite_fit, elite_id);
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

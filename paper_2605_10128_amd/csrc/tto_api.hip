@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/tto.h: argument validation,
 // workspace carving, device table construction and kernel launch order.
 #include "tto_common.h"
+#include "tto_evolve.h"
 #include "tto_mlp.h"
 
 #include <math.h>
@@ -223,6 +224,7 @@ struct tto_grid {
   int n_cu = 0;
   int refine = 1;              // FP64 refinement of near-decision candidates (FP32 flows)
   double refine_margin = 8e-3; // MW
+  std::vector<int> hfrom, hto; // host copies of the branch endpoints
 };
 
 extern "C" {
@@ -324,6 +326,8 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   g->grid_bytes = need;
   g->batch_bytes = batch_bytes_for(d);
   g->L = L;
+  g->hfrom.assign(d->from_bus, d->from_bus + m);
+  g->hto.assign(d->to_bus, d->to_bus + m);
   GridDev& v = g->dev;
   v.n_bus = n; v.n_branch = m; v.slack = d->slack; v.T = g->T; v.TT = g->TT; v.nM = g->nM; v.nC = g->nC;
   v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S; v.SMC = L.SMC;
@@ -908,6 +912,296 @@ tto_status tto_evaluate_capture(tto_grid* g, const tto_batch* bt, const tto_outp
     return fail(st, "%s", msg.c_str());
   }
   *graph = gr;
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// MapElites generation: genome tables, variation, expansion, one generation.
+struct tto_genome_space {
+  GenomeDev d;
+  size_t bytes;
+};
+
+namespace {
+
+struct GenomeLayout {
+  size_t st_order, pos, first, count, bus, moff, mbr, disc, total;
+};
+
+GenomeLayout genome_layout(int n_actions, int n_moved, int n_disc) {
+  GenomeLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += round256(bytes); return at; };
+  L.st_order = take(4 * (size_t)n_actions);
+  L.pos = take(4 * (size_t)n_actions);
+  L.first = take(4 * (size_t)n_actions);
+  L.count = take(4 * (size_t)n_actions);
+  L.bus = take(4 * (size_t)n_actions);
+  L.moff = take(4 * ((size_t)n_actions + 1));
+  L.mbr = take(4 * (size_t)n_moved);
+  L.disc = take(4 * (size_t)n_disc);
+  L.total = o;
+  return L;
+}
+
+tto_status check_genome_desc(const tto_genome_desc* d) {
+  if (!d) return fail(TTO_E_INVALID, "genome desc is NULL");
+  if (d->n_action_slots < 0 || d->n_action_slots > TTO_MAX_RANK || d->n_disc_slots < 0 ||
+      d->n_disc_slots > TTO_MAX_RANK)
+    return fail(TTO_E_RANK, "slot counts (%d, %d) must each be in 0..%d", d->n_action_slots,
+                d->n_disc_slots, TTO_MAX_RANK);
+  if (d->n_actions < 0 || d->n_disc < 0) return fail(TTO_E_INVALID, "negative table size");
+  if (d->n_actions > 0 && (!d->action_bus || !d->action_moved_off || !d->action_moved_br))
+    return fail(TTO_E_INVALID, "action arrays are NULL");
+  if (d->n_disc > 0 && !d->disc_branch) return fail(TTO_E_INVALID, "disc_branch is NULL");
+  if (!(d->mut_mean >= 0.0) || !isfinite(d->mut_mean)) return fail(TTO_E_INVALID, "mut_mean must be finite and >= 0");
+  if (!(d->p_c1 >= 0.0 && d->p_c1 <= 1.0)) return fail(TTO_E_INVALID, "p_c1 must lie in [0, 1]");
+  for (int k = 0; k < 4; ++k)
+    if (d->w_action[k] < 0 || d->w_action[k] > (1 << 20) || d->w_disc[k] < 0 ||
+        d->w_disc[k] > (1 << 20))
+      return fail(TTO_E_INVALID, "operation weights must lie in 0..2^20");
+  if (d->n_actions > 0) {
+    if (d->action_moved_off[0] != 0) return fail(TTO_E_INVALID, "action_moved_off[0] must be 0");
+    for (int a = 0; a < d->n_actions; ++a) {
+      const int len = d->action_moved_off[a + 1] - d->action_moved_off[a];
+      if (len < 1 || len > TTO_MAX_MOVED)
+        return fail(TTO_E_INVALID, "action %d moves %d branches (1..%d allowed)", a, len, TTO_MAX_MOVED);
+    }
+  }
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+tto_status tto_genome_space_bytes(const tto_genome_desc* d, size_t* bytes) {
+  tto_status st = check_genome_desc(d);
+  if (st != TTO_OK) return st;
+  if (!bytes) return fail(TTO_E_INVALID, "bytes is NULL");
+  const int n_moved = d->n_actions > 0 ? d->action_moved_off[d->n_actions] : 0;
+  *bytes = genome_layout(d->n_actions, n_moved, d->n_disc).total;
+  return ok();
+}
+
+tto_status tto_genome_space_create(const tto_grid* g, const tto_genome_desc* d, void* ws,
+                                   size_t bytes, void* stream, tto_genome_space** out) {
+  tto_status st = check_genome_desc(d);
+  if (st != TTO_OK) return st;
+  if (!g || !out) return fail(TTO_E_INVALID, "grid or out is NULL");
+  *out = nullptr;
+  const int nA = d->n_actions, nD = d->n_disc, m = g->m;
+  const int n_moved = nA > 0 ? d->action_moved_off[nA] : 0;
+  for (int a = 0; a < nA; ++a) {
+    const int bus = d->action_bus[a];
+    if (bus < 0 || bus >= g->n_bus) return fail(TTO_E_GRID, "action %d: bus %d out of range", a, bus);
+    for (int p = d->action_moved_off[a]; p < d->action_moved_off[a + 1]; ++p) {
+      const int e = d->action_moved_br[p];
+      if (e < 0 || e >= m) return fail(TTO_E_GRID, "action %d moves branch %d out of range", a, e);
+      if (g->hfrom[e] != bus && g->hto[e] != bus)
+        return fail(TTO_E_GRID, "action %d moves branch %d not incident to bus %d", a, e, bus);
+      for (int q = d->action_moved_off[a]; q < p; ++q)
+        if (d->action_moved_br[q] == e) return fail(TTO_E_GRID, "action %d moves branch %d twice", a, e);
+    }
+  }
+  std::vector<char> seen(m, 0);
+  for (int i = 0; i < nD; ++i) {
+    const int e = d->disc_branch[i];
+    if (e < 0 || e >= m || seen[e]) return fail(TTO_E_GRID, "disc_branch[%d]=%d out of range or repeated", i, e);
+    seen[e] = 1;
+  }
+  const GenomeLayout L = genome_layout(nA, n_moved, nD);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(TTO_E_WORKSPACE, "ws NULL or not 256-byte aligned");
+  if (bytes < L.total) return fail(TTO_E_WORKSPACE, "ws has %zu bytes, needs %zu", bytes, L.total);
+
+  // station order: ascending (bus, action id)
+  std::vector<int> order(nA), pos(nA), first(nA), count(nA);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return d->action_bus[x] < d->action_bus[y]; });
+  for (int p = 0; p < nA; ++p) pos[order[p]] = p;
+  for (int p = 0; p < nA;) {
+    int q = p;
+    while (q < nA && d->action_bus[order[q]] == d->action_bus[order[p]]) ++q;
+    for (int r = p; r < q; ++r) { first[order[r]] = p; count[order[r]] = q - p; }
+    p = q;
+  }
+  int max_len = 0;
+  for (int a = 0; a < nA; ++a)
+    max_len = std::max(max_len, d->action_moved_off[a + 1] - d->action_moved_off[a]);
+
+  char* base = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  auto up = [&](size_t off, const int* src, size_t n) -> hipError_t {
+    return n ? hipMemcpyAsync(base + off, src, 4 * n, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  HIP_TRY(up(L.st_order, order.data(), nA));
+  HIP_TRY(up(L.pos, pos.data(), nA));
+  HIP_TRY(up(L.first, first.data(), nA));
+  HIP_TRY(up(L.count, count.data(), nA));
+  HIP_TRY(up(L.bus, d->action_bus, nA));
+  HIP_TRY(up(L.moff, d->action_moved_off, nA > 0 ? nA + 1 : 0));
+  HIP_TRY(up(L.mbr, d->action_moved_br, n_moved));
+  HIP_TRY(up(L.disc, d->disc_branch, nD));
+  HIP_TRY(hipStreamSynchronize(s));
+
+  tto_genome_space* gs = new tto_genome_space();
+  GenomeDev& v = gs->d;
+  v.n_a = d->n_action_slots; v.n_d = d->n_disc_slots; v.n_actions = nA; v.n_disc = nD;
+  v.max_len = max_len;
+  v.st_order = (const int*)(base + L.st_order); v.pos = (const int*)(base + L.pos);
+  v.first = (const int*)(base + L.first); v.count = (const int*)(base + L.count);
+  v.bus = (const int*)(base + L.bus); v.moff = (const int*)(base + L.moff);
+  v.mbr = (const int*)(base + L.mbr); v.disc = (const int*)(base + L.disc);
+  for (int k = 0; k < 4; ++k) { v.w_act[k] = d->w_action[k]; v.w_disc[k] = d->w_disc[k]; }
+  v.thr_c1 = std::min<unsigned long long>(1ull << 32, (unsigned long long)floor(d->p_c1 * 4294967296.0));
+  // floor(P(K <= k) 2^32) for K ~ Poisson(mut_mean), k = 1 .. N_a - 1, in FP64
+  double term = exp(-d->mut_mean), cdf = term;
+  for (int k = 1; k < kGenomeSlots; ++k) {
+    term = term * d->mut_mean / k;
+    cdf += term;
+    v.poisson[k - 1] = (unsigned long long)floor(cdf * 4294967296.0);
+  }
+  v.poisson[kGenomeSlots - 1] = 1ull << 32;
+  gs->bytes = L.total;
+  *out = gs;
+  return ok();
+}
+
+void tto_genome_space_destroy(tto_genome_space* gs) { delete gs; }
+
+tto_status tto_genome_max_moved(const tto_genome_space* gs, int32_t* per_candidate) {
+  if (!gs || !per_candidate) return fail(TTO_E_INVALID, "NULL argument");
+  *per_candidate = gs->d.n_a * gs->d.max_len;
+  return ok();
+}
+
+tto_status tto_vary(const tto_genome_space* gs, const int64_t* elite_id, const int32_t* elite_genome,
+                    int32_t n_cells, uint64_t seed, const int64_t* generation, int32_t n_child,
+                    int32_t* children, int32_t* b_mc, void* stream) {
+  if (!gs || !elite_id || !generation) return fail(TTO_E_INVALID, "NULL argument");
+  const int G = gs->d.n_a + gs->d.n_d;
+  if (G > 0 && !elite_genome) return fail(TTO_E_INVALID, "elite_genome is NULL");
+  if (n_cells < 1 || n_cells > TTO_MAX_CELLS)
+    return fail(TTO_E_INVALID, "n_cells %d not in 1..%d", n_cells, TTO_MAX_CELLS);
+  if (n_child < 0) return fail(TTO_E_INVALID, "n_child must be >= 0");
+  if (n_child > 0 && G > 0 && !children) return fail(TTO_E_INVALID, "children is NULL");
+  HIP_TRY(launch_vary(gs->d, elite_id, elite_genome, n_cells, seed, generation, n_child,
+                      children, b_mc, (hipStream_t)stream));
+  return ok();
+}
+
+tto_status tto_genome_expand(const tto_genome_space* gs, const int32_t* genomes, int32_t n,
+                             int32_t* open, int32_t* split_bus, int32_t* moved_off,
+                             int32_t* moved_br, int64_t moved_cap, void* stream) {
+  if (!gs) return fail(TTO_E_INVALID, "genome space is NULL");
+  if (n < 0) return fail(TTO_E_INVALID, "n must be >= 0");
+  if (n == 0) return ok();
+  const GenomeDev& d = gs->d;
+  if (d.n_a + d.n_d > 0 && !genomes) return fail(TTO_E_INVALID, "genomes is NULL");
+  if (d.n_d > 0 && !open) return fail(TTO_E_INVALID, "open is NULL");
+  if (d.n_a > 0 && (!split_bus || !moved_off || !moved_br)) return fail(TTO_E_INVALID, "split arrays are NULL");
+  if ((int64_t)n * d.n_a > (int64_t)INT32_MAX / std::max(1, d.max_len))
+    return fail(TTO_E_INVALID, "n too large");
+  if (d.n_a > 0 && moved_cap < (int64_t)n * d.n_a * d.max_len)
+    return fail(TTO_E_WORKSPACE, "moved_cap %lld < %lld", (long long)moved_cap,
+                (long long)n * d.n_a * d.max_len);
+  HIP_TRY(launch_expand(d, genomes, n, open, split_bus, moved_off, moved_br, (hipStream_t)stream));
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+struct GenLayout {
+  size_t children, b_mc, open, sbus, moff, mbr, status, fit, cell, total;
+};
+
+GenLayout gen_layout(const GenomeDev& d, int n_child) {
+  GenLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += round256(std::max<size_t>(bytes, 4)); return at; };
+  const size_t n = (size_t)n_child;
+  L.children = take(4 * n * (d.n_a + d.n_d));
+  if (d.n_a + d.n_d == 0) L.children = 0, o = 0;
+  L.b_mc = o; o += 256;
+  L.open = take(4 * n * d.n_d);
+  L.sbus = take(4 * n * d.n_a);
+  L.moff = take(4 * (n * d.n_a + 1));
+  L.mbr = take(4 * n * d.n_a * std::max(d.max_len, 1));
+  L.status = take(n);
+  L.fit = take(8 * n);
+  L.cell = take(4 * n);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+tto_status tto_generation_bytes(const tto_grid* g, const tto_genome_space* gs, int32_t n_child,
+                                size_t* bytes) {
+  if (!g || !gs || !bytes) return fail(TTO_E_INVALID, "NULL argument");
+  if (n_child < 1 || n_child > g->max_batch)
+    return fail(TTO_E_INVALID, "n_child %d not in 1..max_batch=%d", n_child, g->max_batch);
+  *bytes = gen_layout(gs->d, n_child).total;
+  return ok();
+}
+
+tto_status tto_generation(tto_grid* g, const tto_genome_space* gs, const tto_repertoire* rep,
+                          uint64_t seed, int32_t n_child, const tto_outputs* out, void* gen_ws,
+                          size_t gen_bytes, void* batch_ws, size_t batch_bytes, void* stream) {
+  if (!g || !gs || !rep) return fail(TTO_E_INVALID, "grid, genome space or repertoire is NULL");
+  const GenomeDev& d = gs->d;
+  const int G = d.n_a + d.n_d;
+  if (rep->n_cells < 1 || rep->n_cells > TTO_MAX_CELLS)
+    return fail(TTO_E_INVALID, "n_cells %d not in 1..%d", rep->n_cells, TTO_MAX_CELLS);
+  if (!rep->fitness || !rep->id || !rep->generation || (G > 0 && !rep->genome))
+    return fail(TTO_E_INVALID, "repertoire arrays are NULL");
+  if (n_child < 1 || n_child > g->max_batch)
+    return fail(TTO_E_INVALID, "n_child %d not in 1..max_batch=%d", n_child, g->max_batch);
+  const GenLayout L = gen_layout(d, n_child);
+  if (!gen_ws || ((uintptr_t)gen_ws & 255)) return fail(TTO_E_WORKSPACE, "gen_ws NULL or not 256-byte aligned");
+  if (gen_bytes < L.total) return fail(TTO_E_WORKSPACE, "gen_ws has %zu bytes, needs %zu", gen_bytes, L.total);
+  if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < 16 * (size_t)rep->n_cells)
+    return fail(TTO_E_WORKSPACE, "batch_ws NULL, misaligned or too small");
+  if (rep->n_cells != g->dev.n_count_bins * g->dev.n_load_bins)
+    return fail(TTO_E_INVALID, "n_cells %d differs from the descriptor's %d cells", rep->n_cells,
+                g->dev.n_count_bins * g->dev.n_load_bins);
+  char* w = (char*)gen_ws;
+  hipStream_t s = (hipStream_t)stream;
+  int* children = (int*)(w + L.children);
+  HIP_TRY(launch_vary(d, rep->id, rep->genome, rep->n_cells, seed, rep->generation, n_child,
+                      children, (int*)(w + L.b_mc), s));
+  tto_batch bt;
+  bt.n_cand = n_child;
+  bt.n_open_slots = d.n_d;
+  bt.n_split_slots = d.n_a;
+  bt.open = d.n_d ? (const int32_t*)(w + L.open) : nullptr;
+  bt.split_bus = d.n_a ? (const int32_t*)(w + L.sbus) : nullptr;
+  bt.moved_off = d.n_a ? (const int32_t*)(w + L.moff) : nullptr;
+  bt.moved_br = d.n_a ? (const int32_t*)(w + L.mbr) : nullptr;
+  bt.moved_p_mw = nullptr;
+  HIP_TRY(launch_expand(d, children, n_child, (int*)bt.open, (int*)bt.split_bus,
+                        (int*)bt.moved_off, (int*)bt.moved_br, s));
+  tto_outputs o;
+  memset(&o, 0, sizeof(o));
+  if (out) o = *out;
+  if (!o.status) o.status = (uint8_t*)(w + L.status);
+  if (!o.fitness) o.fitness = (double*)(w + L.fit);
+  if (!o.cell) o.cell = (int32_t*)(w + L.cell);
+  tto_status st = tto_evaluate(g, &bt, &o, batch_ws, batch_bytes, stream);
+  if (st != TTO_OK) return st;
+  unsigned long long* key = (unsigned long long*)batch_ws;
+  int* idx = (int*)((char*)batch_ws + 8 * (size_t)rep->n_cells);
+  HIP_TRY(launch_archive_genome(rep->fitness, rep->id, rep->genome, rep->n_cells, o.fitness,
+                                o.cell, o.status, n_child, rep->generation, children, G, key,
+                                idx, s));
+  HIP_TRY(launch_generation_bump(rep->generation, s));
   return ok();
 }
 

@@ -1,0 +1,47 @@
+// Device side of the MapElites generation (DC-Optimizer: Repertoire design,
+// Mutation Alg. 1, Crossover Alg. 2, High-level loop Alg. 3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tto {
+
+constexpr int kGenomeSlots = 8;      // per kind (action, disconnection)
+constexpr int kMaxCells = 4096;      // repertoire cells compacted in LDS by k_vary
+
+// Genome tables and operator parameters.  Actions are addressed in "station
+// order" (ascending (bus, action id)); the actions of one substation form one
+// contiguous range of station positions.
+struct GenomeDev {
+  int n_a, n_d, n_actions, n_disc, max_len;
+  const int* st_order;   // [n_actions] station position -> action id
+  const int* pos;        // [n_actions] action id -> station position
+  const int* first;      // [n_actions] first station position of the action's substation
+  const int* count;      // [n_actions] number of actions at that substation
+  const int* bus;        // [n_actions]
+  const int* moff;       // [n_actions + 1] moved-branch CSR
+  const int* mbr;
+  const int* disc;       // [n_disc] branch id of each disconnection
+  int w_act[4];          // Add, Remove, Change, Identity
+  int w_disc[4];
+  unsigned long long thr_c1;               // parent 1 iff draw < thr_c1 (<= 2^32)
+  unsigned long long poisson[kGenomeSlots]; // floor(P(K <= k) 2^32), k = 1 .. n_a - 1
+};
+
+hipError_t launch_vary(const GenomeDev& gd, const int64_t* elite_id, const int* elite_genome,
+                       int n_cells, uint64_t seed, const int64_t* generation, int n_child,
+                       int* children, int* b_mc, hipStream_t s);
+
+hipError_t launch_expand(const GenomeDev& gd, const int* genomes, int n, int* open, int* sbus,
+                         int* moff, int* mbr, hipStream_t s);
+
+hipError_t launch_archive_genome(double* elite_fit, int64_t* elite_id, int* elite_genome,
+                                 int n_cells, const double* fit, const int* cell,
+                                 const uint8_t* status, int B, const int64_t* generation,
+                                 const int* genomes, int G, unsigned long long* key, int* idx,
+                                 hipStream_t s);
+
+hipError_t launch_generation_bump(int64_t* generation, hipStream_t s);
+
+}  // namespace tto

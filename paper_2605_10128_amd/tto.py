@@ -54,6 +54,18 @@ class tto_outputs(ct.Structure):
     _fields_ = [(f, _vp) for f in OUTPUT_FIELDS]
 
 
+class tto_genome_desc(ct.Structure):
+    _fields_ = [("n_action_slots", _i32), ("n_disc_slots", _i32), ("n_actions", _i32),
+                ("action_bus", _vp), ("action_moved_off", _vp), ("action_moved_br", _vp),
+                ("n_disc", _i32), ("disc_branch", _vp), ("mut_mean", ct.c_double),
+                ("w_action", _i32 * 4), ("w_disc", _i32 * 4), ("p_c1", ct.c_double)]
+
+
+class tto_repertoire(ct.Structure):
+    _fields_ = [("n_cells", _i32), ("fitness", _vp), ("id", _vp), ("genome", _vp),
+                ("generation", _vp)]
+
+
 class tto_mlp_desc(ct.Structure):
     _fields_ = [("d_bits", _i32), ("d_dense", _i32), ("width", _i32), ("max_batch", _i32),
                 ("max_train_batch", _i32)]
@@ -68,6 +80,11 @@ class TTOError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libtto.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    # torch's HIP runtime must be the one the library binds to: loaded first,
+    # its libamdhip64 satisfies the library's dependency by soname, so device
+    # memory and stream handles from torch are valid in library calls (loaded
+    # the other way round, the process would hold two HIP runtimes)
+    import torch  # noqa: F401
     lib = ct.CDLL(LIB_PATH)
     P = ct.POINTER
     sig = {
@@ -107,6 +124,16 @@ def _load():
         "tto_evaluate_capture": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                         _vp, _i32, ct.c_int64, P(_vp)]),
         "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
+        "tto_genome_space_bytes": (_i32, [P(tto_genome_desc), P(ct.c_size_t)]),
+        "tto_genome_space_create": (_i32, [_vp, P(tto_genome_desc), _vp, ct.c_size_t, _vp,
+                                           P(_vp)]),
+        "tto_genome_space_destroy": (None, [_vp]),
+        "tto_genome_max_moved": (_i32, [_vp, P(_i32)]),
+        "tto_vary": (_i32, [_vp, _vp, _vp, _i32, ct.c_uint64, _vp, _i32, _vp, _vp, _vp]),
+        "tto_genome_expand": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, ct.c_int64, _vp]),
+        "tto_generation_bytes": (_i32, [_vp, _vp, _i32, P(ct.c_size_t)]),
+        "tto_generation": (_i32, [_vp, _vp, P(tto_repertoire), ct.c_uint64, _i32,
+                                  P(tto_outputs), _vp, ct.c_size_t, _vp, ct.c_size_t, _vp]),
         "tto_autotune": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                 ct.c_char_p, P(_i32)]),
     }
@@ -127,7 +154,9 @@ EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_cr
             "tto_mlp_n_params", "tto_mlp_set_params", "tto_mlp_get_params", "tto_mlp_forward",
             "tto_mlp_gradients", "tto_mlp_train_step", "tto_topk_smallest",
             "tto_graph_begin", "tto_graph_end", "tto_graph_launch", "tto_graph_destroy",
-            "tto_evaluate_capture"]
+            "tto_evaluate_capture", "tto_genome_space_bytes", "tto_genome_space_create",
+            "tto_genome_space_destroy", "tto_genome_max_moved", "tto_vary", "tto_genome_expand",
+            "tto_generation_bytes", "tto_generation"]
 
 
 def _check(code: int):
@@ -304,6 +333,57 @@ def tto_evaluate_capture(handle, batch: "tto_batch", outputs: "tto_outputs", ws,
                                      ws_bytes, _vp(elite_fit), _vp(elite_id), int(n_cells),
                                      int(id_base), ct.byref(g)))
     return g.value
+
+
+def tto_genome_space_bytes(desc: tto_genome_desc) -> int:
+    n = ct.c_size_t()
+    _check(_lib.tto_genome_space_bytes(ct.byref(desc), ct.byref(n)))
+    return n.value
+
+
+def tto_genome_space_create(grid: int, desc: tto_genome_desc, ws: int, nbytes: int,
+                            stream: int) -> int:
+    h = _vp()
+    _check(_lib.tto_genome_space_create(_vp(grid), ct.byref(desc), _vp(ws), nbytes, _vp(stream),
+                                        ct.byref(h)))
+    return h.value
+
+
+def tto_genome_space_destroy(gs: int):
+    _lib.tto_genome_space_destroy(_vp(gs))
+
+
+def tto_genome_max_moved(gs: int) -> int:
+    n = _i32()
+    _check(_lib.tto_genome_max_moved(_vp(gs), ct.byref(n)))
+    return n.value
+
+
+def tto_vary(gs: int, elite_id: int, elite_genome: int, n_cells: int, seed: int,
+             generation: int, n_child: int, children: int, b_mc: int, stream: int):
+    _check(_lib.tto_vary(_vp(gs), _vp(elite_id), _vp(elite_genome), int(n_cells),
+                         ct.c_uint64(seed), _vp(generation), int(n_child), _vp(children),
+                         _vp(b_mc), _vp(stream)))
+
+
+def tto_genome_expand(gs: int, genomes: int, n: int, open_: int, split_bus: int, moved_off: int,
+                      moved_br: int, moved_cap: int, stream: int):
+    _check(_lib.tto_genome_expand(_vp(gs), _vp(genomes), int(n), _vp(open_), _vp(split_bus),
+                                  _vp(moved_off), _vp(moved_br), int(moved_cap), _vp(stream)))
+
+
+def tto_generation_bytes(grid: int, gs: int, n_child: int) -> int:
+    n = ct.c_size_t()
+    _check(_lib.tto_generation_bytes(_vp(grid), _vp(gs), int(n_child), ct.byref(n)))
+    return n.value
+
+
+def tto_generation(grid: int, gs: int, rep: tto_repertoire, seed: int, n_child: int,
+                   outputs: Optional["tto_outputs"], gen_ws: int, gen_bytes: int, batch_ws: int,
+                   batch_bytes: int, stream: int):
+    _check(_lib.tto_generation(_vp(grid), _vp(gs), ct.byref(rep), ct.c_uint64(seed),
+                               int(n_child), ct.byref(outputs) if outputs is not None else None,
+                               _vp(gen_ws), gen_bytes, _vp(batch_ws), batch_bytes, _vp(stream)))
 
 
 class Graph:
@@ -611,3 +691,117 @@ class Session:
                            _ptr(outputs["fitness"]), _ptr(outputs["cell"]),
                            _ptr(outputs["status"]), B, int(id_base), _ptr(self.batch_ws),
                            self.batch_bytes, self.stream)
+
+
+# ---- MapElites generation on the device -------------------------------------
+class GenomeSpace:
+    """Torch-held genome tables (tto_genome_space_*) of a Session's grid:
+    the split-action set A (bus and moved branches per action), the
+    disconnectable set D and the operator parameters."""
+
+    def __init__(self, session: "Session", action_bus, action_moved, disc_branch,
+                 n_action_slots: int, n_disc_slots: int, mut_mean=2.0,
+                 w_action=(20, 20, 50, 10), w_disc=(25, 25, 50, 0), p_c1=0.5):
+        torch = session.torch
+        self.session = session
+        bus = np.ascontiguousarray(action_bus, dtype=np.int32)
+        off = np.zeros(len(bus) + 1, dtype=np.int32)
+        off[1:] = np.cumsum([len(m) for m in action_moved]) if len(bus) else []
+        br = np.ascontiguousarray(
+            np.concatenate([np.asarray(m, dtype=np.int32) for m in action_moved])
+            if len(bus) else np.zeros(1, np.int32), dtype=np.int32)
+        disc = np.ascontiguousarray(disc_branch, dtype=np.int32)
+        if disc.size == 0:
+            disc = np.zeros(1, np.int32)[:0]
+        self._host = (bus, off, br, disc)
+        self.desc = tto_genome_desc(
+            int(n_action_slots), int(n_disc_slots), len(bus), bus.ctypes.data if len(bus) else 0,
+            off.ctypes.data, br.ctypes.data, len(disc), disc.ctypes.data if len(disc) else 0,
+            float(mut_mean), (_i32 * 4)(*w_action), (_i32 * 4)(*w_disc), float(p_c1))
+        n = tto_genome_space_bytes(self.desc)
+        self.ws = torch.empty(max(n, 256), dtype=torch.uint8, device=session.device)
+        self.handle = tto_genome_space_create(session.handle, self.desc, _ptr(self.ws), n,
+                                              session.stream)
+        self.n_a, self.n_d = int(n_action_slots), int(n_disc_slots)
+        self.G = self.n_a + self.n_d
+        self.max_moved = tto_genome_max_moved(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            tto_genome_space_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vary(self, rep: "Repertoire", seed: int, n_child: int, children=None, b_mc=None):
+        torch, s = self.session.torch, self.session
+        if children is None:
+            children = torch.empty((n_child, max(self.G, 1)), dtype=torch.int32, device=s.device)
+        if b_mc is None:
+            b_mc = torch.empty(1, dtype=torch.int32, device=s.device)
+        tto_vary(self.handle, _ptr(rep.id), _ptr(rep.genome), rep.n_cells, seed,
+                 _ptr(rep.generation), n_child, _ptr(children), _ptr(b_mc), s.stream)
+        return children, b_mc
+
+    def expand(self, genomes, n: Optional[int] = None) -> "DeviceBatch":
+        torch, s = self.session.torch, self.session
+        n = int(genomes.shape[0]) if n is None else n
+        d = s.device
+        op = torch.empty((n, self.n_d), dtype=torch.int32, device=d)
+        sb = torch.empty((n, self.n_a), dtype=torch.int32, device=d)
+        mo = torch.empty(n * self.n_a + 1, dtype=torch.int32, device=d)
+        cap = max(1, n * self.max_moved)
+        mb = torch.empty(cap, dtype=torch.int32, device=d)
+        tto_genome_expand(self.handle, _ptr(genomes), n, _ptr(op) if self.n_d else 0,
+                          _ptr(sb) if self.n_a else 0, _ptr(mo) if self.n_a else 0,
+                          _ptr(mb) if self.n_a else 0, cap, s.stream)
+        return DeviceBatch(n, op, sb, mo, mb, None)
+
+
+class Repertoire:
+    """Device repertoire (tto_repertoire): per cell fitness, id and genome,
+    plus the generation counter."""
+
+    def __init__(self, session: "Session", gs: GenomeSpace, n_cells: Optional[int] = None):
+        torch, d = session.torch, session.device
+        n = session.n_cells if n_cells is None else int(n_cells)
+        self.n_cells = n
+        self.fitness = torch.full((n,), float("-inf"), dtype=torch.float64, device=d)
+        self.id = torch.full((n,), -1, dtype=torch.int64, device=d)
+        self.genome = torch.full((n, max(gs.G, 1)), -1, dtype=torch.int32, device=d)
+        self.generation = torch.zeros(1, dtype=torch.int64, device=d)
+
+    def struct(self) -> tto_repertoire:
+        return tto_repertoire(self.n_cells, _ptr(self.fitness), _ptr(self.id), _ptr(self.genome),
+                              _ptr(self.generation))
+
+
+class Evolver:
+    """One device generation per call (tto_generation) on pre-allocated
+    buffers, so that calls can be captured in a Graph and replayed."""
+
+    def __init__(self, session: "Session", gs: GenomeSpace, rep: Repertoire, n_child: int,
+                 seed: int, outputs=None):
+        torch = session.torch
+        self.session, self.gs, self.rep = session, gs, rep
+        self.n_child, self.seed = int(n_child), int(seed)
+        self.gen_bytes = tto_generation_bytes(session.handle, gs.handle, self.n_child)
+        self.gen_ws = torch.empty(self.gen_bytes, dtype=torch.uint8, device=session.device)
+        self.outputs = outputs
+        self._rep_struct = rep.struct()
+        self._out_struct = (tto_outputs(*[_ptr(outputs.get(f)) for f in OUTPUT_FIELDS])
+                            if outputs is not None else None)
+        G = gs.G
+        self.children = self.gen_ws[: 4 * self.n_child * G].view(torch.int32).view(self.n_child, G)
+        off = (4 * self.n_child * G + 255) // 256 * 256
+        self.b_mc = self.gen_ws[off: off + 4].view(torch.int32)
+
+    def step(self):
+        s = self.session
+        tto_generation(s.handle, self.gs.handle, self._rep_struct, self.seed, self.n_child,
+                       self._out_struct, _ptr(self.gen_ws), self.gen_bytes, _ptr(s.batch_ws),
+                       s.batch_bytes, s.stream)

@@ -294,12 +294,24 @@ def test_vary_split_and_parent_sampling():
 
 
 def test_expand_maps_ids_and_marks_out_of_range():
+    """Ids map to buses / branch ids, out-of-range ids to -2; slots come out
+    in canonical order (by bus, by branch id; invalid, then empty last)."""
     gs = small_space()
     g = np.array([[3, -1, 0, 99, 2, -1, 55, 0]], dtype=np.int32)
     opens, sbus, moved = ev.expand(gs, g)
-    assert sbus.tolist() == [[9, -1, 7, -2]]
-    assert moved == [[3, 103], [], [0, 100], []]
-    assert opens.tolist() == [[202, -1, -2, 200]]
+    assert sbus.tolist() == [[7, 9, -2, -1]]
+    assert moved == [[0, 100], [3, 103], [], []]
+    assert opens.tolist() == [[200, 202, -2, -1]]
+
+
+def test_expand_is_invariant_under_slot_permutations():
+    gs = small_space()
+    rng = np.random.default_rng(14)
+    for _ in range(200):
+        g = np.array(_random_genome(gs, rng), dtype=np.int32)
+        perm = np.concatenate([rng.permutation(4), 4 + rng.permutation(4)])
+        a, b = ev.expand(gs, g[None]), ev.expand(gs, g[perm][None])
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
 
 
 def test_archive_with_genomes_matches_sequential_insertion():
@@ -352,3 +364,10 @@ def test_generation_loop_bookkeeping_on_30_bus_grid():
         allf = [rec["fitness"][k] for rec in log for k in range(16)
                 if rec["ok"][k] and rec["cell"][k] == c]
         assert fit[c] == max(allf)
+
+
+def test_feasible_parent_reads_conflicts_as_empty():
+    gs = small_space()
+    a7, a7b = gs.station_order[gs.first[7]], gs.station_order[gs.first[7] + 1]
+    g = [a7, 99, a7b, -5, 3, 3, 40, -1]
+    assert ev.feasible_parent(gs, g) == [a7, -1, -1, -1, 3, -1, -1, -1]
