@@ -267,6 +267,93 @@ def surrogate_leg(s, w, args, exact_rate):
     return res
 
 
+def evolution_leg(s, w, args):
+    """MapElites generations on the device (Alg. 3 with Alg. 1 and 2): one
+    generation (vary, expand, evaluate, insert) captured as a graph and
+    replayed for an epoch; the variation kernels are also timed alone."""
+    import numpy as np
+    import torch
+    import gridgen as gg
+    from paper_2605_10128_amd import tto
+
+    g = w.grid
+    B = w.batch.n_cand
+    s.set_injections(w.P)          # the screened leg leaves another scenario installed
+    D = np.flatnonzero(~gg.bridges(g.n_bus, g.from_bus, g.to_bus))
+    bus = np.array([b for b, _ in w.split_table])
+    moved = [mv for _, mv in w.split_table]
+    gs = tto.GenomeSpace(s, bus, moved, D, args.evo_slots, args.evo_slots)
+    rep = tto.Repertoire(s, gs)
+    outs = s.alloc_outputs(B)
+    evo = tto.Evolver(s, gs, rep, B, seed=0xE701, outputs=outs)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        evo.step()
+    torch.cuda.synchronize()
+    # variation alone: tto_vary + tto_genome_expand on the generation's buffers
+    kids = torch.empty((B, gs.G), dtype=torch.int32, device=s.device)
+    bmc = torch.empty(1, dtype=torch.int32, device=s.device)
+    op = torch.empty((B, gs.n_d), dtype=torch.int32, device=s.device)
+    sb = torch.empty((B, gs.n_a), dtype=torch.int32, device=s.device)
+    mo = torch.empty(B * gs.n_a + 1, dtype=torch.int32, device=s.device)
+    cap = max(1, B * gs.max_moved)
+    mb = torch.empty(cap, dtype=torch.int32, device=s.device)
+    v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    v0.record(stream)
+    for _ in range(reps):
+        tto.tto_vary(gs.handle, rep.id.data_ptr(), rep.genome.data_ptr(), rep.n_cells, 0xE701,
+                     rep.generation.data_ptr(), B, kids.data_ptr(), bmc.data_ptr(), s.stream)
+        tto.tto_genome_expand(gs.handle, kids.data_ptr(), B, op.data_ptr(), sb.data_ptr(),
+                              mo.data_ptr(), mb.data_ptr(), cap, s.stream)
+    v1.record(stream)
+    torch.cuda.synchronize()
+    vary_ms = v0.elapsed_time(v1) / reps
+    with tto.Graph() as graph:
+        evo.step()
+    K = args.evo_generations
+    gen0 = int(rep.generation.item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(K):
+        graph.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph.close()
+    ms_gen = e0.elapsed_time(e1) / K
+    ids = rep.id.cpu().numpy()
+    fit = rep.fitness.cpu().numpy()
+    occ = ids >= 0
+    st = outs["status"].cpu().numpy()
+    ch = evo.children.cpu().numpy()
+    res = {
+        "value": B / (ms_gen / 1e3),
+        "unit": "evaluated children/s",
+        "ms_per_generation": ms_gen,
+        "children_per_generation": B,
+        "generations_replayed": K,
+        "launch": "hipGraph replay of one generation (vary, expand, evaluate, insert)",
+        "slots": {"actions": gs.n_a, "disconnections": gs.n_d, "|A|": len(bus), "|D|": len(D)},
+        "variation_ms": vary_ms,
+        "variation_frac": vary_ms / ms_gen,
+        "generation_counter": int(rep.generation.item()),
+        "counter_advanced": int(rep.generation.item()) - gen0,
+        "cells_filled": int(occ.sum()),
+        "best_fitness": float(fit[occ].max()) if occ.any() else None,
+        "mean_elite_fitness": float(fit[occ].mean()) if occ.any() else None,
+        "last_generation": {
+            "mutated": int(evo.b_mc.item()),
+            "mean_filled_slots": float((ch != -1).sum(1).mean()),
+            "invalid": int(((st & 2) != 0).sum()),
+            "islanded": int(((st & 3) == 1).sum()),
+        },
+    }
+    log(f"[bench] evolution: {ms_gen:.2f} ms per generation of {B} ({res['value']:,.0f} children/s), "
+        f"variation {vary_ms:.3f} ms, {res['cells_filled']} cells after {res['generation_counter']} generations")
+    gs.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +375,9 @@ def main():
     ap.add_argument("--keep-frac", type=float, default=0.1)
     ap.add_argument("--screen-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-evolution", action="store_true", help="skip the MapElites leg")
+    ap.add_argument("--evo-generations", type=int, default=20)
+    ap.add_argument("--evo-slots", type=int, default=4)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -442,9 +532,12 @@ def main():
         },
         "cpu_baseline": None,
         "surrogate_screened": None,
+        "evolution": None,
     }
     if not args.no_surrogate:
         result["surrogate_screened"] = surrogate_leg(s, w, args, value)
+    if not args.no_evolution and w.split_table:
+        result["evolution"] = evolution_leg(s, w, args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         result["cpu_baseline"] = cpu_baseline(w)

@@ -42,6 +42,12 @@ extern "C" {
 #define TTO_MAX_T 32        /* timesteps per injection set */
 #define TTO_MAX_MOVED 64    /* moved branches summed over a candidate's splits */
 #define TTO_MAX_LOAD_BINS 64
+/* Worst contingency: the first contingency (in the order of the contingency
+ * list) whose |flow| on the worst branch at the worst timestep is within this
+ * many MW of the maximum.  Branches whose flow no contingency changes (bridges
+ * of the post-switch grid) tie exactly, and the order of the list, not
+ * rounding, then picks the reported contingency. */
+#define TTO_WORST_CONT_TIE_MW 0.05
 
 typedef int32_t tto_status;
 enum {
@@ -172,9 +178,11 @@ typedef struct {
  *   n_crit_n1      lambda_c = #{(e,t): f^max_e(t) > fbar_e}
  *   n_crit_n0      lambda_c0 = #{(e,t): |f'_e(t)| > fbar_e}
  *   max_loading    max_{e,t} f^max_e(t) / fbar_e
- *   worst_*        branch id e*, contingency branch id l*, timestep t* of the
- *                  maximum loading (smallest (e, t, l) on exact ties; l* = -1
- *                  when every contingency islands)
+ *   worst_*        branch id e*, timestep t* of the maximum loading (smallest
+ *                  (e, t) on exact ties) and contingency branch id l*, the
+ *                  first contingency within TTO_WORST_CONT_TIE_MW of the
+ *                  maximum |flow| at (e*, t*) (l* = -1 when every
+ *                  contingency islands)
  *   n_island_cont  contingencies skipped because they island the grid
  *   base_flows     [n_cand][n_branch][n_timesteps] post-switch N-0 flows
  *   fmax           [n_cand][n_monitored][n_timesteps]
@@ -298,8 +306,9 @@ tto_status tto_set_sweep_plan(tto_grid* grid, int32_t block, int32_t xcd_group,
  * FP64 refinement of FP32-flow grids (on by default, margin 8e-3 MW): after
  * the FP32 pass, a candidate whose maximum loading lies within margin_mw /
  * fbar of a load-bin edge, whose runner-up (branch, timestep) loading is
- * within margin_mw / min fbar of the maximum, or whose runner-up contingency
- * flow at the arg-max is within 2 margin_mw, is re-evaluated end to end in
+ * within margin_mw / min fbar of the maximum, or with a contingency flow at
+ * (e*, t*) within 2 margin_mw of the worst-contingency cut (maximum minus
+ * TTO_WORST_CONT_TIE_MW), is re-evaluated end to end in
  * FP64 on the GPU in the same tto_evaluate (status bit REFINED).  Capacity:
  * max_batch / 8 (at least 64) candidates per call; further flagged
  * candidates keep FP32 results (status bit REFINE_SKIPPED).  No effect on

@@ -22,6 +22,10 @@ from scipy.sparse import csgraph
 from .metrics import n1_metrics, fitness_f1, descriptor_cell
 
 MAX_RANK = 8
+# Worst contingency reading: flows within this many MW of the maximum at
+# (e*, t*) count as tied and the order of the contingency list decides
+# (branches that no outage affects, such as bridges, tie exactly).
+WORST_CONT_TIE_MW = 0.05
 
 
 @dataclass
@@ -192,30 +196,47 @@ def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], 
     n1 = np.full((len(C), len(M), T), np.nan) if keep_n1 else None
     island = np.zeros(len(C), dtype=bool)
     fmax = np.zeros((len(M), T), dtype=np.float64)
-    argl = np.full((len(M), T), -1, dtype=np.int64)   # first contingency attaining fmax
-    for li in positions:
-        l = int(C[li])
+
+    def contingency_flows(l):
+        """All-branch flows with branch l out (None if that islands)."""
         if not net.in_service[l]:
-            fl = f0                                  # already open: N-0 state
-        else:
-            ins = net.in_service.copy()
-            ins[l] = False
-            if not is_connected(net.n_node, net.fr, net.to, ins):
-                island[li] = True
-                continue
-            fl = solve_flows(net.n_node, net.fr, net.to, net.b, ins, net.P, net.slack)
+            return f0                                # already open: N-0 state
+        ins = net.in_service.copy()
+        ins[l] = False
+        if not is_connected(net.n_node, net.fr, net.to, ins):
+            return None
+        return solve_flows(net.n_node, net.fr, net.to, net.b, ins, net.P, net.slack)
+
+    for li in positions:
+        fl = contingency_flows(int(C[li]))
+        if fl is None:
+            island[li] = True
+            continue
         fm = fl[M]
         if keep_n1:
             n1[li] = fm
-        a = np.abs(fm)
-        upd = (a > fmax) | (argl < 0)
-        argl[upd] = li
-        fmax = np.maximum(fmax, a)
+        fmax = np.maximum(fmax, np.abs(fm))
     res = CandidateResult(valid=True, islanded=False, base_flows=f0, n1_flows=n1, fmax=fmax,
                           island_cont=island, n_switched=cand.n_slots_filled)
     if cont_subset is None:
         lim = np.asarray(grid.limit_mw, dtype=np.float64)[M]
-        met = n1_metrics(fmax, f0[M], lim, argl)
+        met = n1_metrics(fmax, f0[M], lim)
+        if met["worst"] is not None:
+            # worst contingency: first in C order whose |flow| at (e*, t*)
+            # is within the tie tolerance of the maximum (a second pass)
+            e_i, t_i, _ = met["worst"]
+            l_star = -1
+            for li in range(len(C)):
+                if island[li]:
+                    continue
+                if keep_n1:
+                    v = abs(n1[li, e_i, t_i])
+                else:
+                    v = abs(contingency_flows(int(C[li]))[M[e_i], t_i])
+                if v >= fmax[e_i, t_i] - WORST_CONT_TIE_MW:
+                    l_star = li
+                    break
+            met["worst"] = (e_i, t_i, l_star)
         res.metrics = met
         res.metrics["n_island_cont"] = int(island.sum())
         res.fitness = fitness_f1(met["overload_mw"], met["n_crit_n0"], met["n_crit_n1"], w_c0, w_c)

@@ -17,11 +17,12 @@ def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
       lambda_c0 = sum_e 1(|f^n0_e| > fbar_e)      (N-0 critical branches, strict)
 
     Multi-timestep reading: sums run over timesteps as well; the maximum
-    loading rho = max_{e,t} f^max_e(t) / fbar_e.  The arg-max (e*, t*, l*) is the
-    lexicographically smallest index triple attaining max |f^(l)_e(t)| / fbar_e.
+    loading rho = max_{e,t} f^max_e(t) / fbar_e.  (e*, t*) is the
+    lexicographically smallest pair attaining rho; the third entry of "worst"
+    is argl[e*, t*] when argl is given (the candidate evaluation fills in the
+    worst contingency by its own rule).
 
-    fmax, f0: [|M|, T]; limit: [|M|]; argl: [|M|, T] position in C of the first
-    contingency attaining fmax (-1 if none).
+    fmax, f0: [|M|, T]; limit: [|M|]; argl: [|M|, T] positions in C, or None.
     """
     lim = limit[:, None]
     over = np.maximum(fmax - lim, 0.0)

@@ -816,12 +816,23 @@ __global__ void k_zero_int(int* p) { *p = 0; }
 // candidates whose discrete outputs lie within the flow error margin of a
 // decision (a load-bin edge, a runner-up (e, t) loading, a runner-up
 // contingency at (e*, t*)) are queued for the FP64 pass.
+// Dynamic LDS of k_finalize: one flow per active contingency when it fits in
+// 32 KB (else the second pass recomputes the flows).
+template <typename F>
+static inline size_t finalize_lds_bytes(int nC) {
+  const size_t b = sizeof(F) * ((size_t)nC + 1);
+  return b <= 32768 ? b : 0;
+}
+
 template <typename F, int TT>
 __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
                                                  const F* __restrict__ HMC, tto_outputs o,
                                                  const int* __restrict__ map,
                                                  const int* __restrict__ live, int cap,
-                                                 RefineCtl rc) {
+                                                 RefineCtl rc, int cache_flows) {
+  // cache_flows: the launch provides (nC + 1) F of dynamic LDS for the flows
+  // of the worst-contingency passes
+  extern __shared__ unsigned char fin_lds[];
   constexpr int RS = rec_stride(TT);
   const int c = blockIdx.x;
   if (map && c >= min(*live, cap)) return;
@@ -865,10 +876,14 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
   }
   __syncthreads();
   const int be = s_be, bt = s_bt;
-  // arg-max contingency at (e*, t*), same arithmetic as the sweep; v2 keeps
-  // the runner-up value for the near-tie test
-  double bv = -1.0, v2 = -1.0;
+  // worst contingency at (e*, t*), same arithmetic as the sweep: the first
+  // active contingency (C order) whose |flow| is within the tie tolerance of
+  // the maximum.  Pass 1 finds the maximum, pass 2 the first index above the
+  // cut and whether any flow sits within the decision margin of the cut.
+  const double mg = decision_margin(g);
+  double bv = -1.0;
   int bi = INT_MAX;
+  bool band = false;
   bool be_open = false;
   if (be >= 0)
     for (int q = 0; q < inf.k; ++q) be_open |= (inf.open_br[q] == g.mon[be]);
@@ -880,21 +895,29 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     const F* ua = w.UM + (size_t)c * kVSlots * nM + be;
     const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
     const int* act = w.act + (size_t)c * (nC + 1);
-    for (int i = lane; i < inf.n_act; i += 64) {
+    auto flow = [&](int i) -> double {
       const F* ri = rec + (size_t)i * RS;
       F h = HMC[(size_t)act[i] * nM + be];
       for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
-      const double v = (double)fabs_t(fma_t(h, ri[bt], a));
-      if (v > bv) { v2 = bv; bv = v; bi = i; }
-      else if (v > v2) v2 = v;
+      return (double)fabs_t(fma_t(h, ri[bt], a));
+    };
+    F* vbuf = cache_flows ? (F*)fin_lds : nullptr;   // lane i mod 64 owns entry i
+    for (int i = lane; i < inf.n_act; i += 64) {
+      const double v = flow(i);
+      if (vbuf) vbuf[i] = (F)v;
+      bv = fmax(bv, v);
+    }
+    for (int off = 32; off > 0; off >>= 1) bv = fmax(bv, __shfl_xor(bv, off));
+    const double cut = bv - kWorstContTieMW;
+    for (int i = lane; i < inf.n_act; i += 64) {
+      const double v = vbuf ? (double)vbuf[i] : flow(i);
+      if (v >= cut && i < bi) bi = i;
+      band |= fabs(v - cut) <= 2.0 * mg;
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_xor(bv, off), o2 = __shfl_xor(v2, off);
-    const int oi = __shfl_xor(bi, off);
-    const bool take = ov > bv || (ov == bv && oi < bi);
-    v2 = fmax(fmax(v2, o2), take ? bv : ov);
-    if (take) { bv = ov; bi = oi; }
+    bi = min(bi, __shfl_xor(bi, off));
+    band |= __shfl_xor((int)band, off) != 0;
   }
   if (lane == 0) {
     const double so = s_sum, best = s_best;
@@ -909,10 +932,9 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     if (rc.flags) {
       int near = 0;
       if (be >= 0) {
-        const double mg = decision_margin(g);
         const double lim_e = g.lim[g.mon[be]];
         near = (best - s_best2) * g.lim_min <= mg;                     // runner-up (e, t)
-        near |= (inf.n_act > 1 && bv - v2 <= 2.0 * mg);                // runner-up l
+        near |= band;                                                  // worst-contingency cut
         for (int q = 0; q < g.n_load_bins - 1; ++q)                    // load-bin edge
           near |= fabs(best - g.edges[q]) * lim_e <= mg;
       }
@@ -1120,8 +1142,9 @@ static void launch_pass(const GridDev& g, const BatchDev& bt, SweepBufs<F> w,
     default: launch_sweep<F, TT, 256>(g, bt, w, HMC, o.fmax, s, plan); break;
   }
   if (ev) hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL((k_finalize<F, TT>), dim3(bt.B), dim3(64), 0, s, g, w, HMC, o, bt.map,
-                     bt.live, bt.B, rc);
+  const size_t fin_lds = finalize_lds_bytes<F>(g.nC);
+  hipLaunchKernelGGL((k_finalize<F, TT>), dim3(bt.B), dim3(64), fin_lds, s, g, w, HMC, o, bt.map,
+                     bt.live, bt.B, rc, fin_lds > 0 ? 1 : 0);
   if (ev) hipEventRecord(ev[3], s);
 }
 
@@ -1176,8 +1199,10 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     hipLaunchKernelGGL((k_sweep_split_epi<TT, 256>), dim3(rb.B * w64.n_eblk), dim3(256), 0, s,
                        gh, w64, ro.fmax, rb.B, (const int*)rc.list, (const int*)rc.count,
                        (const unsigned long long*)rc.fbuf);
-    hipLaunchKernelGGL((k_finalize<double, TT>), dim3(rb.B), dim3(64), 0, s, gh, w64,
-                       (const double*)g.HMC64, ro, rb.map, rb.live, rb.B, none);
+    const size_t fin_lds = finalize_lds_bytes<double>(g.nC);
+    hipLaunchKernelGGL((k_finalize<double, TT>), dim3(rb.B), dim3(64), fin_lds, s, gh, w64,
+                       (const double*)g.HMC64, ro, rb.map, rb.live, rb.B, none,
+                       fin_lds > 0 ? 1 : 0);
     (void)rp;
   }
   if (ev) hipEventRecord(ev[4], s);

@@ -16,6 +16,7 @@ constexpr int kMaxMoved = TTO_MAX_MOVED;
 constexpr int kVSlots = 8;          // V entries per contingency record
 constexpr double kTauIsland = 1e-9; // |pivot| of the scaled bordered system
 constexpr double kTauCont = 1e-9;   // |1 - H'_ll| of a contingency
+constexpr double kWorstContTieMW = TTO_WORST_CONT_TIE_MW;  // worst-contingency tie tolerance
 constexpr int kGemmN = 32;          // timestep columns of the f0 GEMM (T padded)
 
 // Record of one active contingency in a candidate's sweep list:

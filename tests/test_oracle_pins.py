@@ -374,9 +374,40 @@ def test_archive_strict_and_order_invariant():
     assert not np.isin(bi[bi >= 0], np.flatnonzero(~ok)).any()
 
 
+def test_worst_contingency_on_a_bridge_follows_list_order():
+    """A bridge carries the injection of the side it cuts off, whatever other
+    branch is out, so every non-islanding outage ties on it exactly: the
+    worst contingency is the first non-islanding entry of C, for any order."""
+    from gridgen import Grid
+    # ring 0-1-2-3-0 plus bridge 2-4 to a 90 MW load behind a 50 MW limit
+    fr = np.array([0, 1, 2, 3, 2]); to = np.array([1, 2, 3, 0, 4])
+    grid = Grid(n_bus=5, from_bus=fr, to_bus=to, x_pu=np.array([.1, .2, .15, .12, .1]),
+                limit_mw=np.array([300.0, 300, 300, 300, 50]), slack=0)
+    P = np.array([[90.0], [0.0], [0.0], [0.0], [-90.0]])
+    edges = gg.default_load_edges()
+    cand = o.Candidate(opened=[], splits=[], moved_p=[], n_slots_filled=0)
+    for C in ([0, 1, 2, 3, 4], [3, 1, 4, 0, 2], [4, 2, 0, 1, 3]):
+        for keep in (True, False):
+            r = o.evaluate_candidate(grid, P, np.arange(5), np.array(C), cand, edges, keep_n1=keep)
+            assert r.metrics["worst_branch"] == 4 and r.metrics["max_loading"] == pytest.approx(1.8)
+            first = next(l for l in C if l != 4)          # outage of the bridge islands bus 4
+            assert r.metrics["worst_cont"] == first, (C, keep)
+
+
+def test_worst_contingency_second_pass_matches_stored_tensor():
+    w = gg.build_config(2, B=5)
+    edges = gg.default_load_edges()
+    for c in range(5):
+        cand = o.candidate_from_batch(w.batch, c)
+        a = o.evaluate_candidate(w.grid, w.P, w.M, w.C, cand, edges, keep_n1=True)
+        b = o.evaluate_candidate(w.grid, w.P, w.M, w.C, cand, edges, keep_n1=False)
+        assert a.metrics.get("worst_cont") == b.metrics.get("worst_cont")
+
+
 def test_running_argmax_matches_full_tensor():
-    """The arg-max contingency tracked during the loop equals the first
-    maximiser of the stored N-1 tensor at (e*, t*)."""
+    """The worst contingency is the first entry of C whose |flow| in the
+    stored N-1 tensor at (e*, t*) is within the tie tolerance of the
+    maximum, and f^max is the tensor's maximum."""
     w = gg.build_config(2, B=6, move_frac=0.5)
     edges = gg.default_load_edges()
     for c in range(6):
@@ -388,5 +419,6 @@ def test_running_argmax_matches_full_tensor():
         t_ = r.metrics["worst_t"]
         col = np.abs(r.n1_flows[:, e, t_])
         col = np.where(np.isnan(col), -np.inf, col)
-        assert r.metrics["worst_cont"] == int(w.C[int(np.flatnonzero(col == col.max())[0])])
+        tie = o.dcflow.WORST_CONT_TIE_MW
+        assert r.metrics["worst_cont"] == int(w.C[int(np.flatnonzero(col >= col.max() - tie)[0])])
         np.testing.assert_allclose(r.fmax, np.nanmax(np.abs(r.n1_flows), axis=0))
