@@ -267,6 +267,31 @@ def surrogate_leg(s, w, args, exact_rate):
     return res
 
 
+def worst_k_leg(s, w, n=1024, k=20, reps=3):
+    """Worst-k export (tto_worst_contingencies) for n candidates of the
+    workload: set-up plus one energy per (candidate, contingency)."""
+    import numpy as np
+    import torch
+    from paper_2605_10128_amd import tto
+    n = min(n, w.batch.n_cand)
+    db = tto.device_batch(w.batch.subset(np.arange(n)))
+    s.worst_contingencies(db, k)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ids, en = s.worst_contingencies(db, k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    e = en.cpu().numpy()
+    log(f"[bench] worst-{k} export of {n} candidates: {ms:.2f} ms")
+    return {"candidates": n, "k": k, "ms": ms,
+            "median_top_energy_mw": float(np.nanmedian(e[:, 0])),
+            "note": "set-up plus the overload energy of every (candidate, contingency)"}
+
+
 def evolution_leg(s, w, args):
     """MapElites generations on the device (Alg. 3 with Alg. 1 and 2): one
     generation (vary, expand, evaluate, insert) captured as a graph and
@@ -326,6 +351,15 @@ def evolution_leg(s, w, args):
     occ = ids >= 0
     st = outs["status"].cpu().numpy()
     ch = evo.children.cpu().numpy()
+    # end of an epoch: the elites' worst-20 contingencies for the AC validator
+    elites = rep.genome[torch.as_tensor(np.flatnonzero(occ), device=s.device)].contiguous()
+    w0, w1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0.record(stream)
+    edb = gs.expand(elites)
+    wk_ids, wk_en = s.worst_contingencies(edb, 20)
+    w1.record(stream)
+    torch.cuda.synchronize()
+    export_ms = w0.elapsed_time(w1)
     res = {
         "value": B / (ms_gen / 1e3),
         "unit": "evaluated children/s",
@@ -341,6 +375,8 @@ def evolution_leg(s, w, args):
         "cells_filled": int(occ.sum()),
         "best_fitness": float(fit[occ].max()) if occ.any() else None,
         "mean_elite_fitness": float(fit[occ].mean()) if occ.any() else None,
+        "elite_worst20_export_ms": export_ms,
+        "elite_worst20_top_energy_mw": float(np.nanmax(wk_en[:, 0].cpu().numpy())) if occ.any() else None,
         "last_generation": {
             "mutated": int(evo.b_mc.item()),
             "mean_filled_slots": float((ch != -1).sum(1).mean()),
@@ -533,11 +569,14 @@ def main():
         "cpu_baseline": None,
         "surrogate_screened": None,
         "evolution": None,
+        "worst_k": None,
     }
     if not args.no_surrogate:
         result["surrogate_screened"] = surrogate_leg(s, w, args, value)
     if not args.no_evolution and w.split_table:
         result["evolution"] = evolution_leg(s, w, args)
+    if not args.no_evolution:
+        result["worst_k"] = worst_k_leg(s, w)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         result["cpu_baseline"] = cpu_baseline(w)

@@ -439,6 +439,33 @@ tto_status tto_evaluate_capture(tto_grid* grid, const tto_batch* batch, const tt
                                 tto_graph** graph);
 
 /* ------------------------------------------------------------------------
+ * Worst-k contingencies (AC-Validator section: for every N-1 case the DC
+ * optimizer computes the overload energy on its own and writes out the k
+ * worst cases, k = 20 in the paper, which the AC validator computes first).
+ *
+ * For each candidate of `batch` and each non-islanding contingency l:
+ *   E_l = sum_{e in M, t} max(|f^(l)_e(t)| - fbar_e, 0)   (MW x timesteps)
+ * in the grid's flow precision (an opened monitored branch carries no flow;
+ * a contingency on an opened branch is the post-switch N-0 state).  ids
+ * (device int32 [n_cand][k]) receives the contingency branch ids of the k
+ * largest E_l in descending order, ties to the earlier entry of the
+ * contingency list, energy_mw (device FP64 [n_cand][k]) the E_l; entries past
+ * the candidate's non-islanding contingencies, and every entry of an
+ * islanded or invalid candidate, are -1 and NaN.  The candidate set-up runs
+ * again (batch_ws as for tto_evaluate); wk_ws (device, 256-byte aligned)
+ * holds tto_worst_k_bytes.  No FP64 refinement: near-equal energies may
+ * order differently from FP64 within the flow tolerance.
+ */
+#define TTO_MAX_WORST_K 64
+
+tto_status tto_worst_k_bytes(const tto_grid* grid, int32_t n_cand, size_t* bytes);
+
+tto_status tto_worst_contingencies(tto_grid* grid, const tto_batch* batch, int32_t k,
+                                   int32_t* ids, double* energy_mw, void* batch_ws,
+                                   size_t batch_bytes, void* wk_ws, size_t wk_bytes,
+                                   void* stream);
+
+/* ------------------------------------------------------------------------
  * MapElites generation on the device (DC-Optimizer: Repertoire design,
  * Mutation Alg. 1, Crossover Alg. 2, High-level loop Alg. 3): parents are
  * drawn from the repertoire, varied, expanded into a tto_batch, scored by

@@ -90,3 +90,27 @@ def archive_insert_sequential(best_fit: np.ndarray, best_id: np.ndarray, fitness
             best_fit[c] = fitness[i]
             best_id[c] = id_base + i
     return best_fit, best_id
+
+
+def contingency_energies(n1_flows: np.ndarray, limit: np.ndarray) -> np.ndarray:
+    """Overload energy of every N-1 case on its own (AC-Validator section:
+    the worst-k filter): E_l = sum_{e,t} max(|f^(l)_e(t)| - fbar_e, 0).
+    n1_flows [|C|, |M|, T] with NaN rows for islanding contingencies (their
+    E_l is NaN); limit [|M|]."""
+    n1 = np.asarray(n1_flows, dtype=np.float64)
+    out = np.full(n1.shape[0], np.nan)
+    for li in range(n1.shape[0]):
+        if np.isnan(n1[li]).any():
+            continue
+        out[li] = float(np.maximum(np.abs(n1[li]) - limit[:, None], 0.0).sum())
+    return out
+
+
+def worst_k(energies: np.ndarray, C, k: int):
+    """The k largest energies, descending, ties to the earlier entry of C;
+    islanding (NaN) entries excluded; padded with (-1, NaN)."""
+    order = sorted((li for li in range(len(energies)) if not np.isnan(energies[li])),
+                   key=lambda li: (-energies[li], li))[:k]
+    ids = [int(C[li]) for li in order] + [-1] * (k - len(order))
+    en = [float(energies[li]) for li in order] + [float("nan")] * (k - len(order))
+    return np.array(ids, dtype=np.int64), np.array(en)

@@ -1239,6 +1239,160 @@ int sweep_blocks_per_cu(int flow_f32, int TT, int bs) {
   return flow_f32 ? sweep_occ<float>(TT, bs) : sweep_occ<double>(TT, bs);
 }
 
+// ---------------------------------------------------------------------------
+// Worst-k contingencies (the AC validator's pre-filter: the overload energy
+// of every N-1 case on its own, the k largest written out).
+// k_cont_energy: tile = (candidate, 256 monitored branches) as in the sweep;
+// per active contingency every lane forms sum_t max(|f^(l)_e(t)| - fbar_e, 0)
+// (an opened monitored branch carries no flow), the wave adds it in a fixed
+// butterfly and the four waves add in order into part[c][tile][i].
+template <typename F, int TT>
+__global__ __launch_bounds__(256) void k_cont_energy(GridDev g, SweepBufs<F> w,
+                                                     const F* __restrict__ HMC, int n_eblk,
+                                                     double* __restrict__ part) {
+  constexpr int RS = rec_stride(TT);
+  const int c = blockIdx.y, eb = blockIdx.x;
+  const CandInfo* inf = w.info + c;
+  if (inf->status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;   // uniform per workgroup
+  const int nM = g.nM, nC = g.nC, T = g.T;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int ei = eb * 256 + tid;
+  const bool valid = ei < nM;
+  const int ei_c = valid ? ei : nM - 1;
+  const int e = g.mon[ei_c];
+  const int k = inf->k, r = inf->r, n_act = inf->n_act;
+  bool opened = false;
+  for (int q = 0; q < k; ++q) opened |= (inf->open_br[q] == e);
+  const bool live = valid && !opened;
+  const F lim = (F)g.lim[e];
+  F a[TT], U[kVSlots];
+  const F* fa = w.fM + (size_t)c * TT * nM + ei_c;
+  const F* ua = w.UM + (size_t)c * kVSlots * nM + ei_c;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) a[t] = fa[(size_t)t * nM];
+#pragma unroll
+  for (int j = 0; j < kVSlots; ++j) U[j] = j < r ? ua[(size_t)j * nM] : (F)0;
+  const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
+  const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
+  double* out = part + ((size_t)c * n_eblk + eb) * (nC + 1);
+  __shared__ double s_w[4][64];
+  for (int i0 = 0; i0 < n_act; i0 += 64) {
+    const int cnt = min(64, n_act - i0);
+    for (int q = 0; q < cnt; ++q) {
+      const F* ri = rec + (size_t)(i0 + q) * RS;
+      F h = HMC[(size_t)act[i0 + q] * nM + ei_c];
+#pragma unroll
+      for (int j = 0; j < kVSlots; ++j)
+        if (j < r) h = fma_t(U[j], ri[TT + j], h);
+      F ov = (F)0;
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const F f = fabs_t(fma_t(h, ri[t], a[t]));
+        if (t < T && f > lim) ov += f - lim;
+      }
+      double v = live ? (double)ov : 0.0;
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) s_w[wv][q] = v;
+    }
+    __syncthreads();
+    if (tid < cnt) out[i0 + tid] = ((s_w[0][tid] + s_w[1][tid]) + s_w[2][tid]) + s_w[3][tid];
+    __syncthreads();
+  }
+}
+
+// k_worst_k: one workgroup per candidate; tiles summed in order into the
+// first tile's row, then k rounds of a block arg-max over the total order
+// (energy descending, position in the contingency list ascending), each round
+// restricted to keys below the previous pick.
+template <typename F>
+__global__ __launch_bounds__(256) void k_worst_k(GridDev g, SweepBufs<F> w, int n_eblk,
+                                                 double* __restrict__ part, int kk,
+                                                 int* __restrict__ ids,
+                                                 double* __restrict__ energy) {
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const CandInfo* inf = w.info + c;
+  const int nC = g.nC;
+  const int n_act = (inf->status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) ? 0 : inf->n_act;
+  const int* act = w.act + (size_t)c * (nC + 1);
+  double* row = part + (size_t)c * n_eblk * (nC + 1);
+  for (int i = tid; i < n_act; i += 256) {
+    double sum = row[i];
+    for (int b = 1; b < n_eblk; ++b) sum += row[(size_t)b * (nC + 1) + i];
+    row[i] = sum;
+  }
+  __syncthreads();
+  __shared__ double s_v[256];
+  __shared__ int s_p[256];
+  __shared__ double s_prev_v;
+  __shared__ int s_prev_p;
+  if (tid == 0) { s_prev_v = __builtin_inf(); s_prev_p = -1; }
+  __syncthreads();
+  for (int round = 0; round < kk; ++round) {
+    const double pv = s_prev_v;
+    const int pp = s_prev_p;
+    double bv = -1.0;
+    int bp = INT_MAX;   // position in the active list (C order)
+    for (int i = tid; i < n_act; i += 256) {
+      const double v = row[i];
+      const bool below = v < pv || (v == pv && i > pp);
+      if (below && (v > bv || (v == bv && i < bp))) { bv = v; bp = i; }
+    }
+    s_v[tid] = bv;
+    s_p[tid] = bp;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) {
+        const double ov = s_v[tid + off];
+        const int op = s_p[tid + off];
+        if (ov > s_v[tid] || (ov == s_v[tid] && op < s_p[tid])) { s_v[tid] = ov; s_p[tid] = op; }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const int p = s_p[0];
+      const bool got = p != INT_MAX;
+      ids[(size_t)c * kk + round] = got ? g.cont[act[p]] : -1;
+      energy[(size_t)c * kk + round] = got ? s_v[0] : __builtin_nan("");
+      if (got) { s_prev_v = s_v[0]; s_prev_p = p; }
+      else { s_prev_v = -2.0; }      // nothing left: later rounds find nothing
+    }
+    __syncthreads();
+  }
+}
+
+template <typename F, int TT>
+static hipError_t launch_worst_k_tt(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                                    int kk, int* ids, double* energy, double* part,
+                                    hipStream_t s) {
+  const F* HMC;
+  if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
+  const int n_eblk = (g.nM + 255) / 256;
+  hipLaunchKernelGGL((k_setup<F, TT>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr);
+  if (g.nC > 0)
+    hipLaunchKernelGGL((k_cont_energy<F, TT>), dim3(n_eblk, bt.B), dim3(256), 0, s, g, w, HMC,
+                       n_eblk, part);
+  hipLaunchKernelGGL((k_worst_k<F>), dim3(bt.B), dim3(256), 0, s, g, w, n_eblk, part, kk, ids,
+                     energy);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t launch_worst_k(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w, int kk,
+                          int* ids, double* energy, double* part, hipStream_t s) {
+  switch (g.TT) {
+    case 1: return launch_worst_k_tt<F, 1>(g, bt, w, kk, ids, energy, part, s);
+    case 8: return launch_worst_k_tt<F, 8>(g, bt, w, kk, ids, energy, part, s);
+    case 24: return launch_worst_k_tt<F, 24>(g, bt, w, kk, ids, energy, part, s);
+    default: return launch_worst_k_tt<F, 32>(g, bt, w, kk, ids, energy, part, s);
+  }
+}
+
+template hipError_t launch_worst_k<float>(const GridDev&, const BatchDev&, const SweepBufs<float>&,
+                                          int, int*, double*, double*, hipStream_t);
+template hipError_t launch_worst_k<double>(const GridDev&, const BatchDev&,
+                                           const SweepBufs<double>&, int, int*, double*, double*,
+                                           hipStream_t);
+
 template hipError_t launch_evaluate<float>(const GridDev&, const BatchDev&, const SweepBufs<float>&,
                                            const tto_outputs&, hipStream_t, hipEvent_t*,
                                            const SweepPlan&, const SweepBufs<double>*,

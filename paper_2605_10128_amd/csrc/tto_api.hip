@@ -477,6 +477,60 @@ tto_status tto_evaluate(tto_grid* g, const tto_batch* bt, const tto_outputs* out
   return ok();
 }
 
+tto_status tto_worst_k_bytes(const tto_grid* g, int32_t n_cand, size_t* bytes) {
+  if (!g || !bytes) return fail(TTO_E_INVALID, "NULL argument");
+  if (n_cand < 0 || n_cand > g->max_batch)
+    return fail(TTO_E_INVALID, "n_cand %d not in 0..max_batch=%d", n_cand, g->max_batch);
+  const size_t n_eblk = (size_t)(g->nM + 255) / 256;
+  *bytes = round256(sizeof(double) * (size_t)std::max(n_cand, 1) * n_eblk * ((size_t)g->nC + 1));
+  return ok();
+}
+
+tto_status tto_worst_contingencies(tto_grid* g, const tto_batch* bt, int32_t k, int32_t* ids,
+                                   double* energy_mw, void* batch_ws, size_t batch_bytes,
+                                   void* wk_ws, size_t wk_bytes, void* stream) {
+  if (!g || !bt) return fail(TTO_E_INVALID, "grid or batch is NULL");
+  if (k < 1 || k > TTO_MAX_WORST_K) return fail(TTO_E_INVALID, "k %d not in 1..%d", k, TTO_MAX_WORST_K);
+  if (bt->n_cand < 0 || bt->n_cand > g->max_batch)
+    return fail(TTO_E_INVALID, "n_cand %d not in 0..max_batch=%d", bt->n_cand, g->max_batch);
+  if (bt->n_open_slots < 0 || bt->n_open_slots > TTO_MAX_RANK || bt->n_split_slots < 0 ||
+      bt->n_split_slots > TTO_MAX_RANK)
+    return fail(TTO_E_RANK, "slot counts (%d, %d) must each be in 0..%d", bt->n_open_slots,
+                bt->n_split_slots, TTO_MAX_RANK);
+  if (bt->n_open_slots > 0 && !bt->open) return fail(TTO_E_INVALID, "open is NULL");
+  if (bt->n_split_slots > 0 && (!bt->split_bus || !bt->moved_off || !bt->moved_br))
+    return fail(TTO_E_INVALID, "split arrays are NULL");
+  if (bt->n_cand > 0 && (!ids || !energy_mw)) return fail(TTO_E_INVALID, "ids or energy is NULL");
+  if (!batch_ws || ((uintptr_t)batch_ws & 255)) return fail(TTO_E_WORKSPACE, "batch_ws NULL or not 256-byte aligned");
+  if (batch_bytes < g->batch_bytes)
+    return fail(TTO_E_WORKSPACE, "batch_ws has %zu bytes, needs %zu", batch_bytes, g->batch_bytes);
+  size_t need = 0;
+  tto_status st = tto_worst_k_bytes(g, bt->n_cand, &need);
+  if (st != TTO_OK) return st;
+  if (!wk_ws || ((uintptr_t)wk_ws & 255)) return fail(TTO_E_WORKSPACE, "wk_ws NULL or not 256-byte aligned");
+  if (wk_bytes < need) return fail(TTO_E_WORKSPACE, "wk_ws has %zu bytes, needs %zu", wk_bytes, need);
+  if (bt->n_cand == 0) return ok();
+  BatchDev b;
+  b.B = bt->n_cand; b.no = bt->n_open_slots; b.ns = bt->n_split_slots;
+  b.n_genomes = bt->n_cand;
+  b.open = bt->open; b.sbus = bt->split_bus; b.moff = bt->moved_off; b.mbr = bt->moved_br;
+  b.mp = bt->moved_p_mw;
+  b.map = nullptr;
+  b.live = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  size_t used = 0;
+  if (g->flow_prec == TTO_FLOW_F32) {
+    SweepBufs<float> w = carve_batch<float>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
+    w.slot = nullptr;
+    HIP_TRY(launch_worst_k<float>(g->dev, b, w, k, ids, energy_mw, (double*)wk_ws, s));
+  } else {
+    SweepBufs<double> w = carve_batch<double>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
+    w.slot = nullptr;
+    HIP_TRY(launch_worst_k<double>(g->dev, b, w, k, ids, energy_mw, (double*)wk_ws, s));
+  }
+  return ok();
+}
+
 tto_status tto_set_refine(tto_grid* g, int32_t enable, double margin_mw) {
   if (!g) return fail(TTO_E_INVALID, "grid is NULL");
   if (!(margin_mw >= 0.0) || !isfinite(margin_mw)) return fail(TTO_E_INVALID, "margin must be finite and >= 0");

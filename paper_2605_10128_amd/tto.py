@@ -124,6 +124,9 @@ def _load():
         "tto_evaluate_capture": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                         _vp, _i32, ct.c_int64, P(_vp)]),
         "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
+        "tto_worst_k_bytes": (_i32, [_vp, _i32, P(ct.c_size_t)]),
+        "tto_worst_contingencies": (_i32, [_vp, P(tto_batch), _i32, _vp, _vp, _vp, ct.c_size_t,
+                                           _vp, ct.c_size_t, _vp]),
         "tto_genome_space_bytes": (_i32, [P(tto_genome_desc), P(ct.c_size_t)]),
         "tto_genome_space_create": (_i32, [_vp, P(tto_genome_desc), _vp, ct.c_size_t, _vp,
                                            P(_vp)]),
@@ -156,7 +159,8 @@ EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_cr
             "tto_graph_begin", "tto_graph_end", "tto_graph_launch", "tto_graph_destroy",
             "tto_evaluate_capture", "tto_genome_space_bytes", "tto_genome_space_create",
             "tto_genome_space_destroy", "tto_genome_max_moved", "tto_vary", "tto_genome_expand",
-            "tto_generation_bytes", "tto_generation"]
+            "tto_generation_bytes", "tto_generation", "tto_worst_k_bytes",
+            "tto_worst_contingencies"]
 
 
 def _check(code: int):
@@ -333,6 +337,20 @@ def tto_evaluate_capture(handle, batch: "tto_batch", outputs: "tto_outputs", ws,
                                      ws_bytes, _vp(elite_fit), _vp(elite_id), int(n_cells),
                                      int(id_base), ct.byref(g)))
     return g.value
+
+
+def tto_worst_k_bytes(grid: int, n_cand: int) -> int:
+    n = ct.c_size_t()
+    _check(_lib.tto_worst_k_bytes(_vp(grid), int(n_cand), ct.byref(n)))
+    return n.value
+
+
+def tto_worst_contingencies(grid: int, batch: "tto_batch", k: int, ids: int, energy: int,
+                            batch_ws: int, batch_bytes: int, wk_ws: int, wk_bytes: int,
+                            stream: int):
+    _check(_lib.tto_worst_contingencies(_vp(grid), ct.byref(batch), int(k), _vp(ids),
+                                        _vp(energy), _vp(batch_ws), batch_bytes, _vp(wk_ws),
+                                        wk_bytes, _vp(stream)))
 
 
 def tto_genome_space_bytes(desc: tto_genome_desc) -> int:
@@ -674,6 +692,21 @@ class Session:
                                  self.batch_bytes, _ptr(fit), _ptr(ids),
                                  int(fit.shape[0]) if fit is not None else 0, id_base)
         return Graph(h)
+
+    def worst_contingencies(self, dbatch: DeviceBatch, k: int = 20):
+        """(ids [B][k] int32, energy [B][k] FP64) of the k worst N-1 cases
+        per candidate by overload energy (tto_worst_contingencies)."""
+        torch, d = self.torch, self.device
+        B = dbatch.n_cand
+        ids = torch.empty((B, k), dtype=torch.int32, device=d)
+        en = torch.empty((B, k), dtype=torch.float64, device=d)
+        nb = tto_worst_k_bytes(self.handle, B)
+        if getattr(self, "_wk_ws", None) is None or self._wk_ws.numel() < nb:
+            self._wk_ws = torch.empty(nb, dtype=torch.uint8, device=d)
+        tto_worst_contingencies(self.handle, dbatch.struct(), k, _ptr(ids), _ptr(en),
+                                _ptr(self.batch_ws), self.batch_bytes, _ptr(self._wk_ws),
+                                self._wk_ws.numel(), self.stream)
+        return ids, en
 
     def set_sweep_plan(self, block=256, xcd_group=0, persistent=False):
         tto_set_sweep_plan(self.handle, block, xcd_group, persistent)

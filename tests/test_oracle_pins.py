@@ -422,3 +422,44 @@ def test_running_argmax_matches_full_tensor():
         tie = o.dcflow.WORST_CONT_TIE_MW
         assert r.metrics["worst_cont"] == int(w.C[int(np.flatnonzero(col >= col.max() - tie)[0])])
         np.testing.assert_allclose(r.fmax, np.nanmax(np.abs(r.n1_flows), axis=0))
+
+
+def test_contingency_energies_hand_worked():
+    """Two monitored branches (limits 100 and 50 MW), two timesteps, three
+    contingencies (the second islands):
+      l0: |f| = [[120, 90], [40, 70]] -> 20 + 0 + 0 + 20 = 40
+      l1: islands -> excluded
+      l2: |f| = [[-101, 99], [50, 51]] -> 1 + 0 + 0 + 1 = 2
+    and a fourth with no overload (0).  Worst-2: l0, l2; worst-4 pads."""
+    n1 = np.array([[[120, 90], [40, -70]], [[np.nan, np.nan], [np.nan, np.nan]],
+                   [[-101, 99], [50, 51]], [[10, 20], [30, 40]]], dtype=float)
+    lim = np.array([100.0, 50.0])
+    E = o.contingency_energies(n1, lim)
+    assert E[0] == 40.0 and np.isnan(E[1]) and E[2] == 2.0 and E[3] == 0.0
+    ids, en = o.worst_k(E, [11, 12, 13, 14], 2)
+    assert ids.tolist() == [11, 13] and en.tolist() == [40.0, 2.0]
+    ids, en = o.worst_k(E, [11, 12, 13, 14], 5)
+    assert ids.tolist() == [11, 13, 14, -1, -1] and np.isnan(en[3:]).all()
+    # ties (all zero) go to the earlier entry of C
+    ids, _ = o.worst_k(np.zeros(5), [9, 3, 7, 1, 5], 3)
+    assert ids.tolist() == [9, 3, 7]
+
+
+def test_contingency_energies_bound_the_overload_energy():
+    """f^max >= |f^(l)| gives E_l <= lambda_o for every l, and every (e, t)
+    maximum is attained by some outage, so lambda_o <= sum_l E_l."""
+    w = gg.build_config(2, B=6)
+    edges = gg.default_load_edges()
+    lim = w.grid.limit_mw[w.M]
+    seen = 0
+    for c in range(6):
+        r = o.evaluate_candidate(w.grid, w.P, w.M, w.C, o.candidate_from_batch(w.batch, c), edges,
+                                 keep_n1=True)
+        if r.islanded or not r.valid:
+            continue
+        E = o.contingency_energies(r.n1_flows, lim)
+        lam = r.metrics["overload_mw"]
+        fin = E[~np.isnan(E)]
+        assert fin.max() <= lam + 1e-9 and lam <= fin.sum() + 1e-9
+        seen += lam > 0
+    assert seen >= 1
