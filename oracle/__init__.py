@@ -31,7 +31,7 @@ hand-worked metric examples under tests/golden/.
 from .dcflow import (  # noqa: F401
     Candidate, CandidateResult, candidate_from_batch, validate_candidate,
     post_switch_network, is_connected, solve_flows, evaluate_candidate,
-    evaluate_batch,
+    evaluate_batch, busbar_outage_flows, busbar_metrics, fitness_f2,
 )
 from .metrics import (  # noqa: F401
     n1_metrics, fitness_f1, descriptor_cell, archive_insert_sequential,

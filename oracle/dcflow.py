@@ -267,3 +267,45 @@ def evaluate_batch(grid, P, M, C, batch, load_edges, idx=None, processes: int = 
     ctx = mp.get_context("fork")
     with ctx.Pool(processes) as pool:
         return pool.map(_eval_one, jobs, chunksize=1)
+
+
+def busbar_outage_flows(net: Network, bus: int):
+    """Flows [m, T] of the post-switch network with busbar `bus` out (its node
+    loses every in-service branch and its injection, which the slack picks
+    up; a split's busbar B is another node and stays), or None if the rest of
+    the network islands.  Node `bus` is removed before the re-solve."""
+    ins = net.in_service.copy()
+    ins[(net.fr == bus) | (net.to == bus)] = False
+    keep = np.arange(net.n_node) != bus
+    remap = np.cumsum(keep) - 1
+    fr, to = remap[net.fr], remap[net.to]
+    if not is_connected(net.n_node - 1, fr, to, ins):
+        return None
+    return solve_flows(net.n_node - 1, fr, to, net.b, ins, net.P[keep], int(remap[net.slack]))
+
+
+def busbar_metrics(grid, P: np.ndarray, M, cand: Candidate, busbars) -> dict:
+    """Fitness function heuristics, busbar penalty: with f^(b) the flows under
+    busbar outage b, lambda_b = sum_{e in M, t} max(max_b |f^(b)_e(t)| -
+    fbar_e, 0) over the busbar outages that do not island the grid (counted
+    in n_island).  Candidate assumed valid and connected."""
+    b = 1.0 / np.asarray(grid.x_pu, dtype=np.float64)
+    net = post_switch_network(grid.n_bus, grid.from_bus, grid.to_bus, b, grid.slack, P, cand)
+    M = np.asarray(M, dtype=np.int64)
+    fmax = np.zeros((len(M), P.shape[1]))
+    n_isl = 0
+    for bus in busbars:
+        f = busbar_outage_flows(net, int(bus))
+        if f is None:
+            n_isl += 1
+            continue
+        fmax = np.maximum(fmax, np.abs(f[M]))
+    lim = np.asarray(grid.limit_mw, dtype=np.float64)[M]
+    lam = float(np.maximum(fmax - lim[:, None], 0.0).sum())
+    return dict(lambda_b=lam, n_island=n_isl, fmax=fmax)
+
+
+def fitness_f2(fitness_f1: float, lambda_b: float, lambda_b_pre: float) -> float:
+    """High-level loop, the second study case: lambda_f2 = lambda_f1 -
+    max(lambda_b - lambda_b_pre, 0)."""
+    return fitness_f1 - max(lambda_b - lambda_b_pre, 0.0)

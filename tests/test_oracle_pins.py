@@ -463,3 +463,90 @@ def test_contingency_energies_bound_the_overload_energy():
         assert fin.max() <= lam + 1e-9 and lam <= fin.sum() + 1e-9
         seen += lam > 0
     assert seen >= 1
+
+
+# ------------------------------------------------------ busbar outages
+def _grid(fr, to, x, lim, n):
+    from gridgen import Grid
+    return Grid(n_bus=n, from_bus=np.array(fr), to_bus=np.array(to), x_pu=np.array(x, float),
+                limit_mw=np.array(lim, float), slack=0)
+
+
+def _empty():
+    return Candidate(opened=[], splits=[], moved_p=[], n_slots_filled=0)
+
+
+def test_busbar_outage_radial_chain_closed_form():
+    """Chain 0-1-2-3 (slack 0), loads 10, 20, 30 MW at buses 1..3: losing
+    busbar 3 drops its load (flows 30, 20, 0); losing 1 or 2 islands."""
+    g = _grid([0, 1, 2], [1, 2, 3], [.1, .1, .1], [100, 100, 100], 4)
+    P = np.array([[60.0], [-10.0], [-20.0], [-30.0]])
+    b = 1 / g.x_pu
+    net = o.post_switch_network(4, g.from_bus, g.to_bus, b, 0, P, _empty())
+    f = o.busbar_outage_flows(net, 3)
+    np.testing.assert_allclose(f[:, 0], [30.0, 20.0, 0.0], atol=1e-9)
+    assert o.busbar_outage_flows(net, 1) is None and o.busbar_outage_flows(net, 2) is None
+    met = o.busbar_metrics(g, P, [0, 1, 2], _empty(), [1, 2, 3])
+    assert met["n_island"] == 2 and met["lambda_b"] == 0.0
+
+
+def test_busbar_outage_ring_closed_form():
+    """Ring 0-1-2-3-0, 60 MW load at bus 2: losing busbar 1 leaves the chain
+    0-3-2, so branch (3,0) carries -60 and (2,3) carries -60 MW."""
+    g = _grid([0, 1, 2, 3], [1, 2, 3, 0], [.1, .1, .1, .1], [100, 100, 50, 50], 4)
+    P = np.array([[60.0], [0.0], [-60.0], [0.0]])
+    net = o.post_switch_network(4, g.from_bus, g.to_bus, 1 / g.x_pu, 0, P, _empty())
+    f = o.busbar_outage_flows(net, 1)
+    np.testing.assert_allclose(f[:, 0], [0.0, 0.0, -60.0, -60.0], atol=1e-9)
+    met = o.busbar_metrics(g, P, [0, 1, 2, 3], _empty(), [1])
+    assert met["lambda_b"] == pytest.approx(20.0)        # 10 MW over on each 50 MW branch
+
+
+def test_busbar_outage_equals_injection_to_slack_and_all_but_one_branch_open():
+    """A busbar outage is the injection moved to the slack plus every branch
+    of the bus but one opened: the kept branch then joins a node without
+    injection and carries nothing."""
+    w = gg.build_config(1)
+    g = w.grid
+    b = 1 / g.x_pu
+    net = o.post_switch_network(g.n_bus, g.from_bus, g.to_bus, b, g.slack, w.P, _empty())
+    checked = 0
+    for bus in range(1, g.n_bus):
+        f = o.busbar_outage_flows(net, bus)
+        on = np.flatnonzero((g.from_bus == bus) | (g.to_bus == bus))
+        if f is None or len(on) < 2:
+            continue
+        ins = np.ones(len(g.from_bus), bool)
+        ins[on[:-1]] = False
+        P2 = w.P.copy()
+        P2[g.slack] += P2[bus]
+        P2[bus] = 0.0
+        f2 = o.solve_flows(g.n_bus, g.from_bus, g.to_bus, b, ins, P2, g.slack)
+        np.testing.assert_allclose(f2, f, atol=1e-9)
+        assert np.all(np.abs(f2[on[-1]]) < 1e-9)
+        checked += 1
+    assert checked >= 5
+
+
+def test_busbar_outage_of_a_split_bus_keeps_busbar_b():
+    """Losing busbar A of a split bus keeps the moved branches and the moved
+    injection on busbar B (KCL holds at B)."""
+    w = gg.build_config(1)
+    g = w.grid
+    inc = [np.flatnonzero((g.from_bus == i) | (g.to_bus == i)) for i in range(g.n_bus)]
+    bus = next(i for i in range(1, g.n_bus) if len(inc[i]) >= 3)
+    moved = [int(inc[bus][0])]
+    cand = Candidate(opened=[], splits=[(bus, moved)], moved_p=[np.array([5.0])], n_slots_filled=1)
+    net = o.post_switch_network(g.n_bus, g.from_bus, g.to_bus, 1 / g.x_pu, g.slack, w.P, cand)
+    f = o.busbar_outage_flows(net, bus)
+    assert f is not None
+    e = moved[0]
+    sign = 1.0 if net.fr[e] == g.n_bus else -1.0     # orientation out of busbar B
+    assert sign * f[e, 0] == pytest.approx(5.0)       # B's only branch carries its injection
+    for x in inc[bus][1:]:
+        assert f[x, 0] == 0.0
+
+
+def test_fitness_f2_clips_at_the_pre_optimisation_penalty():
+    assert o.fitness_f2(-100.0, 30.0, 50.0) == -100.0
+    assert o.fitness_f2(-100.0, 80.0, 50.0) == -130.0
