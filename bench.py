@@ -267,6 +267,51 @@ def surrogate_leg(s, w, args, exact_rate):
     return res
 
 
+def busbar_leg(s, w, ptdf, n_busbars=128, reps=3):
+    """Busbar outages (lambda_b, lambda_f2) over the whole batch for a seeded
+    busbar set: set-up, one FP64 bordered system per (candidate, busbar) and
+    the busbar-outage sweep."""
+    import numpy as np
+    import torch
+    import gridgen as gg
+    from paper_2605_10128_amd import tto
+    g = w.grid
+    buses = gg.select_busbars(g, n_busbars, seed=0xBB00 + w.cfg)
+    bset = s.busbar_set(buses, ptdf)
+    db = tto.device_batch(w.batch)
+    out = s.evaluate(db)
+    empty = tto.device_batch(w.batch.subset(np.zeros(1, dtype=np.int64)))
+    empty.open.fill_(-1)
+    empty.split_bus.fill_(-1)
+    pre_l, _, _ = s.busbar_evaluate(bset, empty)
+    torch.cuda.synchronize()
+    pre = float(pre_l.item())
+    s.busbar_evaluate(bset, db, pre, out["fitness"])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lam, nis, f2 = s.busbar_evaluate(bset, db, pre, out["fitness"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    B = w.batch.n_cand
+    lam, nis, f2 = lam.cpu().numpy(), nis.cpu().numpy(), f2.cpu().numpy()
+    f1 = out["fitness"].cpu().numpy()
+    ok = np.isfinite(lam)
+    log(f"[bench] busbar outages: {len(buses)} busbars x {B} candidates in {ms:.2f} ms "
+        f"({B / (ms / 1e3):,.0f} topologies/s), lambda_b_pre {pre:.1f} MW")
+    bset.close()
+    return {"busbars": int(len(buses)), "candidates": B, "ms": ms,
+            "value": B / (ms / 1e3), "unit": "topologies/s (lambda_b of every candidate)",
+            "lambda_b_pre_mw": pre,
+            "lambda_b_median_mw": float(np.median(lam[ok])) if ok.any() else None,
+            "islanding_outages_mean": float(nis[ok].mean()) if ok.any() else None,
+            "f2_below_f1": int((f2[ok] < f1[ok]).sum()),
+            "note": "set-up, an FP64 bordered system per (candidate, busbar), FP32 busbar sweep"}
+
+
 def worst_k_leg(s, w, n=1024, k=20, reps=3):
     """Worst-k export (tto_worst_contingencies) for n candidates of the
     workload: set-up plus one energy per (candidate, contingency)."""
@@ -412,6 +457,7 @@ def main():
     ap.add_argument("--screen-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-evolution", action="store_true", help="skip the MapElites leg")
+    ap.add_argument("--no-busbar", action="store_true", help="skip the busbar-outage leg")
     ap.add_argument("--evo-generations", type=int, default=20)
     ap.add_argument("--evo-slots", type=int, default=4)
     args = ap.parse_args()
@@ -570,6 +616,7 @@ def main():
         "surrogate_screened": None,
         "evolution": None,
         "worst_k": None,
+        "busbar": None,
     }
     if not args.no_surrogate:
         result["surrogate_screened"] = surrogate_leg(s, w, args, value)
@@ -577,6 +624,9 @@ def main():
         result["evolution"] = evolution_leg(s, w, args)
     if not args.no_evolution:
         result["worst_k"] = worst_k_leg(s, w)
+    if not args.no_busbar:
+        s.set_injections(w.P)
+        result["busbar"] = busbar_leg(s, w, ptdf)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample)")
         result["cpu_baseline"] = cpu_baseline(w)

@@ -28,7 +28,7 @@ import numpy as np
 
 __all__ = [
     "Grid", "Batch", "make_grid", "bridges", "make_injections",
-    "select_sets", "make_split_table", "make_candidates", "make_candidates_cfg1",
+    "select_sets", "select_busbars", "make_split_table", "make_candidates", "make_candidates_cfg1",
     "make_candidates_cfg2", "make_candidates_ranked", "CONFIGS", "build_config",
     "default_load_edges", "EMPTY",
 ]
@@ -234,6 +234,15 @@ def _random_assignment(rng, inc_list, max_tries=64):
             return [inc_list[i] for i in range(d) if bits[i]]
     # fallback: move exactly one branch
     return [inc_list[int(rng.integers(0, d))]]
+
+
+def select_busbars(grid: Grid, n: int, seed: int, max_degree: int = 16) -> np.ndarray:
+    """Seeded busbar outage set: n distinct non-slack buses with 1..max_degree
+    branches (a stand-in for the operator's busbar outage list)."""
+    deg = np.bincount(np.concatenate([grid.from_bus, grid.to_bus]), minlength=grid.n_bus)
+    ok = np.flatnonzero((deg >= 1) & (deg <= max_degree) & (np.arange(grid.n_bus) != grid.slack))
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(ok, size=min(n, len(ok)), replace=False)).astype(np.int32)
 
 
 def make_split_table(grid: Grid, size: int, seed: int, min_degree: int = 3):

@@ -466,6 +466,59 @@ tto_status tto_worst_contingencies(tto_grid* grid, const tto_batch* batch, int32
                                    void* stream);
 
 /* ------------------------------------------------------------------------
+ * Busbar outages (Problem formulation: the busbar outage set O_b; Fitness
+ * function heuristics: busbar penalty lambda_b; High-level loop: lambda_f2).
+ *
+ * A busbar outage of bus b removes every in-service branch on b's node of the
+ * post-switch grid and the injection on that node, which the slack takes over
+ * (when the candidate splits b, the outage takes busbar A: the moved branches
+ * and moved injection on busbar B stay).  With f^(b) the flows of that state,
+ *   lambda_b = sum_{e in M, t} max(max_b |f^(b)_e(t)| - fbar_e, 0)
+ * over the outages that leave the rest of the grid connected (the others are
+ * counted in n_island), and
+ *   lambda_f2 = lambda_f1 - max(lambda_b - lambda_b_pre, 0)
+ * with lambda_b_pre the value of the pre-optimisation topology (evaluate the
+ * empty candidate first).  Flows in the grid's flow precision; the per-
+ * outage systems in FP64 (same islanding test as tto_evaluate).
+ */
+typedef struct tto_busbars tto_busbars;   /* opaque host handle */
+
+/* Device bytes of a busbar set (host only). */
+tto_status tto_busbar_set_bytes(const tto_grid* grid, int32_t n_busbars, size_t* bytes);
+
+/*
+ * buses: host [n_busbars] distinct bus ids, not the slack, each with 1..16
+ * branches in the base grid (else TTO_E_GRID).  ptdf: the grid's PTDF again
+ * (device FP64 [n_branch][n_bus], read during this call only).  ws: device,
+ * 256-byte aligned, tto_busbar_set_bytes long, caller-owned and kept until
+ * tto_busbar_set_destroy.  Synchronises `stream`.
+ */
+tto_status tto_busbar_set_create(const tto_grid* grid, int32_t n_busbars, const int32_t* buses,
+                                 const double* ptdf, void* ws, size_t bytes, void* stream,
+                                 tto_busbars** out);
+
+void tto_busbar_set_destroy(tto_busbars* set);
+
+/* Bytes of bb_ws for tto_busbar_evaluate on n_cand candidates (host only). */
+tto_status tto_busbar_bytes(const tto_grid* grid, const tto_busbars* set, int32_t n_cand,
+                            size_t* bytes);
+
+/*
+ * lambda_b (device FP64 [n_cand], may be NULL), n_island (device int32
+ * [n_cand], may be NULL) and, when fitness_f2 is not NULL, lambda_f2 from
+ * fitness_f1 (device FP64 [n_cand], tto_evaluate's fitness of the same batch)
+ * and a finite lambda_b_pre.  p_mw: the injections installed with
+ * tto_set_injections (device FP64 [n_bus][n_timesteps]).  Islanded or invalid
+ * candidates get NaN, 0 and -inf.  The candidate set-up runs again
+ * (batch_ws as for tto_evaluate).  Asynchronous.
+ */
+tto_status tto_busbar_evaluate(tto_grid* grid, const tto_busbars* set, const tto_batch* batch,
+                               const double* p_mw, double lambda_b_pre, const double* fitness_f1,
+                               double* lambda_b, int32_t* n_island, double* fitness_f2,
+                               void* batch_ws, size_t batch_bytes, void* bb_ws, size_t bb_bytes,
+                               void* stream);
+
+/* ------------------------------------------------------------------------
  * MapElites generation on the device (DC-Optimizer: Repertoire design,
  * Mutation Alg. 1, Crossover Alg. 2, High-level loop Alg. 3): parents are
  * drawn from the repertoire, varied, expanded into a tto_batch, scored by

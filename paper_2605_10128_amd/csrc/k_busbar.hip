@@ -1,0 +1,412 @@
+// Busbar outages (Fitness function heuristics: busbar penalty lambda_b; High-
+// level loop: lambda_f2 = lambda_f1 - max(lambda_b - lambda_b_pre, 0)).
+//
+// A busbar outage b removes every in-service branch on bus b's node of the
+// post-switch grid (a split's busbar B is another node and keeps its branches
+// and its moved injection) and loses the injection P_A(t) left on that node,
+// which the slack picks up.  On the device this is the candidate's bordered
+// system on the base grid with the busbar's branches as extra openings, all
+// but one of them: once P_A has moved to the slack, the node carries no
+// injection, so the one branch kept in service carries no flow (opening all
+// of them would make the system singular).  The base flows are shifted to
+// f0 - PTDF_{:,b} P_A.  An outage whose system fails the pivot test islands
+// the grid and is skipped and counted.
+//
+//   k_bb_setup     one wave per (candidate, busbar): genome parse in the set-up
+//                  kernel's column order, bordered matrix, FP64 LU with the
+//                  islanding test, solutions z(t) and P_A(t) stored.
+//   k_bb_sweep     tile (candidate, 256 monitored branches) as in the N-1
+//                  sweep: the candidate's U rows from the set-up, the busbar's
+//                  own columns gathered per outage, the maximum over outages
+//                  kept in registers; tile sums of max(f^max - fbar, 0).
+//   k_bb_finalize  fixed-order sums: lambda_b, islanding count, lambda_f2.
+#include "tto_busbar.h"
+
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+
+namespace tto {
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_bb_tables(const double* __restrict__ ptdf, int n_bus,
+                                                   int m, const int* __restrict__ mon, int nM,
+                                                   const int* __restrict__ bus, int nb,
+                                                   double* __restrict__ PB,
+                                                   double* __restrict__ PBM) {
+  const int ib = blockIdx.y;
+  const int b = bus[ib];
+  for (int x = blockIdx.x * 256 + threadIdx.x; x < m; x += gridDim.x * 256)
+    PB[(size_t)ib * m + x] = ptdf[(size_t)x * n_bus + b];
+  for (int ei = blockIdx.x * 256 + threadIdx.x; ei < nM; ei += gridDim.x * 256)
+    PBM[(size_t)ib * nM + ei] = ptdf[(size_t)mon[ei] * n_bus + b];
+}
+
+struct BbShared {
+  int op[kBbMaxR];            // openings: the candidate's, then the busbar's
+  int sbus[kMaxRank], sslot[kMaxRank];
+  int moff[kMaxRank + 1];
+  int mbr[kMaxMoved];
+  double msg[kMaxMoved], msign[kMaxMoved];
+  double inv_s[kMaxRank];
+  double bK[kBbMaxR];
+  int ids[kBbMaxDeg];
+  int rm[kBbMaxDeg], rmc[kBbMaxDeg];   // moved branches opened by the outage
+  int k, kk, s, R, d, jb, skip, nrm;
+  double M[kBbMaxR][kBbMaxR + 1];
+  int piv[kBbMaxR];
+  double pa[32];
+};
+
+template <typename F, int TT>
+__global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBufs<F> w,
+                                                 BusbarDev bb, const double* __restrict__ P,
+                                                 BusbarRecs<F> rr) {
+  const int ib = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const int T = g.T, m = g.n_branch, nb = bb.nb;
+  const size_t rec = (size_t)c * nb + ib;
+  int* H = rr.hdr + rec * kBbHdr;
+  __shared__ BbShared sh;
+  const int status = w.info[c].status;
+  if (status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) {
+    if (tid == 0) { H[0] = 0; H[1] = 0; H[2] = 0; H[3] = 2; }
+    return;
+  }
+  const int bus = bb.bus[ib];
+  if (tid == 0) {
+    int k = 0, s = 0, jb = -1;
+    for (int i = 0; i < bt.no; ++i) {
+      const int v = bt.open[(size_t)c * bt.no + i];
+      if (v >= 0 && v < m && k < kMaxRank) sh.op[k++] = v;
+    }
+    int lo[kMaxRank], hi[kMaxRank];
+    for (int j = 0; j < bt.ns; ++j) {
+      const int sb = bt.sbus[(size_t)c * bt.ns + j];
+      if (sb == -1 || s >= kMaxRank) continue;
+      sh.sbus[s] = sb;
+      sh.sslot[s] = j;
+      lo[s] = bt.moff[(size_t)c * bt.ns + j];
+      hi[s] = bt.moff[(size_t)c * bt.ns + j + 1];
+      if (sb == bus) jb = s;
+      ++s;
+    }
+    // branches on the busbar's node: incident in the base grid, in service,
+    // not moved to busbar B of a split of this bus
+    int d = 0;
+    for (int p = bb.inc_off[ib]; p < bb.inc_off[ib + 1]; ++p) {
+      const int x = bb.inc_br[p];
+      bool off = false;
+      for (int q = 0; q < k; ++q) off |= sh.op[q] == x;
+      if (jb >= 0)
+        for (int q = lo[jb]; q < hi[jb]; ++q) off |= bt.mbr[q] == x;
+      if (!off && d < kBbMaxDeg) sh.ids[d++] = x;
+    }
+    int kk = k;
+    for (int q = 0; q + 1 < d; ++q) sh.op[kk++] = sh.ids[q];
+    // moved lists without the branches this outage opens (a split of a
+    // neighbour may have moved a branch of the busbar)
+    int nm = 0, nrm = 0;
+    for (int j = 0; j < s; ++j) {
+      sh.moff[j] = nm;
+      double ssum = 0.0;
+      for (int p = lo[j]; p < hi[j] && nm < kMaxMoved; ++p) {
+        const int e = bt.mbr[p];
+        const double sg = g.from[e] == sh.sbus[j] ? 1.0 : -1.0;
+        bool opened_here = false;
+        for (int q = k; q < kk; ++q) opened_here |= sh.op[q] == e;
+        if (opened_here) {
+          if (nrm < kBbMaxDeg) { sh.rm[nrm] = e; sh.rmc[nrm] = 2 * j + (sg > 0.0 ? 1 : 0); ++nrm; }
+          continue;
+        }
+        sh.mbr[nm] = e;
+        sh.msign[nm] = sg;
+        sh.msg[nm] = sg * g.b[e];
+        ssum += g.b[e];
+        ++nm;
+      }
+      sh.inv_s[j] = ssum > 0.0 ? 1.0 / ssum : 0.0;
+    }
+    sh.moff[s] = nm;
+    for (int q = 0; q < kk; ++q) sh.bK[q] = g.b[sh.op[q]];
+    sh.k = k; sh.kk = kk; sh.s = s; sh.R = kk + s; sh.d = d; sh.jb = jb; sh.nrm = nrm;
+  }
+  __syncthreads();
+  const int k = sh.k, kk = sh.kk, R = sh.R, d = sh.d, jb = sh.jb;
+  if (tid < TT) {
+    double pa = 0.0;
+    if (tid < T) {
+      pa = P[(size_t)bus * T + tid];
+      if (jb >= 0 && bt.mp) pa -= bt.mp[((size_t)c * bt.ns + sh.sslot[jb]) * T + tid];
+    }
+    sh.pa[tid] = pa;
+  }
+  // bordered matrix, as in the set-up with the extended opening list
+  const size_t mm = m;
+  for (int idx = tid; idx < R * R; idx += 64) {
+    const int i = idx / R, q = idx - i * R;
+    double v = 0.0;
+    if (i < kk) {
+      const size_t ki = (size_t)sh.op[i] * mm;
+      if (q < kk) {
+        v = (i == q ? 1.0 : 0.0) - sh.bK[i] * g.S[ki + sh.op[q]];
+      } else {
+        const int j = q - kk;
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) v += sh.msg[p] * g.S[ki + sh.mbr[p]];
+        v *= sh.bK[i];
+      }
+    } else {
+      const int j = i - kk;
+      if (q < kk) {
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p)
+          v += sh.msg[p] * g.S[(size_t)sh.mbr[p] * mm + sh.op[q]];
+      } else {
+        const int j2 = q - kk;
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) {
+          const size_t bp = (size_t)sh.mbr[p] * mm;
+          for (int p2 = sh.moff[j2]; p2 < sh.moff[j2 + 1]; ++p2) {
+            v -= sh.msg[p] * sh.msg[p2] * g.S[bp + sh.mbr[p2]];
+            if (sh.mbr[p] == sh.mbr[p2]) v += sh.msign[p] * sh.msign[p2] * g.b[sh.mbr[p]];
+          }
+        }
+      }
+      v *= sh.inv_s[j];
+    }
+    sh.M[i][q] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double minpiv = DBL_MAX;
+    for (int p = 0; p < R; ++p) {
+      int best = p;
+      double bv = fabs(sh.M[p][p]);
+      for (int i = p + 1; i < R; ++i)
+        if (fabs(sh.M[i][p]) > bv) { bv = fabs(sh.M[i][p]); best = i; }
+      sh.piv[p] = best;
+      if (best != p)
+        for (int q = 0; q < R; ++q) { const double t = sh.M[p][q]; sh.M[p][q] = sh.M[best][q]; sh.M[best][q] = t; }
+      minpiv = fmin(minpiv, bv);
+      if (bv > 0.0) {
+        for (int i = p + 1; i < R; ++i) {
+          const double f = sh.M[i][p] / sh.M[p][p];
+          sh.M[i][p] = f;
+          for (int q = p + 1; q < R; ++q) sh.M[i][q] -= f * sh.M[p][q];
+        }
+      }
+    }
+    sh.skip = (R > 0 && minpiv < kTauIsland) ? 1 : 0;
+    H[0] = R; H[1] = k; H[2] = d; H[3] = sh.skip;
+    for (int q = 0; q < kBbMaxDeg; ++q) {
+      H[4 + q] = q < d ? sh.ids[q] : -1;
+      H[4 + kBbMaxDeg + q] = q < sh.nrm ? sh.rm[q] : -1;
+      H[4 + 2 * kBbMaxDeg + q] = q < sh.nrm ? sh.rmc[q] : -1;
+    }
+  }
+  __syncthreads();
+  F* z = rr.z + rec * kBbMaxR * TT;
+  if (tid < TT) {
+    rr.pa[rec * TT + tid] = (F)sh.pa[tid];
+  }
+  if (sh.skip) return;
+  // z(t) = M^{-1} rhs(t) with the base flows shifted by the lost injection
+  if (tid < TT) {
+    const int t = tid;
+    double x[kBbMaxR];
+    for (int q = 0; q < kBbMaxR; ++q) x[q] = 0.0;
+    if (t < T) {
+      const double pa = sh.pa[t];
+      const double* PBr = bb.PB + (size_t)ib * m;
+      for (int q = 0; q < R; ++q) {
+        if (q < kk) {
+          const int x0 = sh.op[q];
+          x[q] = g.f0[(size_t)x0 * T + t] - PBr[x0] * pa;
+        } else {
+          const int j = q - kk;
+          double phi = 0.0;
+          for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) {
+            const int e = sh.mbr[p];
+            phi += sh.msign[p] * (g.f0[(size_t)e * T + t] - PBr[e] * pa);
+          }
+          const double pj = bt.mp ? bt.mp[((size_t)c * bt.ns + sh.sslot[j]) * T + t] : 0.0;
+          x[q] = (pj - phi) * sh.inv_s[j];
+        }
+      }
+      for (int p = 0; p < R; ++p) {
+        const int pv = sh.piv[p];
+        if (pv != p) { const double tt = x[p]; x[p] = x[pv]; x[pv] = tt; }
+        for (int i = p + 1; i < R; ++i) x[i] -= sh.M[i][p] * x[p];
+      }
+      for (int p = R - 1; p >= 0; --p) {
+        double v = x[p];
+        for (int q = p + 1; q < R; ++q) v -= sh.M[p][q] * x[q];
+        x[p] = v / sh.M[p][p];
+      }
+    }
+    for (int q = 0; q < kBbMaxR; ++q) z[(size_t)q * TT + t] = (F)x[q];
+  }
+}
+
+template <typename F, int TT>
+__global__ __launch_bounds__(256) void k_bb_sweep(GridDev g, SweepBufs<F> w, BusbarDev bb,
+                                                  BusbarRecs<F> rr, int n_eblk) {
+  const int c = blockIdx.y, eb = blockIdx.x, tid = threadIdx.x;
+  const int nM = g.nM, nC = g.nC, T = g.T, nb = bb.nb;
+  const CandInfo* inf = w.info + c;
+  const bool bad = inf->status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
+  const int ei = eb * 256 + tid;
+  const bool valid = ei < nM && !bad;
+  const int ei_c = ei < nM ? ei : nM - 1;
+  const int e = g.mon[ei_c];
+  const int kc = bad ? 0 : inf->k, rc = bad ? 0 : inf->r;
+  bool opened = false;
+  for (int q = 0; q < kc; ++q) opened |= (inf->open_br[q] == e);
+  F U[kVSlots];
+  const F* ua = w.UM + (size_t)c * kVSlots * nM + ei_c;
+#pragma unroll
+  for (int q = 0; q < kVSlots; ++q) U[q] = q < rc ? ua[(size_t)q * nM] : (F)0;
+  F f0e[TT], acc[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) { f0e[t] = t < T ? (F)g.f0[(size_t)e * T + t] : (F)0; acc[t] = (F)0; }
+  const F be = (F)g.b[e];
+  const size_t nMC = (size_t)nM + nC;
+  for (int ib = 0; ib < nb && !bad; ++ib) {
+    const size_t rec = (size_t)c * nb + ib;
+    const int* H = rr.hdr + rec * kBbHdr;
+    if (H[3]) continue;
+    const int k = H[1], d = H[2];
+    const int kk = k + (d > 0 ? d - 1 : 0);
+    bool removed = opened;
+    for (int q = 0; q < d; ++q) removed |= H[4 + q] == e;
+    const F* z = rr.z + rec * kBbMaxR * TT;
+    const F* pa = rr.pa + rec * TT;
+    const F pb = (F)bb.PBM[(size_t)ib * nM + ei_c];
+    F f[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) f[t] = f0e[t] - pb * pa[t];
+#pragma unroll
+    for (int q = 0; q < kMaxRank; ++q) {
+      if (q < k) {
+        const F u = U[q];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) f[t] += u * z[(size_t)q * TT + t];
+      }
+    }
+    for (int q = k; q < kk; ++q) {
+      const F u = be * (F)g.SMC[(size_t)H[4 + q - k] * nMC + ei_c];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) f[t] += u * z[(size_t)q * TT + t];
+    }
+    // split columns without the moved branches the outage opens:
+    // u_j(e) + b_e msg_r S_re for each such branch r of split j
+    F uj[kMaxRank];
+#pragma unroll
+    for (int j = 0; j < kMaxRank; ++j) uj[j] = (k + j < rc) ? U[k + j] : (F)0;
+    for (int q = 0; q < kBbMaxDeg; ++q) {
+      const int r = H[4 + kBbMaxDeg + q];
+      if (r < 0) break;
+      const int code = H[4 + 2 * kBbMaxDeg + q];
+      const double msg = (code & 1 ? 1.0 : -1.0) * g.b[r];
+      const F add = (F)(msg * (double)be * g.SMC[(size_t)r * nMC + ei_c]);
+#pragma unroll
+      for (int j = 0; j < kMaxRank; ++j)
+        if (j == (code >> 1)) uj[j] += add;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxRank; ++j) {
+      if (k + j < rc) {
+        const F u = uj[j];
+        const int q = kk + j;
+#pragma unroll
+        for (int t = 0; t < TT; ++t) f[t] += u * z[(size_t)q * TT + t];
+      }
+    }
+    if (!removed) {
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const F v = f[t] < (F)0 ? -f[t] : f[t];
+        acc[t] = acc[t] > v ? acc[t] : v;
+      }
+    }
+  }
+  double ov = 0.0;
+  if (valid) {
+    const double lim = g.lim[e];
+    for (int t = 0; t < T && t < TT; ++t) {
+      const double v = (double)acc[t] - lim;
+      if (v > 0.0) ov += v;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) ov += __shfl_xor(ov, off);
+  __shared__ double s_w[4];
+  if ((tid & 63) == 0) s_w[tid >> 6] = ov;
+  __syncthreads();
+  if (tid == 0) rr.part[(size_t)c * n_eblk + eb] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void k_bb_finalize(SweepBufs<F> w, BusbarDev bb,
+                                                     BusbarRecs<F> rr, int B, int n_eblk,
+                                                     double pre, const double* __restrict__ f1,
+                                                     double* __restrict__ lam,
+                                                     int* __restrict__ n_isl,
+                                                     double* __restrict__ f2) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= B) return;
+  const bool bad = w.info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
+  double sum = 0.0;
+  for (int b = 0; b < n_eblk; ++b) sum += rr.part[(size_t)c * n_eblk + b];
+  int cnt = 0;
+  for (int ib = 0; ib < bb.nb; ++ib) cnt += rr.hdr[((size_t)c * bb.nb + ib) * kBbHdr + 3] == 1;
+  if (lam) lam[c] = bad ? __builtin_nan("") : sum;
+  if (n_isl) n_isl[c] = bad ? 0 : cnt;
+  if (f2 && f1) f2[c] = bad ? -__builtin_inf() : f1[c] - fmax(sum - pre, 0.0);
+}
+
+template <typename F, int TT>
+hipError_t launch_busbar_tt(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                            const BusbarDev& bb, const BusbarRecs<F>& rr, const double* P,
+                            double pre, const double* f1, double* lam, int* n_isl, double* f2,
+                            hipStream_t s) {
+  const int n_eblk = (g.nM + 255) / 256;
+  if (bb.nb > 0)
+    hipLaunchKernelGGL((k_bb_setup<F, TT>), dim3(bb.nb, bt.B), dim3(64), 0, s, g, bt, w, bb, P, rr);
+  hipLaunchKernelGGL((k_bb_sweep<F, TT>), dim3(n_eblk, bt.B), dim3(256), 0, s, g, w, bb, rr,
+                     n_eblk);
+  hipLaunchKernelGGL((k_bb_finalize<F>), dim3((bt.B + 255) / 256), dim3(256), 0, s, w, bb, rr,
+                     bt.B, n_eblk, pre, f1, lam, n_isl, f2);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_busbar_tables(const double* ptdf, int n_bus, int m, const int* mon, int nM,
+                                const int* bus, int nb, double* PB, double* PBM, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bb_tables, dim3((m + 255) / 256, nb), dim3(256), 0, s, ptdf, n_bus, m,
+                     mon, nM, bus, nb, PB, PBM);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t launch_busbar(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                         const BusbarDev& bb, const BusbarRecs<F>& rr, const double* P,
+                         double pre, const double* f1, double* lam, int* n_isl, double* f2,
+                         hipStream_t s) {
+  switch (g.TT) {
+    case 1: return launch_busbar_tt<F, 1>(g, bt, w, bb, rr, P, pre, f1, lam, n_isl, f2, s);
+    case 8: return launch_busbar_tt<F, 8>(g, bt, w, bb, rr, P, pre, f1, lam, n_isl, f2, s);
+    case 24: return launch_busbar_tt<F, 24>(g, bt, w, bb, rr, P, pre, f1, lam, n_isl, f2, s);
+    default: return launch_busbar_tt<F, 32>(g, bt, w, bb, rr, P, pre, f1, lam, n_isl, f2, s);
+  }
+}
+
+template hipError_t launch_busbar<float>(const GridDev&, const BatchDev&, const SweepBufs<float>&,
+                                         const BusbarDev&, const BusbarRecs<float>&,
+                                         const double*, double, const double*, double*, int*,
+                                         double*, hipStream_t);
+template hipError_t launch_busbar<double>(const GridDev&, const BatchDev&,
+                                          const SweepBufs<double>&, const BusbarDev&,
+                                          const BusbarRecs<double>&, const double*, double,
+                                          const double*, double*, int*, double*, hipStream_t);
+
+}  // namespace tto

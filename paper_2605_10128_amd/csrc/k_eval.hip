@@ -1387,6 +1387,25 @@ hipError_t launch_worst_k(const GridDev& g, const BatchDev& bt, const SweepBufs<
   }
 }
 
+// Candidate set-up alone (f', U and the contingency records), for the
+// busbar-outage pass that reuses the candidate's U rows.
+template <typename F>
+hipError_t launch_setup(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                        hipStream_t s) {
+  switch (g.TT) {
+    case 1: hipLaunchKernelGGL((k_setup<F, 1>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
+    case 8: hipLaunchKernelGGL((k_setup<F, 8>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
+    case 24: hipLaunchKernelGGL((k_setup<F, 24>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
+    default: hipLaunchKernelGGL((k_setup<F, 32>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_setup<float>(const GridDev&, const BatchDev&, const SweepBufs<float>&,
+                                        hipStream_t);
+template hipError_t launch_setup<double>(const GridDev&, const BatchDev&,
+                                         const SweepBufs<double>&, hipStream_t);
+
 template hipError_t launch_worst_k<float>(const GridDev&, const BatchDev&, const SweepBufs<float>&,
                                           int, int*, double*, double*, hipStream_t);
 template hipError_t launch_worst_k<double>(const GridDev&, const BatchDev&,

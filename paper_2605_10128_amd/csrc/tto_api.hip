@@ -1260,3 +1260,183 @@ tto_status tto_generation(tto_grid* g, const tto_genome_space* gs, const tto_rep
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Busbar outages (lambda_b, lambda_f2).
+#include "tto_busbar.h"
+
+struct tto_busbars {
+  BusbarDev d;
+  int nb;
+  size_t bytes;
+};
+
+namespace {
+
+struct BbLayout {
+  size_t bus, inc_off, inc_br, PB, PBM, total;
+};
+
+BbLayout bb_layout(int nb, int n_inc, int m, int nM) {
+  BbLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t at = o; o += round256(std::max<size_t>(b, 4)); return at; };
+  L.bus = take(4 * (size_t)nb);
+  L.inc_off = take(4 * ((size_t)nb + 1));
+  L.inc_br = take(4 * (size_t)n_inc);
+  L.PB = take(8 * (size_t)nb * m);
+  L.PBM = take(8 * (size_t)nb * nM);
+  L.total = o;
+  return L;
+}
+
+template <typename F>
+size_t bb_recs_bytes(int B, int nb, int TT, int n_eblk, BusbarRecs<F>* rr, void* base) {
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t at = o; o += round256(std::max<size_t>(b, 4)); return at; };
+  const size_t n = (size_t)B * nb;
+  const size_t h = take(4 * n * kBbHdr);
+  const size_t z = take(sizeof(F) * n * kBbMaxR * TT);
+  const size_t pa = take(sizeof(F) * n * TT);
+  const size_t part = take(8 * (size_t)B * n_eblk);
+  if (rr && base) {
+    char* b = (char*)base;
+    rr->hdr = (int*)(b + h); rr->z = (F*)(b + z); rr->pa = (F*)(b + pa); rr->part = (double*)(b + part);
+  }
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+tto_status tto_busbar_set_bytes(const tto_grid* g, int32_t n_busbars, size_t* bytes) {
+  if (!g || !bytes) return fail(TTO_E_INVALID, "NULL argument");
+  if (n_busbars < 0) return fail(TTO_E_INVALID, "n_busbars must be >= 0");
+  *bytes = bb_layout(n_busbars, n_busbars * kBbMaxDeg, g->m, g->nM).total;
+  return ok();
+}
+
+tto_status tto_busbar_set_create(const tto_grid* g, int32_t n_busbars, const int32_t* buses,
+                                 const double* ptdf, void* ws, size_t bytes, void* stream,
+                                 tto_busbars** out) {
+  if (!g || !out) return fail(TTO_E_INVALID, "grid or out is NULL");
+  *out = nullptr;
+  if (n_busbars < 0 || (n_busbars > 0 && (!buses || !ptdf)))
+    return fail(TTO_E_INVALID, "bad busbar list or NULL ptdf");
+  const int nb = n_busbars, n = g->n_bus, m = g->m;
+  std::vector<std::vector<int>> inc(n);
+  for (int e = 0; e < m; ++e) { inc[g->hfrom[e]].push_back(e); inc[g->hto[e]].push_back(e); }
+  std::vector<int> off(nb + 1, 0), br;
+  std::vector<char> seen(n, 0);
+  for (int i = 0; i < nb; ++i) {
+    const int b = buses[i];
+    if (b < 0 || b >= n || seen[b]) return fail(TTO_E_GRID, "busbar %d: bus %d out of range or repeated", i, b);
+    if (b == g->slack) return fail(TTO_E_GRID, "busbar %d is the slack bus", i);
+    if (inc[b].empty() || (int)inc[b].size() > kBbMaxDeg)
+      return fail(TTO_E_GRID, "bus %d has %zu branches (1..%d allowed)", b, inc[b].size(), kBbMaxDeg);
+    seen[b] = 1;
+    br.insert(br.end(), inc[b].begin(), inc[b].end());
+    off[i + 1] = (int)br.size();
+  }
+  const BbLayout L = bb_layout(nb, (int)br.size(), m, g->nM);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(TTO_E_WORKSPACE, "ws NULL or not 256-byte aligned");
+  size_t need = 0;
+  tto_status st = tto_busbar_set_bytes(g, nb, &need);
+  if (st != TTO_OK) return st;
+  if (bytes < need) return fail(TTO_E_WORKSPACE, "ws has %zu bytes, needs %zu", bytes, need);
+  char* base = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  if (nb > 0) {
+    HIP_TRY(hipMemcpyAsync(base + L.bus, buses, 4 * (size_t)nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + L.inc_off, off.data(), 4 * off.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + L.inc_br, br.data(), 4 * br.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_busbar_tables(ptdf, n, m, g->dev.mon, g->nM, (const int*)(base + L.bus), nb,
+                                 (double*)(base + L.PB), (double*)(base + L.PBM), s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  tto_busbars* bs = new tto_busbars();
+  bs->nb = nb;
+  bs->bytes = need;
+  bs->d.nb = nb;
+  bs->d.bus = (const int*)(base + L.bus);
+  bs->d.inc_off = (const int*)(base + L.inc_off);
+  bs->d.inc_br = (const int*)(base + L.inc_br);
+  bs->d.PB = (const double*)(base + L.PB);
+  bs->d.PBM = (const double*)(base + L.PBM);
+  *out = bs;
+  return ok();
+}
+
+void tto_busbar_set_destroy(tto_busbars* bs) { delete bs; }
+
+tto_status tto_busbar_bytes(const tto_grid* g, const tto_busbars* bs, int32_t n_cand,
+                            size_t* bytes) {
+  if (!g || !bs || !bytes) return fail(TTO_E_INVALID, "NULL argument");
+  if (n_cand < 0 || n_cand > g->max_batch)
+    return fail(TTO_E_INVALID, "n_cand %d not in 0..max_batch=%d", n_cand, g->max_batch);
+  const int n_eblk = (g->nM + 255) / 256;
+  *bytes = g->flow_prec == TTO_FLOW_F32
+               ? bb_recs_bytes<float>(std::max(n_cand, 1), bs->nb, g->TT, n_eblk, nullptr, nullptr)
+               : bb_recs_bytes<double>(std::max(n_cand, 1), bs->nb, g->TT, n_eblk, nullptr, nullptr);
+  return ok();
+}
+
+tto_status tto_busbar_evaluate(tto_grid* g, const tto_busbars* bs, const tto_batch* bt,
+                               const double* p_mw, double lambda_b_pre, const double* fitness_f1,
+                               double* lambda_b, int32_t* n_island, double* fitness_f2,
+                               void* batch_ws, size_t batch_bytes, void* bb_ws, size_t bb_bytes,
+                               void* stream) {
+  if (!g || !bs || !bt) return fail(TTO_E_INVALID, "grid, busbar set or batch is NULL");
+  if (bt->n_cand < 0 || bt->n_cand > g->max_batch)
+    return fail(TTO_E_INVALID, "n_cand %d not in 0..max_batch=%d", bt->n_cand, g->max_batch);
+  if (bt->n_open_slots < 0 || bt->n_open_slots > TTO_MAX_RANK || bt->n_split_slots < 0 ||
+      bt->n_split_slots > TTO_MAX_RANK)
+    return fail(TTO_E_RANK, "slot counts (%d, %d) must each be in 0..%d", bt->n_open_slots,
+                bt->n_split_slots, TTO_MAX_RANK);
+  if (bt->n_open_slots > 0 && !bt->open) return fail(TTO_E_INVALID, "open is NULL");
+  if (bt->n_split_slots > 0 && (!bt->split_bus || !bt->moved_off || !bt->moved_br))
+    return fail(TTO_E_INVALID, "split arrays are NULL");
+  if (bs->nb > 0 && !p_mw) return fail(TTO_E_INVALID, "p_mw is NULL");
+  if (fitness_f2 && (!fitness_f1 || !isfinite(lambda_b_pre)))
+    return fail(TTO_E_INVALID, "fitness_f2 needs fitness_f1 and a finite lambda_b_pre");
+  if (!batch_ws || ((uintptr_t)batch_ws & 255)) return fail(TTO_E_WORKSPACE, "batch_ws NULL or not 256-byte aligned");
+  if (batch_bytes < g->batch_bytes)
+    return fail(TTO_E_WORKSPACE, "batch_ws has %zu bytes, needs %zu", batch_bytes, g->batch_bytes);
+  size_t need = 0;
+  tto_status st = tto_busbar_bytes(g, bs, bt->n_cand, &need);
+  if (st != TTO_OK) return st;
+  if (!bb_ws || ((uintptr_t)bb_ws & 255)) return fail(TTO_E_WORKSPACE, "bb_ws NULL or not 256-byte aligned");
+  if (bb_bytes < need) return fail(TTO_E_WORKSPACE, "bb_ws has %zu bytes, needs %zu", bb_bytes, need);
+  if (bt->n_cand == 0) return ok();
+  BatchDev b;
+  b.B = bt->n_cand; b.no = bt->n_open_slots; b.ns = bt->n_split_slots;
+  b.n_genomes = bt->n_cand;
+  b.open = bt->open; b.sbus = bt->split_bus; b.moff = bt->moved_off; b.mbr = bt->moved_br;
+  b.mp = bt->moved_p_mw;
+  b.map = nullptr;
+  b.live = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  const int n_eblk = (g->nM + 255) / 256;
+  size_t used = 0;
+  if (g->flow_prec == TTO_FLOW_F32) {
+    SweepBufs<float> w = carve_batch<float>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
+    w.slot = nullptr;
+    BusbarRecs<float> rr;
+    bb_recs_bytes<float>(bt->n_cand, bs->nb, g->TT, n_eblk, &rr, bb_ws);
+    HIP_TRY(launch_setup<float>(g->dev, b, w, s));
+    HIP_TRY(launch_busbar<float>(g->dev, b, w, bs->d, rr, p_mw, lambda_b_pre, fitness_f1,
+                                 lambda_b, n_island, fitness_f2, s));
+  } else {
+    SweepBufs<double> w = carve_batch<double>(bt->n_cand, g->nM, g->nC, g->TT, batch_ws, &used);
+    w.slot = nullptr;
+    BusbarRecs<double> rr;
+    bb_recs_bytes<double>(bt->n_cand, bs->nb, g->TT, n_eblk, &rr, bb_ws);
+    HIP_TRY(launch_setup<double>(g->dev, b, w, s));
+    HIP_TRY(launch_busbar<double>(g->dev, b, w, bs->d, rr, p_mw, lambda_b_pre, fitness_f1,
+                                  lambda_b, n_island, fitness_f2, s));
+  }
+  return ok();
+}
+
+}  // extern "C"

@@ -156,6 +156,9 @@ int gemm_ksplit(int m, int n);
 // after finalize and after the FP64 refinement pass.  rw/rc: refinement
 // buffers and control (FP32 flows only; rc.cap == 0 disables).
 template <typename F>
+hipError_t launch_setup(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                        hipStream_t s);
+template <typename F>
 hipError_t launch_worst_k(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w, int kk,
                           int* ids, double* energy, double* part, hipStream_t s);
 template <typename F>

@@ -124,6 +124,12 @@ def _load():
         "tto_evaluate_capture": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                         _vp, _i32, ct.c_int64, P(_vp)]),
         "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
+        "tto_busbar_set_bytes": (_i32, [_vp, _i32, P(ct.c_size_t)]),
+        "tto_busbar_set_create": (_i32, [_vp, _i32, _vp, _vp, _vp, ct.c_size_t, _vp, P(_vp)]),
+        "tto_busbar_set_destroy": (None, [_vp]),
+        "tto_busbar_bytes": (_i32, [_vp, _vp, _i32, P(ct.c_size_t)]),
+        "tto_busbar_evaluate": (_i32, [_vp, _vp, P(tto_batch), _vp, ct.c_double, _vp, _vp, _vp,
+                                       _vp, _vp, ct.c_size_t, _vp, ct.c_size_t, _vp]),
         "tto_worst_k_bytes": (_i32, [_vp, _i32, P(ct.c_size_t)]),
         "tto_worst_contingencies": (_i32, [_vp, P(tto_batch), _i32, _vp, _vp, _vp, ct.c_size_t,
                                            _vp, ct.c_size_t, _vp]),
@@ -160,7 +166,8 @@ EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_cr
             "tto_evaluate_capture", "tto_genome_space_bytes", "tto_genome_space_create",
             "tto_genome_space_destroy", "tto_genome_max_moved", "tto_vary", "tto_genome_expand",
             "tto_generation_bytes", "tto_generation", "tto_worst_k_bytes",
-            "tto_worst_contingencies"]
+            "tto_worst_contingencies", "tto_busbar_set_bytes", "tto_busbar_set_create",
+            "tto_busbar_set_destroy", "tto_busbar_bytes", "tto_busbar_evaluate"]
 
 
 def _check(code: int):
@@ -337,6 +344,39 @@ def tto_evaluate_capture(handle, batch: "tto_batch", outputs: "tto_outputs", ws,
                                      ws_bytes, _vp(elite_fit), _vp(elite_id), int(n_cells),
                                      int(id_base), ct.byref(g)))
     return g.value
+
+
+def tto_busbar_set_bytes(grid: int, n_busbars: int) -> int:
+    n = ct.c_size_t()
+    _check(_lib.tto_busbar_set_bytes(_vp(grid), int(n_busbars), ct.byref(n)))
+    return n.value
+
+
+def tto_busbar_set_create(grid: int, n_busbars: int, buses: int, ptdf: int, ws: int, nbytes: int,
+                          stream: int) -> int:
+    h = _vp()
+    _check(_lib.tto_busbar_set_create(_vp(grid), int(n_busbars), _vp(buses), _vp(ptdf), _vp(ws),
+                                      nbytes, _vp(stream), ct.byref(h)))
+    return h.value
+
+
+def tto_busbar_set_destroy(handle: int):
+    _lib.tto_busbar_set_destroy(_vp(handle))
+
+
+def tto_busbar_bytes(grid: int, bset: int, n_cand: int) -> int:
+    n = ct.c_size_t()
+    _check(_lib.tto_busbar_bytes(_vp(grid), _vp(bset), int(n_cand), ct.byref(n)))
+    return n.value
+
+
+def tto_busbar_evaluate(grid: int, bset: int, batch: "tto_batch", p_mw: int, lambda_b_pre: float,
+                        fitness_f1: int, lambda_b: int, n_island: int, fitness_f2: int,
+                        batch_ws: int, batch_bytes: int, bb_ws: int, bb_bytes: int, stream: int):
+    _check(_lib.tto_busbar_evaluate(_vp(grid), _vp(bset), ct.byref(batch), _vp(p_mw),
+                                    float(lambda_b_pre), _vp(fitness_f1), _vp(lambda_b),
+                                    _vp(n_island), _vp(fitness_f2), _vp(batch_ws), batch_bytes,
+                                    _vp(bb_ws), bb_bytes, _vp(stream)))
 
 
 def tto_worst_k_bytes(grid: int, n_cand: int) -> int:
@@ -693,6 +733,28 @@ class Session:
                                  int(fit.shape[0]) if fit is not None else 0, id_base)
         return Graph(h)
 
+    def busbar_set(self, buses, ptdf) -> "BusbarSet":
+        return BusbarSet(self, buses, ptdf)
+
+    def busbar_evaluate(self, bset: "BusbarSet", dbatch: DeviceBatch, lambda_b_pre=float("nan"),
+                        fitness_f1=None):
+        """(lambda_b [B], n_island [B], lambda_f2 [B] or None) of the busbar
+        outages (tto_busbar_evaluate) under the installed injections."""
+        torch, d = self.torch, self.device
+        B = dbatch.n_cand
+        lam = torch.empty(B, dtype=torch.float64, device=d)
+        nis = torch.empty(B, dtype=torch.int32, device=d)
+        f2 = torch.empty(B, dtype=torch.float64, device=d) if fitness_f1 is not None else None
+        nb = tto_busbar_bytes(self.handle, bset.handle, B)
+        if getattr(self, "_bb_ws", None) is None or self._bb_ws.numel() < nb:
+            self._bb_ws = None
+            self._bb_ws = torch.empty(nb, dtype=torch.uint8, device=d)
+        tto_busbar_evaluate(self.handle, bset.handle, dbatch.struct(), _ptr(self._P),
+                            lambda_b_pre, _ptr(fitness_f1), _ptr(lam), _ptr(nis), _ptr(f2),
+                            _ptr(self.batch_ws), self.batch_bytes, _ptr(self._bb_ws),
+                            self._bb_ws.numel(), self.stream)
+        return lam, nis, f2
+
     def worst_contingencies(self, dbatch: DeviceBatch, k: int = 20):
         """(ids [B][k] int32, energy [B][k] FP64) of the k worst N-1 cases
         per candidate by overload energy (tto_worst_contingencies)."""
@@ -838,3 +900,29 @@ class Evolver:
         tto_generation(s.handle, self.gs.handle, self._rep_struct, self.seed, self.n_child,
                        self._out_struct, _ptr(self.gen_ws), self.gen_bytes, _ptr(s.batch_ws),
                        s.batch_bytes, s.stream)
+
+
+class BusbarSet:
+    """Device busbar outage set O_b of a Session's grid (tto_busbar_set_*)."""
+
+    def __init__(self, session: "Session", buses, ptdf):
+        torch = session.torch
+        self.buses = np.ascontiguousarray(buses, dtype=np.int32)
+        pt = ptdf if hasattr(ptdf, "data_ptr") else torch.as_tensor(
+            np.ascontiguousarray(ptdf, dtype=np.float64), device=session.device)
+        n = tto_busbar_set_bytes(session.handle, len(self.buses))
+        self.ws = torch.empty(n, dtype=torch.uint8, device=session.device)
+        self.handle = tto_busbar_set_create(session.handle, len(self.buses),
+                                            self.buses.ctypes.data if len(self.buses) else 0,
+                                            _ptr(pt), _ptr(self.ws), n, session.stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            tto_busbar_set_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
