@@ -123,17 +123,27 @@ typedef struct {
 /*
  * MapElites descriptor and fitness (DC-Optimizer, repertoire design and the
  * fitness lambda_f1 = -(lambda_o + w_c0 lambda_c0 + w_c lambda_c), weights 200
- * and 50 in the paper).  Two-axis cell: count axis = number of switched
- * elements (openings + splits, clamped to n_count_bins-1); load axis = number
- * of load_edges <= max loading (edges ascending).
- * cell = count * n_load_bins + load_bin.
+ * and 50 in the paper).
+ *   TTO_DESC_COUNT_LOAD: two-axis cell, count axis = number of switched
+ *   elements (openings + splits, clamped to n_count_bins-1), load axis =
+ *   number of load_edges <= max loading (edges ascending);
+ *   cell = count * n_load_bins + load_bin.
+ *   TTO_DESC_PAPER: the repertoire design's three axes, lambda_d = openings
+ *   (0..2), lambda_s = splits (0..3), lambda_r = reassigned assets = branches
+ *   moved by the splits (0..45), each clamped;
+ *   cell = lambda_d + 3 (lambda_s + 4 lambda_r), 552 cells (the printed
+ *   coefficient is garbled; this one maps the ranges one to one).
  */
+enum { TTO_DESC_COUNT_LOAD = 0, TTO_DESC_PAPER = 1 };
+#define TTO_PAPER_CELLS 552
+
 typedef struct {
-  int32_t n_count_bins;         /* >= 1 */
-  int32_t n_load_bins;          /* 1..TTO_MAX_LOAD_BINS */
+  int32_t n_count_bins;         /* >= 1 (count-load map) */
+  int32_t n_load_bins;          /* 1..TTO_MAX_LOAD_BINS (count-load map) */
   const double* load_edges;     /* host [n_load_bins - 1], ascending */
   double w_c0;
   double w_c;
+  int32_t kind;                 /* TTO_DESC_* */
 } tto_descriptor_cfg;
 
 /*

@@ -35,5 +35,5 @@ from .dcflow import (  # noqa: F401
 )
 from .metrics import (  # noqa: F401
     n1_metrics, fitness_f1, descriptor_cell, archive_insert_sequential,
-    contingency_energies, worst_k,
+    contingency_energies, worst_k, descriptor_cell_paper,
 )

@@ -19,7 +19,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 from scipy.sparse import csgraph
 
-from .metrics import n1_metrics, fitness_f1, descriptor_cell
+from .metrics import n1_metrics, fitness_f1, descriptor_cell, descriptor_cell_paper
 
 MAX_RANK = 8
 # Worst contingency reading: flows within this many MW of the maximum at
@@ -176,7 +176,8 @@ class CandidateResult:
 def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], cand: Candidate,
                        load_edges: np.ndarray, n_count_bins: int = 32, w_c0: float = 200.0,
                        w_c: float = 50.0, keep_n1: bool = True,
-                       cont_subset: Optional[Sequence[int]] = None) -> CandidateResult:
+                       cont_subset: Optional[Sequence[int]] = None,
+                       descriptor: str = "count_load") -> CandidateResult:
     """Full oracle evaluation of one candidate (steps 1-4 of the definition).
 
     cont_subset restricts the contingency loop to some positions of C (the
@@ -240,8 +241,12 @@ def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], 
         res.metrics = met
         res.metrics["n_island_cont"] = int(island.sum())
         res.fitness = fitness_f1(met["overload_mw"], met["n_crit_n0"], met["n_crit_n1"], w_c0, w_c)
-        res.cell = descriptor_cell(cand.n_slots_filled, met["max_loading"], load_edges,
-                                   n_count_bins)
+        if descriptor == "paper":
+            res.cell = descriptor_cell_paper(len(cand.opened), len(cand.splits),
+                                             sum(len(mv) for _, mv in cand.splits))
+        else:
+            res.cell = descriptor_cell(cand.n_slots_filled, met["max_loading"], load_edges,
+                                       n_count_bins)
         if met["worst"] is not None:
             e_i, t_i, l_i = met["worst"]
             res.metrics["worst_branch"] = int(M[e_i])

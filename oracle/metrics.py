@@ -74,6 +74,16 @@ def descriptor_cell(n_switched: int, max_loading: float, load_edges: np.ndarray,
     return count * n_load_bins + b
 
 
+def descriptor_cell_paper(n_open: int, n_split: int, n_moved: int) -> int:
+    """Repertoire design, the paper's map: lambda_d (disconnections, 0..2),
+    lambda_s (splits, 0..3), lambda_r (reassigned assets, 0..45), each
+    clamped; beta = lambda_d + 3 (lambda_s + 4 lambda_r) (reading of the
+    garbled printed coefficient: it maps the three ranges one to one onto
+    0..551)."""
+    ld, ls, lr = min(n_open, 2), min(n_split, 3), min(n_moved, 45)
+    return ld + 3 * (ls + 4 * lr)
+
+
 def archive_insert_sequential(best_fit: np.ndarray, best_id: np.ndarray, fitness, cells,
                               ok, id_base: int = 0):
     """Unbatched insertion (High-level loop): candidates are offered one at a time

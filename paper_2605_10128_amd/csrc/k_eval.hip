@@ -322,6 +322,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     if (tid == 0) {
       inf->status = TTO_ST_ISLANDED;
       inf->r = r; inf->k = k; inf->n_act = 0; inf->n_act_pad = 0; inf->n_island = 0;
+      inf->n_moved = sh.moff[ns];
       inf->n_crit_n0 = 0;
     }
     return;
@@ -542,6 +543,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     inf->n_act_pad = n_act + (n_act & 1);
     inf->n_island = s_nisl;
     inf->n_crit_n0 = s_n0;
+    inf->n_moved = sh.moff[ns];
     for (int q = 0; q < kMaxRank; ++q) inf->open_br[q] = q < k ? sh.open[q] : -1;
   }
 }
@@ -927,6 +929,12 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     int bin = 0;
     for (int q = 0; q < g.n_load_bins - 1; ++q) bin += (g.edges[q] <= best) ? 1 : 0;
     const int cnt = inf.r < g.n_count_bins - 1 ? inf.r : g.n_count_bins - 1;
+    int cell = cnt * g.n_load_bins + bin;
+    if (g.desc_kind == TTO_DESC_PAPER) {
+      // (disconnections, splits, reassigned assets) clamped to 0..2, 0..3, 0..45
+      const int ld = min(inf.k, 2), ls = min(inf.r - inf.k, 3), lr = min(inf.n_moved, 45);
+      cell = ld + 3 * (ls + 4 * lr);
+    }
     const int* act = w.act + (size_t)c * (nC + 1);
     uint8_t st = (uint8_t)inf.status | refined;
     if (rc.flags) {
@@ -935,8 +943,9 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
         const double lim_e = g.lim[g.mon[be]];
         near = (best - s_best2) * g.lim_min <= mg;                     // runner-up (e, t)
         near |= band;                                                  // worst-contingency cut
-        for (int q = 0; q < g.n_load_bins - 1; ++q)                    // load-bin edge
-          near |= fabs(best - g.edges[q]) * lim_e <= mg;
+        if (g.desc_kind == TTO_DESC_COUNT_LOAD)
+          for (int q = 0; q < g.n_load_bins - 1; ++q)                  // load-bin edge
+            near |= fabs(best - g.edges[q]) * lim_e <= mg;
       }
       rc.flags[c] = near;
     }
@@ -950,7 +959,7 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     if (o.worst_t) o.worst_t[oc] = be >= 0 ? bt : -1;
     if (o.worst_cont) o.worst_cont[oc] = (bi != INT_MAX) ? g.cont[act[bi]] : -1;
     if (o.fitness) o.fitness[oc] = fit;
-    if (o.cell) o.cell[oc] = cnt * g.n_load_bins + bin;
+    if (o.cell) o.cell[oc] = cell;
   }
 }
 

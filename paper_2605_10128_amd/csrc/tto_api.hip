@@ -333,6 +333,7 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S; v.SMC = L.SMC;
   v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.f0_hi = L.f0_hi ? L.f0_hi : L.f0; v.mon = L.mon; v.cont = L.cont;
   v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
+  v.desc_kind = TTO_DESC_COUNT_LOAD;
   v.near_margin = -1.0;
   v.gemm_err = L.gemm_err;
   v.lim_min = 1e300;
@@ -393,6 +394,8 @@ tto_status tto_get_base_flows(tto_grid* g, double* out_mw, void* stream) {
 
 tto_status tto_set_descriptor(tto_grid* g, const tto_descriptor_cfg* cfg) {
   if (!g || !cfg) return fail(TTO_E_INVALID, "grid or cfg is NULL");
+  if (cfg->kind != TTO_DESC_COUNT_LOAD && cfg->kind != TTO_DESC_PAPER)
+    return fail(TTO_E_INVALID, "unknown descriptor kind %d", cfg->kind);
   if (cfg->n_count_bins < 1) return fail(TTO_E_INVALID, "n_count_bins must be >= 1");
   if (cfg->n_load_bins < 1 || cfg->n_load_bins > TTO_MAX_LOAD_BINS)
     return fail(TTO_E_INVALID, "n_load_bins must be in 1..%d", TTO_MAX_LOAD_BINS);
@@ -408,6 +411,7 @@ tto_status tto_set_descriptor(tto_grid* g, const tto_descriptor_cfg* cfg) {
                       hipMemcpyHostToDevice));
   g->dev.n_count_bins = cfg->n_count_bins;
   g->dev.n_load_bins = cfg->n_load_bins;
+  g->dev.desc_kind = cfg->kind;
   g->dev.w_c0 = cfg->w_c0;
   g->dev.w_c = cfg->w_c;
   return ok();
@@ -1223,9 +1227,12 @@ tto_status tto_generation(tto_grid* g, const tto_genome_space* gs, const tto_rep
   if (gen_bytes < L.total) return fail(TTO_E_WORKSPACE, "gen_ws has %zu bytes, needs %zu", gen_bytes, L.total);
   if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < 16 * (size_t)rep->n_cells)
     return fail(TTO_E_WORKSPACE, "batch_ws NULL, misaligned or too small");
-  if (rep->n_cells != g->dev.n_count_bins * g->dev.n_load_bins)
+  const int desc_cells = g->dev.desc_kind == TTO_DESC_PAPER
+                             ? TTO_PAPER_CELLS
+                             : g->dev.n_count_bins * g->dev.n_load_bins;
+  if (rep->n_cells != desc_cells)
     return fail(TTO_E_INVALID, "n_cells %d differs from the descriptor's %d cells", rep->n_cells,
-                g->dev.n_count_bins * g->dev.n_load_bins);
+                desc_cells);
   char* w = (char*)gen_ws;
   hipStream_t s = (hipStream_t)stream;
   int* children = (int*)(w + L.children);

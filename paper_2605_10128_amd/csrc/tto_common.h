@@ -52,6 +52,7 @@ struct GridDev {
   const double* edges;  // [n_load_bins - 1]
   double lim_min;       // smallest monitored limit
   int n_count_bins, n_load_bins;
+  int desc_kind;        // TTO_DESC_*
   double w_c0, w_c;
   // Decision margin of an FP32 pass that queues FP64 refinement (< 0: none):
   // near_margin + 4 max|f0 - f0_hi| MW, the second term read from gemm_err
@@ -98,7 +99,7 @@ struct CandInfo {
   int n_act_pad;   // n_act rounded up to even (duplicate of the last record)
   int n_island;    // islanding contingencies
   int n_crit_n0;   // lambda_c0 from the FP64 post-switch flows
-  int pad_;
+  int n_moved;     // branches moved by the candidate's splits (reassigned assets)
   int open_br[kMaxRank];
 };
 

@@ -36,7 +36,11 @@ class tto_grid_desc(ct.Structure):
 
 class tto_descriptor_cfg(ct.Structure):
     _fields_ = [("n_count_bins", _i32), ("n_load_bins", _i32), ("load_edges", _vp),
-                ("w_c0", ct.c_double), ("w_c", ct.c_double)]
+                ("w_c0", ct.c_double), ("w_c", ct.c_double), ("kind", _i32)]
+
+
+TTO_DESC_COUNT_LOAD, TTO_DESC_PAPER = 0, 1
+TTO_PAPER_CELLS = 552
 
 
 class tto_batch(ct.Structure):
@@ -678,13 +682,15 @@ class Session:
         tto_get_base_flows(self.handle, _ptr(out), self.stream)
         return out
 
-    def set_descriptor(self, load_edges, n_count_bins=32, w_c0=200.0, w_c=50.0):
+    def set_descriptor(self, load_edges, n_count_bins=32, w_c0=200.0, w_c=50.0,
+                       kind=TTO_DESC_COUNT_LOAD):
         self._edges = np.ascontiguousarray(load_edges, dtype=np.float64)
         cfg = tto_descriptor_cfg(int(n_count_bins), len(self._edges) + 1,
                                  self._edges.ctypes.data if len(self._edges) else 0,
-                                 float(w_c0), float(w_c))
+                                 float(w_c0), float(w_c), int(kind))
         tto_set_descriptor(self.handle, cfg)
-        self.n_cells = int(n_count_bins) * (len(self._edges) + 1)
+        self.n_cells = (TTO_PAPER_CELLS if kind == TTO_DESC_PAPER
+                        else int(n_count_bins) * (len(self._edges) + 1))
 
     def alloc_outputs(self, B, base_flows=False, fmax=False, n1=False):
         torch, d = self.torch, self.device

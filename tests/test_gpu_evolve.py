@@ -119,10 +119,13 @@ def test_expand_matches_oracle(s500, w500):
         assert br[off[s]:off[s + 1]].tolist() == moved[s], s
 
 
-def _run_loop(w, flow, n_a, n_d, n_actions, n_child, n_gen, seed, processes, max_batch=None):
+def _run_loop(w, flow, n_a, n_d, n_actions, n_child, n_gen, seed, processes, max_batch=None,
+              descriptor="count_load"):
     import torch
     from paper_2605_10128_amd import tto
     sess = make_session(w, flow, max_batch=max_batch or n_child)
+    if descriptor == "paper":
+        sess.set_descriptor(gg.default_load_edges(), kind=tto.TTO_DESC_PAPER)
     dev, orc = spaces(sess, w, n_a, n_d, n_actions, seed=seed)
     rep = tto.Repertoire(sess, dev)
     outs = sess.alloc_outputs(n_child)
@@ -132,7 +135,8 @@ def _run_loop(w, flow, n_a, n_d, n_actions, n_child, n_gen, seed, processes, max
     for g in range(n_gen):
         evo.step()
         torch.cuda.synchronize()
-        state, logs = _oracle_generation(w, orc, seed, g, n_child, edges, state, processes)
+        state, logs = _oracle_generation(w, orc, seed, g, n_child, edges, state, processes,
+                                         descriptor, sess.n_cells)
         kids = evo.children.cpu().numpy()
         assert np.array_equal(kids, logs["children"]), f"generation {g}: children differ"
         st = outs["status"].cpu().numpy()
@@ -162,16 +166,18 @@ def _run_loop(w, flow, n_a, n_d, n_actions, n_child, n_gen, seed, processes, max
     sess.close()
 
 
-def _oracle_generation(w, orc, seed, g, n_child, edges, state, processes):
+def _oracle_generation(w, orc, seed, g, n_child, edges, state, processes,
+                       descriptor="count_load", n_cells=1024):
     import oracle
     if state is None:
         G = orc.n_a + orc.n_d
-        state = (np.full(1024, -np.inf), np.full(1024, -1, dtype=np.int64),
-                 np.full((1024, G), -1, dtype=np.int32))
+        state = (np.full(n_cells, -np.inf), np.full(n_cells, -1, dtype=np.int64),
+                 np.full((n_cells, G), -1, dtype=np.int32))
     fit, ids, gen = state
     kids, b_mc = ev.vary(orc, ids, gen, seed, g, n_child)
     cands = ev.to_candidates(orc, kids)
-    jobs = [(w.grid, w.P, w.M, w.C, cd, edges, dict(keep_n1=False)) for cd in cands]
+    jobs = [(w.grid, w.P, w.M, w.C, cd, edges, dict(keep_n1=False, descriptor=descriptor))
+            for cd in cands]
     if processes > 1:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(processes) as pool:
@@ -191,6 +197,42 @@ def test_generation_loop_matches_oracle_30_bus_f64():
     w = gg.build_config(1)
     log("[loop] 30-bus, FP64, N_a=2, N_d=2, 64 children x 6 generations")
     _run_loop(w, tto.TTO_FLOW_F64, 2, 2, 24, 64, 6, seed=77, processes=1)
+
+
+def test_generation_loop_paper_descriptor_30_bus_f64():
+    """The same loop on the paper's 552-cell (disconnections, splits,
+    reassigned assets) map."""
+    from paper_2605_10128_amd import tto
+    w = gg.build_config(1)
+    log("[loop] 30-bus, FP64, paper descriptor, N_a=3, N_d=2, 64 children x 4 generations")
+    _run_loop(w, tto.TTO_FLOW_F64, 3, 2, 24, 64, 4, seed=91, processes=1, descriptor="paper")
+
+
+def test_paper_descriptor_cells_500_bus_f32():
+    """Cells of the paper map for a batch with splits: integers from the
+    candidate alone, equal to the oracle's for every connected candidate."""
+    import torch
+    import oracle
+    from paper_2605_10128_amd import tto
+    w = gg.build_config(2, B=512)
+    sess = make_session(w, tto.TTO_FLOW_F32, max_batch=512)
+    sess.set_descriptor(gg.default_load_edges(), kind=tto.TTO_DESC_PAPER)
+    out = sess.evaluate(tto.device_batch(w.batch))
+    torch.cuda.synchronize()
+    st, cell = out["status"].cpu().numpy(), out["cell"].cpu().numpy()
+    seen = set()
+    for c in range(512):
+        cd = oracle.candidate_from_batch(w.batch, c)
+        if st[c] & 3:
+            assert cell[c] == -1
+            continue
+        want = oracle.descriptor_cell_paper(len(cd.opened), len(cd.splits),
+                                            sum(len(mv) for _, mv in cd.splits))
+        assert cell[c] == want, c
+        seen.add(want)
+    assert len(seen) >= 10 and max(seen) < 552
+    log(f"[descriptor] paper map: {len(seen)} distinct cells over 512 candidates")
+    sess.close()
 
 
 def test_generation_loop_matches_oracle_500_bus_f64():

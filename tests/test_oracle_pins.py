@@ -550,3 +550,15 @@ def test_busbar_outage_of_a_split_bus_keeps_busbar_b():
 def test_fitness_f2_clips_at_the_pre_optimisation_penalty():
     assert o.fitness_f2(-100.0, 30.0, 50.0) == -100.0
     assert o.fitness_f2(-100.0, 80.0, 50.0) == -130.0
+
+
+def test_paper_descriptor_is_a_bijection_of_the_clamped_ranges():
+    """lambda_d in 0..2, lambda_s in 0..3, lambda_r in 0..45 map one to one
+    onto the 3 x 4 x 46 = 552 cells; larger counts clamp."""
+    cells = {o.descriptor_cell_paper(d, s_, r) for d in range(3) for s_ in range(4)
+             for r in range(46)}
+    assert cells == set(range(552))
+    assert o.descriptor_cell_paper(0, 0, 0) == 0
+    assert o.descriptor_cell_paper(1, 1, 1) == 1 + 3 * (1 + 4)
+    assert o.descriptor_cell_paper(2, 3, 45) == 551
+    assert o.descriptor_cell_paper(7, 8, 99) == 551
