@@ -431,6 +431,20 @@ def evolution_leg(s, w, args):
     }
     log(f"[bench] evolution: {ms_gen:.2f} ms per generation of {B} ({res['value']:,.0f} children/s), "
         f"variation {vary_ms:.3f} ms, {res['cells_filled']} cells after {res['generation_counter']} generations")
+    # the same loop on the paper's (disconnections, splits, reassigned assets) map
+    s.set_descriptor(gg.default_load_edges(), kind=tto.TTO_DESC_PAPER)
+    rep2 = tto.Repertoire(s, gs)
+    evo2 = tto.Evolver(s, gs, rep2, B, seed=0xE702)
+    for _ in range(K):
+        evo2.step()
+    torch.cuda.synchronize()
+    ids2, fit2 = rep2.id.cpu().numpy(), rep2.fitness.cpu().numpy()
+    occ2 = ids2 >= 0
+    res["paper_map"] = {"cells": tto.TTO_PAPER_CELLS, "generations": K,
+                        "cells_filled": int(occ2.sum()),
+                        "best_fitness": float(fit2[occ2].max()) if occ2.any() else None}
+    log(f"[bench] evolution on the paper map: {int(occ2.sum())} of {tto.TTO_PAPER_CELLS} cells after {K} generations")
+    s.set_descriptor(gg.default_load_edges())
     gs.close()
     return res
 
