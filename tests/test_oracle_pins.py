@@ -562,3 +562,41 @@ def test_paper_descriptor_is_a_bijection_of_the_clamped_ranges():
     assert o.descriptor_cell_paper(1, 1, 1) == 1 + 3 * (1 + 4)
     assert o.descriptor_cell_paper(2, 3, 45) == 551
     assert o.descriptor_cell_paper(7, 8, 99) == 551
+
+
+# ------------------------------------------------------ PTDF and bridges
+def test_ptdf_radial_chain_and_divider():
+    """Chain 0-1-2 (slack 0): one MW from bus 2 crosses both branches towards
+    the slack (PTDF -1 on branches oriented away from it).  Two parallel
+    paths 0-1 (x = 0.1) and 0-2-1 (x = 0.1 + 0.3): the direct branch carries
+    0.4 / 0.5 of a transfer into bus 1."""
+    from oracle.ptdf import ptdf
+    P = ptdf(3, [0, 1], [1, 2], [10.0, 10.0], 0)
+    np.testing.assert_allclose(P, [[0, -1, -1], [0, 0, -1]], atol=1e-12)
+    P = ptdf(3, [0, 0, 2], [1, 2, 1], [10.0, 10.0, 1 / 0.3], 0)
+    assert P[0, 1] == pytest.approx(-0.8)
+    assert P[1, 1] == pytest.approx(-0.2) and P[2, 1] == pytest.approx(-0.2)
+
+
+def test_ptdf_kirchhoff_at_every_bus():
+    """Every column is a unit transfer from bus j to the slack: the net
+    outflow of its flows is +1 at j, -1 at the slack, 0 elsewhere."""
+    from oracle.ptdf import ptdf
+    w = gg.build_config(1)
+    g = w.grid
+    P = ptdf(g.n_bus, g.from_bus, g.to_bus, 1 / g.x_pu, g.slack)
+    A = np.zeros((len(g.from_bus), g.n_bus))
+    A[np.arange(len(g.from_bus)), g.from_bus] = 1
+    A[np.arange(len(g.from_bus)), g.to_bus] = -1
+    want = np.eye(g.n_bus)
+    want[g.slack] -= 1
+    want[:, g.slack] = 0
+    np.testing.assert_allclose(A.T @ P, want, atol=1e-10)
+
+
+def test_bridges_brute_force_against_tarjan_generator():
+    from oracle.ptdf import bridges
+    for cfg in (1, 2):
+        g = gg.build_config(cfg, B=1).grid
+        assert np.array_equal(bridges(g.n_bus, g.from_bus, g.to_bus),
+                              gg.bridges(g.n_bus, g.from_bus, g.to_bus))
