@@ -449,6 +449,30 @@ tto_status tto_evaluate_capture(tto_grid* grid, const tto_batch* batch, const tt
                                 tto_graph** graph);
 
 /* ------------------------------------------------------------------------
+ * Importer on the device (Importer section: the optimizer starts from the
+ * PTDF of the pre-optimisation topology; branches whose opening would split
+ * the grid are not disconnectable).
+ *
+ * tto_ptdf_build: PTDF[e][j] = b_e (X[from_e][j] - X[to_e][j]) with X the
+ * inverse of the nodal susceptance matrix without the slack row and column
+ * (X's slack row and column zero), by blocked Gauss-Jordan elimination on
+ * the FP64 MFMA.  Host arrays as in tto_grid_desc; ptdf: device FP64
+ * [n_branch][n_bus] out, ready for tto_grid_desc.ptdf.  ws: device, 256-byte
+ * aligned, tto_ptdf_bytes long (about 8 (n_bus - 1)^2 bytes).  TTO_E_GRID for
+ * bad branches, susceptances or a disconnected grid.  Synchronises `stream`.
+ *
+ * tto_bridges: is_bridge (device uint8 [n_branch]) = 1 iff the branch is a
+ * bridge of the grid, i.e. H_ee = b_e S_ee = 1 (tested as 1 - H_ee < 1e-9).
+ */
+tto_status tto_ptdf_bytes(int32_t n_bus, int32_t n_branch, size_t* bytes);
+
+tto_status tto_ptdf_build(int32_t n_bus, int32_t n_branch, int32_t slack, const int32_t* from_bus,
+                          const int32_t* to_bus, const double* susceptance, double* ptdf,
+                          void* ws, size_t bytes, void* stream);
+
+tto_status tto_bridges(const tto_grid* grid, uint8_t* is_bridge, void* stream);
+
+/* ------------------------------------------------------------------------
  * Worst-k contingencies (AC-Validator section: for every N-1 case the DC
  * optimizer computes the overload energy on its own and writes out the k
  * worst cases, k = 20 in the paper, which the AC validator computes first).

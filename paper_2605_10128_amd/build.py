@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtto.so")
-SOURCES = ["tto_api.hip", "k_grid.hip", "k_eval.hip", "k_archive.hip", "k_evolve.hip", "k_busbar.hip", "k_mlp.hip"]
+SOURCES = ["tto_api.hip", "k_grid.hip", "k_eval.hip", "k_archive.hip", "k_evolve.hip", "k_busbar.hip", "k_ptdf.hip", "k_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

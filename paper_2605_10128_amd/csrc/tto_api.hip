@@ -1447,3 +1447,94 @@ tto_status tto_busbar_evaluate(tto_grid* g, const tto_busbars* bs, const tto_bat
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Importer on the device: PTDF and bridges.
+namespace {
+
+struct PtdfLayout {
+  size_t A, P, off, nbr, wgt, from, to, b, total;
+};
+
+PtdfLayout ptdf_layout(int n, int m) {
+  PtdfLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t at = o; o += round256(std::max<size_t>(b, 4)); return at; };
+  const size_t Np = (size_t)gj_padded(n);
+  L.A = take(8 * Np * Np);
+  L.P = take(8 * 64 * 64);
+  L.off = take(4 * ((size_t)n + 1));
+  L.nbr = take(4 * 2 * (size_t)m);
+  L.wgt = take(8 * 2 * (size_t)m);
+  L.from = take(4 * (size_t)m);
+  L.to = take(4 * (size_t)m);
+  L.b = take(8 * (size_t)m);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+tto_status tto_ptdf_bytes(int32_t n_bus, int32_t n_branch, size_t* bytes) {
+  if (!bytes) return fail(TTO_E_INVALID, "bytes is NULL");
+  if (n_bus < 2 || n_branch < 1) return fail(TTO_E_INVALID, "need n_bus >= 2 and n_branch >= 1");
+  *bytes = ptdf_layout(n_bus, n_branch).total;
+  return ok();
+}
+
+tto_status tto_ptdf_build(int32_t n_bus, int32_t n_branch, int32_t slack, const int32_t* from_bus,
+                          const int32_t* to_bus, const double* susceptance, double* ptdf,
+                          void* ws, size_t bytes, void* stream) {
+  if (n_bus < 2 || n_branch < 1) return fail(TTO_E_INVALID, "need n_bus >= 2 and n_branch >= 1");
+  if (!from_bus || !to_bus || !susceptance || !ptdf) return fail(TTO_E_INVALID, "NULL array");
+  if (slack < 0 || slack >= n_bus) return fail(TTO_E_GRID, "slack %d out of range", slack);
+  const int n = n_bus, m = n_branch;
+  std::vector<std::vector<std::pair<int, double>>> adj(n);
+  std::vector<int> par(n);
+  std::iota(par.begin(), par.end(), 0);
+  int comps = n;
+  for (int e = 0; e < m; ++e) {
+    const int a = from_bus[e], b = to_bus[e];
+    if (a < 0 || a >= n || b < 0 || b >= n || a == b) return fail(TTO_E_GRID, "branch %d endpoints invalid", e);
+    if (!(susceptance[e] > 0.0) || !isfinite(susceptance[e]))
+      return fail(TTO_E_GRID, "branch %d susceptance must be finite and > 0", e);
+    adj[a].push_back({b, susceptance[e]});
+    adj[b].push_back({a, susceptance[e]});
+    const int ra = uf_find(par, a), rb = uf_find(par, b);
+    if (ra != rb) { par[ra] = rb; --comps; }
+  }
+  if (comps != 1) return fail(TTO_E_GRID, "grid is not connected (%d components)", comps);
+  const PtdfLayout L = ptdf_layout(n, m);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(TTO_E_WORKSPACE, "ws NULL or not 256-byte aligned");
+  if (bytes < L.total) return fail(TTO_E_WORKSPACE, "ws has %zu bytes, needs %zu", bytes, L.total);
+  std::vector<int> off(n + 1, 0), nbr;
+  std::vector<double> wgt;
+  for (int v = 0; v < n; ++v) {
+    for (const auto& pr : adj[v]) { nbr.push_back(pr.first); wgt.push_back(pr.second); }
+    off[v + 1] = (int)nbr.size();
+  }
+  char* base = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(base + L.off, off.data(), 4 * off.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + L.nbr, nbr.data(), 4 * nbr.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + L.wgt, wgt.data(), 8 * wgt.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + L.from, from_bus, 4 * (size_t)m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + L.to, to_bus, 4 * (size_t)m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + L.b, susceptance, 8 * (size_t)m, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_ptdf((const int*)(base + L.off), (const int*)(base + L.nbr),
+                      (const double*)(base + L.wgt), n, m, slack, (const int*)(base + L.from),
+                      (const int*)(base + L.to), (const double*)(base + L.b),
+                      (double*)(base + L.A), (double*)(base + L.P), ptdf, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return ok();
+}
+
+tto_status tto_bridges(const tto_grid* g, uint8_t* is_bridge, void* stream) {
+  if (!g || !is_bridge) return fail(TTO_E_INVALID, "NULL argument");
+  HIP_TRY(launch_bridges(g->dev.S, g->dev.b, g->m, is_bridge, (hipStream_t)stream));
+  return ok();
+}
+
+}  // extern "C"

@@ -156,6 +156,13 @@ int gemm_ksplit(int m, int n);
 // ev: NULL or 5 events recorded before set-up, after set-up, after the sweep,
 // after finalize and after the FP64 refinement pass.  rw/rc: refinement
 // buffers and control (FP32 flows only; rc.cap == 0 disables).
+// importer on the device (k_ptdf.hip)
+int gj_padded(int n_bus);
+hipError_t launch_ptdf(const int* off, const int* nbr, const double* wgt, int n, int m,
+                       int slack, const int* from, const int* to, const double* b, double* A,
+                       double* Pbuf, double* ptdf, hipStream_t s);
+hipError_t launch_bridges(const double* S, const double* b, int m, uint8_t* out, hipStream_t s);
+
 template <typename F>
 hipError_t launch_setup(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
                         hipStream_t s);

@@ -128,6 +128,9 @@ def _load():
         "tto_evaluate_capture": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                         _vp, _i32, ct.c_int64, P(_vp)]),
         "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
+        "tto_ptdf_bytes": (_i32, [_i32, _i32, P(ct.c_size_t)]),
+        "tto_ptdf_build": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ct.c_size_t, _vp]),
+        "tto_bridges": (_i32, [_vp, _vp, _vp]),
         "tto_busbar_set_bytes": (_i32, [_vp, _i32, P(ct.c_size_t)]),
         "tto_busbar_set_create": (_i32, [_vp, _i32, _vp, _vp, _vp, ct.c_size_t, _vp, P(_vp)]),
         "tto_busbar_set_destroy": (None, [_vp]),
@@ -171,7 +174,8 @@ EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_cr
             "tto_genome_space_destroy", "tto_genome_max_moved", "tto_vary", "tto_genome_expand",
             "tto_generation_bytes", "tto_generation", "tto_worst_k_bytes",
             "tto_worst_contingencies", "tto_busbar_set_bytes", "tto_busbar_set_create",
-            "tto_busbar_set_destroy", "tto_busbar_bytes", "tto_busbar_evaluate"]
+            "tto_busbar_set_destroy", "tto_busbar_bytes", "tto_busbar_evaluate",
+            "tto_ptdf_bytes", "tto_ptdf_build", "tto_bridges"]
 
 
 def _check(code: int):
@@ -348,6 +352,37 @@ def tto_evaluate_capture(handle, batch: "tto_batch", outputs: "tto_outputs", ws,
                                      ws_bytes, _vp(elite_fit), _vp(elite_id), int(n_cells),
                                      int(id_base), ct.byref(g)))
     return g.value
+
+
+def tto_ptdf_bytes(n_bus: int, n_branch: int) -> int:
+    n = ct.c_size_t()
+    _check(_lib.tto_ptdf_bytes(int(n_bus), int(n_branch), ct.byref(n)))
+    return n.value
+
+
+def tto_ptdf_build(n_bus: int, n_branch: int, slack: int, from_bus: int, to_bus: int,
+                   susceptance: int, ptdf: int, ws: int, nbytes: int, stream: int):
+    _check(_lib.tto_ptdf_build(int(n_bus), int(n_branch), int(slack), _vp(from_bus), _vp(to_bus),
+                               _vp(susceptance), _vp(ptdf), _vp(ws), nbytes, _vp(stream)))
+
+
+def tto_bridges(grid: int, out: int, stream: int):
+    _check(_lib.tto_bridges(_vp(grid), _vp(out), _vp(stream)))
+
+
+def ptdf_device(n_bus, from_bus, to_bus, susceptance, slack=0, device="cuda"):
+    """PTDF [n_branch][n_bus] (device FP64 tensor) built on the GPU."""
+    import torch
+    fr = np.ascontiguousarray(from_bus, dtype=np.int32)
+    to = np.ascontiguousarray(to_bus, dtype=np.int32)
+    b = np.ascontiguousarray(susceptance, dtype=np.float64)
+    out = torch.empty((len(fr), int(n_bus)), dtype=torch.float64, device=device)
+    nb = tto_ptdf_bytes(int(n_bus), len(fr))
+    ws = torch.empty(nb, dtype=torch.uint8, device=device)
+    tto_ptdf_build(int(n_bus), len(fr), int(slack), fr.ctypes.data, to.ctypes.data, b.ctypes.data,
+                   _ptr(out), _ptr(ws), nb, int(torch.cuda.current_stream().cuda_stream))
+    del ws
+    return out
 
 
 def tto_busbar_set_bytes(grid: int, n_busbars: int) -> int:
@@ -643,7 +678,11 @@ class Session:
         self.n_bus, self.n_branch, self.T = int(n_bus), len(h["from_bus"]), int(n_timesteps)
         self.nM, self.nC = len(h["mon"]), len(h["cont"])
         self.max_batch = int(max_batch)
-        ptdf_t = torch.as_tensor(np.ascontiguousarray(ptdf, dtype=np.float64), device=self.device)
+        if hasattr(ptdf, "data_ptr") and ptdf.is_cuda:     # e.g. from ptdf_device
+            ptdf_t = ptdf.to(torch.float64).contiguous()
+        else:
+            ptdf_t = torch.as_tensor(np.ascontiguousarray(ptdf, dtype=np.float64),
+                                     device=self.device)
         cptr = lambda a: a.ctypes.data
         self.desc = tto_grid_desc(
             self.n_bus, self.n_branch, int(slack), self.T, cptr(h["from_bus"]), cptr(h["to_bus"]),
@@ -738,6 +777,12 @@ class Session:
                                  self.batch_bytes, _ptr(fit), _ptr(ids),
                                  int(fit.shape[0]) if fit is not None else 0, id_base)
         return Graph(h)
+
+    def bridges(self):
+        """Bridge mask [n_branch] (device uint8) of the grid (tto_bridges)."""
+        out = self.torch.empty(self.n_branch, dtype=self.torch.uint8, device=self.device)
+        tto_bridges(self.handle, _ptr(out), self.stream)
+        return out
 
     def busbar_set(self, buses, ptdf) -> "BusbarSet":
         return BusbarSet(self, buses, ptdf)
