@@ -487,7 +487,6 @@ def main():
     import torch
     import gridgen as gg
     from paper_2605_10128_amd import tto
-    from paper_2605_10128_amd.ptdf import build_ptdf
 
     torch.cuda.set_device(0)
     spec = gg.CONFIGS[args.config]
@@ -497,7 +496,10 @@ def main():
     log(f"[bench] workload cfg{args.config} B={B} built in {time.perf_counter() - t0:.1f}s")
     g = w.grid
     b = 1.0 / g.x_pu
-    ptdf = build_ptdf(g.n_bus, g.from_bus, g.to_bus, b)
+    t0 = time.perf_counter()
+    ptdf = tto.ptdf_device(g.n_bus, g.from_bus, g.to_bus, b, g.slack)   # importer on the GPU
+    torch.cuda.synchronize()
+    ptdf_ms = (time.perf_counter() - t0) * 1e3
     flow = tto.TTO_FLOW_F32 if args.flow == "f32" else tto.TTO_FLOW_F64
     gemm = tto.TTO_GEMM_F32 if args.flow == "f32" else tto.TTO_GEMM_F64
     s = tto.Session(g.n_bus, g.from_bus, g.to_bus, b, g.limit_mw, ptdf, w.M, w.C, w.P.shape[1],
@@ -602,6 +604,7 @@ def main():
         "dtype": "f32" if args.flow == "f32" else "f64",
         "data": "synthetic",
         "config": {
+            "ptdf_build_ms": ptdf_ms,
             "workload": f"{spec['name']}: n={g.n_bus}, m={g.n_branch}, T={T}, B={B}, "
                         f"|M|={len(w.M)}, |C|={len(w.C)}, rank 0..8 (exact evaluation)",
             "flow_precision": args.flow,

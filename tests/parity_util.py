@@ -19,12 +19,11 @@ def log(msg: str):
 
 def make_session(w, flow_prec, gemm_prec=None, max_batch=None, edges=None):
     from paper_2605_10128_amd import tto
-    from paper_2605_10128_amd.ptdf import build_ptdf
     grid = w.grid
     b = 1.0 / grid.x_pu
     if gemm_prec is None:
         gemm_prec = tto.TTO_GEMM_F64 if flow_prec == tto.TTO_FLOW_F64 else tto.TTO_GEMM_F32
-    ptdf = build_ptdf(grid.n_bus, grid.from_bus, grid.to_bus, b, grid.slack)
+    ptdf = tto.ptdf_device(grid.n_bus, grid.from_bus, grid.to_bus, b, grid.slack)
     s = tto.Session(grid.n_bus, grid.from_bus, grid.to_bus, b, grid.limit_mw, ptdf, w.M, w.C,
                     w.P.shape[1], flow_precision=flow_prec, gemm_precision=gemm_prec,
                     max_batch=max_batch or w.batch.n_cand, slack=grid.slack)

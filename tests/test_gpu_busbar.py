@@ -26,13 +26,12 @@ def _busbars(w, n, seed, include_splits=True):
 def _run(cfg, flow, B, n_bb, move_frac=0.0):
     import torch
     from paper_2605_10128_amd import tto
-    from paper_2605_10128_amd.ptdf import build_ptdf
     w = gg.build_config(cfg, B=B, move_frac=move_frac)
     g = w.grid
     fp = tto.TTO_FLOW_F64 if flow == "f64" else tto.TTO_FLOW_F32
     sess = make_session(w, fp, max_batch=B)
     buses = _busbars(w, n_bb, seed=cfg)
-    ptdf = build_ptdf(g.n_bus, g.from_bus, g.to_bus, 1.0 / g.x_pu, g.slack)
+    ptdf = tto.ptdf_device(g.n_bus, g.from_bus, g.to_bus, 1.0 / g.x_pu, g.slack)
     bset = sess.busbar_set(buses, ptdf)
     db = tto.device_batch(w.batch)
     out = sess.evaluate(db)
@@ -89,11 +88,10 @@ def test_busbar_outages_match_oracle(cfg, flow, B, n_bb, move):
 
 def test_busbar_set_rejects_bad_buses():
     from paper_2605_10128_amd import tto
-    from paper_2605_10128_amd.ptdf import build_ptdf
     w = gg.build_config(1)
     g = w.grid
     sess = make_session(w, tto.TTO_FLOW_F64, max_batch=8)
-    ptdf = build_ptdf(g.n_bus, g.from_bus, g.to_bus, 1.0 / g.x_pu, g.slack)
+    ptdf = tto.ptdf_device(g.n_bus, g.from_bus, g.to_bus, 1.0 / g.x_pu, g.slack)
     for buses in ([g.slack], [3, 3], [g.n_bus]):
         with pytest.raises(tto.TTOError) as ei:
             sess.busbar_set(np.array(buses), ptdf)

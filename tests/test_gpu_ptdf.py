@@ -48,15 +48,14 @@ def test_bridges_match_connectivity(cfg):
 
 def test_session_from_device_ptdf():
     """A grid created from the device PTDF gives the same base flows and
-    evaluation as one created from the host PTDF (within FP64 rounding)."""
+    evaluation as one created from the oracle's PTDF (within FP64 rounding)."""
     import torch
     from paper_2605_10128_amd import tto
-    from paper_2605_10128_amd.ptdf import build_ptdf
     w = gg.build_config(2, B=64)
     g = w.grid
     b = 1.0 / g.x_pu
     out = {}
-    for name, P in (("host", build_ptdf(g.n_bus, g.from_bus, g.to_bus, b, g.slack)),
+    for name, P in (("host", optdf.ptdf(g.n_bus, g.from_bus, g.to_bus, b, g.slack)),
                     ("device", tto.ptdf_device(g.n_bus, g.from_bus, g.to_bus, b, g.slack))):
         s = tto.Session(g.n_bus, g.from_bus, g.to_bus, b, g.limit_mw, P, w.M, w.C, w.P.shape[1],
                         flow_precision=tto.TTO_FLOW_F64, gemm_precision=tto.TTO_GEMM_F64,
