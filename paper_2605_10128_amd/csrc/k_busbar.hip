@@ -34,13 +34,34 @@ __global__ __launch_bounds__(256) void k_bb_tables(const double* __restrict__ pt
                                                    int m, const int* __restrict__ mon, int nM,
                                                    const int* __restrict__ bus, int nb,
                                                    double* __restrict__ PB,
-                                                   double* __restrict__ PBM) {
+                                                   double* __restrict__ PBM,
+                                                   float* __restrict__ PBM32) {
   const int ib = blockIdx.y;
   const int b = bus[ib];
   for (int x = blockIdx.x * 256 + threadIdx.x; x < m; x += gridDim.x * 256)
     PB[(size_t)ib * m + x] = ptdf[(size_t)x * n_bus + b];
-  for (int ei = blockIdx.x * 256 + threadIdx.x; ei < nM; ei += gridDim.x * 256)
-    PBM[(size_t)ib * nM + ei] = ptdf[(size_t)mon[ei] * n_bus + b];
+  for (int ei = blockIdx.x * 256 + threadIdx.x; ei < nM; ei += gridDim.x * 256) {
+    const double v = ptdf[(size_t)mon[ei] * n_bus + b];
+    PBM[(size_t)ib * nM + ei] = v;
+    PBM32[(size_t)ib * nM + ei] = (float)v;
+  }
+}
+
+// H of the busbars' branches against the monitored set: HB[p][ei] = b_e S_{x,e}
+__global__ __launch_bounds__(256) void k_bb_htile(const double* __restrict__ S,
+                                                  const double* __restrict__ bsus,
+                                                  const int* __restrict__ mon, int nM, int m,
+                                                  const int* __restrict__ inc_br,
+                                                  double* __restrict__ HB,
+                                                  float* __restrict__ HB32) {
+  const int p = blockIdx.y;
+  const size_t x = (size_t)inc_br[p];
+  for (int ei = blockIdx.x * 256 + threadIdx.x; ei < nM; ei += gridDim.x * 256) {
+    const int e = mon[ei];
+    const double v = bsus[e] * S[x * m + e];
+    HB[(size_t)p * nM + ei] = v;
+    HB32[(size_t)p * nM + ei] = (float)v;
+  }
 }
 
 struct BbShared {
@@ -51,13 +72,48 @@ struct BbShared {
   double msg[kMaxMoved], msign[kMaxMoved];
   double inv_s[kMaxRank];
   double bK[kBbMaxR];
-  int ids[kBbMaxDeg];
+  int ids[kBbMaxDeg], pos[kBbMaxDeg];  // the busbar's branches and their H-tile rows
   int rm[kBbMaxDeg], rmc[kBbMaxDeg];   // moved branches opened by the outage
   int k, kk, s, R, d, jb, skip, nrm;
   double M[kBbMaxR][kBbMaxR + 1];
   int piv[kBbMaxR];
   double pa[32];
 };
+
+// One thread per candidate: the genome parse shared by all busbar outages
+// (same column order as the set-up kernel).
+template <typename F>
+__global__ __launch_bounds__(256) void k_bb_parse(GridDev g, BatchDev bt, SweepBufs<F> w,
+                                                  BbCand* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= bt.B) return;
+  BbCand& cd = out[c];
+  if (w.info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) { cd.k = 0; cd.s = 0; cd.nm = 0; return; }
+  const int m = g.n_branch;
+  int k = 0, s = 0, nm = 0;
+  for (int i = 0; i < bt.no; ++i) {
+    const int v = bt.open[(size_t)c * bt.no + i];
+    if (v >= 0 && v < m && k < kMaxRank) cd.op[k++] = v;
+  }
+  for (int j = 0; j < bt.ns; ++j) {
+    const int sb = bt.sbus[(size_t)c * bt.ns + j];
+    if (sb == -1 || s >= kMaxRank) continue;
+    cd.sbus[s] = sb;
+    cd.sslot[s] = j;
+    cd.moff[s] = nm;
+    const int lo = bt.moff[(size_t)c * bt.ns + j], hi = bt.moff[(size_t)c * bt.ns + j + 1];
+    for (int p = lo; p < hi && nm < kMaxMoved; ++p) {
+      const int e = bt.mbr[p];
+      cd.mbr[nm] = e;
+      cd.msgn[nm] = g.from[e] == sb ? 1 : -1;
+      cd.mb[nm] = g.b[e];
+      ++nm;
+    }
+    ++s;
+  }
+  cd.moff[s] = nm;
+  cd.k = k; cd.s = s; cd.nm = nm;
+}
 
 template <typename F, int TT>
 __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBufs<F> w,
@@ -74,22 +130,21 @@ __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBu
     return;
   }
   const int bus = bb.bus[ib];
+  __shared__ BbCand cd;
+  {
+    const int* src = (const int*)(rr.cand + c);
+    int* dst = (int*)&cd;
+    for (int i = tid; i < (int)(sizeof(BbCand) / 4); i += 64) dst[i] = src[i];
+  }
+  __syncthreads();
   if (tid == 0) {
-    int k = 0, s = 0, jb = -1;
-    for (int i = 0; i < bt.no; ++i) {
-      const int v = bt.open[(size_t)c * bt.no + i];
-      if (v >= 0 && v < m && k < kMaxRank) sh.op[k++] = v;
-    }
-    int lo[kMaxRank], hi[kMaxRank];
-    for (int j = 0; j < bt.ns; ++j) {
-      const int sb = bt.sbus[(size_t)c * bt.ns + j];
-      if (sb == -1 || s >= kMaxRank) continue;
-      sh.sbus[s] = sb;
-      sh.sslot[s] = j;
-      lo[s] = bt.moff[(size_t)c * bt.ns + j];
-      hi[s] = bt.moff[(size_t)c * bt.ns + j + 1];
-      if (sb == bus) jb = s;
-      ++s;
+    const int k = cd.k, s = cd.s;
+    int jb = -1;
+    for (int q = 0; q < k; ++q) sh.op[q] = cd.op[q];
+    for (int j = 0; j < s; ++j) {
+      sh.sbus[j] = cd.sbus[j];
+      sh.sslot[j] = cd.sslot[j];
+      if (cd.sbus[j] == bus) jb = j;
     }
     // branches on the busbar's node: incident in the base grid, in service,
     // not moved to busbar B of a split of this bus
@@ -99,8 +154,8 @@ __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBu
       bool off = false;
       for (int q = 0; q < k; ++q) off |= sh.op[q] == x;
       if (jb >= 0)
-        for (int q = lo[jb]; q < hi[jb]; ++q) off |= bt.mbr[q] == x;
-      if (!off && d < kBbMaxDeg) sh.ids[d++] = x;
+        for (int q = cd.moff[jb]; q < cd.moff[jb + 1]; ++q) off |= cd.mbr[q] == x;
+      if (!off && d < kBbMaxDeg) { sh.ids[d] = x; sh.pos[d] = p; ++d; }
     }
     int kk = k;
     for (int q = 0; q + 1 < d; ++q) sh.op[kk++] = sh.ids[q];
@@ -110,19 +165,23 @@ __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBu
     for (int j = 0; j < s; ++j) {
       sh.moff[j] = nm;
       double ssum = 0.0;
-      for (int p = lo[j]; p < hi[j] && nm < kMaxMoved; ++p) {
-        const int e = bt.mbr[p];
-        const double sg = g.from[e] == sh.sbus[j] ? 1.0 : -1.0;
-        bool opened_here = false;
-        for (int q = k; q < kk; ++q) opened_here |= sh.op[q] == e;
-        if (opened_here) {
-          if (nrm < kBbMaxDeg) { sh.rm[nrm] = e; sh.rmc[nrm] = 2 * j + (sg > 0.0 ? 1 : 0); ++nrm; }
+      for (int p = cd.moff[j]; p < cd.moff[j + 1]; ++p) {
+        const int e = cd.mbr[p];
+        const double sg = (double)cd.msgn[p];
+        int here = -1;   // index among the busbar's branches when the outage opens it
+        for (int q = 0; q + 1 < d; ++q) here = sh.ids[q] == e ? q : here;
+        if (here >= 0) {
+          if (nrm < kBbMaxDeg) {
+            sh.rm[nrm] = e;
+            sh.rmc[nrm] = 2 * j + (sg > 0.0 ? 1 : 0) + 256 * here;
+            ++nrm;
+          }
           continue;
         }
         sh.mbr[nm] = e;
         sh.msign[nm] = sg;
-        sh.msg[nm] = sg * g.b[e];
-        ssum += g.b[e];
+        sh.msg[nm] = sg * cd.mb[p];
+        ssum += cd.mb[p];
         ++nm;
       }
       sh.inv_s[j] = ssum > 0.0 ? 1.0 / ssum : 0.0;
@@ -175,31 +234,40 @@ __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBu
     sh.M[i][q] = v;
   }
   __syncthreads();
-  if (tid == 0) {
-    double minpiv = DBL_MAX;
-    for (int p = 0; p < R; ++p) {
-      int best = p;
-      double bv = fabs(sh.M[p][p]);
-      for (int i = p + 1; i < R; ++i)
-        if (fabs(sh.M[i][p]) > bv) { bv = fabs(sh.M[i][p]); best = i; }
-      sh.piv[p] = best;
-      if (best != p)
-        for (int q = 0; q < R; ++q) { const double t = sh.M[p][q]; sh.M[p][q] = sh.M[best][q]; sh.M[best][q] = t; }
-      minpiv = fmin(minpiv, bv);
-      if (bv > 0.0) {
-        for (int i = p + 1; i < R; ++i) {
-          const double f = sh.M[i][p] / sh.M[p][p];
-          sh.M[i][p] = f;
-          for (int q = p + 1; q < R; ++q) sh.M[i][q] -= f * sh.M[p][q];
-        }
-      }
+  // LU with partial pivoting by one wave: the pivot row is the first row of
+  // largest |entry| (shuffle arg-max), each lane eliminates its own row
+  double minpiv = DBL_MAX;
+  for (int p = 0; p < R; ++p) {
+    double bv = (tid >= p && tid < R) ? fabs(sh.M[tid][p]) : -1.0;
+    int bi = tid;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
     }
+    minpiv = fmin(minpiv, bv);
+    if (bi != p && tid < R) {
+      const double t = sh.M[p][tid];
+      sh.M[p][tid] = sh.M[bi][tid];
+      sh.M[bi][tid] = t;
+    }
+    if (tid == 0) sh.piv[p] = bi;
+    __syncthreads();
+    if (bv > 0.0 && tid > p && tid < R) {
+      const double f = sh.M[tid][p] / sh.M[p][p];
+      sh.M[tid][p] = f;
+      for (int q = p + 1; q < R; ++q) sh.M[tid][q] -= f * sh.M[p][q];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
     sh.skip = (R > 0 && minpiv < kTauIsland) ? 1 : 0;
     H[0] = R; H[1] = k; H[2] = d; H[3] = sh.skip;
     for (int q = 0; q < kBbMaxDeg; ++q) {
-      H[4 + q] = q < d ? sh.ids[q] : -1;
-      H[4 + kBbMaxDeg + q] = q < sh.nrm ? sh.rm[q] : -1;
-      H[4 + 2 * kBbMaxDeg + q] = q < sh.nrm ? sh.rmc[q] : -1;
+      H[kBbIds + q] = q < d ? sh.ids[q] : -1;
+      H[kBbRm + q] = q < sh.nrm ? sh.rm[q] : -1;
+      H[kBbRmc + q] = q < sh.nrm ? sh.rmc[q] : -1;
+      H[kBbPos + q] = q < d ? sh.pos[q] : -1;
     }
   }
   __syncthreads();
@@ -267,66 +335,105 @@ __global__ __launch_bounds__(256) void k_bb_sweep(GridDev g, SweepBufs<F> w, Bus
   F f0e[TT], acc[TT];
 #pragma unroll
   for (int t = 0; t < TT; ++t) { f0e[t] = t < T ? (F)g.f0[(size_t)e * T + t] : (F)0; acc[t] = (F)0; }
-  const F be = (F)g.b[e];
-  const size_t nMC = (size_t)nM + nC;
-  for (int ib = 0; ib < nb && !bad; ++ib) {
+  const F* HB;
+  const F* PBM;
+  if constexpr (sizeof(F) == 4) { HB = bb.HB32; PBM = bb.PBM32; } else { HB = bb.HB; PBM = bb.PBM; }
+  // records staged through LDS, double-buffered: the workgroup loads outage
+  // ib + 1 into registers (coalesced) while it computes outage ib from LDS
+  constexpr int ZN = kBbMaxR * TT, ZP = ZN + TT;
+  constexpr int PER = (ZP + 255) / 256;
+  __shared__ F zs[2][ZP];
+  __shared__ int hs[2][kBbHdr];
+  F rz[PER];
+  int rh = 0;
+  auto fetch = [&](int ib) {
     const size_t rec = (size_t)c * nb + ib;
-    const int* H = rr.hdr + rec * kBbHdr;
-    if (H[3]) continue;
-    const int k = H[1], d = H[2];
-    const int kk = k + (d > 0 ? d - 1 : 0);
-    bool removed = opened;
-    for (int q = 0; q < d; ++q) removed |= H[4 + q] == e;
-    const F* z = rr.z + rec * kBbMaxR * TT;
-    const F* pa = rr.pa + rec * TT;
-    const F pb = (F)bb.PBM[(size_t)ib * nM + ei_c];
-    F f[TT];
+    const F* zsrc = rr.z + rec * ZN;
+    const F* psrc = rr.pa + rec * TT;
 #pragma unroll
-    for (int t = 0; t < TT; ++t) f[t] = f0e[t] - pb * pa[t];
+    for (int u = 0; u < PER; ++u) {
+      const int i = tid + 256 * u;
+      rz[u] = i < ZN ? zsrc[i] : (i < ZP ? psrc[i - ZN] : (F)0);
+    }
+    if (tid < kBbHdr) rh = rr.hdr[rec * kBbHdr + tid];
+  };
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < kMaxRank; ++q) {
-      if (q < k) {
-        const F u = U[q];
+    for (int u = 0; u < PER; ++u) {
+      const int i = tid + 256 * u;
+      if (i < ZP) zs[buf][i] = rz[u];
+    }
+    if (tid < kBbHdr) hs[buf][tid] = rh;
+  };
+  if (!bad && nb > 0) {
+    fetch(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int ib = 0; ib < nb && !bad; ++ib) {
+    const int buf = ib & 1;
+    if (ib + 1 < nb) fetch(ib + 1);
+    const int* H = hs[buf];
+    if (H[3] == 0) {
+      const int k = H[1], d = H[2];
+      const int kk = k + (d > 0 ? d - 1 : 0);
+      bool removed = opened;
+      for (int q = 0; q < d; ++q) removed |= H[kBbIds + q] == e;
+      const F* z = zs[buf];
+      const F* pa = zs[buf] + ZN;
+      const F pb = PBM[(size_t)ib * nM + ei_c];
+      F f[TT];
 #pragma unroll
-        for (int t = 0; t < TT; ++t) f[t] += u * z[(size_t)q * TT + t];
+      for (int t = 0; t < TT; ++t) f[t] = f0e[t] - pb * pa[t];
+#pragma unroll
+      for (int q = 0; q < kMaxRank; ++q) {
+        if (q < k) {
+          const F u = U[q];
+#pragma unroll
+          for (int t = 0; t < TT; ++t) f[t] += u * z[q * TT + t];
+        }
+      }
+      for (int q = k; q < kk; ++q) {
+        const F u = HB[(size_t)H[kBbPos + q - k] * nM + ei_c];
+#pragma unroll
+        for (int t = 0; t < TT; ++t) f[t] += u * z[q * TT + t];
+      }
+      // split columns without the moved branches the outage opens:
+      // u_j(e) + b_e msg_r S_re for each such branch r of split j
+      F uj[kMaxRank];
+#pragma unroll
+      for (int j = 0; j < kMaxRank; ++j) uj[j] = (k + j < rc) ? U[k + j] : (F)0;
+      for (int q = 0; q < kBbMaxDeg; ++q) {
+        const int r = H[kBbRm + q];
+        if (r < 0) break;
+        const int code = H[kBbRmc + q];
+        const F msg = (code & 1 ? (F)1 : (F)-1) * (F)g.b[r];
+        const F add = msg * HB[(size_t)H[kBbPos + (code >> 8)] * nM + ei_c];
+        const int jr = (code >> 1) & 127;
+#pragma unroll
+        for (int j = 0; j < kMaxRank; ++j)
+          if (j == jr) uj[j] += add;
+      }
+#pragma unroll
+      for (int j = 0; j < kMaxRank; ++j) {
+        if (k + j < rc) {
+          const F u = uj[j];
+          const int q = kk + j;
+#pragma unroll
+          for (int t = 0; t < TT; ++t) f[t] += u * z[q * TT + t];
+        }
+      }
+      if (!removed) {
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          const F v = f[t] < (F)0 ? -f[t] : f[t];
+          acc[t] = acc[t] > v ? acc[t] : v;
+        }
       }
     }
-    for (int q = k; q < kk; ++q) {
-      const F u = be * (F)g.SMC[(size_t)H[4 + q - k] * nMC + ei_c];
-#pragma unroll
-      for (int t = 0; t < TT; ++t) f[t] += u * z[(size_t)q * TT + t];
-    }
-    // split columns without the moved branches the outage opens:
-    // u_j(e) + b_e msg_r S_re for each such branch r of split j
-    F uj[kMaxRank];
-#pragma unroll
-    for (int j = 0; j < kMaxRank; ++j) uj[j] = (k + j < rc) ? U[k + j] : (F)0;
-    for (int q = 0; q < kBbMaxDeg; ++q) {
-      const int r = H[4 + kBbMaxDeg + q];
-      if (r < 0) break;
-      const int code = H[4 + 2 * kBbMaxDeg + q];
-      const double msg = (code & 1 ? 1.0 : -1.0) * g.b[r];
-      const F add = (F)(msg * (double)be * g.SMC[(size_t)r * nMC + ei_c]);
-#pragma unroll
-      for (int j = 0; j < kMaxRank; ++j)
-        if (j == (code >> 1)) uj[j] += add;
-    }
-#pragma unroll
-    for (int j = 0; j < kMaxRank; ++j) {
-      if (k + j < rc) {
-        const F u = uj[j];
-        const int q = kk + j;
-#pragma unroll
-        for (int t = 0; t < TT; ++t) f[t] += u * z[(size_t)q * TT + t];
-      }
-    }
-    if (!removed) {
-#pragma unroll
-      for (int t = 0; t < TT; ++t) {
-        const F v = f[t] < (F)0 ? -f[t] : f[t];
-        acc[t] = acc[t] > v ? acc[t] : v;
-      }
-    }
+    __syncthreads();                      // everyone is done with buffer buf
+    if (ib + 1 < nb) stash(buf ^ 1);
+    __syncthreads();
   }
   double ov = 0.0;
   if (valid) {
@@ -368,8 +475,10 @@ hipError_t launch_busbar_tt(const GridDev& g, const BatchDev& bt, const SweepBuf
                             double pre, const double* f1, double* lam, int* n_isl, double* f2,
                             hipStream_t s) {
   const int n_eblk = (g.nM + 255) / 256;
-  if (bb.nb > 0)
+  if (bb.nb > 0) {
+    hipLaunchKernelGGL((k_bb_parse<F>), dim3((bt.B + 255) / 256), dim3(256), 0, s, g, bt, w, rr.cand);
     hipLaunchKernelGGL((k_bb_setup<F, TT>), dim3(bb.nb, bt.B), dim3(64), 0, s, g, bt, w, bb, P, rr);
+  }
   hipLaunchKernelGGL((k_bb_sweep<F, TT>), dim3(n_eblk, bt.B), dim3(256), 0, s, g, w, bb, rr,
                      n_eblk);
   hipLaunchKernelGGL((k_bb_finalize<F>), dim3((bt.B + 255) / 256), dim3(256), 0, s, w, bb, rr,
@@ -380,10 +489,15 @@ hipError_t launch_busbar_tt(const GridDev& g, const BatchDev& bt, const SweepBuf
 }  // namespace
 
 hipError_t launch_busbar_tables(const double* ptdf, int n_bus, int m, const int* mon, int nM,
-                                const int* bus, int nb, double* PB, double* PBM, hipStream_t s) {
+                                const int* bus, int nb, double* PB, double* PBM, float* PBM32,
+                                const double* S, const double* b, const int* inc_br, int n_inc,
+                                double* HB, float* HB32, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bb_tables, dim3((m + 255) / 256, nb), dim3(256), 0, s, ptdf, n_bus, m,
-                     mon, nM, bus, nb, PB, PBM);
+                     mon, nM, bus, nb, PB, PBM, PBM32);
+  if (n_inc > 0)
+    hipLaunchKernelGGL(k_bb_htile, dim3((nM + 255) / 256, n_inc), dim3(256), 0, s, S, b, mon, nM,
+                       m, inc_br, HB, HB32);
   return hipGetLastError();
 }
 

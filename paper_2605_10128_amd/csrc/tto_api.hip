@@ -1281,7 +1281,7 @@ struct tto_busbars {
 namespace {
 
 struct BbLayout {
-  size_t bus, inc_off, inc_br, PB, PBM, total;
+  size_t bus, inc_off, inc_br, PB, PBM, PBM32, HB, HB32, total;
 };
 
 BbLayout bb_layout(int nb, int n_inc, int m, int nM) {
@@ -1293,6 +1293,9 @@ BbLayout bb_layout(int nb, int n_inc, int m, int nM) {
   L.inc_br = take(4 * (size_t)n_inc);
   L.PB = take(8 * (size_t)nb * m);
   L.PBM = take(8 * (size_t)nb * nM);
+  L.PBM32 = take(4 * (size_t)nb * nM);
+  L.HB = take(8 * (size_t)n_inc * nM);
+  L.HB32 = take(4 * (size_t)n_inc * nM);
   L.total = o;
   return L;
 }
@@ -1306,9 +1309,11 @@ size_t bb_recs_bytes(int B, int nb, int TT, int n_eblk, BusbarRecs<F>* rr, void*
   const size_t z = take(sizeof(F) * n * kBbMaxR * TT);
   const size_t pa = take(sizeof(F) * n * TT);
   const size_t part = take(8 * (size_t)B * n_eblk);
+  const size_t cand = take(sizeof(BbCand) * (size_t)B);
   if (rr && base) {
     char* b = (char*)base;
     rr->hdr = (int*)(b + h); rr->z = (F*)(b + z); rr->pa = (F*)(b + pa); rr->part = (double*)(b + part);
+    rr->cand = (BbCand*)(b + cand);
   }
   return o;
 }
@@ -1359,7 +1364,10 @@ tto_status tto_busbar_set_create(const tto_grid* g, int32_t n_busbars, const int
     HIP_TRY(hipMemcpyAsync(base + L.inc_off, off.data(), 4 * off.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(base + L.inc_br, br.data(), 4 * br.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_busbar_tables(ptdf, n, m, g->dev.mon, g->nM, (const int*)(base + L.bus), nb,
-                                 (double*)(base + L.PB), (double*)(base + L.PBM), s));
+                                 (double*)(base + L.PB), (double*)(base + L.PBM),
+                                 (float*)(base + L.PBM32), g->dev.S, g->dev.b,
+                                 (const int*)(base + L.inc_br), (int)br.size(),
+                                 (double*)(base + L.HB), (float*)(base + L.HB32), s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   tto_busbars* bs = new tto_busbars();
@@ -1371,6 +1379,10 @@ tto_status tto_busbar_set_create(const tto_grid* g, int32_t n_busbars, const int
   bs->d.inc_br = (const int*)(base + L.inc_br);
   bs->d.PB = (const double*)(base + L.PB);
   bs->d.PBM = (const double*)(base + L.PBM);
+  bs->d.PBM32 = (const float*)(base + L.PBM32);
+  bs->d.n_inc = (int)br.size();
+  bs->d.HB = (const double*)(base + L.HB);
+  bs->d.HB32 = (const float*)(base + L.HB32);
   *out = bs;
   return ok();
 }

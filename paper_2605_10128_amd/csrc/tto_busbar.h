@@ -9,9 +9,13 @@ namespace tto {
 constexpr int kBbMaxDeg = 16;                        // branches on one busbar
 constexpr int kBbMaxR = kMaxRank + kBbMaxDeg - 1;    // candidate rank + busbar openings
 // record header: R, k, d, state (0 solved, 1 islanding, 2 candidate skipped),
-// the busbar's branches (kBbMaxDeg), then the moved branches that the outage
-// removes from their split (kBbMaxDeg ids and kBbMaxDeg codes 2 j + (sg > 0))
-constexpr int kBbHdr = 4 + 3 * kBbMaxDeg;
+// the busbar's branches (kBbMaxDeg ids), the moved branches that the outage
+// removes from their split (kBbMaxDeg ids, kBbMaxDeg codes 2 j + (sg > 0) +
+// 256 q with q the branch's index among the busbar's branches), and the
+// busbar's branches' positions in the set's H tile (kBbMaxDeg)
+constexpr int kBbHdr = 4 + 4 * kBbMaxDeg;
+constexpr int kBbIds = 4, kBbRm = 4 + kBbMaxDeg, kBbRmc = 4 + 2 * kBbMaxDeg,
+              kBbPos = 4 + 3 * kBbMaxDeg;
 
 // Busbar set: the buses whose (main) busbar can fail, their base-grid
 // incident branches and the PTDF columns of those buses.
@@ -22,11 +26,29 @@ struct BusbarDev {
   const int* inc_br;    // incident branch ids (base grid)
   const double* PB;     // [nb][m]  PTDF_{x, bus}
   const double* PBM;    // [nb][nM] PTDF_{mon[ei], bus}
+  const float* PBM32;   // the same in FP32
+  int n_inc;
+  const double* HB;     // [n_inc][nM] H_{mon[ei], inc_br[p]} = b_e S_{e, x}
+  const float* HB32;    // the same in FP32
+};
+
+// A candidate's genome parsed once for all its busbar outages (openings in
+// slot order, splits in slot order with their moved branches).
+struct BbCand {
+  int k, s, nm, pad;
+  int op[kMaxRank];
+  int sbus[kMaxRank], sslot[kMaxRank];
+  int moff[kMaxRank + 1];
+  int pad2[3];
+  int mbr[kMaxMoved];
+  int msgn[kMaxMoved];       // +1 if the branch leaves the split bus
+  double mb[kMaxMoved];      // susceptance of each moved branch
 };
 
 // Per (candidate, busbar) solution of the bordered system.
 template <typename F>
 struct BusbarRecs {
+  BbCand* cand;   // [B]
   int* hdr;   // [B][nb][kBbHdr]
   F* z;       // [B][nb][kBbMaxR][TT]
   F* pa;      // [B][nb][TT] injection lost with the busbar
@@ -34,7 +56,9 @@ struct BusbarRecs {
 };
 
 hipError_t launch_busbar_tables(const double* ptdf, int n_bus, int m, const int* mon, int nM,
-                                const int* bus, int nb, double* PB, double* PBM, hipStream_t s);
+                                const int* bus, int nb, double* PB, double* PBM, float* PBM32,
+                                const double* S, const double* b, const int* inc_br, int n_inc,
+                                double* HB, float* HB32, hipStream_t s);
 
 template <typename F>
 hipError_t launch_busbar(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
