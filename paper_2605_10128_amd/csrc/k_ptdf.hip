@@ -48,30 +48,54 @@ __global__ __launch_bounds__(256) void k_lap_rows(const int* __restrict__ off,
   row[r] = d;
 }
 
-// In-place Gauss-Jordan inverse of the 64 x 64 diagonal block (SPD).
+// In-place Gauss-Jordan inverse of the 64 x 64 diagonal block (SPD).  Thread
+// t holds the 4 x 4 sub-block at rows 4 (t / 16), columns 4 (t % 16) in
+// registers; for pivot p the owners of row p and of column p publish them
+// through LDS, double-buffered by the pivot's parity, so one barrier per
+// pivot separates the writes from the reads (a buffer is rewritten two pivots
+// later, after every thread has passed the barrier in between).
 __global__ __launch_bounds__(256) void k_gj_diag(double* __restrict__ A, int Np, int kb,
                                                  double* __restrict__ Pbuf) {
-  __shared__ double a[kGjB][kGjB + 1];
-  __shared__ double prow[kGjB], pcol[kGjB];
+  __shared__ double prow[2][kGjB], pcol[2][kGjB];
   const int tid = threadIdx.x;
+  const int i0 = 4 * (tid >> 4), j0 = 4 * (tid & 15);
   const size_t k0 = (size_t)kb * kGjB;
-  for (int idx = tid; idx < kGjB * kGjB; idx += 256)
-    a[idx / kGjB][idx % kGjB] = A[(k0 + idx / kGjB) * Np + k0 + idx % kGjB];
-  __syncthreads();
+  double a[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[r][c] = A[(k0 + i0 + r) * Np + k0 + j0 + c];
   for (int p = 0; p < kGjB; ++p) {
-    const double inv = 1.0 / a[p][p];
-    if (tid < kGjB) { prow[tid] = a[p][tid] * inv; pcol[tid] = a[tid][p]; }
+    const int buf = p & 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (i0 + r == p) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) prow[buf][j0 + c] = a[r][c];
+      }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (j0 + c == p) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pcol[buf][i0 + r] = a[r][c];
+      }
     __syncthreads();
-    if (tid < kGjB) prow[p] = inv;
-    __syncthreads();
-    for (int idx = tid; idx < kGjB * kGjB; idx += 256) {
-      const int i = idx / kGjB, j = idx % kGjB;
-      if (i == p) a[i][j] = prow[j];
-      else a[i][j] = (j == p ? 0.0 : a[i][j]) - pcol[i] * prow[j];
-    }
-    __syncthreads();
+    const double inv = 1.0 / prow[buf][p];
+    double rw[4], cl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rw[c] = j0 + c == p ? inv : prow[buf][j0 + c] * inv;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cl[r] = pcol[buf][i0 + r];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        a[r][c] = i0 + r == p ? rw[c] : (j0 + c == p ? 0.0 : a[r][c]) - cl[r] * rw[c];
   }
-  for (int idx = tid; idx < kGjB * kGjB; idx += 256) Pbuf[idx] = a[idx / kGjB][idx % kGjB];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Pbuf[(size_t)(i0 + r) * kGjB + j0 + c] = a[r][c];
 }
 
 // 64 x 64 tile product on the MFMA: wave w computes rows 32 (w / 2) + [0, 32)
