@@ -77,6 +77,7 @@ struct BbShared {
   int k, kk, s, R, d, jb, skip, nrm;
   double M[kBbMaxR][kBbMaxR + 1];
   int piv[kBbMaxR];
+  int perm[kBbMaxR];   // row q of the factors is row perm[q] of the system
   double pa[32];
 };
 
@@ -261,6 +262,13 @@ __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBu
     __syncthreads();
   }
   if (tid == 0) {
+    // the row interchanges composed: the factors hold whole swapped rows, so
+    // the right-hand side is permuted once before the triangular solves
+    for (int q = 0; q < R; ++q) sh.perm[q] = q;
+    for (int p = 0; p < R; ++p) {
+      const int pv = sh.piv[p];
+      const int t = sh.perm[p]; sh.perm[p] = sh.perm[pv]; sh.perm[pv] = t;
+    }
     sh.skip = (R > 0 && minpiv < kTauIsland) ? 1 : 0;
     H[0] = R; H[1] = k; H[2] = d; H[3] = sh.skip;
     for (int q = 0; q < kBbMaxDeg; ++q) {
@@ -276,40 +284,57 @@ __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBu
     rr.pa[rec * TT + tid] = (F)sh.pa[tid];
   }
   if (sh.skip) return;
-  // z(t) = M^{-1} rhs(t) with the base flows shifted by the lost injection
+  // z(t) = M^{-1} rhs(t) with the base flows shifted by the lost injection;
+  // every index into x is a compile-time constant, so x stays in registers
   if (tid < TT) {
     const int t = tid;
     double x[kBbMaxR];
+#pragma unroll
     for (int q = 0; q < kBbMaxR; ++q) x[q] = 0.0;
     if (t < T) {
       const double pa = sh.pa[t];
       const double* PBr = bb.PB + (size_t)ib * m;
-      for (int q = 0; q < R; ++q) {
-        if (q < kk) {
-          const int x0 = sh.op[q];
-          x[q] = g.f0[(size_t)x0 * T + t] - PBr[x0] * pa;
-        } else {
-          const int j = q - kk;
-          double phi = 0.0;
-          for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) {
-            const int e = sh.mbr[p];
-            phi += sh.msign[p] * (g.f0[(size_t)e * T + t] - PBr[e] * pa);
+#pragma unroll
+      for (int q = 0; q < kBbMaxR; ++q) {
+        if (q < R) {
+          const int row = sh.perm[q];
+          double v;
+          if (row < kk) {
+            const int x0 = sh.op[row];
+            v = g.f0[(size_t)x0 * T + t] - PBr[x0] * pa;
+          } else {
+            const int j = row - kk;
+            double phi = 0.0;
+            for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) {
+              const int e = sh.mbr[p];
+              phi += sh.msign[p] * (g.f0[(size_t)e * T + t] - PBr[e] * pa);
+            }
+            const double pj = bt.mp ? bt.mp[((size_t)c * bt.ns + sh.sslot[j]) * T + t] : 0.0;
+            v = (pj - phi) * sh.inv_s[j];
           }
-          const double pj = bt.mp ? bt.mp[((size_t)c * bt.ns + sh.sslot[j]) * T + t] : 0.0;
-          x[q] = (pj - phi) * sh.inv_s[j];
+          x[q] = v;
         }
       }
-      for (int p = 0; p < R; ++p) {
-        const int pv = sh.piv[p];
-        if (pv != p) { const double tt = x[p]; x[p] = x[pv]; x[pv] = tt; }
-        for (int i = p + 1; i < R; ++i) x[i] -= sh.M[i][p] * x[p];
+#pragma unroll
+      for (int p = 0; p < kBbMaxR; ++p) {
+        if (p < R) {
+#pragma unroll
+          for (int i = p + 1; i < kBbMaxR; ++i)
+            if (i < R) x[i] -= sh.M[i][p] * x[p];
+        }
       }
-      for (int p = R - 1; p >= 0; --p) {
-        double v = x[p];
-        for (int q = p + 1; q < R; ++q) v -= sh.M[p][q] * x[q];
-        x[p] = v / sh.M[p][p];
+#pragma unroll
+      for (int p = kBbMaxR - 1; p >= 0; --p) {
+        if (p < R) {
+          double v = x[p];
+#pragma unroll
+          for (int q = p + 1; q < kBbMaxR; ++q)
+            if (q < R) v -= sh.M[p][q] * x[q];
+          x[p] = v / sh.M[p][p];
+        }
       }
     }
+#pragma unroll
     for (int q = 0; q < kBbMaxR; ++q) z[(size_t)q * TT + t] = (F)x[q];
   }
 }
