@@ -97,3 +97,58 @@ def test_busbar_set_rejects_bad_buses():
             sess.busbar_set(np.array(buses), ptdf)
         assert ei.value.code == tto.TTO_E_GRID
     sess.close()
+
+
+def test_busbar_full_size_sampled():
+    """The benchmarked workload (2000 buses, T = 24, 16384 candidates, the
+    seeded 128-busbar set, FP32 flows) in one launch: lambda_b and the
+    islanding count of sampled candidates against the oracle's re-solves,
+    lambda_b of the unswitched grid likewise, and lambda_f2's definition and
+    the status conventions on every candidate."""
+    import torch
+    from paper_2605_10128_amd import tto
+    w = gg.build_config(3)
+    g = w.grid
+    B = w.batch.n_cand
+    sess = make_session(w, tto.TTO_FLOW_F32, max_batch=B)
+    buses = gg.select_busbars(g, 128, seed=0xBB00 + w.cfg)
+    ptdf = tto.ptdf_device(g.n_bus, g.from_bus, g.to_bus, 1.0 / g.x_pu, g.slack)
+    bset = sess.busbar_set(buses, ptdf)
+    db = tto.device_batch(w.batch)
+    out = sess.evaluate(db)
+    empty = tto.device_batch(w.batch.subset(np.zeros(1, dtype=np.int64)))
+    empty.open.fill_(-1)
+    empty.split_bus.fill_(-1)
+    pre_l, pre_n, _ = sess.busbar_evaluate(bset, empty)
+    torch.cuda.synchronize()
+    pre = float(pre_l.item())
+    lam, nis, f2 = sess.busbar_evaluate(bset, db, pre, out["fitness"])
+    torch.cuda.synchronize()
+    lam, nis, f2 = lam.cpu().numpy(), nis.cpu().numpy(), f2.cpu().numpy()
+    st = out["status"].cpu().numpy()
+    fit = out["fitness"].cpu().numpy()
+    lim = g.limit_mw[w.M]
+
+    def bound(fm):
+        return TOL_F32 * ((fm > lim[:, None] - TOL_F32).sum() + 1)
+
+    empty_c = oracle.Candidate(opened=[], splits=[], moved_p=[], n_slots_filled=0)
+    ref = oracle.busbar_metrics(g, w.P, w.M, empty_c, buses)
+    assert int(pre_n.item()) == ref["n_island"]
+    assert abs(pre - ref["lambda_b"]) <= bound(ref["fmax"])
+    bad = (st & 3) != 0
+    assert np.isnan(lam[bad]).all() and (nis[bad] == 0).all() and np.isneginf(f2[bad]).all()
+    ok = ~bad
+    assert (lam[ok] >= 0).all() and (nis[ok] >= 0).all() and (nis[ok] <= len(buses)).all()
+    np.testing.assert_allclose(f2[ok], fit[ok] - np.maximum(lam[ok] - pre, 0.0), rtol=0, atol=1e-9)
+    rng = np.random.default_rng(33)
+    sample = rng.choice(np.flatnonzero(ok), size=6, replace=False)
+    for c in sample:
+        cand = oracle.candidate_from_batch(w.batch, int(c))
+        r = oracle.busbar_metrics(g, w.P, w.M, cand, buses)
+        assert nis[c] == r["n_island"], (c, nis[c], r["n_island"])
+        assert abs(lam[c] - r["lambda_b"]) <= bound(r["fmax"]), (c, lam[c], r["lambda_b"])
+    log(f"[busbar] full size: {B} candidates x {len(buses)} busbars, lambda_b_pre {pre:.1f} MW, "
+        f"{int(bad.sum())} candidates skipped, sampled {sample.tolist()} match the oracle")
+    bset.close()
+    sess.close()
