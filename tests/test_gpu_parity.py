@@ -226,3 +226,61 @@ def test_refinement_off_and_default_counts(tto):
     o2 = to_numpy(s.evaluate(db))
     torch.cuda.synchronize()
     assert ((o2["status"] & (tto.TTO_ST_REFINED | tto.TTO_ST_REFINE_SKIPPED)) == 0).all()
+
+
+def test_benchmarked_launch_sampled_against_oracle(tto):
+    """The benchmarked launch (2000 buses, T = 24, 16384 candidates, |M| =
+    1200, |C| = 1600, FP32 flows with the default refinement, 256-lane sweep
+    tiles), checked on sampled outputs the oracle computes one by one: the
+    candidate's islanding status and lambda_c0 from the oracle's post-switch
+    N-0 flows, the reported worst N-1 flow (e*, l*, t*) re-solved by the
+    oracle equal to rho times the limit, and no sampled contingency loading a
+    monitored branch above rho."""
+    import torch
+    import oracle
+    w = gg.build_config(3)
+    B = w.batch.n_cand
+    s = make_session(w, tto.TTO_FLOW_F32, max_batch=B)
+    s.set_sweep_plan(256, 1, False)
+    o = to_numpy(s.evaluate(tto.device_batch(w.batch)))
+    torch.cuda.synchronize()
+    lim = w.grid.limit_mw[w.M]
+    edges = gg.default_load_edges()
+    rng = np.random.default_rng(2000)
+    ns = (w.batch.split_bus >= 0).sum(1)
+    pick = sorted(set(rng.choice(np.flatnonzero(ns >= 1), size=4, replace=False).tolist()) |
+                  set(rng.choice(B, size=4, replace=False).tolist()))
+    checked = 0
+    for c in pick:
+        cand = oracle.candidate_from_batch(w.batch, c)
+        st = int(o["status"][c])
+        positions = sorted(rng.choice(len(w.C), size=8, replace=False).tolist())
+        if st & 3 == 0 and o["worst_cont"][c] >= 0:
+            positions = sorted(set(positions) | {int(np.flatnonzero(w.C == o["worst_cont"][c])[0])})
+        r = oracle.evaluate_candidate(w.grid, w.P, w.M, w.C, cand, edges, keep_n1=True,
+                                      cont_subset=positions)
+        if not r.valid:
+            assert st & 2, c
+            continue
+        if r.islanded:
+            assert st & 1, c
+            continue
+        assert st & 3 == 0, (c, st)
+        f0M = np.abs(r.base_flows[w.M])
+        if np.abs(f0M - lim[:, None]).min() > 1e-9:
+            assert o["n_crit_n0"][c] == int((f0M > lim[:, None]).sum()), c
+        rho = float(o["max_loading"][c])
+        e_pos = int(np.flatnonzero(w.M == o["worst_branch"][c])[0])
+        l_pos = int(np.flatnonzero(w.C == o["worst_cont"][c])[0])
+        f_worst = abs(r.n1_flows[l_pos, e_pos, int(o["worst_t"][c])])
+        assert abs(f_worst - rho * lim[e_pos]) <= TOL_F32 + 1e-6 * f_worst, (c, f_worst, rho)
+        for li in positions:
+            row = r.n1_flows[li]
+            if np.isnan(row).any():
+                continue
+            assert (np.abs(row) / lim[:, None]).max() <= rho + TOL_F32 / lim.min(), (c, li)
+        checked += 1
+    log(f"[parity] benchmarked launch: {B} candidates, {checked} of {len(pick)} sampled "
+        f"candidates checked against the oracle")
+    assert checked >= 4
+    s.close()
