@@ -302,3 +302,59 @@ def test_genome_space_rejects_bad_tables(s500, w500):
     rep = tto.Repertoire(s500, gs, n_cells=100)          # not the descriptor's 1024 cells
     with pytest.raises(tto.TTOError):
         tto.Evolver(s500, gs, rep, 16, 1).step()
+
+
+def test_generation_at_benchmarked_size():
+    """The benchmarked generation (2000 buses, 16384 children, N_a = N_d = 4,
+    the 4096-action table, FP32 flows) after two device generations: the
+    third generation's children bit-exact against the oracle's variation from
+    the same repertoire, their expansion exact, and the insertion of the
+    device's evaluations equal to the oracle's one-at-a-time insertion."""
+    import torch
+    from paper_2605_10128_amd import tto
+    w = gg.build_config(3)
+    g = w.grid
+    B = w.batch.n_cand
+    sess = make_session(w, tto.TTO_FLOW_F32, max_batch=B)
+    D = np.flatnonzero(~gg.bridges(g.n_bus, g.from_bus, g.to_bus)).astype(np.int32)
+    bus = np.array([b for b, _ in w.split_table], dtype=np.int32)
+    moved = [mv for _, mv in w.split_table]
+    gs = tto.GenomeSpace(sess, bus, moved, D, 4, 4)
+    orc = ev.GenomeSpace(bus, moved, D, 4, 4)
+    rep = tto.Repertoire(sess, gs)
+    outs = sess.alloc_outputs(B)
+    seed = 0xE701
+    evo = tto.Evolver(sess, gs, rep, B, seed=seed, outputs=outs)
+    evo.step()
+    evo.step()
+    torch.cuda.synchronize()
+    fit0 = rep.fitness.cpu().numpy()
+    id0 = rep.id.cpu().numpy()
+    gen0 = rep.genome.cpu().numpy()
+    g0 = int(rep.generation.item())
+    evo.step()
+    torch.cuda.synchronize()
+    kids = evo.children.cpu().numpy()
+    want, want_b = ev.vary(orc, id0, gen0[:, :gs.G], seed, g0, B)
+    assert int(evo.b_mc.item()) == want_b
+    bad = np.flatnonzero(np.any(kids != want, axis=1))
+    assert bad.size == 0, f"{bad.size} children differ, first {bad[:5]}"
+    db = gs.expand(torch.as_tensor(kids, device=sess.device))
+    torch.cuda.synchronize()
+    opens, sbus, mv = ev.expand(orc, kids)
+    assert np.array_equal(db.open.cpu().numpy(), opens)
+    assert np.array_equal(db.split_bus.cpu().numpy(), sbus)
+    off, br = db.moved_off.cpu().numpy(), db.moved_br.cpu().numpy()
+    for s_ in range(0, B * gs.n_a, 97):
+        assert br[off[s_]:off[s_ + 1]].tolist() == mv[s_], s_
+    st = outs["status"].cpu().numpy()
+    ok = (st & 3) == 0
+    f_, i_, gm = ev.archive_insert_genomes(fit0, id0, gen0, outs["fitness"].cpu().numpy(),
+                                           outs["cell"].cpu().numpy(), ok, kids, g0 * B)
+    assert int(rep.generation.item()) == g0 + 1
+    assert np.array_equal(rep.id.cpu().numpy(), i_)
+    assert np.array_equal(rep.fitness.cpu().numpy(), f_)
+    assert np.array_equal(rep.genome.cpu().numpy(), gm)
+    log(f"[evolve] benchmarked size: generation {g0}, {B} children identical, b_mc={want_b}, "
+        f"{int((i_ >= 0).sum())} cells after insertion")
+    sess.close()
