@@ -94,3 +94,53 @@ def test_worst_k_consistent_with_evaluate():
     assert np.all(np.isnan(e0[~ok]))
     log(f"[worst-k] 256 candidates: max E_l / lambda_o median {np.median(e0[ok & (lam > 0)] / lam[ok & (lam > 0)]):.3f}")
     sess.close()
+
+
+def test_worst_k_benchmarked_size_sampled():
+    """The benchmarked export (2000 buses, T = 24, 1024 candidates, k = 20,
+    FP32): for sampled candidates the oracle re-solves the 20 listed
+    contingencies and 8 others; the listed energies equal the oracle's
+    within tolerance and descend, no listed contingency islands, and no
+    unlisted sampled contingency exceeds the 20th energy."""
+    import torch
+    import oracle
+    from paper_2605_10128_amd import tto
+    w = gg.build_config(3, B=1024)
+    K = 20
+    sess = make_session(w, tto.TTO_FLOW_F32, max_batch=1024)
+    db = tto.device_batch(w.batch)
+    out = sess.evaluate(db)
+    ids, en = sess.worst_contingencies(db, K)
+    torch.cuda.synchronize()
+    ids, en = ids.cpu().numpy(), en.cpu().numpy()
+    st = out["status"].cpu().numpy()
+    lim = w.grid.limit_mw[w.M]
+    edges = gg.default_load_edges()
+    rng = np.random.default_rng(20)
+    ok = np.flatnonzero((st & 3) == 0)
+    checked = 0
+    for c in rng.choice(ok, size=4, replace=False):
+        c = int(c)
+        listed = [int(np.flatnonzero(w.C == i)[0]) for i in ids[c] if i >= 0]
+        others = [p for p in rng.choice(len(w.C), size=12, replace=False).tolist()
+                  if p not in listed][:8]
+        cand = oracle.candidate_from_batch(w.batch, c)
+        r = oracle.evaluate_candidate(w.grid, w.P, w.M, w.C, cand, edges, keep_n1=True,
+                                      cont_subset=sorted(listed + others))
+        assert r.valid and not r.islanded
+        E = oracle.contingency_energies(r.n1_flows, lim)
+        assert np.all(np.diff(en[c][: len(listed)]) <= 0), c
+        for j, p in enumerate(listed):
+            assert not np.isnan(E[p]), (c, p)
+            n_over = int((np.abs(r.n1_flows[p]) > lim[:, None] - TOL_F32).sum())
+            assert abs(en[c][j] - E[p]) <= TOL_F32 * (n_over + 1), (c, p, en[c][j], E[p])
+        kth = en[c][len(listed) - 1] if listed else -np.inf
+        for p in others:
+            if np.isnan(E[p]):
+                continue
+            n_over = int((np.abs(r.n1_flows[p]) > lim[:, None] - TOL_F32).sum())
+            assert E[p] <= kth + TOL_F32 * (n_over + 1), (c, p, E[p], kth)
+        checked += 1
+    log(f"[worst-k] benchmarked size: 1024 candidates, k = {K}, {checked} sampled candidates "
+        f"checked against the oracle")
+    sess.close()
