@@ -138,58 +138,73 @@ __global__ __launch_bounds__(64) void k_bb_setup(GridDev g, BatchDev bt, SweepBu
     for (int i = tid; i < (int)(sizeof(BbCand) / 4); i += 64) dst[i] = src[i];
   }
   __syncthreads();
-  if (tid == 0) {
-    const int k = cd.k, s = cd.s;
-    int jb = -1;
-    for (int q = 0; q < k; ++q) sh.op[q] = cd.op[q];
-    for (int j = 0; j < s; ++j) {
-      sh.sbus[j] = cd.sbus[j];
-      sh.sslot[j] = cd.sslot[j];
-      if (cd.sbus[j] == bus) jb = j;
-    }
+  // The outage's lists, one lane per element (the workgroup is one wave):
+  // openings, the busbar's in-service branches, the moved lists without the
+  // branches this outage opens, in the set-up kernel's order.
+  {
+    const int k = cd.k, s = cd.s, nmc = cd.nm;
+    const unsigned long long below = (1ull << tid) - 1ull;
+    if (tid < k) sh.op[tid] = cd.op[tid];
+    if (tid < s) { sh.sbus[tid] = cd.sbus[tid]; sh.sslot[tid] = cd.sslot[tid]; }
+    const unsigned long long jm = __ballot(tid < s && cd.sbus[tid] == bus);
+    const int jb = jm ? 63 - __clzll(jm) : -1;
     // branches on the busbar's node: incident in the base grid, in service,
-    // not moved to busbar B of a split of this bus
-    int d = 0;
-    for (int p = bb.inc_off[ib]; p < bb.inc_off[ib + 1]; ++p) {
-      const int x = bb.inc_br[p];
+    // not moved to busbar B of a split of this bus (at most kBbMaxDeg)
+    const int p0 = bb.inc_off[ib], n_inc = bb.inc_off[ib + 1] - p0;
+    bool keep = false;
+    int x = -1;
+    if (tid < n_inc) {
+      x = bb.inc_br[p0 + tid];
       bool off = false;
-      for (int q = 0; q < k; ++q) off |= sh.op[q] == x;
+      for (int q = 0; q < k; ++q) off |= cd.op[q] == x;
       if (jb >= 0)
         for (int q = cd.moff[jb]; q < cd.moff[jb + 1]; ++q) off |= cd.mbr[q] == x;
-      if (!off && d < kBbMaxDeg) { sh.ids[d] = x; sh.pos[d] = p; ++d; }
+      keep = !off;
     }
-    int kk = k;
-    for (int q = 0; q + 1 < d; ++q) sh.op[kk++] = sh.ids[q];
-    // moved lists without the branches this outage opens (a split of a
-    // neighbour may have moved a branch of the busbar)
-    int nm = 0, nrm = 0;
-    for (int j = 0; j < s; ++j) {
-      sh.moff[j] = nm;
+    const unsigned long long km = __ballot(keep);
+    const int d = min(__popcll(km), kBbMaxDeg);
+    const int rk = __popcll(km & below);
+    if (keep && rk < kBbMaxDeg) { sh.ids[rk] = x; sh.pos[rk] = p0 + tid; }
+    __syncthreads();
+    const int kk = k + (d > 0 ? d - 1 : 0);
+    if (tid + 1 < d) sh.op[k + tid] = sh.ids[tid];
+    // moved branches: kept in their split, or opened by this outage (then
+    // recorded with their index among the busbar's branches)
+    bool kept = false, rem = false;
+    int e = -1, jme = 0, here = -1;
+    double sg = 0.0, mbv = 0.0;
+    if (tid < nmc) {
+      e = cd.mbr[tid];
+      while (jme + 1 < s && cd.moff[jme + 1] <= tid) ++jme;
+      sg = (double)cd.msgn[tid];
+      mbv = cd.mb[tid];
+      for (int q = 0; q + 1 < d; ++q) here = sh.ids[q] == e ? q : here;
+      rem = here >= 0;
+      kept = !rem;
+    }
+    const unsigned long long kmask = __ballot(kept), rmask = __ballot(rem);
+    const int kr = __popcll(kmask & below), rr_ = __popcll(rmask & below);
+    if (kept) { sh.mbr[kr] = e; sh.msign[kr] = sg; sh.msg[kr] = sg * mbv; }
+    if (rem && rr_ < kBbMaxDeg) {
+      sh.rm[rr_] = e;
+      sh.rmc[rr_] = 2 * jme + (sg > 0.0 ? 1 : 0) + 256 * here;
+    }
+    if (tid <= s) {
+      const int first = cd.moff[tid];
+      sh.moff[tid] = __popcll(kmask & (first >= 64 ? ~0ull : (1ull << first) - 1ull));
+    }
+    if (tid < s) {
       double ssum = 0.0;
-      for (int p = cd.moff[j]; p < cd.moff[j + 1]; ++p) {
-        const int e = cd.mbr[p];
-        const double sg = (double)cd.msgn[p];
-        int here = -1;   // index among the busbar's branches when the outage opens it
-        for (int q = 0; q + 1 < d; ++q) here = sh.ids[q] == e ? q : here;
-        if (here >= 0) {
-          if (nrm < kBbMaxDeg) {
-            sh.rm[nrm] = e;
-            sh.rmc[nrm] = 2 * j + (sg > 0.0 ? 1 : 0) + 256 * here;
-            ++nrm;
-          }
-          continue;
-        }
-        sh.mbr[nm] = e;
-        sh.msign[nm] = sg;
-        sh.msg[nm] = sg * cd.mb[p];
-        ssum += cd.mb[p];
-        ++nm;
-      }
-      sh.inv_s[j] = ssum > 0.0 ? 1.0 / ssum : 0.0;
+      for (int p = cd.moff[tid]; p < cd.moff[tid + 1]; ++p)
+        if ((kmask >> p) & 1ull) ssum += cd.mb[p];
+      sh.inv_s[tid] = ssum > 0.0 ? 1.0 / ssum : 0.0;
     }
-    sh.moff[s] = nm;
-    for (int q = 0; q < kk; ++q) sh.bK[q] = g.b[sh.op[q]];
-    sh.k = k; sh.kk = kk; sh.s = s; sh.R = kk + s; sh.d = d; sh.jb = jb; sh.nrm = nrm;
+    __syncthreads();
+    if (tid < kk) sh.bK[tid] = g.b[sh.op[tid]];
+    if (tid == 0) {
+      sh.k = k; sh.kk = kk; sh.s = s; sh.R = kk + s; sh.d = d; sh.jb = jb;
+      sh.nrm = min(__popcll(rmask), kBbMaxDeg);
+    }
   }
   __syncthreads();
   const int k = sh.k, kk = sh.kk, R = sh.R, d = sh.d, jb = sh.jb;
