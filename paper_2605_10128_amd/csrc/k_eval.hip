@@ -378,16 +378,21 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     const int e = g.mon[ei];
     bool opened = false;
     for (int q = 0; q < k; ++q) opened |= (sh.open[q] == e);
+    // loads that depend on the row alone go out before the column gather,
+    // so that their latency overlaps it
+    double f0e[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) f0e[t] = t < T ? g.f0[(size_t)e * T + t] : 0.0;
+    const double be = g.b[e], lim = g.lim[e];
     double W[kMaxRank], U[kMaxRank];
     gather_column(g.SMC, nMC, ei, sh, W);
-    u_from_w(e, g.b[e], W, U);
-    const double lim = g.lim[e];
+    u_from_w(e, be, W, U);
     F* fo = w.fM + (size_t)c * TT * nM + ei;   // [c][t][ei]: coalesced across threads
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
       double fp = 0.0;
       if (t < T && !opened) {
-        fp = g.f0[(size_t)e * T + t];
+        fp = f0e[t];
 #pragma unroll
         for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
         n0 += fabs(fp) > lim;
@@ -433,17 +438,24 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     int l = 0;
     double V[kMaxRank], U[kMaxRank];
     double inv_d = 0.0;
+    double f0l[TT];
+    double s_ll = 0.0, b_l = 0.0;
 #pragma unroll
     for (int q = 0; q < kMaxRank; ++q) { V[q] = 0.0; U[q] = 0.0; }
     if (li < nC) {
       l = g.cont[li];
+      // row-only loads first (their latency overlaps the column gather)
+      s_ll = g.S[(size_t)l * m + l];
+      b_l = g.b[l];
+#pragma unroll
+      for (int t = 0; t < TT; ++t) f0l[t] = t < T ? g.f0[(size_t)l * T + t] : 0.0;
       for (int q = 0; q < k; ++q) opened |= (sh.open[q] == l);
       if (opened) {
         active = true;  // already open: the N-0 state (phi = 0)
       } else {
         double W[kMaxRank];
         gather_column(g.SMC, nMC, nM + li, sh, W);
-        const double bl = g.b[l];
+        const double bl = b_l;
         // right-hand side of the factor column: R_q = b_{K_q} W_q (openings),
         // R_{k+j} = (ps_j - W_{k+j}) / s_j with ps_j = sg_l if l is moved by j
 #pragma unroll
@@ -464,7 +476,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
         }
         u_from_w(l, bl, W, U);
         lu_solve(sh.M, sh.piv, r, V);
-        double hll = bl * g.S[(size_t)l * m + l];
+        double hll = bl * s_ll;
 #pragma unroll
         for (int q = 0; q < kMaxRank; ++q) hll += U[q] * V[q];
         const double d = 1.0 - hll;
@@ -499,7 +511,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
             if (slot < TT) {
               // phi_l(t) = f'_l(t) / (1 - H'_ll), zero for an already opened l
               if (slot < T && !opened) {
-                double fl = g.f0[(size_t)l * T + slot];
+                double fl = f0l[slot];
 #pragma unroll
                 for (int q = 0; q < kMaxRank; ++q) fl += U[q] * s_x[q][slot];
                 v = fl * inv_d;
