@@ -358,7 +358,7 @@ template <typename F, int TT>
 __global__ __launch_bounds__(256) void k_bb_sweep(GridDev g, SweepBufs<F> w, BusbarDev bb,
                                                   BusbarRecs<F> rr, int n_eblk) {
   const int c = blockIdx.y, eb = blockIdx.x, tid = threadIdx.x;
-  const int nM = g.nM, nC = g.nC, T = g.T, nb = bb.nb;
+  const int nM = g.nM, T = g.T, nb = bb.nb;
   const CandInfo* inf = w.info + c;
   const bool bad = inf->status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
   const int ei = eb * 256 + tid;
