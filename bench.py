@@ -479,8 +479,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(candidates shard along the batch; see the design notes)"}))
+        print(json.dumps({"error": "runs on one GPU only; --gpus must be 1 (candidates would "
+                                   "shard along the batch across GPUs, not implemented)"}))
         sys.exit(2)
 
     import numpy as np

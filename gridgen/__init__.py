@@ -9,7 +9,7 @@ section: disconnectable branches are those whose removal does not island the
 grid, found with Tarjan's bridge algorithm); it is never used to decide any
 output of the method.
 
-Recipe (see the workload description in the design notes):
+Recipe:
   * spanning tree: random recursive tree over a random bus permutation,
   * chords: uniform bus pairs, no self loops, no parallel branches,
   * reactance x ~ U(0.01, 0.3) pu, thermal limit ~ U(50, 300) MW, slack bus 0,

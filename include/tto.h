@@ -59,7 +59,7 @@ enum {
   TTO_E_RANK = -3,        /* slot counts beyond TTO_MAX_RANK per kind */
   TTO_E_WORKSPACE = -4,   /* workspace NULL, misaligned or too small */
   TTO_E_HIP = -5,         /* a HIP runtime call failed */
-  TTO_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+  TTO_E_UNSUPPORTED = -6  /* valid request the library does not implement */
 };
 
 /* Arithmetic of the flows (N-0 and N-1 sweep).  Candidate set-up (the rank-r
@@ -307,7 +307,7 @@ tto_status tto_profile_read(tto_grid* grid, double* ms);
  * order (longest tiles first).  Default: block 256, no grouping, not
  * persistent.  TTO_E_INVALID for other block sizes or xcd_group values;
  * TTO_E_UNSUPPORTED for
- * blocks 64/128 and for persistent != 0, which this build switches off.
+ * blocks 64/128 and for persistent != 0, which the library switches off.
  */
 tto_status tto_set_sweep_plan(tto_grid* grid, int32_t block, int32_t xcd_group,
                               int32_t persistent);

@@ -548,7 +548,7 @@ static tto_status apply_plan(tto_grid* g, int bs, int xcd, int persistent) {
   // 64/128-lane tiles and the persistent grid are switched off: a GPU test
   // exercising them did not finish and the cause has not been found.
   if (bs != 256 || persistent)
-    return fail(TTO_E_UNSUPPORTED, "sweep plan (block %d, persistent %d) is disabled in this build",
+    return fail(TTO_E_UNSUPPORTED, "sweep plan (block %d, persistent %d) is disabled",
                 bs, persistent);
   SweepPlan p;
   p.bs = bs;
