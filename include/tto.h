@@ -85,6 +85,11 @@ enum {
                                   and was recomputed in FP64 */
 #define TTO_ST_REFINE_SKIPPED 0x08u  /* near a decision threshold but beyond
                                         the refinement capacity: FP32 result */
+#define TTO_ST_NONFINITE 0x10u  /* set together with INVALID: the injections
+                                   (the grid's or the candidate's moved
+                                   amounts) hold a NaN or an infinity, so no
+                                   flow is defined; decided after the
+                                   encoding rules and the islanding test */
 
 typedef struct tto_grid tto_grid;   /* opaque host handle */
 
@@ -251,6 +256,9 @@ void tto_grid_destroy(tto_grid* grid);
  * generation positive; balancing is the caller's duty) and compute the base
  * flows f0 = PTDF * P with the MFMA GEMM in the grid's GEMM precision.
  * Asynchronous on `stream`; p_mw may be freed once the stream has passed.
+ * Non-finite entries are not rejected here (that would need a host
+ * synchronisation): every connected, encodable candidate evaluated under
+ * them gets status INVALID | NONFINITE and never enters the repertoire.
  */
 tto_status tto_set_injections(tto_grid* grid, const double* p_mw, void* stream);
 

@@ -22,6 +22,8 @@ from scipy.sparse import csgraph
 from .metrics import n1_metrics, fitness_f1, descriptor_cell, descriptor_cell_paper
 
 MAX_RANK = 8
+# Encoding limit: moved branches summed over one candidate's splits.
+MAX_MOVED = 64
 # Worst contingency reading: flows within this many MW of the maximum at
 # (e*, t*) count as tied and the order of the contingency list decides
 # (branches that no outage affects, such as bridges, tie exactly).
@@ -56,10 +58,14 @@ def validate_candidate(n_bus: int, from_bus, to_bus, cand: Candidate) -> bool:
     Valid iff: opened ids in range and distinct; split buses in range and
     distinct; every split moves a non-empty list of distinct branches that are
     incident to its bus; no moved branch is also opened; rank (filled slots)
-    at most 8.
+    at most 8; at most 64 moved branches over all splits.  (Genome of the
+    Repertoire design section: distinct substations, distinct branches.)  A
+    branch may be moved by the splits at both of its ends.
     """
     m = len(from_bus)
     if len(cand.opened) + len(cand.splits) > MAX_RANK:
+        return False
+    if sum(len(mv) for _, mv in cand.splits) > MAX_MOVED:
         return False
     if any(e < 0 or e >= m for e in cand.opened):
         return False
@@ -125,7 +131,12 @@ def post_switch_network(n_bus: int, from_bus, to_bus, b, slack: int, P: np.ndarr
 
 def is_connected(n_node: int, fr, to, in_service) -> bool:
     """True iff the in-service branches join all nodes into one component
-    (library connected-components routine on the undirected graph)."""
+    (library connected-components routine on the undirected graph).
+
+    Islanding is a property of the post-switch graph over every node (the
+    buses and the split buses' busbars B): a node left without an in-service
+    branch is an island of its own whatever its injection, as the paper's
+    importer decides islands from the graph (bridges) alone."""
     idx = np.flatnonzero(in_service)
     if n_node <= 1:
         return True
@@ -171,6 +182,7 @@ class CandidateResult:
     fitness: float = float("-inf")
     cell: int = -1
     n_switched: int = 0
+    nonfinite: bool = False
 
 
 def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], cand: Candidate,
@@ -189,6 +201,11 @@ def evaluate_candidate(grid, P: np.ndarray, M: Sequence[int], C: Sequence[int], 
     net = post_switch_network(grid.n_bus, grid.from_bus, grid.to_bus, b, grid.slack, P, cand)
     if not is_connected(net.n_node, net.fr, net.to, net.in_service):
         return CandidateResult(valid=True, islanded=True, n_switched=cand.n_slots_filled)
+    if not np.all(np.isfinite(net.P)):
+        # a NaN or infinite injection (the grid's or a moved amount): no flow
+        # is defined; decided after the encoding rules and the islanding test
+        return CandidateResult(valid=False, islanded=False, nonfinite=True,
+                               n_switched=cand.n_slots_filled)
     f0 = solve_flows(net.n_node, net.fr, net.to, net.b, net.in_service, net.P, net.slack)
     M = np.asarray(M, dtype=np.int64)
     C = np.asarray(C, dtype=np.int64)
@@ -260,8 +277,17 @@ def _eval_one(args):
     return evaluate_candidate(grid, P, M, C, cand, edges, **kw)
 
 
+def _one_thread_per_worker():
+    """Pool initializer: each worker process runs its library calls (sparse LU,
+    BLAS) on one thread, so that P workers use P cores, not P x cores."""
+    from threadpoolctl import threadpool_limits
+    global _WORKER_LIMITS
+    _WORKER_LIMITS = threadpool_limits(1)
+
+
 def evaluate_batch(grid, P, M, C, batch, load_edges, idx=None, processes: int = 1, **kw):
-    """Evaluate candidates (optionally a subset idx) with a process pool."""
+    """Evaluate candidates (optionally a subset idx), one candidate per task
+    of a pool of single-threaded worker processes."""
     if idx is None:
         idx = range(batch.n_cand)
     cands = [candidate_from_batch(batch, int(c)) for c in idx]
@@ -270,7 +296,7 @@ def evaluate_batch(grid, P, M, C, batch, load_edges, idx=None, processes: int = 
         return [_eval_one(j) for j in jobs]
     import multiprocessing as mp
     ctx = mp.get_context("fork")
-    with ctx.Pool(processes) as pool:
+    with ctx.Pool(processes, initializer=_one_thread_per_worker) as pool:
         return pool.map(_eval_one, jobs, chunksize=1)
 
 

@@ -4,4 +4,4 @@ the C ABI in include/tto.h; ``paper_2605_10128_amd.tto`` is its ctypes
 binding.  Submodules are imported lazily so that building does not need the
 library to exist yet."""
 
-__all__ = ["tto", "ptdf", "build"]
+__all__ = ["tto", "screen", "build"]

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   __shared__ SetupShared sh;
   __shared__ double s_x[kMaxRank][TT];
   __shared__ int s_wcnt[4];
-  __shared__ int s_base, s_n0, s_nisl;
+  __shared__ int s_base, s_n0, s_nisl, s_bad;
   __shared__ F s_stage[4][64][17];   // record staging, one slab per wave
 
   // -- genome parse in stages: slot values, ranges, moved-branch data, checks
@@ -196,6 +196,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     s_base = 0;
     s_n0 = 0;
     s_nisl = 0;
+    s_bad = 0;
   }
   __syncthreads();
   {
@@ -349,8 +350,14 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
       x[q] = v;
     }
     if (t < T) lu_solve(sh.M, sh.piv, r, x);
+    // a non-finite moved injection reaches x(t) (NaN times 0 stays NaN)
+    bool bad = false;
 #pragma unroll
-    for (int q = 0; q < kMaxRank; ++q) s_x[q][t] = (t < T) ? x[q] : 0.0;
+    for (int q = 0; q < kMaxRank; ++q) {
+      s_x[q][t] = (t < T) ? x[q] : 0.0;
+      bad |= (t < T) && !isfinite(x[q]);
+    }
+    if (bad) atomicAdd(&s_bad, 1);
   }
   __syncthreads();
 
@@ -371,8 +378,10 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     }
   };
 
-  // monitored rows: f'_M and U_M
-  int n0 = 0;
+  // monitored rows: f'_M and U_M.  A non-finite grid injection makes every
+  // base flow non-finite (the product with a zero PTDF entry included), so
+  // the monitored rows' f0 see it.
+  int n0 = 0, nbad = 0;
   for (int ei = tid; ei < nM; ei += 256) {
     keep_in_loop();
     const int e = g.mon[ei];
@@ -383,6 +392,8 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     double f0e[TT];
 #pragma unroll
     for (int t = 0; t < TT; ++t) f0e[t] = t < T ? g.f0[(size_t)e * T + t] : 0.0;
+#pragma unroll
+    for (int t = 0; t < TT; ++t) nbad += !isfinite(f0e[t]);
     const double be = g.b[e], lim = g.lim[e];
     double W[kMaxRank], U[kMaxRank];
     gather_column(g.SMC, nMC, ei, sh, W);
@@ -404,6 +415,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     for (int q = 0; q < kVSlots; ++q) uo[(size_t)q * nM] = opened ? (F)0 : (F)U[q];
   }
   if (n0) atomicAdd(&s_n0, n0);
+  if (nbad) atomicAdd(&s_bad, nbad);
 
   // optional full post-switch base flows
   if (base_out) {
@@ -547,7 +559,13 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     for (int q = tid; q < RS; q += 256) dst[q] = src[q];
     if (tid == 0) act[n_act] = act[n_act - 1];
   }
-  if (tid == 0) {
+  if (tid == 0 && s_bad) {
+    // non-finite injections: no metric is defined, the candidate is skipped
+    inf->status = TTO_ST_INVALID | TTO_ST_NONFINITE;
+    inf->r = r; inf->k = k; inf->n_act = 0; inf->n_act_pad = 0; inf->n_island = 0;
+    inf->n_moved = sh.moff[ns];
+    inf->n_crit_n0 = 0;
+  } else if (tid == 0) {
     inf->status = 0;
     inf->r = r;
     inf->k = k;

@@ -5,8 +5,11 @@ A generation of candidates is scored by the surrogate network
 (tto_topk_smallest over the predicted overload), compacted into a batch
 (tto_batch_gather) and only those are evaluated exactly (tto_evaluate) and
 offered to the archive.  The network is trained on exact evaluations the DC
-evaluator itself produces.  Every numerical step runs in the library's
-kernels; this module only moves arrays and chains the calls.
+evaluator itself produces.  The network's forward and backward passes, the
+optimiser, the selection, the gather and the evaluation run in the library's
+kernels; the data preparation around them (the injection summary, the
+training targets taken from exact outputs and their standardisation) is host
+NumPy in this module.
 
 The paper scores every mutated candidate exactly (DC-Optimizer section);
 the screen is an addition for large generations.  Feature encoding: one bit

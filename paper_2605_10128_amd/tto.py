@@ -20,6 +20,7 @@ TTO_FLOW_F64, TTO_FLOW_F32 = 0, 1
 TTO_GEMM_F64, TTO_GEMM_F32, TTO_GEMM_BF16, TTO_GEMM_F16 = 0, 1, 2, 3
 TTO_GEMM_BF16X3, TTO_GEMM_F16X3 = 4, 5
 TTO_ST_ISLANDED, TTO_ST_INVALID, TTO_ST_REFINED, TTO_ST_REFINE_SKIPPED = 1, 2, 4, 8
+TTO_ST_NONFINITE = 0x10
 TTO_MAX_RANK, TTO_MAX_T, TTO_MAX_MOVED, TTO_MAX_LOAD_BINS = 8, 32, 64, 64
 
 _vp = ct.c_void_p

@@ -1,0 +1,218 @@
+"""Element-wise oracle parity of whole launches against the stored oracle
+fixtures (written by tests/golden/make_fixtures.py, which calls only the
+oracle): the benchmarked launch (2000 buses, T = 24, 16384 candidates, 1200
+monitored x 1600 contingencies, FP32 flows, the benchmark's sweep plan), the
+500-bus batch (all 4096 candidates, FP64 and FP32 flows) and the 6000-bus
+precision grid (every GEMM mode's f^max against the oracle's).
+
+Per candidate (Fitness function heuristics): status, count of islanding
+contingencies, f^max element by element within the flow tolerance, lambda_o,
+lambda_c, lambda_c0, max loading, the arg-max (e*, t*, l*), fitness and cell.
+A discrete output must equal the oracle's unless the oracle's own FP64 value
+lies within the decision tolerance of its threshold (the fixture stores that
+distance); there the device value must be one of the answers valid within
+that tolerance.  The FP32 path takes its load-bin, arg-max and worst-
+contingency decisions in FP64 by refinement, so those are compared at FP64
+size; lambda_c and lambda_c0 are compared at the flow tolerance.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gridgen as gg
+from parity_util import TOL_F32, TOL_F64, log, make_session, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DEC_F64 = 1e-6      # FP64 decision size: device FP64 flows agree with the oracle far below it
+
+
+def _fixture(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing oracle fixture {path} (python tests/golden/make_fixtures.py)")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+@pytest.fixture(scope="module")
+def tto():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_10128_amd import tto as t
+    return t
+
+
+def check(fx, i, o, c, w, tol, dec, fmax=None, fmax_tol=None):
+    """Candidate c of device outputs o against fixture row i.  tol: flow
+    tolerance (MW) for values and the critical counts; dec: decision size
+    (MW) for the refined decisions (load bin, arg-max, worst contingency)."""
+    lim = w.grid.limit_mw[w.M]
+    st = int(o["status"][c])
+    if not fx["valid"][i]:
+        assert st & 2, (c, st)
+        return "invalid"
+    if fx["islanded"][i]:
+        assert st & 1, (c, st)
+        assert o["cell"][c] == -1 and o["fitness"][c] == -np.inf, c
+        return "islanded"
+    assert st & 3 == 0, (c, st)
+    assert o["n_island_cont"][c] == fx["n_island_cont"][i], c
+    near = []
+    # lambda_c0 (FP64 post-switch flows on every path)
+    if fx["margin0"][i] > tol:
+        assert o["n_crit_n0"][c] == fx["n_crit_n0"][i], c
+    else:
+        near.append("c0")
+        assert abs(int(o["n_crit_n0"][c]) - int(fx["n_crit_n0"][i])) <= 1, c
+    # lambda_o, lambda_c from f^max (oracle f^max stored in FP32, far inside tol)
+    fm = fx["fmax"][i].astype(np.float64) if i < len(fx["fmax"]) else None
+    if fm is not None and not np.isnan(fm).any():
+        n_over = int((fm > lim[:, None] - tol).sum())
+        lo = int((fm > lim[:, None] + tol).sum())
+        assert lo <= o["n_crit_n1"][c] <= n_over, (c, lo, n_over, o["n_crit_n1"][c])
+        if lo == n_over:
+            assert o["n_crit_n1"][c] == fx["n_crit_n1"][i], c
+        else:
+            near.append("c")
+    else:
+        n_over = int(fx["n_crit_n1"][i]) + 64
+    assert abs(o["overload_mw"][c] - fx["overload_mw"][i]) <= tol * (n_over + 1), c
+    assert abs(o["max_loading"][c] - fx["max_loading"][i]) <= tol / lim.min() + 1e-12, c
+    # arg-max (e*, t*)
+    if fx["gap"][i] > 2 * dec / lim.min():
+        assert o["worst_branch"][c] == fx["worst_branch"][i], c
+        assert o["worst_t"][c] == fx["worst_t"][i], c
+        same_et = True
+    else:
+        near.append("et")
+        same_et = (o["worst_branch"][c] == fx["worst_branch"][i] and
+                   o["worst_t"][c] == fx["worst_t"][i])
+        if fm is not None:
+            e_pos = int(np.flatnonzero(w.M == o["worst_branch"][c])[0])
+            r = fm / lim[:, None]
+            assert r[e_pos, o["worst_t"][c]] >= r.max() - 2 * dec / lim.min() - 1e-9, c
+    # worst contingency l*
+    if same_et and fx["cut_dist"][i] > 2 * dec:
+        assert o["worst_cont"][c] == fx["worst_cont"][i], c
+    else:
+        near.append("l")
+        if same_et and "worst_col" in fx:
+            col = np.where(np.isnan(fx["worst_col"][i]), -np.inf, fx["worst_col"][i])
+            cut = col.max() - 0.05
+            l_pos = int(np.flatnonzero(w.C == o["worst_cont"][c])[0])
+            assert col[l_pos] >= cut - 2 * dec, c
+            assert np.all(col[:l_pos] < cut + 2 * dec), c
+    # fitness and cell
+    d_c = abs(int(o["n_crit_n1"][c]) - int(fx["n_crit_n1"][i]))
+    d_c0 = abs(int(o["n_crit_n0"][c]) - int(fx["n_crit_n0"][i]))
+    fit_tol = tol * (n_over + 1) + 50.0 * d_c + 200.0 * d_c0 + 1e-9
+    assert abs(o["fitness"][c] - fx["fitness"][i]) <= fit_tol, (c, o["fitness"][c], fx["fitness"][i])
+    if fx["edge_dist"][i] > dec / lim.min():
+        assert o["cell"][c] == fx["cell"][i], c
+    else:
+        near.append("cell")
+        assert o["cell"][c] // 32 == fx["cell"][i] // 32, c
+    if fmax is not None and fm is not None:
+        np.testing.assert_allclose(fmax, fm, atol=fmax_tol, rtol=0, err_msg=f"fmax cand {c}")
+    return "near:" + ",".join(near) if near else "exact"
+
+
+def _summary(kinds):
+    out = {}
+    for k in kinds:
+        out[k] = out.get(k, 0) + 1
+    return out
+
+
+def test_benchmarked_launch_against_oracle_fixtures(tto):
+    """The benchmark's launch: 16384 candidates in one tto_evaluate, FP32 flows,
+    default refinement, 256-lane tiles in the XCD-grouped order.  Seventeen
+    candidates (rank 0..8, with and without splits) element by element; a
+    second launch that also writes f^max must reproduce every output of the
+    first bit for bit and match the oracle's f^max within 1e-2 MW."""
+    import torch
+    fx = _fixture("oracle_batch_2000bus.npz")
+    w = gg.build_config(3)
+    B = w.batch.n_cand
+    assert B == 16384
+    s = make_session(w, tto.TTO_FLOW_F32, max_batch=B)
+    s.set_sweep_plan(256, 1, False)
+    db = tto.device_batch(w.batch)
+    o = to_numpy(s.evaluate(db))
+    o2 = to_numpy(s.evaluate(db, fmax=True))
+    torch.cuda.synchronize()
+    for k in o:
+        np.testing.assert_array_equal(o[k], o2[k], err_msg=f"{k}: launch with f^max differs")
+    kinds = []
+    worst = 0.0
+    for i, c in enumerate(fx["idx"].tolist()):
+        kinds.append(check(fx, i, o, c, w, TOL_F32, DEC_F64, fmax=o2["fmax"][c], fmax_tol=TOL_F32))
+        if fx["valid"][i] and not fx["islanded"][i]:
+            worst = max(worst, float(np.abs(o2["fmax"][c] - fx["fmax"][i]).max()))
+    log(f"[fixtures] benchmarked launch: {len(kinds)} candidates {_summary(kinds)}; "
+        f"f^max max error {worst:.3e} MW; refined {int(((o['status'] & 4) != 0).sum())}")
+    assert sum(k.startswith(("exact", "near")) for k in kinds) >= 14
+    s.close()
+
+
+@pytest.mark.parametrize("flow", ["f64", "f32"])
+def test_plain_batch_every_candidate_against_oracle(tto, flow):
+    """All 4096 candidates of the 500-bus batch (1-4 openings, 0-2 splits, N-1
+    over all 800 branches) in one launch; f^max element-wise for the first 64."""
+    import torch
+    fx = _fixture("oracle_plain_500bus.npz")
+    w = gg.build_config(2)
+    fl = tto.TTO_FLOW_F64 if flow == "f64" else tto.TTO_FLOW_F32
+    tol = TOL_F64 if flow == "f64" else TOL_F32
+    s = make_session(w, fl, max_batch=w.batch.n_cand)
+    o = to_numpy(s.evaluate(tto.device_batch(w.batch), fmax=True))
+    torch.cuda.synchronize()
+    assert np.array_equal(fx["idx"], np.arange(w.batch.n_cand))
+    kinds = []
+    for i in range(w.batch.n_cand):
+        fmx = o["fmax"][i] if i < len(fx["fmax"]) else None
+        kinds.append(check(fx, i, o, i, w, tol, DEC_F64 if flow == "f32" else tol,
+                           fmax=fmx, fmax_tol=tol))
+    summ = _summary(kinds)
+    log(f"[fixtures] 500-bus batch {flow}: {summ}; refined "
+        f"{int(((o['status'] & 4) != 0).sum())}")
+    assert summ.get("exact", 0) >= 0.5 * w.batch.n_cand
+    s.close()
+
+
+def test_precision_grid_every_gemm_mode_against_oracle(tto):
+    """6000 buses, T = 24, 2000 monitored x 3000 contingencies: four candidates
+    (ranks 2, 4, 6, 8 with splits), f^max of every flow/GEMM mode against the
+    oracle's, errors in MW (max, p99); FP64 flows and the FP32-accurate modes
+    also match every discrete output."""
+    import torch
+    fx = _fixture("oracle_precision_6000bus.npz")
+    w = gg.build_config(4)
+    idx = fx["idx"].tolist()
+    sub = w.batch.subset(idx)
+    ws = gg.Workload(cfg=4, grid=w.grid, P=w.P, M=w.M, C=w.C, batch=sub, split_table=w.split_table)
+    modes = [("f64", tto.TTO_FLOW_F64, tto.TTO_GEMM_F64, TOL_F64, True),
+             ("f32", tto.TTO_FLOW_F32, tto.TTO_GEMM_F32, TOL_F32, True),
+             ("bf16x3", tto.TTO_FLOW_F32, tto.TTO_GEMM_BF16X3, 0.1, True),
+             ("f16x3", tto.TTO_FLOW_F32, tto.TTO_GEMM_F16X3, 0.1, True),
+             ("f16", tto.TTO_FLOW_F32, tto.TTO_GEMM_F16, 5.0, False),
+             ("bf16", tto.TTO_FLOW_F32, tto.TTO_GEMM_BF16, 30.0, False)]
+    ok = [i for i in range(len(idx)) if fx["valid"][i] and not fx["islanded"][i]]
+    assert len(ok) >= 3
+    for name, fl, gm, bound, discrete in modes:
+        s = make_session(ws, fl, gm, max_batch=len(idx))
+        o = to_numpy(s.evaluate(tto.device_batch(sub), fmax=True))
+        torch.cuda.synchronize()
+        d = np.concatenate([np.abs(o["fmax"][i] - fx["fmax"][i]).ravel() for i in ok])
+        log(f"[fixtures] 6000-bus {name}: f^max vs oracle max {d.max():.3e} MW, "
+            f"p99 {np.quantile(d, 0.99):.3e} MW over {len(ok)} candidates")
+        assert d.max() <= bound, name
+        if discrete:
+            kinds = [check(fx, i, o, i, ws, max(bound, TOL_F64), DEC_F64 if fl else TOL_F64)
+                     for i in range(len(idx))]
+            log(f"[fixtures] 6000-bus {name}: {_summary(kinds)}")
+        s.close()
