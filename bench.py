@@ -465,7 +465,8 @@ def main():
     ap.add_argument("--flow", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default="auto",
-                    help="sweep plan 'auto' (autotune) or 'block,xcd,persistent', e.g. 64,1,0")
+                    help="sweep plan 'auto' (autotune) or 'lanes,branches_per_lane,order,persistent', "
+                         "e.g. 256,2,1,0")
     ap.add_argument("--sweep-plans", action="store_true",
                     help="also report the sweep time of every plan (stderr)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay check")
@@ -528,21 +529,25 @@ def main():
     log(f"[bench] grid ready; ws grid {s.grid_bytes/2**30:.2f} GiB batch {s.batch_bytes/2**30:.2f} GiB")
     if args.sweep_plans:
         tto.tto_profile_enable(s.handle, True)
-        for plan in [(256, 0, 0), (256, 1, 0), (256, 2, 0)]:
-            s.set_sweep_plan(*plan)
-            ts = []
-            for _ in range(3):
-                s.evaluate(db, out)
-                ts.append(tto.tto_profile_read(s.handle)[1])
-            log(f"[bench] plan block={plan[0]} xcd={plan[1]} persistent={plan[2]}: "
-                f"sweep {sorted(ts)[1]:.3f} ms")
+        for npl in (1, 2):
+            for lanes in (64, 128, 256):
+                for order in (0, 1, 2):
+                    for pers in ((False, True) if order == 0 else (False,)):
+                        s.set_sweep_plan(lanes, npl, order, pers)
+                        ts = []
+                        for _ in range(3):
+                            s.evaluate(db, out)
+                            ts.append(tto.tto_profile_read(s.handle)[1])
+                        log(f"[bench] plan lanes={lanes} npl={npl} order={order} "
+                            f"persistent={int(pers)}: sweep {sorted(ts)[1]:.3f} ms")
         tto.tto_profile_enable(s.handle, False)
     if args.plan == "auto":
         chosen = s.autotune(db, out)   # untimed: picks the sweep launch shape
     else:
-        bs, x, p = (int(v) for v in args.plan.split(","))
-        s.set_sweep_plan(bs, bool(x), bool(p))
-        chosen = {"block": bs, "xcd_group": bool(x), "persistent": bool(p), "from_cache": False}
+        lanes, npl, order, p = (int(v) for v in args.plan.split(","))
+        s.set_sweep_plan(lanes, npl, order, bool(p))
+        chosen = {"lanes": lanes, "branches_per_lane": npl, "order": order, "persistent": bool(p),
+                  "from_cache": False}
     log(f"[bench] sweep plan {chosen}")
 
     for i in range(args.warmup):
@@ -624,7 +629,8 @@ def main():
                         f"|M|={len(w.M)}, |C|={len(w.C)}, rank 0..8 (exact evaluation)",
             "flow_precision": args.flow,
             "candidates_ok": int(ok.sum()),
-            "sweep_plan": {k: chosen[k] for k in ("block", "xcd_group", "persistent")},
+            "sweep_plan": {k: chosen[k] for k in ("lanes", "branches_per_lane", "order",
+                                                  "persistent")},
             "launch": "eager (timed), graph replay checked",
             "graph_replay_ms_per_step": graph_ms,
             "islanded": int(((o["status"] & 1) != 0).sum()),

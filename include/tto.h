@@ -36,7 +36,7 @@ extern "C" {
 #endif
 
 #define TTO_VERSION_MAJOR 1
-#define TTO_VERSION_MINOR 0
+#define TTO_VERSION_MINOR 1
 
 #define TTO_MAX_RANK 8      /* openings + splits per candidate */
 #define TTO_MAX_T 32        /* timesteps per injection set */
@@ -304,21 +304,28 @@ tto_status tto_profile_enable(tto_grid* grid, int32_t enable);
 tto_status tto_profile_read(tto_grid* grid, double* ms);
 
 /*
- * Launch shape of the N-1 sweep (batching of uneven-rank candidates).  A
- * tile is one candidate x `block` monitored branches (64, 128 or 256 lanes).
- * xcd_group 1 deals the tiles of one candidate onto one XCD (shared L2 for
- * its contingency records); xcd_group 2 deals each XCD a contiguous range of
- * the monitored-block-major tile order (each XCD then streams one or two
- * column blocks of H[M, C] for many candidates); 0 uses the hardware's
- * round-robin order.  persistent != 0 launches a machine-sized grid
- * whose workgroups pull tiles from a counter in rank-descending candidate
- * order (longest tiles first).  Default: block 256, no grouping, not
- * persistent.  TTO_E_INVALID for other block sizes or xcd_group values;
- * TTO_E_UNSUPPORTED for
- * blocks 64/128 and for persistent != 0, which the library switches off.
+ * Launch shape of the N-1 sweep (batching of uneven-rank candidates in one
+ * launch).  The unit of work is one wave: a candidate and branches_per_lane
+ * consecutive chunks of 64 monitored branches (one lane per branch of each
+ * chunk, every timestep in registers); waves share no memory and never wait
+ * on each other, and each candidate's rank fixes its wave's loop.
+ *   lanes              workgroup size 64, 128 or 256 (1, 2 or 4 waves)
+ *   branches_per_lane  1 or 2 (2: each contingency record read by a wave
+ *                      feeds two branches; FP32 flows only)
+ *   order              0: hardware order of the work items; 1: each XCD
+ *                      takes a contiguous candidate-major range (a
+ *                      candidate's waves share its records in one L2); 2:
+ *                      chunk-major ranges (an XCD streams few column blocks
+ *                      of H[M, C] across many candidates)
+ *   persistent         1: a machine-sized grid whose waves pull work items
+ *                      from a counter in rank-descending candidate order
+ *                      (order is then ignored)
+ * Every plan gives bitwise the same outputs.  Default 256, 1, 0, 0.
+ * TTO_E_INVALID for values out of range, TTO_E_UNSUPPORTED for 2 branches
+ * per lane on an FP64 grid.
  */
-tto_status tto_set_sweep_plan(tto_grid* grid, int32_t block, int32_t xcd_group,
-                              int32_t persistent);
+tto_status tto_set_sweep_plan(tto_grid* grid, int32_t lanes, int32_t branches_per_lane,
+                              int32_t order, int32_t persistent);
 
 /*
  * FP64 refinement of FP32-flow grids (on by default, margin 8e-3 MW): after
@@ -333,16 +340,19 @@ tto_status tto_set_sweep_plan(tto_grid* grid, int32_t block, int32_t xcd_group,
  * FP64 grids.
  */
 tto_status tto_set_refine(tto_grid* grid, int32_t enable, double margin_mw);
-tto_status tto_get_sweep_plan(tto_grid* grid, int32_t* block, int32_t* xcd_group,
-                              int32_t* persistent);
+tto_status tto_get_sweep_plan(tto_grid* grid, int32_t* lanes, int32_t* branches_per_lane,
+                              int32_t* order, int32_t* persistent);
 
 /*
- * Autotuner: times every sweep plan on this batch (three tto_evaluate calls
- * each, median of the sweep stage by HIP events), keeps the fastest.  With a
- * non-empty cache_path, a line "<device> <shape>|<block> <xcd> <persistent>"
- * is looked up first (no timing when found) and appended after tuning.
- * chosen (optional, int32[4]) receives block, xcd, persistent and 1 if the
- * cache answered.  Synchronises `stream`; overwrites the outputs.
+ * Autotuner: times the sweep plans on this batch (three tto_evaluate calls
+ * each, median of the sweep stage by HIP events) and keeps the fastest.  The
+ * search covers workgroup sizes 64/128/256 x branches per lane 1/2 (2 on
+ * FP32 grids) x the three item orders, plus the persistent grid.  With a
+ * non-empty cache_path, a line "<device> <shape>|<lanes> <branches per lane>
+ * <order> <persistent>" is looked up first (no timing when found) and
+ * appended after tuning.  chosen (optional, int32[5]) receives lanes,
+ * branches per lane, order, persistent and 1 if the cache answered.
+ * Synchronises `stream`; overwrites the outputs.
  */
 tto_status tto_autotune(tto_grid* grid, const tto_batch* batch, const tto_outputs* out,
                         void* batch_ws, size_t batch_bytes, void* stream,

@@ -579,10 +579,14 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
 }
 
 // ---------------------------------------------------------------------------
-// N-1 sweep.  Thread = (candidate, monitored branch), all timesteps in
-// registers; contingencies are consumed in pairs so that the running maximum
-// takes one 3-input max per two flows.  Contingency records (phi, V) are
-// wave-uniform; the H row entries are per lane.
+// N-1 sweep.  The unit of work is one wave: a candidate and NP consecutive
+// chunks of 64 monitored branches (one lane per branch of each chunk, NP = 1
+// or 2 branches per lane), all timesteps in registers.  Contingencies are
+// consumed in pairs, so that the running maximum takes one 3-input max per
+// two flows.  The contingency records (phi_l(t), V_l) are wave-uniform
+// scalar loads, each feeding NP branches per lane; the H[M, C] entries are
+// per lane.  Waves share nothing (no LDS, no barrier): a workgroup is a
+// group of independent waves.
 __device__ inline float fabs_t(float v) { return fabsf(v); }
 __device__ inline double fabs_t(double v) { return fabs(v); }
 __device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -590,59 +594,99 @@ __device__ inline double fma_t(double a, double b, double c) { return __builtin_
 __device__ inline float max3_t(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
 __device__ inline double max3_t(double a, double b, double c) { return fmax(a, fmax(b, c)); }
 
-template <typename F, int TT, int R>
+// Contingency pairs [i0, i1) of candidate c for the lanes' monitored
+// positions ei[p] (p < NP, clamped into range): acc[p][t] = max |f^(l)|.
+template <typename F, int TT, int R, int NP>
 __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>& w,
-                                           const F* __restrict__ HMC, int c, int ei_c,
-                                           int i0, int n_act_pad, F* acc, F* a) {
+                                           const F* __restrict__ HMC, int c, const int* ei,
+                                           int i0, int i1, F (*acc)[TT]) {
   constexpr int RS = rec_stride(TT);
   const int nM = g.nM, nC = g.nC;
-  F U[R > 0 ? R : 1];
-  const F* fa = w.fM + (size_t)c * TT * nM + ei_c;
-  const F* ua = w.UM + (size_t)c * kVSlots * nM + ei_c;
+  F U[NP][R > 0 ? R : 1], a[NP][TT];
 #pragma unroll
-  for (int t = 0; t < TT; ++t) { a[t] = fa[(size_t)t * nM]; acc[t] = (F)0; }
+  for (int p = 0; p < NP; ++p) {
+    const F* fa = w.fM + (size_t)c * TT * nM + ei[p];
+    const F* ua = w.UM + (size_t)c * kVSlots * nM + ei[p];
 #pragma unroll
-  for (int j = 0; j < R; ++j) U[j] = ua[(size_t)j * nM];
+    for (int t = 0; t < TT; ++t) { a[p][t] = fa[(size_t)t * nM]; acc[p][t] = (F)0; }
+#pragma unroll
+    for (int j = 0; j < R; ++j) U[p][j] = ua[(size_t)j * nM];
+  }
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
-  if (n_act_pad <= i0) return;
+  if (i1 <= i0) return;
   // Software pipeline: the H entries of the next pair are in flight while the
   // current pair is consumed (the last prefetch re-reads an in-range pair).
-  F hn0 = HMC[(size_t)act[i0] * nM + ei_c];
-  F hn1 = HMC[(size_t)act[i0 + 1] * nM + ei_c];
-  for (int i = i0; i < n_act_pad; i += 2) {
-    F h0 = hn0, h1 = hn1;
-    const int nx = (i + 2 < n_act_pad) ? i + 2 : i;
-    hn0 = HMC[(size_t)act[nx] * nM + ei_c];
-    hn1 = HMC[(size_t)act[nx + 1] * nM + ei_c];
+  F hn0[NP], hn1[NP];
+  {
+    const size_t c0 = (size_t)act[i0] * nM, c1 = (size_t)act[i0 + 1] * nM;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) { hn0[p] = HMC[c0 + ei[p]]; hn1[p] = HMC[c1 + ei[p]]; }
+  }
+  for (int i = i0; i < i1; i += 2) {
+    F h0[NP], h1[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) { h0[p] = hn0[p]; h1[p] = hn1[p]; }
+    const int nx = (i + 2 < i1) ? i + 2 : i;
+    {
+      const size_t c0 = (size_t)act[nx] * nM, c1 = (size_t)act[nx + 1] * nM;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) { hn0[p] = HMC[c0 + ei[p]]; hn1[p] = HMC[c1 + ei[p]]; }
+    }
     const F* r0 = rec + (size_t)i * RS;
     const F* r1 = r0 + RS;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      h0 = fma_t(U[j], r0[TT + j], h0);
-      h1 = fma_t(U[j], r1[TT + j], h1);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        h0[p] = fma_t(U[p][j], r0[TT + j], h0[p]);
+        h1[p] = fma_t(U[p][j], r1[TT + j], h1[p]);
+      }
     }
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
-      const F g0 = fma_t(h0, r0[t], a[t]);
-      const F g1 = fma_t(h1, r1[t], a[t]);
-      acc[t] = max3_t(acc[t], fabs_t(g0), fabs_t(g1));
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const F g0 = fma_t(h0[p], r0[t], a[p][t]);
+        const F g1 = fma_t(h1[p], r1[t], a[p][t]);
+        acc[p][t] = max3_t(acc[p][t], fabs_t(g0), fabs_t(g1));
+      }
     }
   }
 }
 
-// Per-thread reduction over timesteps of a tile's f^max and the tile's
-// partial (sums, counts, top-2 loading, arg-max), shared by both sweeps.
-template <typename F, int TT, int BS>
-__device__ __forceinline__ void tile_epilogue(const GridDev& g, const SweepBufs<F>& w,
-                                              double* __restrict__ fmax_out, int c, int eb,
-                                              int oc, const F* acc) {
-  constexpr int NW = BS / 64;
+// Rank dispatch: the rank-r factor is a compile-time loop bound.
+template <typename F, int TT, int NP>
+__device__ __forceinline__ void sweep_rank(const GridDev& g, const SweepBufs<F>& w,
+                                           const F* __restrict__ HMC, int c, int r,
+                                           const int* ei, int i0, int i1, F (*acc)[TT]) {
+  switch (r) {
+    case 0: sweep_core<F, TT, 0, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    case 1: sweep_core<F, TT, 1, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    case 2: sweep_core<F, TT, 2, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    case 3: sweep_core<F, TT, 3, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    case 4: sweep_core<F, TT, 4, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    case 5: sweep_core<F, TT, 5, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    case 6: sweep_core<F, TT, 6, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    case 7: sweep_core<F, TT, 7, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+    default: sweep_core<F, TT, 8, NP>(g, w, HMC, c, ei, i0, i1, acc); break;
+  }
+}
+
+// Reduction of one 64-branch chunk of candidate c: f^max out (optional),
+// then over timesteps and lanes the chunk's overload sum, critical count,
+// top-2 loading and arg-max, written to part[c][chunk] by lane 0.  The wave
+// butterfly is fixed and the finalize kernel adds the chunks in increasing
+// order, so every launch shape gives bitwise the same outputs.
+template <typename F, int TT>
+__device__ __forceinline__ void chunk_epilogue(const GridDev& g, const SweepBufs<F>& w,
+                                               double* __restrict__ fmax_out, int c, int chunk,
+                                               int oc, const F* acc) {
   const CandInfo* inf = w.info + c;
   const int k = inf->k;
   const int nM = g.nM, T = g.T;
-  const int tid = threadIdx.x;
-  const int ei = eb * BS + tid;
+  const int lane = threadIdx.x & 63;
+  const int ei = chunk * 64 + lane;
   const bool valid = ei < nM;
   const int ei_c = valid ? ei : nM - 1;
   const int e = g.mon[ei_c];
@@ -667,9 +711,8 @@ __device__ __forceinline__ void tile_epilogue(const GridDev& g, const SweepBufs<
       }
     }
   }
-  // deterministic wave butterfly (every lane ends with the same values), then
-  // the waves of the tile in increasing monitored order; best2 tracks the
-  // runner-up loading for the near-tie test of the FP32 pass
+  // deterministic wave butterfly (every lane ends with the same values);
+  // best2 tracks the runner-up loading for the near-tie test of the FP32 pass
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     so += __shfl_xor(so, off);
@@ -681,165 +724,135 @@ __device__ __forceinline__ void tile_epilogue(const GridDev& g, const SweepBufs<
     best2 = fmax(fmax(best2, s2), lo);
     if (take) { best = b2; be = e2; bt = t2; }
   }
-  Partial* out = w.part + (size_t)c * w.n_eblk + eb;
-  if constexpr (NW == 1) {
-    if (tid == 0) {
-      Partial p;
-      p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
-      p.pad_ = 0;
-      *out = p;
-    }
-  } else {
-    __shared__ Partial s_p[NW];
-    if ((tid & 63) == 0) {
-      Partial p;
-      p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
-      p.pad_ = 0;
-      s_p[tid >> 6] = p;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      Partial p = s_p[0];
-      for (int q = 1; q < NW; ++q) {
-        p.sum_o += s_p[q].sum_o;
-        p.cnt_c += s_p[q].cnt_c;
-        const bool take = s_p[q].best > p.best;
-        p.best2 = fmax(fmax(p.best2, s_p[q].best2), take ? p.best : s_p[q].best);
-        if (take) { p.best = s_p[q].best; p.best_e = s_p[q].best_e; p.best_t = s_p[q].best_t; }
-      }
-      *out = p;
-    }
-    __syncthreads();
+  if (lane == 0) {
+    Partial p;
+    p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
+    p.pad_ = 0;
+    w.part[(size_t)c * w.n_eblk + chunk] = p;
   }
 }
 
-// Sweep launch.  Non-persistent: one workgroup per tile over a 1-D grid;
-// workgroups are dealt to the 8 XCDs round-robin, so with xcd grouping the
-// tiles of one candidate are remapped onto one XCD (its records then come
-// into one L2).  Persistent: a machine-sized grid pulls tiles from a counter
-// in rank-descending candidate order (longest tiles first).
-// One tile = one candidate x BS consecutive monitored branches (one lane
-// each).  Writes the tile's partial reduction.
-template <typename F, int TT, int BS>
-__device__ __forceinline__ void sweep_tile(const GridDev& g, const SweepBufs<F>& w,
+// One wave: candidate c, chunks [wb * NPL, wb * NPL + NPL) clipped to the
+// monitored set (a candidate's last wave may hold one chunk only).
+template <typename F, int TT, int NPL>
+__device__ __forceinline__ void sweep_wave(const GridDev& g, const SweepBufs<F>& w,
                                            const F* __restrict__ HMC,
-                                           double* __restrict__ fmax_out, int c, int eb,
-                                           int oc) {
-  constexpr int NW = BS / 64;
-  // The tile's candidate is uniform by construction on every launch path;
-  // stating it keeps the per-candidate pointers in scalar registers.
+                                           double* __restrict__ fmax_out, int c, int wb, int oc) {
+  // stated wave-uniform: the per-candidate pointers stay in scalar registers
+  // and the contingency loop stays a scalar loop (records through the scalar
+  // cache)
   c = __builtin_amdgcn_readfirstlane(c);
-  eb = __builtin_amdgcn_readfirstlane(eb);
+  wb = __builtin_amdgcn_readfirstlane(wb);
   oc = __builtin_amdgcn_readfirstlane(oc);
   const CandInfo* inf = w.info + c;
-  const int status = inf->status;
-  if (status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;   // uniform per tile
-  const int r = inf->r, k = inf->k, n_act_pad = inf->n_act_pad;
-  const int nM = g.nM, T = g.T;
-  const int tid = threadIdx.x;
-  const int ei = eb * BS + tid;
-  const bool valid = ei < nM;
-  const int ei_c = valid ? ei : nM - 1;
-  // waves lying wholly past the monitored set skip the sweep (uniform per wave)
-  const bool wave_live = eb * BS + (int)(tid & ~63) < nM;
-  // wave-uniform by construction; readfirstlane keeps the contingency loop a
-  // scalar loop (its records then load through the scalar cache)
-  const int n_pairs = __builtin_amdgcn_readfirstlane(wave_live ? n_act_pad : 0);
-  F acc[TT], a[TT];
-  switch (r) {
-    case 0: sweep_core<F, TT, 0>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    case 1: sweep_core<F, TT, 1>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    case 2: sweep_core<F, TT, 2>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    case 3: sweep_core<F, TT, 3>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    case 4: sweep_core<F, TT, 4>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    case 5: sweep_core<F, TT, 5>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    case 6: sweep_core<F, TT, 6>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    case 7: sweep_core<F, TT, 7>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
-    default: sweep_core<F, TT, 8>(g, w, HMC, c, ei_c, 0, n_pairs, acc, a); break;
+  if (inf->status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;   // uniform per wave
+  const int r = __builtin_amdgcn_readfirstlane(inf->r);
+  const int n_pairs = __builtin_amdgcn_readfirstlane(inf->n_act_pad);
+  const int nM = g.nM;
+  const int lane = threadIdx.x & 63;
+  const int ch0 = wb * NPL;
+  const int np = min(NPL, w.n_eblk - ch0);
+  int ei[NPL];
+#pragma unroll
+  for (int p = 0; p < NPL; ++p) ei[p] = min((ch0 + p) * 64 + lane, nM - 1);
+  F acc[NPL][TT];
+  if (NPL == 2 && np == 2) {
+    sweep_rank<F, TT, NPL>(g, w, HMC, c, r, ei, 0, n_pairs, acc);
+    chunk_epilogue<F, TT>(g, w, fmax_out, c, ch0, oc, acc[0]);
+    chunk_epilogue<F, TT>(g, w, fmax_out, c, ch0 + 1, oc, acc[NPL - 1]);
+  } else {
+    sweep_rank<F, TT, 1>(g, w, HMC, c, r, ei, 0, n_pairs, acc);
+    chunk_epilogue<F, TT>(g, w, fmax_out, c, ch0, oc, acc[0]);
   }
-  tile_epilogue<F, TT, BS>(g, w, fmax_out, c, eb, oc, acc);
 }
 
-template <typename F, int TT, int BS>
-__global__ __launch_bounds__(BS) void k_sweep(GridDev g, SweepBufs<F> w,
-                                              const F* __restrict__ HMC,
-                                              double* __restrict__ fmax_out, int n_cand, int xcd,
-                                              const int* __restrict__ map,
-                                              const int* __restrict__ live) {
+// Work item u of a sweep: (candidate, wave block) in the plan's order.
+__device__ __forceinline__ void sweep_item(int u, int nc, int n_wb, int order, int* c, int* wb) {
+  if (order == 2) { *wb = u / nc; *c = u - *wb * nc; }
+  else { *c = u / n_wb; *wb = u - *c * n_wb; }
+}
+
+// One wave per work item.  Workgroups are dealt to the 8 XCDs round-robin;
+// order != 0 remaps workgroup q so that each XCD takes a contiguous range of
+// the item order: order 1 candidate-major (the waves of a candidate share its
+// records in one L2), order 2 block-major (an XCD streams few column blocks
+// of H[M, C] for many candidates).  The grid is a multiple of 8.
+template <typename F, int TT, int NPL>
+__global__ __launch_bounds__(256) void k_sweep(GridDev g, SweepBufs<F> w,
+                                               const F* __restrict__ HMC,
+                                               double* __restrict__ fmax_out, int n_cand,
+                                               int order, const int* __restrict__ map,
+                                               const int* __restrict__ live) {
   int nc = n_cand;
   if (live) nc = min(*live, n_cand);
-  const int n_tiles = nc * w.n_eblk;
-  // Workgroup w runs on XCD w % 8.  xcd != 0: the 8 XCDs take contiguous
-  // ranges of the tile order.  xcd == 1 orders tiles candidate-major (the
-  // tiles of a candidate share its records in one L2); xcd == 2 orders them
-  // monitored-block-major (each XCD streams at most two column blocks of
-  // H[M, C] across many candidates, which then stay in its L2).
+  const int n_wb = (w.n_eblk + NPL - 1) / NPL;
+  const int wpg = (int)(blockDim.x >> 6);
   int q = blockIdx.x;
-  if (xcd) q = (q & 7) * (int)(gridDim.x >> 3) + (q >> 3);
-  if (q >= n_tiles) return;
-  int c, eb;
-  if (xcd == 2) { eb = q / nc; c = q - eb * nc; }
-  else { c = q / w.n_eblk; eb = q - c * w.n_eblk; }
-  sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, c, eb, map ? map[c] : c);
+  if (order) q = (q & 7) * (int)(gridDim.x >> 3) + (q >> 3);
+  const int u = q * wpg + (int)(threadIdx.x >> 6);
+  if (u >= nc * n_wb) return;   // uniform per wave
+  int c, wb;
+  sweep_item(u, nc, n_wb, order, &c, &wb);
+  sweep_wave<F, TT, NPL>(g, w, HMC, fmax_out, c, wb, map ? map[c] : c);
 }
 
-// Persistent variant: a machine-sized grid pulls rank-ordered tiles from a
-// counter until none are left (every wave reaches the exit).
-template <typename F, int TT, int BS>
-__global__ __launch_bounds__(BS) void k_sweep_persistent(GridDev g, SweepBufs<F> w,
-                                                         const F* __restrict__ HMC,
-                                                         double* __restrict__ fmax_out,
-                                                         int n_cand, int* __restrict__ counter,
-                                                         const int* __restrict__ order) {
-  const int n_tiles = n_cand * w.n_eblk;
-  __shared__ int s_q;
+// Persistent variant: a machine-sized grid whose waves each pull work items
+// from a counter (lane 0 increments it, the wave reads lane 0's ticket), in
+// rank-descending candidate order, until the items run out.  Waves never wait
+// on each other; every pull increments the counter, so every wave reaches the
+// exit after at most n_items + n_waves pulls in all.
+template <typename F, int TT, int NPL>
+__global__ __launch_bounds__(256) void k_sweep_pull(GridDev g, SweepBufs<F> w,
+                                                    const F* __restrict__ HMC,
+                                                    double* __restrict__ fmax_out, int n_cand,
+                                                    int* __restrict__ counter,
+                                                    const int* __restrict__ order) {
+  const int n_wb = (w.n_eblk + NPL - 1) / NPL;
+  const int n_items = n_cand * n_wb;
+  const int lane = threadIdx.x & 63;
   for (;;) {
-    if (threadIdx.x == 0) s_q = atomicAdd(counter, 1);
-    __syncthreads();
-    const int q = s_q;
-    __syncthreads();
-    if (q >= n_tiles) break;   // every wave of the grid reaches this exit
-    const int ci = q / w.n_eblk;
-    sweep_tile<F, TT, BS>(g, w, HMC, fmax_out, order[ci], q - ci * w.n_eblk, order[ci]);
+    int u = 0;
+    if (lane == 0) u = atomicAdd(counter, 1);
+    u = __builtin_amdgcn_readfirstlane(u);
+    if (u >= n_items) break;
+    const int ci = u / n_wb;
+    const int c = order[ci];
+    sweep_wave<F, TT, NPL>(g, w, HMC, fmax_out, c, u - ci * n_wb, c);
   }
 }
 
-// Stable rank-descending order of the candidates (invalid and islanded
-// last), by ballot compaction per rank; one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_rank_order(const CandInfo* __restrict__ info, int B,
-                                                     int* __restrict__ order) {
-  __shared__ int s_wc[16];
-  __shared__ int s_base;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) s_base = 0;
-  __syncthreads();
-  for (int key = kMaxRank; key >= -1; --key) {
-    for (int b0 = 0; b0 < B; b0 += 1024) {
-      const int c = b0 + tid;
-      bool take = false;
-      if (c < B) {
-        const bool bad = info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
-        take = (key == -1) ? bad : (!bad && info[c].r == key);
-      }
-      const unsigned long long mask = __ballot(take);
-      if (lane == 0) s_wc[wid] = __popcll(mask);
-      __syncthreads();
-      int off = s_base;
-      for (int q = 0; q < wid; ++q) off += s_wc[q];
-      off += __popcll(mask & ((1ull << lane) - 1ull));
-      if (take) order[off] = c;
-      __syncthreads();
-      if (tid == 0) {
-        int s = 0;
-        for (int q = 0; q < 16; ++q) s += s_wc[q];
-        s_base += s;
-      }
-      __syncthreads();
-    }
-  }
+// Rank-descending candidate order for the persistent sweep by counting sort
+// (three small launches; the order within a rank depends on scheduling, which
+// changes only which wave does an item, never a result).  cnt[0..10]: the
+// ten rank classes (8 down to 0, then islanded/invalid), cnt[11..21] their
+// running slots.
+__global__ __launch_bounds__(256) void k_rank_count(const CandInfo* __restrict__ info, int B,
+                                                    int* __restrict__ cnt) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= B) return;
+  const bool bad = info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
+  atomicAdd(&cnt[bad ? 9 : kMaxRank - info[c].r], 1);
 }
 
-__global__ void k_zero_int(int* p) { *p = 0; }
+__global__ void k_rank_offsets(int* __restrict__ cnt) {
+  if (threadIdx.x != 0) return;
+  int s = 0;
+  for (int k = 0; k < 10; ++k) { cnt[11 + k] = s; s += cnt[k]; }
+}
+
+__global__ __launch_bounds__(256) void k_rank_place(const CandInfo* __restrict__ info, int B,
+                                                    int* __restrict__ cnt,
+                                                    int* __restrict__ order) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= B) return;
+  const bool bad = info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
+  order[atomicAdd(&cnt[11 + (bad ? 9 : kMaxRank - info[c].r)], 1)] = c;
+}
+
+// Counter block of the persistent sweep cleared by a kernel (graph-safe).
+__global__ void k_zero_ints(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
 
 // ---------------------------------------------------------------------------
 // Finalize one candidate per wave.  Main pass: outputs at index c.  FP64
@@ -1033,11 +1046,11 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
 
 // ---------------------------------------------------------------------------
 // FP64 refinement sweep, split over contingency ranges so that a handful of
-// queued candidates still fill the machine: workgroup (candidate, monitored
-// block, range s of S) merges the f^max of its range into fbuf by an atomic
-// max on the bit patterns (the values are >= 0, so the integer order is the
-// numeric order: order-free and exact); k_sweep_split_epi then runs the usual
-// tile epilogue on the merged maxima.
+// queued candidates still fill the machine: wave (candidate, 64-branch chunk,
+// range s of S) merges the f^max of its range into fbuf by an atomic max on
+// the bit patterns (the values are >= 0, so the integer order is the numeric
+// order: order-free and exact); k_sweep_split_epi then runs the chunk
+// epilogue on the merged maxima.
 __global__ __launch_bounds__(256) void k_zero_live_u64(unsigned long long* __restrict__ p,
                                                        const int* __restrict__ live, int cap,
                                                        size_t per) {
@@ -1046,87 +1059,94 @@ __global__ __launch_bounds__(256) void k_zero_live_u64(unsigned long long* __res
     p[i] = 0ull;
 }
 
-template <int TT, int BS>
-__global__ __launch_bounds__(BS) void k_sweep_split(GridDev g, SweepBufs<double> w,
-                                                    const double* __restrict__ HMC, int n_cand,
-                                                    int S, const int* __restrict__ live,
-                                                    unsigned long long* __restrict__ fbuf) {
+template <int TT>
+__global__ __launch_bounds__(256) void k_sweep_split(GridDev g, SweepBufs<double> w,
+                                                     const double* __restrict__ HMC, int n_cand,
+                                                     int S, const int* __restrict__ live,
+                                                     unsigned long long* __restrict__ fbuf) {
   const int nc = min(*live, n_cand);
-  int q = blockIdx.x;
-  if (q >= nc * w.n_eblk * S) return;
-  const int sr = __builtin_amdgcn_readfirstlane(q % S);
-  q /= S;
-  const int c = __builtin_amdgcn_readfirstlane(q / w.n_eblk);
-  const int eb = __builtin_amdgcn_readfirstlane(q - c * w.n_eblk);
+  int u = blockIdx.x * 4 + (int)(threadIdx.x >> 6);   // one wave per (range, chunk, candidate)
+  if (u >= nc * w.n_eblk * S) return;
+  const int sr = __builtin_amdgcn_readfirstlane(u % S);
+  u /= S;
+  const int c = __builtin_amdgcn_readfirstlane(u / w.n_eblk);
+  const int chunk = __builtin_amdgcn_readfirstlane(u - c * w.n_eblk);
   const CandInfo* inf = w.info + c;
   if (inf->status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;
   const int r = inf->r, n_act_pad = inf->n_act_pad, nM = g.nM;
   const int per = ((n_act_pad >> 1) + S - 1) / S;       // pairs per range
-  const int i0 = 2 * sr * per;
-  const int i1 = min(n_act_pad, 2 * (sr + 1) * per);
-  const int tid = threadIdx.x;
-  const int ei = eb * BS + tid;
+  const int i0 = __builtin_amdgcn_readfirstlane(2 * sr * per);
+  const int i1 = __builtin_amdgcn_readfirstlane(min(n_act_pad, 2 * (sr + 1) * per));
+  const int ei = chunk * 64 + (int)(threadIdx.x & 63);
   const bool valid = ei < nM;
-  const int ei_c = valid ? ei : nM - 1;
-  const bool wave_live = eb * BS + (int)(tid & ~63) < nM;
-  const int end = __builtin_amdgcn_readfirstlane(wave_live ? i1 : 0);
-  double acc[TT], a[TT];
-  switch (r) {
-    case 0: sweep_core<double, TT, 0>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    case 1: sweep_core<double, TT, 1>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    case 2: sweep_core<double, TT, 2>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    case 3: sweep_core<double, TT, 3>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    case 4: sweep_core<double, TT, 4>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    case 5: sweep_core<double, TT, 5>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    case 6: sweep_core<double, TT, 6>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    case 7: sweep_core<double, TT, 7>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-    default: sweep_core<double, TT, 8>(g, w, HMC, c, ei_c, i0, end, acc, a); break;
-  }
+  const int ei_c[1] = {valid ? ei : nM - 1};
+  double acc[1][TT];
+  sweep_rank<double, TT, 1>(g, w, HMC, c, r, ei_c, i0, i1, acc);
   if (valid && i0 < i1) {
     unsigned long long* out = fbuf + (size_t)c * TT * nM + ei;
 #pragma unroll
     for (int t = 0; t < TT; ++t)
-      atomicMax(out + (size_t)t * nM, (unsigned long long)__double_as_longlong(acc[t]));
+      atomicMax(out + (size_t)t * nM, (unsigned long long)__double_as_longlong(acc[0][t]));
   }
 }
 
-template <int TT, int BS>
-__global__ __launch_bounds__(BS) void k_sweep_split_epi(GridDev g, SweepBufs<double> w,
-                                                        double* __restrict__ fmax_out,
-                                                        int n_cand, const int* __restrict__ map,
-                                                        const int* __restrict__ live,
-                                                        const unsigned long long* __restrict__ fbuf) {
+template <int TT>
+__global__ __launch_bounds__(256) void k_sweep_split_epi(GridDev g, SweepBufs<double> w,
+                                                         double* __restrict__ fmax_out,
+                                                         int n_cand, const int* __restrict__ map,
+                                                         const int* __restrict__ live,
+                                                         const unsigned long long* __restrict__ fbuf) {
   const int nc = min(*live, n_cand);
-  const int q = blockIdx.x;
-  if (q >= nc * w.n_eblk) return;
-  const int c = __builtin_amdgcn_readfirstlane(q / w.n_eblk);
-  const int eb = __builtin_amdgcn_readfirstlane(q - c * w.n_eblk);
+  const int u = blockIdx.x * 4 + (int)(threadIdx.x >> 6);   // one wave per (candidate, chunk)
+  if (u >= nc * w.n_eblk) return;
+  const int c = __builtin_amdgcn_readfirstlane(u / w.n_eblk);
+  const int chunk = __builtin_amdgcn_readfirstlane(u - c * w.n_eblk);
   const int oc = __builtin_amdgcn_readfirstlane(map[c]);
   if (w.info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID)) return;
   const int nM = g.nM;
-  const int ei_c = min(eb * BS + (int)threadIdx.x, nM - 1);
+  const int ei_c = min(chunk * 64 + (int)(threadIdx.x & 63), nM - 1);
   const unsigned long long* in = fbuf + (size_t)c * TT * nM + ei_c;
   double acc[TT];
 #pragma unroll
   for (int t = 0; t < TT; ++t) acc[t] = __longlong_as_double((long long)in[(size_t)t * nM]);
-  tile_epilogue<double, TT, BS>(g, w, fmax_out, c, eb, oc, acc);
+  chunk_epilogue<double, TT>(g, w, fmax_out, c, chunk, oc, acc);
 }
 
-template <typename F, int TT, int BS>
-static void launch_sweep(const GridDev& g, const BatchDev& bt, SweepBufs<F> w, const F* HMC,
-                         double* fmax_out, hipStream_t s, const SweepPlan& plan) {
-  w.n_eblk = (g.nM + BS - 1) / BS;
-  const int tiles = w.n_eblk * bt.B;
+// Sweep launch for a plan: lanes per workgroup (64, 128 or 256 = 1, 2 or 4
+// independent waves), 1 or 2 monitored branches per lane, item order and the
+// persistent variant.
+template <typename F, int TT, int NPL>
+static void launch_sweep_npl(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                             const F* HMC, double* fmax_out, hipStream_t s, const SweepPlan& plan) {
+  const int wpg = plan.lanes / 64;
+  const long n_items = (long)bt.B * ((w.n_eblk + NPL - 1) / NPL);
   if (plan.persistent) {
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, w.counter);
-    hipLaunchKernelGGL(k_rank_order, dim3(1), dim3(1024), 0, s, w.info, bt.B, w.order);
-    const int grid = std::min(tiles, std::max(plan.grid, 1));
-    hipLaunchKernelGGL((k_sweep_persistent<F, TT, BS>), dim3(grid), dim3(BS), 0, s, g, w, HMC,
+    const int nb = (bt.B + 255) / 256;
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, w.counter, 32);
+    hipLaunchKernelGGL(k_rank_count, dim3(nb), dim3(256), 0, s, (const CandInfo*)w.info, bt.B,
+                       w.counter + 8);
+    hipLaunchKernelGGL(k_rank_offsets, dim3(1), dim3(64), 0, s, w.counter + 8);
+    hipLaunchKernelGGL(k_rank_place, dim3(nb), dim3(256), 0, s, (const CandInfo*)w.info, bt.B,
+                       w.counter + 8, w.order);
+    const long groups = (n_items + wpg - 1) / wpg;
+    const int grid = (int)std::min<long>(groups, std::max(plan.grid, 1));
+    hipLaunchKernelGGL((k_sweep_pull<F, TT, NPL>), dim3(grid), dim3(plan.lanes), 0, s, g, w, HMC,
                        fmax_out, bt.B, w.counter, (const int*)w.order);
   } else {
-    hipLaunchKernelGGL((k_sweep<F, TT, BS>), dim3((tiles + 7) / 8 * 8), dim3(BS), 0, s, g, w,
-                       HMC, fmax_out, bt.B, plan.xcd, bt.map, bt.live);
+    const long groups = (n_items + wpg - 1) / wpg;
+    hipLaunchKernelGGL((k_sweep<F, TT, NPL>), dim3((unsigned)((groups + 7) / 8 * 8)),
+                       dim3(plan.lanes), 0, s, g, w, HMC, fmax_out, bt.B, plan.order, bt.map,
+                       bt.live);
   }
+}
+
+template <typename F, int TT>
+static void launch_sweep(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                         const F* HMC, double* fmax_out, hipStream_t s, const SweepPlan& plan) {
+  if constexpr (sizeof(F) == 4) {
+    if (plan.npl == 2) { launch_sweep_npl<F, TT, 2>(g, bt, w, HMC, fmax_out, s, plan); return; }
+  }
+  launch_sweep_npl<F, TT, 1>(g, bt, w, HMC, fmax_out, s, plan);
 }
 
 // Refinement queue: the flagged candidates in index order, the first `cap`
@@ -1171,15 +1191,11 @@ static void launch_pass(const GridDev& g, const BatchDev& bt, SweepBufs<F> w,
                         const SweepPlan& plan, const RefineCtl& rc) {
   const F* HMC;
   if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
-  w.n_eblk = (g.nM + plan.bs - 1) / plan.bs;
+  w.n_eblk = (g.nM + 63) / 64;   // partials per candidate: one per 64-branch chunk
   if (ev) hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_setup<F, TT>), dim3(bt.B), dim3(256), 0, s, g, bt, w, o.base_flows);
   if (ev) hipEventRecord(ev[1], s);
-  switch (plan.bs) {
-    case 64: launch_sweep<F, TT, 64>(g, bt, w, HMC, o.fmax, s, plan); break;
-    case 128: launch_sweep<F, TT, 128>(g, bt, w, HMC, o.fmax, s, plan); break;
-    default: launch_sweep<F, TT, 256>(g, bt, w, HMC, o.fmax, s, plan); break;
-  }
+  launch_sweep<F, TT>(g, bt, w, HMC, o.fmax, s, plan);
   if (ev) hipEventRecord(ev[2], s);
   const size_t fin_lds = finalize_lds_bytes<F>(g.nC);
   hipLaunchKernelGGL((k_finalize<F, TT>), dim3(bt.B), dim3(64), fin_lds, s, g, w, HMC, o, bt.map,
@@ -1220,29 +1236,26 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     RefineCtl none = rc;
     none.list = nullptr;
     none.flags = nullptr;
-    SweepPlan rp = plan;
-    rp.persistent = 0;
     GridDev gh = g;
     gh.f0 = g.f0_hi;   // FP64-GEMM base flows
     gh.near_margin = -1.0;
     SweepBufs<double> w64 = *rw;
-    w64.n_eblk = (g.nM + 255) / 256;
+    w64.n_eblk = (g.nM + 63) / 64;
     constexpr int kSplit = 8;
     hipLaunchKernelGGL((k_setup<double, TT>), dim3(rb.B), dim3(256), 0, s, gh, rb, w64,
                        (double*)nullptr);
     hipLaunchKernelGGL(k_zero_live_u64, dim3(1024), dim3(256), 0, s, rc.fbuf,
                        (const int*)rc.count, rc.cap, (size_t)TT * g.nM);
-    hipLaunchKernelGGL((k_sweep_split<TT, 256>), dim3(rb.B * w64.n_eblk * kSplit), dim3(256), 0,
-                       s, gh, w64, (const double*)g.HMC64, rb.B, kSplit, (const int*)rc.count,
+    hipLaunchKernelGGL((k_sweep_split<TT>), dim3((rb.B * w64.n_eblk * kSplit + 3) / 4), dim3(256),
+                       0, s, gh, w64, (const double*)g.HMC64, rb.B, kSplit, (const int*)rc.count,
                        rc.fbuf);
-    hipLaunchKernelGGL((k_sweep_split_epi<TT, 256>), dim3(rb.B * w64.n_eblk), dim3(256), 0, s,
-                       gh, w64, ro.fmax, rb.B, (const int*)rc.list, (const int*)rc.count,
+    hipLaunchKernelGGL((k_sweep_split_epi<TT>), dim3((rb.B * w64.n_eblk + 3) / 4), dim3(256), 0,
+                       s, gh, w64, ro.fmax, rb.B, (const int*)rc.list, (const int*)rc.count,
                        (const unsigned long long*)rc.fbuf);
     const size_t fin_lds = finalize_lds_bytes<double>(g.nC);
     hipLaunchKernelGGL((k_finalize<double, TT>), dim3(rb.B), dim3(64), fin_lds, s, gh, w64,
                        (const double*)g.HMC64, ro, rb.map, rb.live, rb.B, none,
                        fin_lds > 0 ? 1 : 0);
-    (void)rp;
   }
   if (ev) hipEventRecord(ev[4], s);
   return hipGetLastError();
@@ -1261,21 +1274,24 @@ hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs
   }
 }
 
-// Occupancy of the sweep for a plan (workgroups per CU), for persistent grids.
-template <typename F>
-static int sweep_occ(int TT, int bs) {
+// Occupancy of the persistent sweep for a plan (workgroups per CU).
+template <typename F, int NPL>
+static int pull_occ(int TT, int lanes) {
   int n = 0;
   const void* fn = nullptr;
-#define TTO_OCC(TTV, BSV) if (TT == TTV && bs == BSV) fn = (const void*)&k_sweep_persistent<F, TTV, BSV>;
-  TTO_OCC(1, 64) TTO_OCC(1, 128) TTO_OCC(1, 256) TTO_OCC(8, 64) TTO_OCC(8, 128) TTO_OCC(8, 256)
-  TTO_OCC(24, 64) TTO_OCC(24, 128) TTO_OCC(24, 256) TTO_OCC(32, 64) TTO_OCC(32, 128) TTO_OCC(32, 256)
-#undef TTO_OCC
-  if (fn && hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, bs, 0) != hipSuccess) n = 0;
+  switch (TT) {
+    case 1: fn = (const void*)&k_sweep_pull<F, 1, NPL>; break;
+    case 8: fn = (const void*)&k_sweep_pull<F, 8, NPL>; break;
+    case 24: fn = (const void*)&k_sweep_pull<F, 24, NPL>; break;
+    default: fn = (const void*)&k_sweep_pull<F, 32, NPL>; break;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, lanes, 0) != hipSuccess) n = 0;
   return n;
 }
 
-int sweep_blocks_per_cu(int flow_f32, int TT, int bs) {
-  return flow_f32 ? sweep_occ<float>(TT, bs) : sweep_occ<double>(TT, bs);
+int sweep_blocks_per_cu(int flow_f32, int TT, int lanes, int npl) {
+  if (flow_f32) return npl == 2 ? pull_occ<float, 2>(TT, lanes) : pull_occ<float, 1>(TT, lanes);
+  return pull_occ<double, 1>(TT, lanes);
 }
 
 // ---------------------------------------------------------------------------

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <numeric>
 #include <string>
+#include <array>
 #include <vector>
 
 using namespace tto;
@@ -220,7 +221,7 @@ struct tto_grid {
   bool profile = false;
   bool recorded = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  SweepPlan plan = {256, 0, 0, 0};
+  SweepPlan plan = {256, 1, 0, 0, 0};
   int n_cu = 0;
   int refine = 1;              // FP64 refinement of near-decision candidates (FP32 flows)
   double refine_margin = 8e-3; // MW
@@ -543,37 +544,42 @@ tto_status tto_set_refine(tto_grid* g, int32_t enable, double margin_mw) {
   return ok();
 }
 
-static tto_status apply_plan(tto_grid* g, int bs, int xcd, int persistent) {
-  if (bs != 64 && bs != 128 && bs != 256) return fail(TTO_E_INVALID, "block must be 64, 128 or 256");
-  // 64/128-lane tiles and the persistent grid are switched off: a GPU test
-  // exercising them did not finish and the cause has not been found.
-  if (bs != 256 || persistent)
-    return fail(TTO_E_UNSUPPORTED, "sweep plan (block %d, persistent %d) is disabled",
-                bs, persistent);
+static tto_status apply_plan(tto_grid* g, int lanes, int npl, int order, int persistent) {
+  if (lanes != 64 && lanes != 128 && lanes != 256)
+    return fail(TTO_E_INVALID, "lanes must be 64, 128 or 256");
+  if (npl != 1 && npl != 2) return fail(TTO_E_INVALID, "branches per lane must be 1 or 2");
+  if (npl == 2 && g->flow_prec != TTO_FLOW_F32)
+    return fail(TTO_E_UNSUPPORTED, "2 branches per lane need FP32 flows");
+  if (order < 0 || order > 2) return fail(TTO_E_INVALID, "order must be 0, 1 or 2");
+  if (persistent != 0 && persistent != 1) return fail(TTO_E_INVALID, "persistent must be 0 or 1");
   SweepPlan p;
-  p.bs = bs;
-  if (xcd < 0 || xcd > 2) return fail(TTO_E_INVALID, "xcd_group must be 0, 1 or 2");
-  p.xcd = xcd;
-  p.persistent = persistent ? 1 : 0;
+  p.lanes = lanes;
+  p.npl = npl;
+  p.order = order;
+  p.persistent = persistent;
   p.grid = 0;
   if (p.persistent) {
-    const int occ = sweep_blocks_per_cu(g->flow_prec == TTO_FLOW_F32, g->TT, bs);
-    if (occ <= 0) return fail(TTO_E_HIP, "occupancy query failed for block %d", bs);
+    const int occ = sweep_blocks_per_cu(g->flow_prec == TTO_FLOW_F32, g->TT, lanes, npl);
+    if (occ <= 0) return fail(TTO_E_HIP, "occupancy query failed for %d lanes", lanes);
     p.grid = occ * std::max(g->n_cu, 1);
   }
   g->plan = p;
   return ok();
 }
 
-tto_status tto_set_sweep_plan(tto_grid* g, int32_t block, int32_t xcd_group, int32_t persistent) {
+tto_status tto_set_sweep_plan(tto_grid* g, int32_t lanes, int32_t branches_per_lane,
+                              int32_t order, int32_t persistent) {
   if (!g) return fail(TTO_E_INVALID, "grid is NULL");
-  return apply_plan(g, block, xcd_group, persistent);
+  return apply_plan(g, lanes, branches_per_lane, order, persistent);
 }
 
-tto_status tto_get_sweep_plan(tto_grid* g, int32_t* block, int32_t* xcd_group, int32_t* persistent) {
-  if (!g || !block || !xcd_group || !persistent) return fail(TTO_E_INVALID, "NULL argument");
-  *block = g->plan.bs;
-  *xcd_group = g->plan.xcd;
+tto_status tto_get_sweep_plan(tto_grid* g, int32_t* lanes, int32_t* branches_per_lane,
+                              int32_t* order, int32_t* persistent) {
+  if (!g || !lanes || !branches_per_lane || !order || !persistent)
+    return fail(TTO_E_INVALID, "NULL argument");
+  *lanes = g->plan.lanes;
+  *branches_per_lane = g->plan.npl;
+  *order = g->plan.order;
   *persistent = g->plan.persistent;
   return ok();
 }
@@ -588,7 +594,7 @@ tto_status tto_autotune(tto_grid* g, const tto_batch* bt, const tto_outputs* out
   HIP_TRY(hipGetDeviceProperties(&prop, g->device));
   snprintf(key, sizeof(key), "%s m=%d M=%d C=%d T=%d flow=%d B=%d", prop.gcnArchName, g->m, g->nM,
            g->nC, g->T, g->flow_prec, bt->n_cand);
-  // cached choice: lines "<key>|<block> <xcd> <persistent>"
+  // cached choice: lines "<key>|<lanes> <branches per lane> <order> <persistent>"
   if (cache_path && cache_path[0]) {
     FILE* f = fopen(cache_path, "r");
     if (f) {
@@ -597,25 +603,36 @@ tto_status tto_autotune(tto_grid* g, const tto_batch* bt, const tto_outputs* out
         char* bar = strchr(line, '|');
         if (!bar) continue;
         *bar = 0;
-        int b = 0, x = 0, p = 0;
-        if (strcmp(line, key) == 0 && sscanf(bar + 1, "%d %d %d", &b, &x, &p) == 3) {
+        int v[4] = {0, 0, 0, 0};
+        if (strcmp(line, key) == 0 && sscanf(bar + 1, "%d %d %d %d", &v[0], &v[1], &v[2], &v[3]) == 4) {
           fclose(f);
-          tto_status st = apply_plan(g, b, x, p);
-          if (st == TTO_OK && chosen) { chosen[0] = b; chosen[1] = x; chosen[2] = p; chosen[3] = 1; }
+          tto_status st = apply_plan(g, v[0], v[1], v[2], v[3]);
+          if (st == TTO_OK && chosen) {
+            for (int q = 0; q < 4; ++q) chosen[q] = v[q];
+            chosen[4] = 1;
+          }
           return st;
         }
       }
       fclose(f);
     }
   }
-  const int cands[][3] = {{256, 0, 0}, {256, 1, 0}, {256, 2, 0}};
+  // search space: workgroup size x branches per lane x item order, plus the
+  // persistent grid at the two branch-per-lane settings
+  std::vector<std::array<int, 4>> cands;
+  const int max_npl = g->flow_prec == TTO_FLOW_F32 ? 2 : 1;
+  for (int npl = 1; npl <= max_npl; ++npl) {
+    for (int lanes : {64, 128, 256})
+      for (int order = 0; order < 3; ++order) cands.push_back({lanes, npl, order, 0});
+    cands.push_back({256, npl, 0, 1});
+  }
   const bool prof0 = g->profile;
   tto_status st = tto_profile_enable(g, 1);
   if (st != TTO_OK) return st;
   double best_ms = 1e30;
   int best = 0;
-  for (int i = 0; i < (int)(sizeof(cands) / sizeof(cands[0])); ++i) {
-    st = apply_plan(g, cands[i][0], cands[i][1], cands[i][2]);
+  for (int i = 0; i < (int)cands.size(); ++i) {
+    st = apply_plan(g, cands[i][0], cands[i][1], cands[i][2], cands[i][3]);
     if (st != TTO_OK) return st;
     double t[3];
     for (int rep = 0; rep < 3; ++rep) {
@@ -630,13 +647,17 @@ tto_status tto_autotune(tto_grid* g, const tto_batch* bt, const tto_outputs* out
     if (t[1] < best_ms) { best_ms = t[1]; best = i; }
   }
   tto_profile_enable(g, prof0 ? 1 : 0);
-  st = apply_plan(g, cands[best][0], cands[best][1], cands[best][2]);
+  const std::array<int, 4> b = cands[best];
+  st = apply_plan(g, b[0], b[1], b[2], b[3]);
   if (st != TTO_OK) return st;
-  if (chosen) { chosen[0] = cands[best][0]; chosen[1] = cands[best][1]; chosen[2] = cands[best][2]; chosen[3] = 0; }
+  if (chosen) {
+    for (int q = 0; q < 4; ++q) chosen[q] = b[q];
+    chosen[4] = 0;
+  }
   if (cache_path && cache_path[0]) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "%s|%d %d %d\n", key, cands[best][0], cands[best][1], cands[best][2]);
+      fprintf(f, "%s|%d %d %d %d\n", key, b[0], b[1], b[2], b[3]);
       fclose(f);
     }
   }

@@ -123,17 +123,19 @@ struct SweepBufs {
   F* rec;           // [B][nC+1][rec_stride(TT)]
   int* act;         // [B][nC+1] contingency index of each record
   int* slot;        // [B][nC] record of each contingency or -1 (optional)
-  Partial* part;    // [B][ceil(nM / 64)] (n_eblk used per plan)
-  int* counter;     // persistent-sweep tile counter
-  int* order;       // [B] rank-descending candidate order
-  int n_eblk;
+  Partial* part;    // [B][n_eblk] one per chunk of 64 monitored branches
+  int* counter;     // [64] persistent sweep: work counter, rank histogram and slots
+  int* order;       // [B] rank-descending candidate order (persistent sweep)
+  int n_eblk;       // ceil(nM / 64)
 };
 
-// Launch shape of the N-1 sweep (chosen by the autotuner).
+// Launch shape of the N-1 sweep (chosen by the autotuner).  The unit of
+// work is one wave: a candidate and npl chunks of 64 monitored branches.
 struct SweepPlan {
-  int bs;           // monitored branches per tile: 64, 128 or 256 lanes
-  int xcd;          // group the tiles of a candidate onto one XCD
-  int persistent;   // machine-sized grid pulling rank-ordered tiles
+  int lanes;        // workgroup size: 64, 128 or 256 (1, 2 or 4 independent waves)
+  int npl;          // monitored branches per lane: 1 or 2 (2: FP32 flows only)
+  int order;        // 0 hardware, 1 XCD candidate-major, 2 XCD chunk-major
+  int persistent;   // machine-sized grid of waves pulling rank-ordered items
   int grid;         // persistent grid size (workgroups)
 };
 
@@ -174,7 +176,7 @@ hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs
                            const tto_outputs& out, hipStream_t s, hipEvent_t* ev,
                            const SweepPlan& plan, const SweepBufs<double>* rw,
                            const RefineCtl& rc);
-int sweep_blocks_per_cu(int flow_f32, int TT, int bs);
+int sweep_blocks_per_cu(int flow_f32, int TT, int lanes, int npl);
 hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
                           const int* cell, const uint8_t* status, int B, int64_t id_base,
                           unsigned long long* key, int* idx, hipStream_t s);

@@ -106,7 +106,7 @@ def _load():
                                       ct.c_size_t, _vp]),
         "tto_profile_enable": (_i32, [_vp, _i32]),
         "tto_profile_read": (_i32, [_vp, P(ct.c_double)]),
-        "tto_set_sweep_plan": (_i32, [_vp, _i32, _i32, _i32]),
+        "tto_set_sweep_plan": (_i32, [_vp, _i32, _i32, _i32, _i32]),
         "tto_set_refine": (_i32, [_vp, _i32, ct.c_double]),
         "tto_batch_gather": (_i32, [P(tto_batch), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp,
                                     P(tto_batch), _vp]),
@@ -128,7 +128,7 @@ def _load():
         "tto_graph_destroy": (None, [_vp]),
         "tto_evaluate_capture": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
                                         _vp, _i32, ct.c_int64, P(_vp)]),
-        "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32)]),
+        "tto_get_sweep_plan": (_i32, [_vp, P(_i32), P(_i32), P(_i32), P(_i32)]),
         "tto_ptdf_bytes": (_i32, [_i32, _i32, P(ct.c_size_t)]),
         "tto_ptdf_build": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, ct.c_size_t, _vp]),
         "tto_bridges": (_i32, [_vp, _vp, _vp]),
@@ -247,27 +247,30 @@ def tto_profile_read(handle: int):
     return list(ms)
 
 
-def tto_set_sweep_plan(handle: int, block: int, xcd_group: int, persistent: bool):
-    _check(_lib.tto_set_sweep_plan(_vp(handle), block, int(xcd_group), int(persistent)))
+def tto_set_sweep_plan(handle: int, lanes: int = 256, branches_per_lane: int = 1, order: int = 0,
+                       persistent: bool = False):
+    _check(_lib.tto_set_sweep_plan(_vp(handle), int(lanes), int(branches_per_lane), int(order),
+                                   int(persistent)))
 
 
 def tto_set_refine(handle: int, enable: bool, margin_mw: float = 8e-3):
     _check(_lib.tto_set_refine(_vp(handle), 1 if enable else 0, float(margin_mw)))
 
 
-def tto_get_sweep_plan(handle: int):
-    b, x, p = _i32(), _i32(), _i32()
-    _check(_lib.tto_get_sweep_plan(_vp(handle), ct.byref(b), ct.byref(x), ct.byref(p)))
-    return b.value, int(x.value), bool(p.value)
+def tto_get_sweep_plan(handle: int) -> dict:
+    v = [_i32() for _ in range(4)]
+    _check(_lib.tto_get_sweep_plan(_vp(handle), *[ct.byref(x) for x in v]))
+    return {"lanes": v[0].value, "branches_per_lane": v[1].value, "order": v[2].value,
+            "persistent": bool(v[3].value)}
 
 
 def tto_autotune(handle: int, batch: tto_batch, outputs: tto_outputs, ws: int, ws_bytes: int,
                  stream: int, cache_path: str = ""):
-    ch = (_i32 * 4)()
+    ch = (_i32 * 5)()
     _check(_lib.tto_autotune(_vp(handle), ct.byref(batch), ct.byref(outputs), _vp(ws), ws_bytes,
                              _vp(stream), cache_path.encode(), ch))
-    return {"block": ch[0], "xcd_group": int(ch[1]), "persistent": bool(ch[2]),
-            "from_cache": bool(ch[3])}
+    return {"lanes": ch[0], "branches_per_lane": ch[1], "order": ch[2],
+            "persistent": bool(ch[3]), "from_cache": bool(ch[4])}
 
 
 def tto_topk_smallest(score: int, n: int, stride: int, k: int, idx_out: int, stream: int):
@@ -822,8 +825,8 @@ class Session:
                                 self._wk_ws.numel(), self.stream)
         return ids, en
 
-    def set_sweep_plan(self, block=256, xcd_group=0, persistent=False):
-        tto_set_sweep_plan(self.handle, block, xcd_group, persistent)
+    def set_sweep_plan(self, lanes=256, branches_per_lane=1, order=0, persistent=False):
+        tto_set_sweep_plan(self.handle, lanes, branches_per_lane, order, persistent)
 
     def new_archive(self, n_cells=None):
         n = self.n_cells if n_cells is None else n_cells

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version():
     from paper_2605_10128_amd import tto
-    assert tto.tto_version() == (1, 0)
+    assert tto.tto_version() == (1, 1)
 
 
 def _desc(tto, n=4, fr=(0, 1, 2, 3), to=(1, 2, 3, 0), mon=(0, 1, 2, 3), cont=(0, 1, 2, 3), **kw):

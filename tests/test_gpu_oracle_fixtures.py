@@ -130,7 +130,7 @@ def _summary(kinds):
 
 def test_benchmarked_launch_against_oracle_fixtures(tto):
     """The benchmark's launch: 16384 candidates in one tto_evaluate, FP32 flows,
-    default refinement, 256-lane tiles in the XCD-grouped order.  Seventeen
+    default refinement, the launch shape the autotuner picks.  Seventeen
     candidates (rank 0..8, with and without splits) element by element; a
     second launch that also writes f^max must reproduce every output of the
     first bit for bit and match the oracle's f^max within 1e-2 MW."""
@@ -140,8 +140,9 @@ def test_benchmarked_launch_against_oracle_fixtures(tto):
     B = w.batch.n_cand
     assert B == 16384
     s = make_session(w, tto.TTO_FLOW_F32, max_batch=B)
-    s.set_sweep_plan(256, 1, False)
     db = tto.device_batch(w.batch)
+    plan = s.autotune(db)            # the benchmark's launch shape
+    log(f"[fixtures] benchmarked plan {plan}")
     o = to_numpy(s.evaluate(db))
     o2 = to_numpy(s.evaluate(db, fmax=True))
     torch.cuda.synchronize()

@@ -131,26 +131,34 @@ def test_repeat_runs_bitwise_identical(tto):
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
 
 
-PLANS = [(256, 0, False), (256, 1, False), (256, 2, False)]
-DISABLED_PLANS = [(64, 0, False), (128, 0, False), (256, 0, True)]
+# (lanes, branches per lane, order, persistent)
+PLANS = [(lanes, npl, order, False) for npl in (1, 2) for lanes in (64, 128, 256)
+         for order in (0, 1, 2)] + [(256, 1, 0, True), (256, 2, 0, True), (64, 2, 1, True)]
 
 
-def test_disabled_sweep_plans_are_rejected(tto):
-    """64/128-lane tiles and the persistent grid are switched off (a GPU test
-    of them did not finish; cause not found): the ABI refuses them."""
+def test_sweep_plan_arguments_checked(tto):
+    """Out-of-range launch shapes are refused; 2 branches per lane needs FP32
+    flows."""
     w = gg.build_config(1)
     s = make_session(w, tto.TTO_FLOW_F64)
-    for plan in DISABLED_PLANS:
+    for plan, code in (((32, 1, 0, 0), tto.TTO_E_INVALID), ((512, 1, 0, 0), tto.TTO_E_INVALID),
+                       ((256, 3, 0, 0), tto.TTO_E_INVALID), ((256, 1, 3, 0), tto.TTO_E_INVALID),
+                       ((256, 1, 0, 2), tto.TTO_E_INVALID), ((256, 2, 0, 0), tto.TTO_E_UNSUPPORTED)):
         with pytest.raises(tto.TTOError) as ei:
-            s.set_sweep_plan(*plan)
-        assert ei.value.code == tto.TTO_E_UNSUPPORTED
+            tto.tto_set_sweep_plan(s.handle, *plan)
+        assert ei.value.code == code, plan
+    s.set_sweep_plan(128, 1, 2, True)
+    assert tto.tto_get_sweep_plan(s.handle) == {"lanes": 128, "branches_per_lane": 1, "order": 2,
+                                                 "persistent": True}
 
 
-def test_sweep_plans_agree(tto):
-    """Every launch shape (tile width, XCD grouping, persistent rank-ordered
-    grid) gives the same discrete outputs; sums agree to rounding."""
+@pytest.mark.parametrize("cfg,B", [(3, 96), (2, 300)])
+def test_sweep_plans_agree(tto, cfg, B):
+    """Every launch shape (workgroup size, branches per lane, item order, the
+    persistent grid) gives bitwise the same outputs, f^max included: the
+    chunk partials are reduced in one fixed order whatever the shape."""
     import torch
-    w = gg.build_config(3, B=96)
+    w = gg.build_config(cfg, B=B)
     s = make_session(w, tto.TTO_FLOW_F32)
     db = tto.device_batch(w.batch)
     ref = None
@@ -162,10 +170,16 @@ def test_sweep_plans_agree(tto):
         if ref is None:
             ref = o
             continue
-        for key in ("status", "n_island_cont", "n_crit_n1", "n_crit_n0", "worst_branch",
-                    "worst_cont", "worst_t", "cell", "fmax", "max_loading"):
+        for key in o:
             np.testing.assert_array_equal(o[key], ref[key], err_msg=f"{plan} {key}")
-        np.testing.assert_allclose(o["overload_mw"], ref["overload_mw"], rtol=1e-12, atol=1e-9)
+    s64 = make_session(w, tto.TTO_FLOW_F64)
+    ref64 = to_numpy(s64.evaluate(db, fmax=True))
+    for plan in [p for p in PLANS if p[1] == 1]:
+        s64.set_sweep_plan(*plan)
+        o = to_numpy(s64.evaluate(db, fmax=True))
+        torch.cuda.synchronize()
+        for key in o:
+            np.testing.assert_array_equal(o[key], ref64[key], err_msg=f"f64 {plan} {key}")
 
 
 def test_autotune_and_cache(tto, tmp_path):
@@ -175,11 +189,12 @@ def test_autotune_and_cache(tto, tmp_path):
     db = tto.device_batch(w.batch)
     cache = str(tmp_path / "plans.txt")
     first = s.autotune(db, cache_path=cache)
-    assert not first["from_cache"] and first["block"] == 256
+    assert not first["from_cache"]
     again = s.autotune(db, cache_path=cache)
-    assert again["from_cache"] and again["block"] == first["block"]
-    assert tto.tto_get_sweep_plan(s.handle) == (first["block"], first["xcd_group"],
-                                                first["persistent"])
+    keys = ("lanes", "branches_per_lane", "order", "persistent")
+    assert again["from_cache"] and all(again[k] == first[k] for k in keys)
+    assert tto.tto_get_sweep_plan(s.handle) == {k: first[k] for k in keys}
+    log(f"[autotune] 500-bus, 512 candidates: {first}")
     o = to_numpy(s.evaluate(db))
     torch.cuda.synchronize()
     idx = list(range(0, 512, 64))
@@ -241,7 +256,7 @@ def test_benchmarked_launch_sampled_against_oracle(tto):
     w = gg.build_config(3)
     B = w.batch.n_cand
     s = make_session(w, tto.TTO_FLOW_F32, max_batch=B)
-    s.set_sweep_plan(256, 1, False)
+    s.set_sweep_plan(256, 2, 1, False)
     o = to_numpy(s.evaluate(tto.device_batch(w.batch)))
     torch.cuda.synchronize()
     lim = w.grid.limit_mw[w.M]
