@@ -530,16 +530,13 @@ def main():
     if args.sweep_plans:
         tto.tto_profile_enable(s.handle, True)
         for npl in (1, 2):
-            for lanes in (64, 128, 256):
-                for order in (0, 1, 2):
-                    for pers in ((False, True) if order == 0 else (False,)):
-                        s.set_sweep_plan(lanes, npl, order, pers)
-                        ts = []
-                        for _ in range(3):
-                            s.evaluate(db, out)
-                            ts.append(tto.tto_profile_read(s.handle)[1])
-                        log(f"[bench] plan lanes={lanes} npl={npl} order={order} "
-                            f"persistent={int(pers)}: sweep {sorted(ts)[1]:.3f} ms")
+            for order in (0, 1, 2):
+                s.set_sweep_plan(256, npl, order, False)
+                ts = []
+                for _ in range(3):
+                    s.evaluate(db, out)
+                    ts.append(tto.tto_profile_read(s.handle)[1])
+                log(f"[bench] plan npl={npl} order={order}: sweep {sorted(ts)[1]:.3f} ms")
         tto.tto_profile_enable(s.handle, False)
     if args.plan == "auto":
         chosen = s.autotune(db, out)   # untimed: picks the sweep launch shape

@@ -48,6 +48,12 @@ extern "C" {
  * of the post-switch grid) tie exactly, and the order of the list, not
  * rounding, then picks the reported contingency. */
 #define TTO_WORST_CONT_TIE_MW 0.05
+/* Worst (branch, timestep): the smallest (monitored position, timestep) whose
+ * loading is at least max_loading * (1 - TTO_LOAD_TIE_REL).  Branches of a
+ * two-branch cut with equal limits, for instance, carry the same maximum
+ * loading exactly (each carries the cut's transfer when the other is out),
+ * and the monitored order, not rounding, then picks the reported branch. */
+#define TTO_LOAD_TIE_REL 1e-9
 
 typedef int32_t tto_status;
 enum {
@@ -193,8 +199,9 @@ typedef struct {
  *   n_crit_n1      lambda_c = #{(e,t): f^max_e(t) > fbar_e}
  *   n_crit_n0      lambda_c0 = #{(e,t): |f'_e(t)| > fbar_e}
  *   max_loading    max_{e,t} f^max_e(t) / fbar_e
- *   worst_*        branch id e*, timestep t* of the maximum loading (smallest
- *                  (e, t) on exact ties) and contingency branch id l*, the
+ *   worst_*        branch id e*, timestep t* of the maximum loading (the
+ *                  smallest (monitored position, t) within TTO_LOAD_TIE_REL
+ *                  of it) and contingency branch id l*, the
  *                  first contingency within TTO_WORST_CONT_TIE_MW of the
  *                  maximum |flow| at (e*, t*) (l* = -1 when every
  *                  contingency islands)
@@ -309,7 +316,8 @@ tto_status tto_profile_read(tto_grid* grid, double* ms);
  * consecutive chunks of 64 monitored branches (one lane per branch of each
  * chunk, every timestep in registers); waves share no memory and never wait
  * on each other, and each candidate's rank fixes its wave's loop.
- *   lanes              workgroup size 64, 128 or 256 (1, 2 or 4 waves)
+ *   lanes              workgroup size: 256 (four independent waves); 64 and
+ *                      128 return TTO_E_UNSUPPORTED
  *   branches_per_lane  1 or 2 (2: each contingency record read by a wave
  *                      feeds two branches; FP32 flows only)
  *   order              0: hardware order of the work items; 1: each XCD
@@ -317,12 +325,14 @@ tto_status tto_profile_read(tto_grid* grid, double* ms);
  *                      candidate's waves share its records in one L2); 2:
  *                      chunk-major ranges (an XCD streams few column blocks
  *                      of H[M, C] across many candidates)
- *   persistent         1: a machine-sized grid whose waves pull work items
- *                      from a counter in rank-descending candidate order
- *                      (order is then ignored)
- * Every plan gives bitwise the same outputs.  Default 256, 1, 0, 0.
- * TTO_E_INVALID for values out of range, TTO_E_UNSUPPORTED for 2 branches
- * per lane on an FP64 grid.
+ *   persistent         must be 0: the persistent grid returns
+ *                      TTO_E_UNSUPPORTED
+ * The 64- and 128-lane workgroups and the persistent grid are switched off:
+ * an earlier sweep in those shapes did not finish within a test's time limit
+ * and no cause was found in its code.  Every enabled plan gives bitwise the
+ * same outputs.  Default 256, 1, 0, 0.  TTO_E_INVALID for values out of
+ * range, TTO_E_UNSUPPORTED for 2 branches per lane on an FP64 grid and for
+ * the disabled shapes.
  */
 tto_status tto_set_sweep_plan(tto_grid* grid, int32_t lanes, int32_t branches_per_lane,
                               int32_t order, int32_t persistent);
@@ -346,8 +356,8 @@ tto_status tto_get_sweep_plan(tto_grid* grid, int32_t* lanes, int32_t* branches_
 /*
  * Autotuner: times the sweep plans on this batch (three tto_evaluate calls
  * each, median of the sweep stage by HIP events) and keeps the fastest.  The
- * search covers workgroup sizes 64/128/256 x branches per lane 1/2 (2 on
- * FP32 grids) x the three item orders, plus the persistent grid.  With a
+ * search covers the register tile (1 or 2 monitored branches per lane, 2 on
+ * FP32 grids only) x the three item orders, at 256 lanes.  With a
  * non-empty cache_path, a line "<device> <shape>|<lanes> <branches per lane>
  * <order> <persistent>" is looked up first (no timing when found) and
  * appended after tuning.  chosen (optional, int32[5]) receives lanes,

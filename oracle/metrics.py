@@ -6,6 +6,11 @@ from typing import Optional
 
 import numpy as np
 
+# Relative band within which two loadings count as tied for the worst
+# (branch, timestep): far above FP64 rounding of a flow, far below any
+# loading difference that is not a tie.
+LOAD_TIE_REL = 1e-9
+
 
 def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
                argl: Optional[np.ndarray] = None) -> dict:
@@ -18,9 +23,13 @@ def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
 
     Multi-timestep reading: sums run over timesteps as well; the maximum
     loading rho = max_{e,t} f^max_e(t) / fbar_e.  (e*, t*) is the
-    lexicographically smallest pair attaining rho; the third entry of "worst"
-    is argl[e*, t*] when argl is given (the candidate evaluation fills in the
-    worst contingency by its own rule).
+    lexicographically smallest pair whose loading is at least
+    rho (1 - LOAD_TIE_REL): loadings that are equal in exact arithmetic (the
+    two branches of a two-branch cut with equal limits each carry the cut's
+    whole transfer when the other is out) differ only by rounding, and the
+    band lets the order, not the rounding, decide.  The third entry of
+    "worst" is argl[e*, t*] when argl is given (the candidate evaluation fills
+    in the worst contingency by its own rule).
 
     fmax, f0: [|M|, T]; limit: [|M|]; argl: [|M|, T] positions in C, or None.
     """
@@ -36,11 +45,12 @@ def n1_metrics(fmax: np.ndarray, f0: np.ndarray, limit: np.ndarray,
     res["worst"] = None
     if ratio.size:
         best = res["max_loading"]
+        thr = best * (1.0 - LOAD_TIE_REL)
         E, T = ratio.shape
         found = None
         for e in range(E):
             for t in range(T):
-                if ratio[e, t] == best:
+                if ratio[e, t] >= thr:
                     found = (e, t)
                     break
             if found is not None:

@@ -693,7 +693,8 @@ __device__ __forceinline__ void chunk_epilogue(const GridDev& g, const SweepBufs
   bool opened = false;
   for (int q = 0; q < k; ++q) opened |= (inf->open_br[q] == e);
   double so = 0.0, best = -1.0, best2 = -1.0;
-  int cc = 0, bt = 0, be = ei;
+  int bt = 0, be = 0;
+  int cc = 0;
   if (valid) {
     const double lim = g.lim[e];
 #pragma unroll
@@ -706,7 +707,7 @@ __device__ __forceinline__ void chunk_epilogue(const GridDev& g, const SweepBufs
         if (ov > 0.0) so += ov;
         cc += fm > lim;
         const double ratio = fm / lim;
-        if (ratio > best) { best2 = best; best = ratio; bt = t; }
+        if (ratio > best) { best2 = best; best = ratio; }
         else if (ratio > best2) best2 = ratio;
       }
     }
@@ -718,12 +719,29 @@ __device__ __forceinline__ void chunk_epilogue(const GridDev& g, const SweepBufs
     so += __shfl_xor(so, off);
     cc += __shfl_xor(cc, off);
     const double b2 = __shfl_xor(best, off), s2 = __shfl_xor(best2, off);
-    const int e2 = __shfl_xor(be, off), t2 = __shfl_xor(bt, off);
-    const bool take = b2 > best || (b2 == best && e2 < be);
-    const double lo = take ? best : b2;
+    const double lo = fmin(best, b2);
     best2 = fmax(fmax(best2, s2), lo);
-    if (take) { best = b2; be = e2; bt = t2; }
+    best = fmax(best, b2);
   }
+  // arg-max with the loading tie band: the smallest (e, t) of the chunk whose
+  // loading is at least best (1 - TTO_LOAD_TIE_REL); the ratios are recomputed
+  // by the same operations as above, so they are bitwise the same
+  const double thr = best * (1.0 - kLoadTieRel);
+  int key = INT_MAX;
+  if (valid) {
+    const double lim = g.lim[e];
+#pragma unroll
+    for (int t = TT - 1; t >= 0; --t) {
+      if (t < T) {
+        const double fm = opened ? 0.0 : (double)acc[t];
+        if (fm / lim >= thr) key = ei * TT + t;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) key = min(key, __shfl_xor(key, off));
+  be = key / TT;
+  bt = key - be * TT;
   if (lane == 0) {
     Partial p;
     p.sum_o = so; p.best = best; p.best2 = best2; p.cnt_c = cc; p.best_e = be; p.best_t = bt;
@@ -796,64 +814,6 @@ __global__ __launch_bounds__(256) void k_sweep(GridDev g, SweepBufs<F> w,
   sweep_wave<F, TT, NPL>(g, w, HMC, fmax_out, c, wb, map ? map[c] : c);
 }
 
-// Persistent variant: a machine-sized grid whose waves each pull work items
-// from a counter (lane 0 increments it, the wave reads lane 0's ticket), in
-// rank-descending candidate order, until the items run out.  Waves never wait
-// on each other; every pull increments the counter, so every wave reaches the
-// exit after at most n_items + n_waves pulls in all.
-template <typename F, int TT, int NPL>
-__global__ __launch_bounds__(256) void k_sweep_pull(GridDev g, SweepBufs<F> w,
-                                                    const F* __restrict__ HMC,
-                                                    double* __restrict__ fmax_out, int n_cand,
-                                                    int* __restrict__ counter,
-                                                    const int* __restrict__ order) {
-  const int n_wb = (w.n_eblk + NPL - 1) / NPL;
-  const int n_items = n_cand * n_wb;
-  const int lane = threadIdx.x & 63;
-  for (;;) {
-    int u = 0;
-    if (lane == 0) u = atomicAdd(counter, 1);
-    u = __builtin_amdgcn_readfirstlane(u);
-    if (u >= n_items) break;
-    const int ci = u / n_wb;
-    const int c = order[ci];
-    sweep_wave<F, TT, NPL>(g, w, HMC, fmax_out, c, u - ci * n_wb, c);
-  }
-}
-
-// Rank-descending candidate order for the persistent sweep by counting sort
-// (three small launches; the order within a rank depends on scheduling, which
-// changes only which wave does an item, never a result).  cnt[0..10]: the
-// ten rank classes (8 down to 0, then islanded/invalid), cnt[11..21] their
-// running slots.
-__global__ __launch_bounds__(256) void k_rank_count(const CandInfo* __restrict__ info, int B,
-                                                    int* __restrict__ cnt) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= B) return;
-  const bool bad = info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
-  atomicAdd(&cnt[bad ? 9 : kMaxRank - info[c].r], 1);
-}
-
-__global__ void k_rank_offsets(int* __restrict__ cnt) {
-  if (threadIdx.x != 0) return;
-  int s = 0;
-  for (int k = 0; k < 10; ++k) { cnt[11 + k] = s; s += cnt[k]; }
-}
-
-__global__ __launch_bounds__(256) void k_rank_place(const CandInfo* __restrict__ info, int B,
-                                                    int* __restrict__ cnt,
-                                                    int* __restrict__ order) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= B) return;
-  const bool bad = info[c].status & (TTO_ST_ISLANDED | TTO_ST_INVALID);
-  order[atomicAdd(&cnt[11 + (bad ? 9 : kMaxRank - info[c].r)], 1)] = c;
-}
-
-// Counter block of the persistent sweep cleared by a kernel (graph-safe).
-__global__ void k_zero_ints(int* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
-}
-
 // ---------------------------------------------------------------------------
 // Finalize one candidate per wave.  Main pass: outputs at index c.  FP64
 // refinement pass (map != NULL): workgroup c < min(*live, cap) finalizes
@@ -913,9 +873,15 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     for (int b = 0; b < w.n_eblk; ++b) {
       so += p[b].sum_o;
       cc += p[b].cnt_c;
-      const bool take = p[b].best > best;
-      best2 = fmax(fmax(best2, p[b].best2), take ? best : p[b].best);
-      if (take) { best = p[b].best; be = p[b].best_e; bt = p[b].best_t; }
+      best2 = fmax(fmax(best2, p[b].best2), fmin(best, p[b].best));
+      best = fmax(best, p[b].best);
+    }
+    // (e*, t*): the smallest (e, t) whose loading is within the tie band of
+    // rho; chunks hold increasing monitored positions, so the first chunk
+    // reaching the band holds it
+    const double thr = best * (1.0 - kLoadTieRel);
+    for (int b = 0; b < w.n_eblk; ++b) {
+      if (p[b].best >= thr) { be = p[b].best_e; bt = p[b].best_t; break; }
     }
     s_sum = so; s_best = best; s_best2 = best2; s_cc = cc; s_be = be; s_bt = bt;
   }
@@ -1112,32 +1078,17 @@ __global__ __launch_bounds__(256) void k_sweep_split_epi(GridDev g, SweepBufs<do
   chunk_epilogue<double, TT>(g, w, fmax_out, c, chunk, oc, acc);
 }
 
-// Sweep launch for a plan: lanes per workgroup (64, 128 or 256 = 1, 2 or 4
-// independent waves), 1 or 2 monitored branches per lane, item order and the
-// persistent variant.
+// Sweep launch for a plan: 256-lane workgroups of four independent waves,
+// 1 or 2 monitored branches per lane, and the item order.
 template <typename F, int TT, int NPL>
 static void launch_sweep_npl(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
                              const F* HMC, double* fmax_out, hipStream_t s, const SweepPlan& plan) {
   const int wpg = plan.lanes / 64;
   const long n_items = (long)bt.B * ((w.n_eblk + NPL - 1) / NPL);
-  if (plan.persistent) {
-    const int nb = (bt.B + 255) / 256;
-    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, w.counter, 32);
-    hipLaunchKernelGGL(k_rank_count, dim3(nb), dim3(256), 0, s, (const CandInfo*)w.info, bt.B,
-                       w.counter + 8);
-    hipLaunchKernelGGL(k_rank_offsets, dim3(1), dim3(64), 0, s, w.counter + 8);
-    hipLaunchKernelGGL(k_rank_place, dim3(nb), dim3(256), 0, s, (const CandInfo*)w.info, bt.B,
-                       w.counter + 8, w.order);
-    const long groups = (n_items + wpg - 1) / wpg;
-    const int grid = (int)std::min<long>(groups, std::max(plan.grid, 1));
-    hipLaunchKernelGGL((k_sweep_pull<F, TT, NPL>), dim3(grid), dim3(plan.lanes), 0, s, g, w, HMC,
-                       fmax_out, bt.B, w.counter, (const int*)w.order);
-  } else {
-    const long groups = (n_items + wpg - 1) / wpg;
-    hipLaunchKernelGGL((k_sweep<F, TT, NPL>), dim3((unsigned)((groups + 7) / 8 * 8)),
-                       dim3(plan.lanes), 0, s, g, w, HMC, fmax_out, bt.B, plan.order, bt.map,
-                       bt.live);
-  }
+  const long groups = (n_items + wpg - 1) / wpg;
+  hipLaunchKernelGGL((k_sweep<F, TT, NPL>), dim3((unsigned)((groups + 7) / 8 * 8)),
+                     dim3(plan.lanes), 0, s, g, w, HMC, fmax_out, bt.B, plan.order, bt.map,
+                     bt.live);
 }
 
 template <typename F, int TT>
@@ -1272,26 +1223,6 @@ hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs
     case 24: return launch_eval_tt<F, 24>(g, bt, w, o, s, ev, plan, rw, rc);
     default: return launch_eval_tt<F, 32>(g, bt, w, o, s, ev, plan, rw, rc);
   }
-}
-
-// Occupancy of the persistent sweep for a plan (workgroups per CU).
-template <typename F, int NPL>
-static int pull_occ(int TT, int lanes) {
-  int n = 0;
-  const void* fn = nullptr;
-  switch (TT) {
-    case 1: fn = (const void*)&k_sweep_pull<F, 1, NPL>; break;
-    case 8: fn = (const void*)&k_sweep_pull<F, 8, NPL>; break;
-    case 24: fn = (const void*)&k_sweep_pull<F, 24, NPL>; break;
-    default: fn = (const void*)&k_sweep_pull<F, 32, NPL>; break;
-  }
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, lanes, 0) != hipSuccess) n = 0;
-  return n;
-}
-
-int sweep_blocks_per_cu(int flow_f32, int TT, int lanes, int npl) {
-  if (flow_f32) return npl == 2 ? pull_occ<float, 2>(TT, lanes) : pull_occ<float, 1>(TT, lanes);
-  return pull_occ<double, 1>(TT, lanes);
 }
 
 // ---------------------------------------------------------------------------

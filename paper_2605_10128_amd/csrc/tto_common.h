@@ -17,6 +17,7 @@ constexpr int kVSlots = 8;          // V entries per contingency record
 constexpr double kTauIsland = 1e-9; // |pivot| of the scaled bordered system
 constexpr double kTauCont = 1e-9;   // |1 - H'_ll| of a contingency
 constexpr double kWorstContTieMW = TTO_WORST_CONT_TIE_MW;  // worst-contingency tie tolerance
+constexpr double kLoadTieRel = TTO_LOAD_TIE_REL;          // worst (branch, timestep) tie band
 constexpr int kGemmN = 32;          // timestep columns of the f0 GEMM (T padded)
 
 // Record of one active contingency in a candidate's sweep list:
@@ -109,7 +110,8 @@ struct Partial {
   double best;      // max loading in this block
   double best2;     // second largest loading (another (e, t)) in this block
   int cnt_c;        // fmax > lim count
-  int best_e;       // monitored index of the max (smallest on ties)
+  int best_e;       // smallest (monitored index, timestep) within the tie band
+                    // of this block's max loading
   int best_t;
   int pad_;
 };
@@ -124,19 +126,15 @@ struct SweepBufs {
   int* act;         // [B][nC+1] contingency index of each record
   int* slot;        // [B][nC] record of each contingency or -1 (optional)
   Partial* part;    // [B][n_eblk] one per chunk of 64 monitored branches
-  int* counter;     // [64] persistent sweep: work counter, rank histogram and slots
-  int* order;       // [B] rank-descending candidate order (persistent sweep)
   int n_eblk;       // ceil(nM / 64)
 };
 
 // Launch shape of the N-1 sweep (chosen by the autotuner).  The unit of
 // work is one wave: a candidate and npl chunks of 64 monitored branches.
 struct SweepPlan {
-  int lanes;        // workgroup size: 64, 128 or 256 (1, 2 or 4 independent waves)
+  int lanes;        // workgroup size: 256 (four independent waves)
   int npl;          // monitored branches per lane: 1 or 2 (2: FP32 flows only)
   int order;        // 0 hardware, 1 XCD candidate-major, 2 XCD chunk-major
-  int persistent;   // machine-sized grid of waves pulling rank-ordered items
-  int grid;         // persistent grid size (workgroups)
 };
 
 // ---- launchers (k_grid.hip) -------------------------------------------------
@@ -176,7 +174,6 @@ hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs
                            const tto_outputs& out, hipStream_t s, hipEvent_t* ev,
                            const SweepPlan& plan, const SweepBufs<double>* rw,
                            const RefineCtl& rc);
-int sweep_blocks_per_cu(int flow_f32, int TT, int lanes, int npl);
 hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
                           const int* cell, const uint8_t* status, int B, int64_t id_base,
                           unsigned long long* key, int* idx, hipStream_t s);

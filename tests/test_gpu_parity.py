@@ -131,32 +131,58 @@ def test_repeat_runs_bitwise_identical(tto):
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
 
 
-# (lanes, branches per lane, order, persistent)
-PLANS = [(lanes, npl, order, False) for npl in (1, 2) for lanes in (64, 128, 256)
-         for order in (0, 1, 2)] + [(256, 1, 0, True), (256, 2, 0, True), (64, 2, 1, True)]
+# (lanes, branches per lane, order, persistent): the enabled launch shapes
+PLANS = [(256, npl, order, False) for npl in (1, 2) for order in (0, 1, 2)]
+# Shapes the library refuses (TTO_E_UNSUPPORTED): an earlier sweep in these
+# shapes (64/128-lane tiles, a persistent grid pulling rank-ordered tiles) did
+# not finish within a GPU test's time limit and no cause was found in its
+# code, so they stay off the GPU.
+DISABLED_PLANS = [(lanes, npl, order, False) for npl in (1, 2) for lanes in (64, 128)
+                  for order in (0, 1, 2)] + [(256, 1, 0, True), (256, 2, 0, True),
+                                             (64, 2, 1, True)]
 
 
 def test_sweep_plan_arguments_checked(tto):
     """Out-of-range launch shapes are refused; 2 branches per lane needs FP32
-    flows."""
+    flows; the disabled shapes are refused as unsupported."""
     w = gg.build_config(1)
     s = make_session(w, tto.TTO_FLOW_F64)
     for plan, code in (((32, 1, 0, 0), tto.TTO_E_INVALID), ((512, 1, 0, 0), tto.TTO_E_INVALID),
                        ((256, 3, 0, 0), tto.TTO_E_INVALID), ((256, 1, 3, 0), tto.TTO_E_INVALID),
-                       ((256, 1, 0, 2), tto.TTO_E_INVALID), ((256, 2, 0, 0), tto.TTO_E_UNSUPPORTED)):
+                       ((256, 1, 0, 2), tto.TTO_E_INVALID), ((256, 2, 0, 0), tto.TTO_E_UNSUPPORTED),
+                       *((p, tto.TTO_E_UNSUPPORTED) for p in DISABLED_PLANS if p[1] == 1)):
         with pytest.raises(tto.TTOError) as ei:
             tto.tto_set_sweep_plan(s.handle, *plan)
         assert ei.value.code == code, plan
-    s.set_sweep_plan(128, 1, 2, True)
-    assert tto.tto_get_sweep_plan(s.handle) == {"lanes": 128, "branches_per_lane": 1, "order": 2,
-                                                 "persistent": True}
+    s.set_sweep_plan(256, 1, 2, False)
+    assert tto.tto_get_sweep_plan(s.handle) == {"lanes": 256, "branches_per_lane": 1, "order": 2,
+                                                 "persistent": False}
+
+
+@pytest.mark.skip(reason="64/128-lane and persistent sweep shapes are disabled in the library: "
+                         "an earlier sweep in these shapes did not finish within a GPU test's "
+                         "time limit and no cause was found in its code")
+@pytest.mark.parametrize("plan", DISABLED_PLANS)
+def test_disabled_sweep_plans_agree(tto, plan):
+    """Kept for the disabled shapes: each would have to give bitwise the
+    outputs of the default plan."""
+    import torch
+    w = gg.build_config(3, B=96)
+    s = make_session(w, tto.TTO_FLOW_F32)
+    db = tto.device_batch(w.batch)
+    ref = to_numpy(s.evaluate(db, fmax=True))
+    s.set_sweep_plan(*plan)
+    o = to_numpy(s.evaluate(db, fmax=True))
+    torch.cuda.synchronize()
+    for key in o:
+        np.testing.assert_array_equal(o[key], ref[key], err_msg=f"{plan} {key}")
 
 
 @pytest.mark.parametrize("cfg,B", [(3, 96), (2, 300)])
 def test_sweep_plans_agree(tto, cfg, B):
-    """Every launch shape (workgroup size, branches per lane, item order, the
-    persistent grid) gives bitwise the same outputs, f^max included: the
-    chunk partials are reduced in one fixed order whatever the shape."""
+    """Every enabled launch shape (branches per lane, item order) gives
+    bitwise the same outputs, f^max included: the chunk partials are reduced
+    in one fixed order whatever the shape."""
     import torch
     w = gg.build_config(cfg, B=B)
     s = make_session(w, tto.TTO_FLOW_F32)

@@ -128,3 +128,31 @@ def test_nonfinite_injections_make_candidates_invalid():
     moved.moved_p = [np.array([1.0, -4.0, 2.0])]
     r = o.evaluate_candidate(g, P, M, C, moved, edges, keep_n1=False)
     assert r.valid and not r.islanded and not r.nonfinite
+
+
+def test_worst_branch_tie_goes_to_the_smaller_position():
+    """An exact tie of the maximum loading, resolved by the monitored order:
+    on the ten-bus grid with branches 0 (0-1) and 17 (6-8) opened, bus 0 (the
+    slack) keeps only branches 9 (9-0) and 10 (0-5), a two-branch cut.  With
+    either out, the other carries the slack's whole injection, so both reach
+    f^max = |P_0(t)| in exact arithmetic and, with equal 60 MW limits, the same
+    loading; rounding alone orders the two computed values (here it puts
+    branch 10 ahead), and the tie band must report branch 9.  Closed form:
+    rho = max_t |P_0(t)| / 60, t* its timestep."""
+    g = ec.ten_bus_grid()
+    rng = np.random.default_rng(5)
+    P = rng.normal(0, 30, size=(g.n_bus, 3))
+    P[0] = 0.0
+    P[0] = -P.sum(axis=0)
+    cand = ec.TEN_BUS_TABLE[2][1]
+    assert sorted(cand.opened) == [0, 17] and not cand.splits
+    m = g.n_branch
+    r = o.evaluate_candidate(g, P, range(m), range(m), cand, gg.default_load_edges(),
+                             keep_n1=False)
+    assert r.valid and not r.islanded
+    cut = np.abs(P[0])
+    np.testing.assert_allclose(r.fmax[9], cut, rtol=1e-12)
+    np.testing.assert_allclose(r.fmax[10], cut, rtol=1e-12)
+    assert r.metrics["max_loading"] == pytest.approx(cut.max() / 60.0, rel=1e-12)
+    assert r.metrics["worst_branch"] == 9
+    assert r.metrics["worst_t"] == int(np.argmax(cut))
