@@ -300,6 +300,26 @@ tto_status tto_archive_insert(tto_grid* grid, double* elite_fitness, int64_t* el
                               void* batch_ws, size_t batch_bytes, void* stream);
 
 /*
+ * Allocation-free form of tto_archive_insert, for callers that cannot
+ * allocate or pass a workspace (code under graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same update, with the same
+ * arguments less batch_ws, its per-cell scratch held in a static device
+ * array of the library (16 * TTO_ARCHIVE_NOALLOC_MAX_CELLS bytes = 1 MiB per
+ * GPU, kept until the process ends; its address is taken when the first
+ * grid is created on a device).  Calls no allocator.  The grid's device must
+ * be current (TTO_E_INVALID otherwise); n_cells above
+ * TTO_ARCHIVE_NOALLOC_MAX_CELLS returns TTO_E_WORKSPACE.  Every call on one
+ * GPU shares that array and clears the part it uses by a kernel before use:
+ * calls that overlap on one GPU (different streams, no ordering between
+ * them) race and must not be issued.  Asynchronous.
+ */
+#define TTO_ARCHIVE_NOALLOC_MAX_CELLS 65536
+tto_status tto_archive_insert_noalloc(tto_grid* grid, double* elite_fitness, int64_t* elite_id,
+                                      int32_t n_cells, const double* fitness,
+                                      const int32_t* cell, const uint8_t* status,
+                                      int32_t n_cand, int64_t id_base, void* stream);
+
+/*
  * Stage timing of tto_evaluate (tracing aid): when enabled, every
  * tto_evaluate records HIP events on its stream around its stages
  * (candidate set-up, N-1 sweep, finalize, FP64 refinement).

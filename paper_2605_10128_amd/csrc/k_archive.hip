@@ -13,6 +13,9 @@
 
 #include <limits.h>
 
+#include <mutex>
+#include <vector>
+
 namespace tto {
 
 __device__ inline unsigned long long order_key(double d) {
@@ -95,6 +98,36 @@ hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, con
   hipLaunchKernelGGL(k_arch_apply, dim3(cdiv(n_cells, 256)), dim3(256), 0, s, fit, idx, n_cells,
                      id_base, elite_fit, elite_id);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free insertion: per cell a 64-bit key, then per
+// cell a 32-bit winner index (the layout of the caller's workspace in
+// tto_archive_insert).  One copy per GPU, held until the process ends; its
+// address on each device is taken once, with that device current, when the
+// first grid is created there.
+static __device__ __align__(256) unsigned char scratch[16 * (size_t)kArchiveStaticCells];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // device address of `scratch`, per device
+}  // namespace
+
+hipError_t archive_scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* archive_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= (int)g_scratch_ptr.size()) return nullptr;
+  return g_scratch_ptr[device];
 }
 
 hipError_t launch_archive_genome(double* elite_fit, int64_t* elite_id, int* elite_genome,

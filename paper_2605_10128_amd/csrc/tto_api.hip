@@ -315,8 +315,12 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   }
   HIP_TRY(hipStreamSynchronize(s));
 
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  // device address of the allocation-free insertion's scratch (once per device)
+  HIP_TRY(archive_scratch_init(dev));
   tto_grid* g = new tto_grid();
-  HIP_TRY(hipGetDevice(&g->device));
+  g->device = dev;
   g->n_bus = n; g->m = m; g->slack = d->slack; g->T = d->n_timesteps; g->TT = tile_T(d->n_timesteps);
   g->nM = d->n_monitored; g->nC = d->n_contingency;
   g->flow_prec = d->flow_precision; g->gemm_prec = d->gemm_precision; g->max_batch = d->max_batch;
@@ -670,6 +674,30 @@ tto_status tto_archive_insert(tto_grid* g, double* elite_fitness, int64_t* elite
   if (batch_bytes < need) return fail(TTO_E_WORKSPACE, "batch_ws has %zu bytes, needs %zu", batch_bytes, need);
   unsigned long long* key = (unsigned long long*)batch_ws;
   int* idx = (int*)((char*)batch_ws + 8 * (size_t)n_cells);
+  HIP_TRY(launch_archive(elite_fitness, elite_id, n_cells, fitness, cell, status, n_cand, id_base,
+                         key, idx, (hipStream_t)stream));
+  return ok();
+}
+
+tto_status tto_archive_insert_noalloc(tto_grid* g, double* elite_fitness, int64_t* elite_id,
+                                      int32_t n_cells, const double* fitness, const int32_t* cell,
+                                      const uint8_t* status, int32_t n_cand, int64_t id_base,
+                                      void* stream) {
+  if (!g || !elite_fitness || !elite_id) return fail(TTO_E_INVALID, "grid or elite arrays NULL");
+  if (n_cells < 1) return fail(TTO_E_INVALID, "n_cells must be >= 1");
+  if (n_cells > TTO_ARCHIVE_NOALLOC_MAX_CELLS)
+    return fail(TTO_E_WORKSPACE, "n_cells %d exceeds the static scratch (%d cells)", n_cells,
+                TTO_ARCHIVE_NOALLOC_MAX_CELLS);
+  if (n_cand < 0) return fail(TTO_E_INVALID, "n_cand must be >= 0");
+  if (n_cand > 0 && (!fitness || !cell || !status)) return fail(TTO_E_INVALID, "batch arrays NULL");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->device)
+    return fail(TTO_E_INVALID, "device %d is current, the grid lives on device %d", dev, g->device);
+  void* ptr = archive_scratch(g->device);
+  if (!ptr) return fail(TTO_E_HIP, "static scratch of device %d has no address", g->device);
+  unsigned long long* key = (unsigned long long*)ptr;
+  int* idx = (int*)((char*)ptr + 8 * (size_t)n_cells);
   HIP_TRY(launch_archive(elite_fitness, elite_id, n_cells, fitness, cell, status, n_cand, id_base,
                          key, idx, (hipStream_t)stream));
   return ok();

@@ -174,6 +174,11 @@ hipError_t launch_evaluate(const GridDev& g, const BatchDev& bt, const SweepBufs
                            const tto_outputs& out, hipStream_t s, hipEvent_t* ev,
                            const SweepPlan& plan, const SweepBufs<double>* rw,
                            const RefineCtl& rc);
+// Allocation-free insertion: cells covered by the static scratch, its set-up
+// (once per device, that device current) and its device address (NULL before).
+constexpr int kArchiveStaticCells = 65536;
+hipError_t archive_scratch_init(int device);
+void* archive_scratch(int device);
 hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
                           const int* cell, const uint8_t* status, int B, int64_t id_base,
                           unsigned long long* key, int* idx, hipStream_t s);

@@ -22,6 +22,7 @@ TTO_GEMM_BF16X3, TTO_GEMM_F16X3 = 4, 5
 TTO_ST_ISLANDED, TTO_ST_INVALID, TTO_ST_REFINED, TTO_ST_REFINE_SKIPPED = 1, 2, 4, 8
 TTO_ST_NONFINITE = 0x10
 TTO_MAX_RANK, TTO_MAX_T, TTO_MAX_MOVED, TTO_MAX_LOAD_BINS = 8, 32, 64, 64
+TTO_ARCHIVE_NOALLOC_MAX_CELLS = 65536
 
 _vp = ct.c_void_p
 _i32 = ct.c_int32
@@ -104,6 +105,8 @@ def _load():
         "tto_evaluate": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp]),
         "tto_archive_insert": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, ct.c_int64, _vp,
                                       ct.c_size_t, _vp]),
+        "tto_archive_insert_noalloc": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32,
+                                              ct.c_int64, _vp]),
         "tto_profile_enable": (_i32, [_vp, _i32]),
         "tto_profile_read": (_i32, [_vp, P(ct.c_double)]),
         "tto_set_sweep_plan": (_i32, [_vp, _i32, _i32, _i32, _i32]),
@@ -165,7 +168,8 @@ _lib = _load()
 
 EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_create",
             "tto_grid_destroy", "tto_set_injections", "tto_get_base_flows", "tto_set_descriptor",
-            "tto_evaluate", "tto_archive_insert", "tto_profile_enable", "tto_profile_read",
+            "tto_evaluate", "tto_archive_insert", "tto_archive_insert_noalloc",
+            "tto_profile_enable", "tto_profile_read",
             "tto_set_sweep_plan", "tto_get_sweep_plan", "tto_autotune", "tto_set_refine",
             "tto_batch_gather", "tto_mlp_workspace_bytes", "tto_mlp_create", "tto_mlp_destroy",
             "tto_mlp_n_params", "tto_mlp_set_params", "tto_mlp_get_params", "tto_mlp_forward",
@@ -235,6 +239,14 @@ def tto_archive_insert(handle: int, elite_fit: int, elite_id: int, n_cells: int,
     _check(_lib.tto_archive_insert(_vp(handle), _vp(elite_fit), _vp(elite_id), n_cells,
                                    _vp(fitness), _vp(cell), _vp(status), n_cand, id_base, _vp(ws),
                                    ws_bytes, _vp(stream)))
+
+
+def tto_archive_insert_noalloc(handle: int, elite_fit: int, elite_id: int, n_cells: int,
+                               fitness: int, cell: int, status: int, n_cand: int, id_base: int,
+                               stream: int):
+    _check(_lib.tto_archive_insert_noalloc(_vp(handle), _vp(elite_fit), _vp(elite_id), n_cells,
+                                           _vp(fitness), _vp(cell), _vp(status), n_cand, id_base,
+                                           _vp(stream)))
 
 
 def tto_profile_enable(handle: int, enable: bool):
