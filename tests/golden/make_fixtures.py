@@ -14,9 +14,9 @@ plain      500 buses / 800 branches, T = 1, all 4096 candidates (f^max kept for
 Per candidate (Fitness function heuristics, every contingency re-solved from
 scratch in FP64): validity, islanding, the metrics lambda_o, lambda_c,
 lambda_c0, max loading and its arg-max (e*, t*, l*), the count of islanding
-contingencies, fitness lambda_f1 and the descriptor cell; f^max (stored in
-FP32, whose rounding, at most 1.2e-4 MW below 2000 MW, is far inside the
-1e-2 MW flow tolerance it is compared at); and the distances of each
+contingencies, fitness lambda_f1 and the descriptor cell; f^max (FP64, so
+that the FP64 flow tolerance of 1e-6 MW can be applied to it); and the
+distances of each
 discrete decision from its threshold in FP64, so that a test knows where a
 decision is unique at a given flow tolerance:
   margin0   min over monitored (e, t) of ||f'_e(t)| - fbar_e|   (lambda_c0)
@@ -98,7 +98,7 @@ def _one(args):
         n_crit_n1=met["n_crit_n1"], n_crit_n0=met["n_crit_n0"], max_loading=rho,
         worst_branch=met.get("worst_branch", -1), worst_t=met.get("worst_t", -1),
         worst_cont=met.get("worst_cont", -1), fitness=r.fitness, cell=r.cell,
-        fmax=r.fmax.astype(np.float32),
+        fmax=np.asarray(r.fmax, np.float64),
         margin0=float(np.abs(np.abs(f0M) - lim[:, None]).min()),
         gap=float(top[0] - top[1]) if top.size > 1 else np.inf,
         edge_dist=float(np.abs(edges - rho).min()),
@@ -144,7 +144,7 @@ def write(kind: str, procs: int):
     for k in SCALARS_F:
         out[k] = np.array([float(q.get(k, np.nan)) for q in recs], np.float64)
     nM, T, nC = len(w.M), w.P.shape[1], len(w.C)
-    fm = np.full((n_fmax, nM, T), np.nan, np.float32)
+    fm = np.full((n_fmax, nM, T), np.nan, np.float64)
     for i in range(n_fmax):
         if "fmax" in recs[i]:
             fm[i] = recs[i]["fmax"]

@@ -68,7 +68,7 @@ def check(fx, i, o, c, w, tol, dec, fmax=None, fmax_tol=None):
     else:
         near.append("c0")
         assert abs(int(o["n_crit_n0"][c]) - int(fx["n_crit_n0"][i])) <= 1, c
-    # lambda_o, lambda_c from f^max (oracle f^max stored in FP32, far inside tol)
+    # lambda_o, lambda_c from f^max (oracle f^max stored in FP64)
     fm = fx["fmax"][i].astype(np.float64) if i < len(fx["fmax"]) else None
     if fm is not None and not np.isnan(fm).any():
         n_over = int((fm > lim[:, None] - tol).sum())
