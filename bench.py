@@ -8,12 +8,14 @@ captured graph is timed afterwards and reported beside it.  Default workload:
 2000-bus / 3200-branch grid, 24 timesteps, 16384 candidates of rank 0..8,
 1200 monitored x 1600 contingencies, FP32 flows.
 
-A second leg measures the learned pre-screen on the same grid: the network is
-trained on exact evaluations over 8 injection scenarios, then a generation of
-65536 candidates of an unseen scenario is screened (forward, top 10%, gather)
-and the survivors evaluated exactly and archived, again as one captured graph;
-it reports the screened rate next to the exact one, the surrogate's error and
-the agreement of the screened archive with the exact-only archive.
+A second leg measures the learned pre-screen inside the MapElites loop on the
+same grid: the network is trained on exact evaluations of evolved children
+under 8 injection scenarios; on an unseen scenario a screened generation
+(65536 children varied, scored, the best-predicted 10% evaluated exactly and
+inserted) runs as one captured graph; it reports the screened rate next to
+the exact one, the network's error and recall on evolved children, and the
+repertoires reached by screened and exact-only generations at an equal
+exact-evaluation budget.
 
 Prints one JSON line.  `python bench.py --copy-calibration` instead runs a
 plain 1 GiB device copy, the reference for scaling HBM byte counters.
@@ -94,49 +96,61 @@ def copy_calibration():
 
 
 def surrogate_leg(s, w, args, exact_rate):
-    """Train the pre-screen on exact evaluations, then time screened generations."""
+    """The learned pre-screen inside the MapElites loop (Alg. 3).
+
+    Training data are exact evaluations of evolved children that the DC
+    evaluator itself produces: exact-only generations (16384 children each)
+    under 8 injection scenarios.  On an unseen scenario, one screened
+    generation (65536 children varied on the device, scored by the network,
+    the best-predicted tenth evaluated exactly and inserted) is captured as a
+    graph and timed; then screened and exact-only generations run from empty
+    repertoires at an equal exact-evaluation budget (6554 children evaluated
+    exactly per generation), and the repertoires they reach are compared.
+    Finally the 65536 children of one screened generation are all evaluated
+    exactly to measure the network's error and the screen's recall."""
     import numpy as np
     import torch
     import gridgen as gg
     from paper_2605_10128_amd import tto, screen
     grid, T, B = w.grid, w.P.shape[1], s.max_batch
     n_scen = 8
-    per = max(B, (args.train_samples // n_scen) // B * B)
     n_gen = args.screen
     keep = max(1, int(round(args.keep_frac * n_gen)))
     if keep > B:
         raise SystemExit(f"keep {keep} exceeds the evaluation batch {B}")
-    nb = gg.bridges(grid.n_bus, grid.from_bus, grid.to_bus)
-    d_bits = int((~nb).sum()) + len(w.split_table)
+    D = np.flatnonzero(~gg.bridges(grid.n_bus, grid.from_bus, grid.to_bus))
+    bus = np.array([b_ for b_, _ in w.split_table])
+    moved = [mv for _, mv in w.split_table]
+    gs = tto.GenomeSpace(s, bus, moved, D, args.evo_slots, args.evo_slots)
+    n_disc, n_act = len(D), len(bus)
+    d_bits = n_disc + n_act
     scen = [gg.make_injections(grid, T, 0x7000 + i) for i in range(n_scen + 1)]
     scale = screen.FeatureScale.fit([screen.injection_summary(P) for P in scen[:n_scen]])
+    gens_per_scen = max(1, args.train_samples // (n_scen * B))
     out = s.alloc_outputs(B)
     parts, t_eval, t0 = [], 0.0, time.perf_counter()
     for i in range(n_scen):
         s.set_injections(scen[i])
         ref = screen.unswitched_reference(s)
-        b = gg.make_candidates_ranked(grid, per, 0x8000 + i, w.split_table, P=scen[i])
-        off, ids, _ = gg.action_bits(grid, b, len(w.split_table))
-        tg, ok = [], []
-        for c0 in range(0, per, B):
-            db = tto.device_batch(b.subset(np.arange(c0, c0 + B)))
+        rep = tto.Repertoire(s, gs)
+        evo = tto.Evolver(s, gs, rep, B, seed=0x5C00 + i, outputs=out)
+        for _ in range(gens_per_scen):
             torch.cuda.synchronize()
             te = time.perf_counter()
-            s.evaluate(db, out)
+            evo.step()
             torch.cuda.synchronize()
             t_eval += time.perf_counter() - te
+            off, ids = screen.genome_bits(evo.children.cpu().numpy(), gs.n_a, n_disc, n_act)
             t_, ok_ = screen.targets_from_outputs(out, ref)
-            tg.append(t_)
-            ok.append(ok_)
-        parts.append([off, ids, scale.apply(screen.injection_summary(scen[i])),
-                      np.concatenate(tg), np.concatenate(ok)])
+            parts.append([off, ids, scale.apply(screen.injection_summary(scen[i])), t_, ok_])
+    n_train = n_scen * gens_per_scen * B
     tscale = screen.TargetScale.fit(np.concatenate([q[3] for q in parts]),
                                     np.concatenate([q[4] for q in parts]))
     for q in parts:
         q[3] = tscale.apply(q[3])
     data = screen.Dataset.assemble(parts, seed=1)
-    log(f"[bench] surrogate data: {n_scen * per} exact evaluations ({data.n} usable) in "
-        f"{time.perf_counter() - t0:.1f} s ({t_eval:.1f} s on the GPU)")
+    log(f"[bench] surrogate data: {n_train} exact evaluations of evolved children "
+        f"({data.n} usable) in {time.perf_counter() - t0:.1f} s ({t_eval:.1f} s on the GPU)")
     sc = screen.Screener(s, d_bits, T, width=512, max_screen=n_gen, max_keep=keep)
     t0 = time.perf_counter()
     losses = sc.train(data, epochs=args.epochs, batch=4096, lr=1e-3)
@@ -144,132 +158,141 @@ def surrogate_leg(s, w, args, exact_rate):
     t_train = time.perf_counter() - t0
     log(f"[bench] surrogate trained: losses {['%.4f' % x for x in losses]} in {t_train:.1f} s")
 
-    # unseen scenario, one generation
+    # unseen scenario: the screened generation as one captured graph
     P = scen[-1]
     s.set_injections(P)
     ref_h = screen.unswitched_reference(s)
-    gen = gg.make_candidates_ranked(grid, n_gen, 0x9999, w.split_table, P=P)
-    off, ids, _ = gg.action_bits(grid, gen, len(w.split_table))
-    exact = {}
-    for c0 in range(0, n_gen, B):
-        n = min(B, n_gen - c0)
-        o = s.evaluate(tto.device_batch(gen.subset(np.arange(c0, c0 + n))))
-        for k, v in o.items():
-            exact.setdefault(k, []).append(v.cpu().numpy())
-    exact = {k: np.concatenate(v) for k, v in exact.items()}
-    dev = s.device
-    db = tto.device_batch(gen)
-    off_d, ids_d = torch.as_tensor(off, device=dev), torch.as_tensor(ids, device=dev)
-    dense_d = sc.dense_rows(scale, P, n_gen)
-    so = s.alloc_outputs(keep)
-    arch = s.new_archive()
-    sc.screen_and_evaluate(db, off_d, ids_d, dense_d, keep, outputs=so)   # eager warm-up
-    launch = "eager"
-    graph = None
-    try:
-        with tto.Graph() as graph:
-            sc.screen_and_evaluate(db, off_d, ids_d, dense_d, keep, outputs=so)
-            s.archive_insert(arch, so)
-        launch = "hipGraph replay"
-    except tto.TTOError as e:
-        log(f"[bench] screened graph capture unavailable ({e}); eager launches")
-        graph = None
-
-    def one():
-        if graph is not None:
-            graph.launch()
-        else:
-            sc.screen_and_evaluate(db, off_d, ids_d, dense_d, keep, outputs=so)
-            s.archive_insert(arch, so)
-    for _ in range(2):
-        one()
+    row = scale.apply(screen.injection_summary(P))
     stream = torch.cuda.current_stream()
+    so = s.alloc_outputs(keep)
+    rep_t = tto.Repertoire(s, gs)
+    sev = tto.ScreenedEvolver(s, gs, rep_t, sc.net, n_gen, keep, seed=0xC0DE, dense_row=row,
+                              outputs=so)
+    for _ in range(2):
+        sev.step()
+    with tto.Graph() as graph:
+        sev.step()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.screen_steps):
-        one()
+        graph.launch()
     e1.record(stream)
     torch.cuda.synchronize()
     ms_gen = e0.elapsed_time(e1) / args.screen_steps
-    if graph is not None:
-        graph.close()
-    # stage split of one eager generation (events on the launch stream)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    ev[0].record(stream)
-    sc.predict(off_d, ids_d, dense_d, n_gen)
-    ev[1].record(stream)
-    sc.select(n_gen, keep)
-    ev[2].record(stream)
-    gb = sc.gather(db, keep)
-    ev[3].record(stream)
-    s.evaluate(gb, so)
-    s.archive_insert(arch, so)
-    ev[4].record(stream)
+    graph.close()
+    # the same generation without the screen, evaluating as many children exactly
+    rep_x = tto.Repertoire(s, gs)
+    xev = tto.Evolver(s, gs, rep_x, keep, seed=0xC0DE)
+    for _ in range(2):
+        xev.step()
+    with tto.Graph() as graph:
+        xev.step()
     torch.cuda.synchronize()
-    stage = [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    e0.record(stream)
+    for _ in range(args.screen_steps):
+        graph.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_exact_keep = e0.elapsed_time(e1) / args.screen_steps
+    graph.close()
 
-    idx = sc.idx[:keep].cpu().numpy()
-    sc.predict(off_d, ids_d, dense_d, n_gen)
+    # equal exact budget from empty repertoires: screened vs exact-only
+    G = args.loop_generations
+    rep_s, rep_e = tto.Repertoire(s, gs), tto.Repertoire(s, gs)
+    ev_s = tto.ScreenedEvolver(s, gs, rep_s, sc.net, n_gen, keep, seed=0xA11, dense_row=row)
+    ev_e = tto.Evolver(s, gs, rep_e, keep, seed=0xA11)
+    curve = []
+    for g in range(G):
+        ev_s.step()
+        ev_e.step()
+        if (g + 1) % max(1, G // 4) == 0 or g + 1 == G:
+            torch.cuda.synchronize()
+            curve.append([g + 1, int((rep_s.id >= 0).sum().item()),
+                          int((rep_e.id >= 0).sum().item())])
+    torch.cuda.synchronize()
+    fs, fe = rep_s.fitness.cpu().numpy(), rep_e.fitness.cpu().numpy()
+    os_, oe = rep_s.id.cpu().numpy() >= 0, rep_e.id.cpu().numpy() >= 0
+    both = os_ & oe
+    loop = {
+        "generations": G, "exact_evaluations_each": G * keep,
+        "screened": {"cells_filled": int(os_.sum()), "best_fitness": float(fs[os_].max()),
+                     "mean_elite_fitness": float(fs[os_].mean())},
+        "exact_only": {"cells_filled": int(oe.sum()), "best_fitness": float(fe[oe].max()),
+                       "mean_elite_fitness": float(fe[oe].mean())},
+        "cells_both": int(both.sum()),
+        "screened_elite_better": int((fs[both] > fe[both]).sum()),
+        "exact_only_elite_better": int((fe[both] > fs[both]).sum()),
+        "mean_fitness_gain_common_cells": float((fs[both] - fe[both]).mean()) if both.any() else None,
+        "cells_curve": curve,
+    }
+    log(f"[bench] screened loop: {G} generations, {G * keep} exact evaluations each: cells "
+        f"{loop['screened']['cells_filled']} vs {loop['exact_only']['cells_filled']}, best "
+        f"{loop['screened']['best_fitness']:.0f} vs {loop['exact_only']['best_fitness']:.0f}, "
+        f"screened better in {loop['screened_elite_better']} of {loop['cells_both']} common cells")
+
+    # the network on one generation of evolved children, all evaluated exactly
+    rep_m = tto.Repertoire(s, gs)
+    ev_m = tto.ScreenedEvolver(s, gs, rep_m, sc.net, n_gen, keep, seed=0xA11, dense_row=row)
+    for _ in range(G):
+        ev_m.step()
+    kids, _ = gs.vary(rep_m, 0xA11, n_gen)
+    torch.cuda.synchronize()
+    kids_h = kids.cpu().numpy()
+    exact = {}
+    for c0 in range(0, n_gen, B):
+        n = min(B, n_gen - c0)
+        o = s.evaluate(gs.expand(kids[c0:c0 + n].contiguous()))
+        for k, v in o.items():
+            exact.setdefault(k, []).append(v.cpu().numpy())
+    exact = {k: np.concatenate(v) for k, v in exact.items()}
+    off, ids = screen.genome_bits(kids_h, gs.n_a, n_disc, n_act)
+    dev = s.device
+    dense_d = sc.dense_rows(scale, P, n_gen)
+    sc.predict(torch.as_tensor(off, device=dev), torch.as_tensor(ids, device=dev), dense_d, n_gen)
+    idx = np.sort(sc.select(n_gen, keep).cpu().numpy())
     y = tscale.invert(sc.y[:n_gen].cpu().numpy()) + ref_h[None, :]
     valid = (exact["status"] & 3) == 0
     truth = screen.raw_targets(exact["max_loading"], exact["overload_mw"])
     fit = np.where(valid, exact["fitness"], -np.inf)
     best = np.argsort(-fit, kind="stable")[:keep]
     recall = len(np.intersect1d(best, idx)) / keep
-    d_lam = exact["overload_mw"] - np.expm1(ref_h[1]) * screen.OVERLOAD_SCALE_MW
-    lam_v = np.where(valid, d_lam, np.inf)
-    m_all, m_scr = d_lam[valid].mean(), d_lam[idx][valid[idx]].mean()
-    m_best = lam_v[np.argsort(lam_v, kind="stable")[:keep]].mean()
-
-    def archive(cands):
-        a = {}
-        for c in cands:
-            if valid[c]:
-                cell = int(exact["cell"][c])
-                e = a.get(cell)
-                if e is None or fit[c] > fit[e] or (fit[c] == fit[e] and c < e):
-                    a[cell] = c
-        return a
-    a_all, a_scr = archive(range(n_gen)), archive(idx.tolist())
-    kept = sum(1 for c, e in a_all.items() if a_scr.get(c) == e)
-    rng = np.random.default_rng(5)
-    kept_rand = []
-    for _ in range(8):   # the method without the network, same exact budget
-        a_r = archive(rng.choice(n_gen, size=keep, replace=False).tolist())
-        kept_rand.append(sum(1 for c, e in a_all.items() if a_r.get(c) == e))
+    lam = np.where(valid, exact["overload_mw"], np.inf)
+    m_all, m_scr = exact["overload_mw"][valid].mean(), exact["overload_mw"][idx][valid[idx]].mean()
+    m_best = lam[np.argsort(lam, kind="stable")[:keep]].mean()
     scr_rate = n_gen / (ms_gen / 1e3)
     res = {
         "value": scr_rate,
         "unit": "screened topologies/s",
         "ms_per_generation": ms_gen,
-        "launch": launch,
+        "launch": "hipGraph replay of one screened generation (vary 65536, features, forward, "
+                  "top 10%, expand, exact evaluation, insertion)",
         "generation": n_gen,
         "exactly_evaluated": keep,
         "vs_exact_only": scr_rate / exact_rate,
-        "stage_ms": {"mlp_forward": stage[0], "top_k": stage[1], "gather": stage[2],
-                     "exact_and_archive": stage[3]},
-        "train": {"exact_evaluations": n_scen * per, "usable": int(data.n),
+        "exact_only_generation_of_kept_size_ms": ms_exact_keep,
+        "screen_overhead_ms": ms_gen - ms_exact_keep,
+        "train": {"exact_evaluations": n_train, "usable": int(data.n),
+                  "source": f"exact-only MapElites generations of {B} children, "
+                            f"{gens_per_scen} per scenario",
                   "scenarios": n_scen, "epochs": args.epochs, "final_loss": losses[-1],
                   "train_s": t_train, "gpu_eval_s": t_eval, "width": 512,
                   "bits": d_bits, "dense": T},
         "error_unseen_scenario": {
+            "children": "one generation of evolved children of a screened run",
             "max_loading_mae": float(np.abs(y[valid, 0] - truth[valid, 0]).mean()),
             "log_overload_mae": float(np.abs(y[valid, 1] - truth[valid, 1]).mean()),
             "log_overload_corr": float(np.corrcoef(y[valid, 1], truth[valid, 1])[0, 1]),
         },
         "recall_top10pct_fitness": recall,
-        "overload_change_mw": {"screened": float(m_scr), "all": float(m_all),
-                               "best_tenth": float(m_best),
-                               "screen_efficiency": float((m_all - m_scr) /
-                                                          max(m_all - m_best, 1e-9))},
-        "archive": {"exact_only_cells": len(a_all), "screened_cells": len(a_scr),
-                    "identical_elites": kept,
-                    "identical_elites_random_tenth": float(np.mean(kept_rand))},
+        "overload_mw": {"screened_tenth": float(m_scr), "all": float(m_all),
+                        "best_tenth": float(m_best),
+                        "screen_efficiency": float((m_all - m_scr) / max(m_all - m_best, 1e-9))},
+        "loop_equal_exact_budget": loop,
     }
-    log(f"[bench] screened: {scr_rate:,.0f} topologies/s ({ms_gen:.2f} ms per {n_gen}), "
-        f"stages {['%.3f' % x for x in stage]} ms, recall {recall:.3f}, "
-        f"archive {kept}/{len(a_all)} identical")
+    log(f"[bench] screened: {scr_rate:,.0f} topologies/s ({ms_gen:.2f} ms per {n_gen}; exact-only "
+        f"generation of {keep}: {ms_exact_keep:.2f} ms), recall {recall:.3f}")
+    gs.close()
     return res
 
 
@@ -472,7 +495,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay check")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the screened leg")
     ap.add_argument("--train-samples", type=int, default=1 << 20)
-    ap.add_argument("--epochs", type=int, default=2)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--loop-generations", type=int, default=24,
+                    help="generations of the screened vs exact-only comparison")
     ap.add_argument("--screen", type=int, default=65536)
     ap.add_argument("--keep-frac", type=float, default=0.1)
     ap.add_argument("--screen-steps", type=int, default=10)

@@ -733,6 +733,34 @@ tto_status tto_generation(tto_grid* grid, const tto_genome_space* gs, const tto_
                           uint64_t seed, int32_t n_child, const tto_outputs* out, void* gen_ws,
                           size_t gen_bytes, void* batch_ws, size_t batch_bytes, void* stream);
 
+/*
+ * Screened generation: Alg. 3 with the learned pre-screen between variation
+ * and evaluation (an addition; the paper scores every child exactly).  On
+ * `stream`: tto_vary of n_child children; their feature rows taken from the
+ * genomes on the device (action a -> bit |D| + a, disconnection d -> bit d,
+ * the network's d_bits must equal |D| + |A|); tto_mlp_forward with dense_row
+ * (device FP32 [d_dense], the generation's injection summary, the same for
+ * every child); the n_keep children with the smallest predicted column 1
+ * (the overload term), ties to the lower child index, kept in child order;
+ * tto_genome_expand, tto_evaluate and insertion of the kept children as in
+ * tto_generation, the new elites' ids being generation * n_child + child
+ * index; then *generation += 1.  n_child <= the network's max_batch, n_keep
+ * <= min(n_child, the grid's max_batch).  gen_ws: device, 256-byte aligned,
+ * tto_screened_generation_bytes long; mlp_ws: the network's batch workspace
+ * (tto_mlp_workspace_bytes); batch_ws as for tto_evaluate.  `out` (may be
+ * NULL) receives the kept children's outputs, entry i for the i-th kept
+ * child.  No host synchronisation (capturable).
+ */
+tto_status tto_screened_generation_bytes(const tto_grid* grid, const tto_genome_space* gs,
+                                         const tto_mlp* net, int32_t n_child, int32_t n_keep,
+                                         size_t* bytes);
+tto_status tto_screened_generation(tto_grid* grid, const tto_genome_space* gs,
+                                   const tto_repertoire* rep, tto_mlp* net,
+                                   const float* dense_row, uint64_t seed, int32_t n_child,
+                                   int32_t n_keep, const tto_outputs* out, void* gen_ws,
+                                   size_t gen_bytes, void* mlp_ws, size_t mlp_bytes,
+                                   void* batch_ws, size_t batch_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

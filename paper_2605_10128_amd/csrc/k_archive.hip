@@ -63,8 +63,9 @@ __global__ __launch_bounds__(256) void k_arch_apply(const double* fit, const int
 }
 
 __global__ __launch_bounds__(256) void k_arch_apply_genome(
-    const double* fit, const int* idx, int n_cells, const int64_t* generation, int B,
-    double* elite_fit, int64_t* elite_id, int* elite_genome, const int* genomes, int G) {
+    const double* fit, const int* idx, int n_cells, const int64_t* generation,
+    const int* id_map, int id_stride, double* elite_fit, int64_t* elite_id, int* elite_genome,
+    const int* genomes, int G) {
   const int cl = blockIdx.x * 256 + threadIdx.x;
   if (cl >= n_cells) return;
   const int i = idx[cl];
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(256) void k_arch_apply_genome(
   const double f = fit[i];
   if (elite_id[cl] == -1 || f > elite_fit[cl]) {
     elite_fit[cl] = f;
-    elite_id[cl] = *generation * (int64_t)B + i;
+    elite_id[cl] = *generation * (int64_t)id_stride + (id_map ? id_map[i] : i);
     for (int j = 0; j < G; ++j) elite_genome[(size_t)cl * G + j] = genomes[(size_t)i * G + j];
   }
 }
@@ -133,11 +134,12 @@ void* archive_scratch(int device) {
 hipError_t launch_archive_genome(double* elite_fit, int64_t* elite_id, int* elite_genome,
                                  int n_cells, const double* fit, const int* cell,
                                  const uint8_t* status, int B, const int64_t* generation,
-                                 const int* genomes, int G, unsigned long long* key, int* idx,
-                                 hipStream_t s) {
+                                 const int* genomes, int G, const int* id_map, int id_stride,
+                                 unsigned long long* key, int* idx, hipStream_t s) {
   launch_winners(n_cells, fit, cell, status, B, key, idx, s);
   hipLaunchKernelGGL(k_arch_apply_genome, dim3(cdiv(n_cells, 256)), dim3(256), 0, s, fit, idx,
-                     n_cells, generation, B, elite_fit, elite_id, elite_genome, genomes, G);
+                     n_cells, generation, id_map, id_stride, elite_fit, elite_id, elite_genome,
+                     genomes, G);
   return hipGetLastError();
 }
 

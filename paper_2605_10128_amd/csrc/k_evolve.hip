@@ -44,6 +44,8 @@
 #include "tto_common.h"
 #include "tto_evolve.h"
 
+#include <algorithm>
+
 #include <limits.h>
 
 namespace tto {
@@ -390,6 +392,94 @@ __global__ void k_gen_bump(int64_t* generation) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *generation += 1;
 }
 
+// ---------------------------------------------------------------------------
+// Screened generation: the learned pre-screen's inputs taken from the
+// children's genomes, and the survivors compacted in child order.
+
+// Feature bits of each genome as a fixed-stride row of G entries: action a ->
+// bit n_disc + a, disconnection d -> bit d (the bit vocabulary of the
+// network: one bit per disconnectable branch, then one per action), empty or
+// out-of-range slots -> -1, which the network's first layer skips.
+__global__ __launch_bounds__(256) void k_genome_bits(GenomeDev gd, const int* __restrict__ genomes,
+                                                     int n, int* __restrict__ off,
+                                                     int* __restrict__ ids) {
+  const int G = gd.n_a + gd.n_d;
+  const size_t total = (size_t)n * G;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += stride) {
+    const int j = (int)(i % (size_t)G);
+    const int v = genomes[i];
+    int bit = -1;
+    if (j < gd.n_a) {
+      if (v >= 0 && v < gd.n_actions) bit = gd.n_disc + v;
+    } else if (v >= 0 && v < gd.n_disc) {
+      bit = v;
+    }
+    ids[i] = bit;
+  }
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c <= (size_t)n; c += stride)
+    off[c] = (int)(c * G);
+}
+
+// The same dense row for every child.
+__global__ __launch_bounds__(256) void k_bcast_row(const float* __restrict__ row, int d, int n,
+                                                   float* __restrict__ out) {
+  const size_t total = (size_t)n * d;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256)
+    out[i] = row[i % (size_t)d];
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int* __restrict__ p, int v, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_mark(const int* __restrict__ idx, int k, int n,
+                                              int* __restrict__ mask) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < k) {
+    const int c = idx[i];
+    if (c >= 0 && c < n) mask[c] = 1;
+  }
+}
+
+// Marked children in increasing index order (one workgroup, ordered scan).
+__global__ __launch_bounds__(1024) void k_compact_marked(const int* __restrict__ mask, int n,
+                                                         int cap, int* __restrict__ list) {
+  __shared__ int s_w[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < n; i0 += 1024) {
+    const int i = i0 + tid;
+    const bool f = i < n && mask[i] != 0;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) s_w[wid] = __popcll(m);
+    __syncthreads();
+    int pos = s_base;
+    for (int q = 0; q < wid; ++q) pos += s_w[q];
+    pos += __popcll(m & ((1ull << lane) - 1ull));
+    if (f && pos < cap) list[pos] = i;
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int q = 0; q < 16; ++q) t += s_w[q];
+      s_base += t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gather_rows(const int* __restrict__ src,
+                                                     const int* __restrict__ list, int k, int G,
+                                                     int* __restrict__ dst) {
+  const size_t total = (size_t)k * G;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+    const size_t r = i / (size_t)G;
+    dst[i] = src[(size_t)list[r] * G + (i - r * G)];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_vary(const GenomeDev& gd, const int64_t* elite_id, const int* elite_genome,
@@ -409,6 +499,38 @@ hipError_t launch_expand(const GenomeDev& gd, const int* genomes, int n, int* op
     const int grid = min((n + 255) / 256, 2048);
     hipLaunchKernelGGL(k_expand_copy, dim3(grid), dim3(256), 0, s, gd, genomes, n, moff, mbr);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_genome_bits(const GenomeDev& gd, const int* genomes, int n, int* off, int* ids,
+                              hipStream_t s) {
+  const long total = (long)n * (gd.n_a + gd.n_d) + n + 1;
+  const int grid = (int)std::min<long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_genome_bits, dim3(grid), dim3(256), 0, s, gd, genomes, n, off, ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_broadcast_row(const float* row, int d, int n, float* out, hipStream_t s) {
+  if (d <= 0 || n <= 0) return hipSuccess;
+  const int grid = (int)std::min<long>(((long)n * d + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_bcast_row, dim3(grid), dim3(256), 0, s, row, d, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_keep_in_order(const int* idx, int k, int n, int* mask, int* list, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min((n + 255) / 256, 1024)), dim3(256), 0, s, mask, 0,
+                     n);
+  if (k > 0)
+    hipLaunchKernelGGL(k_mark, dim3((k + 255) / 256), dim3(256), 0, s, idx, k, n, mask);
+  hipLaunchKernelGGL(k_compact_marked, dim3(1), dim3(1024), 0, s, (const int*)mask, n, k, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const int* src, const int* list, int k, int G, int* dst,
+                              hipStream_t s) {
+  if (k <= 0 || G <= 0) return hipSuccess;
+  const int grid = (int)std::min<long>(((long)k * G + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_gather_rows, dim3(grid), dim3(256), 0, s, src, list, k, G, dst);
   return hipGetLastError();
 }
 

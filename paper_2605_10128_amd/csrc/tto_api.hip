@@ -1302,8 +1302,157 @@ tto_status tto_generation(tto_grid* g, const tto_genome_space* gs, const tto_rep
   unsigned long long* key = (unsigned long long*)batch_ws;
   int* idx = (int*)((char*)batch_ws + 8 * (size_t)rep->n_cells);
   HIP_TRY(launch_archive_genome(rep->fitness, rep->id, rep->genome, rep->n_cells, o.fitness,
-                                o.cell, o.status, n_child, rep->generation, children, G, key,
-                                idx, s));
+                                o.cell, o.status, n_child, rep->generation, children, G,
+                                nullptr, n_child, key, idx, s));
+  HIP_TRY(launch_generation_bump(rep->generation, s));
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Screened generation: the learned pre-screen inside Alg. 3.
+namespace {
+
+struct ScreenLayout {
+  size_t children, b_mc, off, ids, dense, y, topk, mask, list, kept;
+  GenLayout gen;     // expanded batch and outputs of the kept children
+  size_t gen_at, total;
+};
+
+ScreenLayout screen_layout(const GenomeDev& d, int n_child, int n_keep, int d_dense) {
+  ScreenLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += round256(std::max<size_t>(bytes, 4)); return at; };
+  const size_t n = (size_t)n_child, k = (size_t)n_keep, G = (size_t)(d.n_a + d.n_d);
+  L.children = take(4 * n * G);
+  L.b_mc = take(4);
+  L.off = take(4 * (n + 1));
+  L.ids = take(4 * n * G);
+  L.dense = take(4 * n * (size_t)d_dense);
+  L.y = take(8 * n);
+  L.topk = take(4 * k);
+  L.mask = take(4 * n);
+  L.list = take(4 * k);
+  L.kept = take(4 * k * G);
+  L.gen = gen_layout(d, n_keep);
+  L.gen_at = o;
+  L.total = o + L.gen.total;
+  return L;
+}
+
+tto_status check_screen_args(const tto_grid* g, const tto_genome_space* gs, const tto_mlp* net,
+                             int32_t n_child, int32_t n_keep) {
+  if (!g || !gs || !net) return fail(TTO_E_INVALID, "grid, genome space or network is NULL");
+  const GenomeDev& d = gs->d;
+  if (d.n_a + d.n_d < 1) return fail(TTO_E_INVALID, "the genome has no slots");
+  if (net->d.d_bits != d.n_disc + d.n_actions)
+    return fail(TTO_E_INVALID, "network has %d input bits, the genome space %d (|D| + |A|)",
+                net->d.d_bits, d.n_disc + d.n_actions);
+  if (d.n_a + d.n_d > kMlpRowBits) return fail(TTO_E_INVALID, "genome longer than a feature row");
+  if (n_child < 1 || n_child > net->d.max_batch)
+    return fail(TTO_E_INVALID, "n_child %d not in 1..%d (the network's max_batch)", n_child,
+                net->d.max_batch);
+  if (n_keep < 1 || n_keep > n_child || n_keep > g->max_batch)
+    return fail(TTO_E_INVALID, "n_keep %d not in 1..min(n_child, max_batch=%d)", n_keep,
+                g->max_batch);
+  return TTO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tto_status tto_screened_generation_bytes(const tto_grid* g, const tto_genome_space* gs,
+                                         const tto_mlp* net, int32_t n_child, int32_t n_keep,
+                                         size_t* bytes) {
+  tto_status st = check_screen_args(g, gs, net, n_child, n_keep);
+  if (st != TTO_OK) return st;
+  if (!bytes) return fail(TTO_E_INVALID, "bytes is NULL");
+  *bytes = screen_layout(gs->d, n_child, n_keep, net->d.d_dense).total;
+  return ok();
+}
+
+tto_status tto_screened_generation(tto_grid* g, const tto_genome_space* gs,
+                                   const tto_repertoire* rep, tto_mlp* net,
+                                   const float* dense_row, uint64_t seed, int32_t n_child,
+                                   int32_t n_keep, const tto_outputs* out, void* gen_ws,
+                                   size_t gen_bytes, void* mlp_ws, size_t mlp_bytes,
+                                   void* batch_ws, size_t batch_bytes, void* stream) {
+  tto_status st = check_screen_args(g, gs, net, n_child, n_keep);
+  if (st != TTO_OK) return st;
+  if (!rep) return fail(TTO_E_INVALID, "repertoire is NULL");
+  const GenomeDev& d = gs->d;
+  const int G = d.n_a + d.n_d;
+  if (rep->n_cells < 1 || rep->n_cells > TTO_MAX_CELLS)
+    return fail(TTO_E_INVALID, "n_cells %d not in 1..%d", rep->n_cells, TTO_MAX_CELLS);
+  if (!rep->fitness || !rep->id || !rep->generation || !rep->genome)
+    return fail(TTO_E_INVALID, "repertoire arrays are NULL");
+  const int desc_cells = g->dev.desc_kind == TTO_DESC_PAPER
+                             ? TTO_PAPER_CELLS
+                             : g->dev.n_count_bins * g->dev.n_load_bins;
+  if (rep->n_cells != desc_cells)
+    return fail(TTO_E_INVALID, "n_cells %d differs from the descriptor's %d cells", rep->n_cells,
+                desc_cells);
+  const int dd = net->d.d_dense;
+  if (dd > 0 && !dense_row) return fail(TTO_E_INVALID, "dense_row is NULL");
+  const ScreenLayout L = screen_layout(d, n_child, n_keep, dd);
+  if (!gen_ws || ((uintptr_t)gen_ws & 255)) return fail(TTO_E_WORKSPACE, "gen_ws NULL or not 256-byte aligned");
+  if (gen_bytes < L.total) return fail(TTO_E_WORKSPACE, "gen_ws has %zu bytes, needs %zu", gen_bytes, L.total);
+  size_t mlp_need = 0;
+  carve_mlp_batch(&net->d, nullptr, &mlp_need);
+  if (!mlp_ws || ((uintptr_t)mlp_ws & 255)) return fail(TTO_E_WORKSPACE, "mlp_ws NULL or misaligned");
+  if (mlp_bytes < mlp_need) return fail(TTO_E_WORKSPACE, "mlp_ws has %zu bytes, needs %zu", mlp_bytes, mlp_need);
+  if (!batch_ws || ((uintptr_t)batch_ws & 255) || batch_bytes < 16 * (size_t)rep->n_cells)
+    return fail(TTO_E_WORKSPACE, "batch_ws NULL, misaligned or too small");
+  char* w = (char*)gen_ws;
+  hipStream_t s = (hipStream_t)stream;
+  int* children = (int*)(w + L.children);
+  int* off = (int*)(w + L.off);
+  int* ids = (int*)(w + L.ids);
+  float* dense = (float*)(w + L.dense);
+  float* y = (float*)(w + L.y);
+  int* topk = (int*)(w + L.topk);
+  int* list = (int*)(w + L.list);
+  int* kept = (int*)(w + L.kept);
+  // variation, the children's features, the network's predictions
+  HIP_TRY(launch_vary(d, rep->id, rep->genome, rep->n_cells, seed, rep->generation, n_child,
+                      children, (int*)(w + L.b_mc), s));
+  HIP_TRY(launch_genome_bits(d, children, n_child, off, ids, s));
+  if (dd > 0) HIP_TRY(launch_broadcast_row(dense_row, dd, n_child, dense, s));
+  const MlpBatch mb = carve_mlp_batch(&net->d, mlp_ws, &mlp_need);
+  mlp_forward(net->p, mb, off, ids, dd > 0 ? dense : nullptr, n_child, y, s);
+  // the n_keep smallest predicted overload terms, in child order
+  topk_smallest(y + 1, n_child, 2, n_keep, topk, s);
+  HIP_TRY(launch_keep_in_order(topk, n_keep, n_child, (int*)(w + L.mask), list, s));
+  HIP_TRY(launch_gather_rows(children, list, n_keep, G, kept, s));
+  // exact evaluation and insertion of the survivors (ids: child index)
+  char* gw = w + L.gen_at;
+  const GenLayout& GL = L.gen;
+  tto_batch bt;
+  bt.n_cand = n_keep;
+  bt.n_open_slots = d.n_d;
+  bt.n_split_slots = d.n_a;
+  bt.open = d.n_d ? (const int32_t*)(gw + GL.open) : nullptr;
+  bt.split_bus = d.n_a ? (const int32_t*)(gw + GL.sbus) : nullptr;
+  bt.moved_off = d.n_a ? (const int32_t*)(gw + GL.moff) : nullptr;
+  bt.moved_br = d.n_a ? (const int32_t*)(gw + GL.mbr) : nullptr;
+  bt.moved_p_mw = nullptr;
+  HIP_TRY(launch_expand(d, kept, n_keep, (int*)bt.open, (int*)bt.split_bus, (int*)bt.moved_off,
+                        (int*)bt.moved_br, s));
+  tto_outputs o;
+  memset(&o, 0, sizeof(o));
+  if (out) o = *out;
+  if (!o.status) o.status = (uint8_t*)(gw + GL.status);
+  if (!o.fitness) o.fitness = (double*)(gw + GL.fit);
+  if (!o.cell) o.cell = (int32_t*)(gw + GL.cell);
+  st = tto_evaluate(g, &bt, &o, batch_ws, batch_bytes, stream);
+  if (st != TTO_OK) return st;
+  unsigned long long* key = (unsigned long long*)batch_ws;
+  int* idx = (int*)((char*)batch_ws + 8 * (size_t)rep->n_cells);
+  HIP_TRY(launch_archive_genome(rep->fitness, rep->id, rep->genome, rep->n_cells, o.fitness,
+                                o.cell, o.status, n_keep, rep->generation, kept, G, list,
+                                n_child, key, idx, s));
   HIP_TRY(launch_generation_bump(rep->generation, s));
   return ok();
 }

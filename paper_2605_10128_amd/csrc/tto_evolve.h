@@ -36,12 +36,25 @@ hipError_t launch_vary(const GenomeDev& gd, const int64_t* elite_id, const int* 
 hipError_t launch_expand(const GenomeDev& gd, const int* genomes, int n, int* open, int* sbus,
                          int* moff, int* mbr, hipStream_t s);
 
+// Insertion with genomes; the new elite's id is generation * id_stride +
+// (id_map ? id_map[i] : i) for batch entry i.
 hipError_t launch_archive_genome(double* elite_fit, int64_t* elite_id, int* elite_genome,
                                  int n_cells, const double* fit, const int* cell,
                                  const uint8_t* status, int B, const int64_t* generation,
-                                 const int* genomes, int G, unsigned long long* key, int* idx,
-                                 hipStream_t s);
+                                 const int* genomes, int G, const int* id_map, int id_stride,
+                                 unsigned long long* key, int* idx, hipStream_t s);
 
 hipError_t launch_generation_bump(int64_t* generation, hipStream_t s);
+
+// Screened generation helpers: the network's feature rows from genomes
+// (off [n+1], ids [n*G]), one dense row broadcast to n rows, the k chosen
+// children (idx) listed in increasing index order (mask [n] scratch), and a
+// row gather dst[i] = src[list[i]].
+hipError_t launch_genome_bits(const GenomeDev& gd, const int* genomes, int n, int* off, int* ids,
+                              hipStream_t s);
+hipError_t launch_broadcast_row(const float* row, int d, int n, float* out, hipStream_t s);
+hipError_t launch_keep_in_order(const int* idx, int k, int n, int* mask, int* list, hipStream_t s);
+hipError_t launch_gather_rows(const int* src, const int* list, int k, int G, int* dst,
+                              hipStream_t s);
 
 }  // namespace tto

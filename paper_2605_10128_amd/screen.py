@@ -105,6 +105,24 @@ class TargetScale:
         return np.asarray(y, dtype=np.float64) * self.sd + self.mu
 
 
+def genome_bits(genomes, n_a: int, n_disc: int, n_actions: int):
+    """Feature rows of genomes [n][n_a + n_d] as CSR (offsets, ids), the
+    vocabulary of the device's screened generation: action a -> bit
+    n_disc + a, disconnection d (an index into D) -> bit d; empty and
+    out-of-range slots give no bit."""
+    g = np.asarray(genomes, dtype=np.int64)
+    a, d = g[:, :n_a], g[:, n_a:]
+    ids = np.concatenate([np.where((a >= 0) & (a < n_actions), n_disc + a, -1),
+                          np.where((d >= 0) & (d < n_disc), d, -1)], axis=1)
+    big = np.iinfo(np.int64).max
+    ids = np.sort(np.where(ids >= 0, ids, big), axis=1)
+    ok = ids != big
+    # repeated entries of a row give one bit (the network reads a set)
+    ok[:, 1:] &= ids[:, 1:] != ids[:, :-1]
+    off = np.concatenate([[0], np.cumsum(ok.sum(axis=1))]).astype(np.int32)
+    return off, ids[ok].astype(np.int32)
+
+
 class Dataset:
     """Training samples on the device: CSR bits, dense rows, targets."""
 

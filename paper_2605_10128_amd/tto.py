@@ -152,6 +152,10 @@ def _load():
         "tto_vary": (_i32, [_vp, _vp, _vp, _i32, ct.c_uint64, _vp, _i32, _vp, _vp, _vp]),
         "tto_genome_expand": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, ct.c_int64, _vp]),
         "tto_generation_bytes": (_i32, [_vp, _vp, _i32, P(ct.c_size_t)]),
+        "tto_screened_generation_bytes": (_i32, [_vp, _vp, _vp, _i32, _i32, P(ct.c_size_t)]),
+        "tto_screened_generation": (_i32, [_vp, _vp, P(tto_repertoire), _vp, _vp, ct.c_uint64,
+                                           _i32, _i32, _vp, _vp, ct.c_size_t, _vp, ct.c_size_t,
+                                           _vp, ct.c_size_t, _vp]),
         "tto_generation": (_i32, [_vp, _vp, P(tto_repertoire), ct.c_uint64, _i32,
                                   P(tto_outputs), _vp, ct.c_size_t, _vp, ct.c_size_t, _vp]),
         "tto_autotune": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
@@ -180,7 +184,8 @@ EXPORTED = ["tto_version", "tto_last_error", "tto_workspace_bytes", "tto_grid_cr
             "tto_generation_bytes", "tto_generation", "tto_worst_k_bytes",
             "tto_worst_contingencies", "tto_busbar_set_bytes", "tto_busbar_set_create",
             "tto_busbar_set_destroy", "tto_busbar_bytes", "tto_busbar_evaluate",
-            "tto_ptdf_bytes", "tto_ptdf_build", "tto_bridges"]
+            "tto_ptdf_bytes", "tto_ptdf_build", "tto_bridges", "tto_screened_generation_bytes",
+            "tto_screened_generation"]
 
 
 def _check(code: int):
@@ -497,6 +502,25 @@ def tto_generation(grid: int, gs: int, rep: tto_repertoire, seed: int, n_child: 
     _check(_lib.tto_generation(_vp(grid), _vp(gs), ct.byref(rep), ct.c_uint64(seed),
                                int(n_child), ct.byref(outputs) if outputs is not None else None,
                                _vp(gen_ws), gen_bytes, _vp(batch_ws), batch_bytes, _vp(stream)))
+
+
+def tto_screened_generation_bytes(grid: int, gs: int, net: int, n_child: int,
+                                  n_keep: int) -> int:
+    n = ct.c_size_t()
+    _check(_lib.tto_screened_generation_bytes(_vp(grid), _vp(gs), _vp(net), int(n_child),
+                                              int(n_keep), ct.byref(n)))
+    return n.value
+
+
+def tto_screened_generation(grid: int, gs: int, rep: tto_repertoire, net: int, dense_row: int,
+                            seed: int, n_child: int, n_keep: int,
+                            outputs: Optional["tto_outputs"], gen_ws: int, gen_bytes: int,
+                            mlp_ws: int, mlp_bytes: int, batch_ws: int, batch_bytes: int,
+                            stream: int):
+    _check(_lib.tto_screened_generation(
+        _vp(grid), _vp(gs), ct.byref(rep), _vp(net), _vp(dense_row), ct.c_uint64(seed),
+        int(n_child), int(n_keep), ct.byref(outputs) if outputs is not None else None,
+        _vp(gen_ws), gen_bytes, _vp(mlp_ws), mlp_bytes, _vp(batch_ws), batch_bytes, _vp(stream)))
 
 
 class Graph:
@@ -967,6 +991,47 @@ class Evolver:
         tto_generation(s.handle, self.gs.handle, self._rep_struct, self.seed, self.n_child,
                        self._out_struct, _ptr(self.gen_ws), self.gen_bytes, _ptr(s.batch_ws),
                        s.batch_bytes, s.stream)
+
+
+class ScreenedEvolver:
+    """One screened device generation per call (tto_screened_generation):
+    n_child children varied, scored by the network `net`, the n_keep most
+    promising evaluated exactly and inserted.  Buffers are pre-allocated, so
+    calls can be captured in a Graph and replayed.  `dense_row` is the
+    device FP32 [d_dense] injection summary of the current injections."""
+
+    def __init__(self, session: "Session", gs: GenomeSpace, rep: Repertoire, net: "Surrogate",
+                 n_child: int, n_keep: int, seed: int, dense_row=None, outputs=None):
+        torch = session.torch
+        self.session, self.gs, self.rep, self.net = session, gs, rep, net
+        self.n_child, self.n_keep, self.seed = int(n_child), int(n_keep), int(seed)
+        self.gen_bytes = tto_screened_generation_bytes(session.handle, gs.handle, net.handle,
+                                                       self.n_child, self.n_keep)
+        self.gen_ws = torch.empty(self.gen_bytes, dtype=torch.uint8, device=session.device)
+        d = int(net.desc.d_dense)
+        self.dense_row = torch.zeros(max(d, 1), dtype=torch.float32, device=session.device)
+        if dense_row is not None:
+            self.set_dense_row(dense_row)
+        self.outputs = outputs
+        self._rep_struct = rep.struct()
+        self._out_struct = (tto_outputs(*[_ptr(outputs.get(f)) for f in OUTPUT_FIELDS])
+                            if outputs is not None else None)
+        G = gs.G
+        self.children = self.gen_ws[: 4 * self.n_child * G].view(torch.int32).view(self.n_child, G)
+
+    def set_dense_row(self, row):
+        """Copy a new injection summary into the buffer the calls read."""
+        t = self.session.torch.as_tensor(np.ascontiguousarray(row, dtype=np.float32),
+                                         device=self.session.device)
+        self.dense_row[: t.numel()].copy_(t)
+
+    def step(self):
+        s = self.session
+        tto_screened_generation(s.handle, self.gs.handle, self._rep_struct, self.net.handle,
+                                _ptr(self.dense_row), self.seed, self.n_child, self.n_keep,
+                                self._out_struct, _ptr(self.gen_ws), self.gen_bytes,
+                                _ptr(self.net.bws), self.net.bbytes, _ptr(s.batch_ws),
+                                s.batch_bytes, s.stream)
 
 
 class BusbarSet:
