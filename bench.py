@@ -166,8 +166,10 @@ def surrogate_leg(s, w, args, exact_rate):
     stream = torch.cuda.current_stream()
     so = s.alloc_outputs(keep)
     rep_t = tto.Repertoire(s, gs)
+    gain = dict(rule=tto.TTO_SCREEN_GAIN, y_mu=tuple(tscale.mu), y_sd=tuple(tscale.sd),
+                ref=tuple(ref_h), overload_scale_mw=screen.OVERLOAD_SCALE_MW)
     sev = tto.ScreenedEvolver(s, gs, rep_t, sc.net, n_gen, keep, seed=0xC0DE, dense_row=row,
-                              outputs=so)
+                              outputs=so, **gain)
     for _ in range(2):
         sev.step()
     with tto.Graph() as graph:
@@ -197,43 +199,52 @@ def surrogate_leg(s, w, args, exact_rate):
     ms_exact_keep = e0.elapsed_time(e1) / args.screen_steps
     graph.close()
 
-    # equal exact budget from empty repertoires: screened vs exact-only
+    # equal exact budget from empty repertoires: exact-only generations of
+    # `keep` children against screened generations of n_gen children under
+    # both screen rules
     G = args.loop_generations
-    rep_s, rep_e = tto.Repertoire(s, gs), tto.Repertoire(s, gs)
-    ev_s = tto.ScreenedEvolver(s, gs, rep_s, sc.net, n_gen, keep, seed=0xA11, dense_row=row)
-    ev_e = tto.Evolver(s, gs, rep_e, keep, seed=0xA11)
+    runs = {"exact_only": None, "screened_gain": gain, "screened_overload": {}}
+    reps, evs = {}, {}
+    for name, rule in runs.items():
+        reps[name] = tto.Repertoire(s, gs)
+        if rule is None:
+            evs[name] = tto.Evolver(s, gs, reps[name], keep, seed=0xA11)
+        else:
+            evs[name] = tto.ScreenedEvolver(s, gs, reps[name], sc.net, n_gen, keep, seed=0xA11,
+                                            dense_row=row, **rule)
     curve = []
     for g in range(G):
-        ev_s.step()
-        ev_e.step()
+        for name in runs:
+            evs[name].step()
         if (g + 1) % max(1, G // 4) == 0 or g + 1 == G:
             torch.cuda.synchronize()
-            curve.append([g + 1, int((rep_s.id >= 0).sum().item()),
-                          int((rep_e.id >= 0).sum().item())])
+            curve.append([g + 1] + [int((reps[n].id >= 0).sum().item()) for n in runs])
     torch.cuda.synchronize()
-    fs, fe = rep_s.fitness.cpu().numpy(), rep_e.fitness.cpu().numpy()
-    os_, oe = rep_s.id.cpu().numpy() >= 0, rep_e.id.cpu().numpy() >= 0
-    both = os_ & oe
-    loop = {
-        "generations": G, "exact_evaluations_each": G * keep,
-        "screened": {"cells_filled": int(os_.sum()), "best_fitness": float(fs[os_].max()),
-                     "mean_elite_fitness": float(fs[os_].mean())},
-        "exact_only": {"cells_filled": int(oe.sum()), "best_fitness": float(fe[oe].max()),
-                       "mean_elite_fitness": float(fe[oe].mean())},
-        "cells_both": int(both.sum()),
-        "screened_elite_better": int((fs[both] > fe[both]).sum()),
-        "exact_only_elite_better": int((fe[both] > fs[both]).sum()),
-        "mean_fitness_gain_common_cells": float((fs[both] - fe[both]).mean()) if both.any() else None,
-        "cells_curve": curve,
-    }
-    log(f"[bench] screened loop: {G} generations, {G * keep} exact evaluations each: cells "
-        f"{loop['screened']['cells_filled']} vs {loop['exact_only']['cells_filled']}, best "
-        f"{loop['screened']['best_fitness']:.0f} vs {loop['exact_only']['best_fitness']:.0f}, "
-        f"screened better in {loop['screened_elite_better']} of {loop['cells_both']} common cells")
+    fit_of = {n: reps[n].fitness.cpu().numpy() for n in runs}
+    occ_of = {n: reps[n].id.cpu().numpy() >= 0 for n in runs}
+    loop = {"generations": G, "exact_evaluations_each": G * keep,
+            "cells_curve_columns": ["generation"] + list(runs), "cells_curve": curve}
+    fe, oe = fit_of["exact_only"], occ_of["exact_only"]
+    for n in runs:
+        f, o = fit_of[n], occ_of[n]
+        both = o & oe
+        loop[n] = {"cells_filled": int(o.sum()), "best_fitness": float(f[o].max()),
+                   "mean_elite_fitness": float(f[o].mean())}
+        if n != "exact_only":
+            loop[n].update({
+                "cells_both_with_exact_only": int(both.sum()),
+                "elite_better_than_exact_only": int((f[both] > fe[both]).sum()),
+                "elite_worse_than_exact_only": int((f[both] < fe[both]).sum()),
+                "mean_fitness_gain_common_cells":
+                    float((f[both] - fe[both]).mean()) if both.any() else None})
+    log("[bench] screened loop: " + ", ".join(
+        f"{n} {loop[n]['cells_filled']} cells best {loop[n]['best_fitness']:.0f}" for n in runs)
+        + f" ({G} generations, {G * keep} exact evaluations each)")
 
     # the network on one generation of evolved children, all evaluated exactly
     rep_m = tto.Repertoire(s, gs)
-    ev_m = tto.ScreenedEvolver(s, gs, rep_m, sc.net, n_gen, keep, seed=0xA11, dense_row=row)
+    ev_m = tto.ScreenedEvolver(s, gs, rep_m, sc.net, n_gen, keep, seed=0xA11, dense_row=row,
+                               **gain)
     for _ in range(G):
         ev_m.step()
     kids, _ = gs.vary(rep_m, 0xA11, n_gen)
@@ -266,7 +277,8 @@ def surrogate_leg(s, w, args, exact_rate):
         "unit": "screened topologies/s",
         "ms_per_generation": ms_gen,
         "launch": "hipGraph replay of one screened generation (vary 65536, features, forward, "
-                  "top 10%, expand, exact evaluation, insertion)",
+                  "the 10% with the largest predicted gain over their predicted cells' elites, "
+                  "expand, exact evaluation, insertion)",
         "generation": n_gen,
         "exactly_evaluated": keep,
         "vs_exact_only": scr_rate / exact_rate,

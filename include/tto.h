@@ -740,8 +740,16 @@ tto_status tto_generation(tto_grid* grid, const tto_genome_space* gs, const tto_
  * genomes on the device (action a -> bit |D| + a, disconnection d -> bit d,
  * the network's d_bits must equal |D| + |A|); tto_mlp_forward with dense_row
  * (device FP32 [d_dense], the generation's injection summary, the same for
- * every child); the n_keep children with the smallest predicted column 1
- * (the overload term), ties to the lower child index, kept in child order;
+ * every child); the n_keep children with the smallest score, ties to the
+ * lower child index, kept in child order.  The score (cfg NULL or rule
+ * TTO_SCREEN_OVERLOAD) is the predicted column 1 (the overload term).  With
+ * TTO_SCREEN_GAIN the outputs are de-standardised by cfg; each child's
+ * predicted cell is taken from its genome (switch count, or the three-axis
+ * map's counts) and the predicted maximum loading, its predicted fitness is
+ * minus the predicted overload, and it is predicted to enter the repertoire
+ * if that cell is empty or its elite is worse; of the children predicted to
+ * enter each cell, the best predicted (ties to the lower index) comes
+ * first, every other child is ranked by column 1;
  * tto_genome_expand, tto_evaluate and insertion of the kept children as in
  * tto_generation, the new elites' ids being generation * n_child + child
  * index; then *generation += 1.  n_child <= the network's max_batch, n_keep
@@ -749,15 +757,28 @@ tto_status tto_generation(tto_grid* grid, const tto_genome_space* gs, const tto_
  * tto_screened_generation_bytes long; mlp_ws: the network's batch workspace
  * (tto_mlp_workspace_bytes); batch_ws as for tto_evaluate.  `out` (may be
  * NULL) receives the kept children's outputs, entry i for the i-th kept
- * child.  No host synchronisation (capturable).
+ * child, and kept_out (device int32 [n_keep], may be NULL) their child
+ * indices.  No host synchronisation (capturable).
  */
+#define TTO_SCREEN_OVERLOAD 0   /* keep the smallest predicted column 1 */
+#define TTO_SCREEN_GAIN 1       /* first the best-predicted child of every
+                                   cell it is predicted to enter, then the
+                                   smallest predicted column 1 */
+typedef struct {
+  int32_t rule;               /* TTO_SCREEN_OVERLOAD or TTO_SCREEN_GAIN */
+  double y_mu[2], y_sd[2];    /* raw target = output * y_sd + y_mu + ref */
+  double ref[2];              /* (the network learns standardised targets
+                                 relative to the unswitched grid) */
+  double overload_scale_mw;   /* column 1 is log1p(overload / this scale) */
+} tto_screen_cfg;
 tto_status tto_screened_generation_bytes(const tto_grid* grid, const tto_genome_space* gs,
                                          const tto_mlp* net, int32_t n_child, int32_t n_keep,
                                          size_t* bytes);
 tto_status tto_screened_generation(tto_grid* grid, const tto_genome_space* gs,
                                    const tto_repertoire* rep, tto_mlp* net,
-                                   const float* dense_row, uint64_t seed, int32_t n_child,
-                                   int32_t n_keep, const tto_outputs* out, void* gen_ws,
+                                   const float* dense_row, const tto_screen_cfg* cfg,
+                                   uint64_t seed, int32_t n_child, int32_t n_keep,
+                                   const tto_outputs* out, int32_t* kept_out, void* gen_ws,
                                    size_t gen_bytes, void* mlp_ws, size_t mlp_bytes,
                                    void* batch_ws, size_t batch_bytes, void* stream);
 

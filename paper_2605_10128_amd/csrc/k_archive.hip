@@ -92,6 +92,13 @@ static void launch_winners(int n_cells, const double* fit, const int* cell,
   }
 }
 
+hipError_t launch_cell_winners(int n_cells, const double* fit, const int* cell,
+                               const uint8_t* status, int B, unsigned long long* key, int* idx,
+                               hipStream_t s) {
+  launch_winners(n_cells, fit, cell, status, B, key, idx, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_archive(double* elite_fit, int64_t* elite_id, int n_cells, const double* fit,
                           const int* cell, const uint8_t* status, int B, int64_t id_base,
                           unsigned long long* key, int* idx, hipStream_t s) {

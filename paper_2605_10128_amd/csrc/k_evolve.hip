@@ -46,6 +46,7 @@
 
 #include <algorithm>
 
+#include <float.h>
 #include <limits.h>
 
 namespace tto {
@@ -470,6 +471,63 @@ __global__ __launch_bounds__(1024) void k_compact_marked(const int* __restrict__
   }
 }
 
+// Archive-aware screen, first step: each child's predicted cell (from its
+// genome: switch count, or the three-axis map's counts; and the predicted
+// maximum loading) and predicted fitness (minus the predicted overload), and
+// whether it is predicted to enter the repertoire (its predicted cell empty,
+// or its predicted fitness above that cell's elite); children that are not
+// get status INVALID so that the per-cell winner step ignores them.
+__global__ __launch_bounds__(256) void k_screen_predict(
+    GenomeDev gd, const int* __restrict__ genomes, int n, const float* __restrict__ y,
+    ScreenScoreCfg sc, const double* __restrict__ edges, const double* __restrict__ elite_fit,
+    const int64_t* __restrict__ elite_id, double* __restrict__ fit_pred,
+    int* __restrict__ cell_pred, uint8_t* __restrict__ st_pred) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int G = gd.n_a + gd.n_d;
+  const int* g = genomes + (size_t)i * G;
+  int na = 0, nd = 0, moved = 0;
+  for (int j = 0; j < gd.n_a; ++j) {
+    const int v = g[j];
+    if (v >= 0 && v < gd.n_actions) { ++na; moved += action_len(gd, v); }
+  }
+  for (int j = 0; j < gd.n_d; ++j) {
+    const int v = g[gd.n_a + j];
+    nd += (v >= 0 && v < gd.n_disc) ? 1 : 0;
+  }
+  const double rho = (double)y[2 * i] * sc.sd[0] + sc.mu[0] + sc.ref[0];
+  const double lo = (double)y[2 * i + 1] * sc.sd[1] + sc.mu[1] + sc.ref[1];
+  const double fit = -sc.overload_scale * fmax(expm1(lo), 0.0);
+  int cell;
+  if (sc.desc_kind == TTO_DESC_PAPER) {
+    cell = min(nd, 2) + 3 * (min(na, 3) + 4 * min(moved, 45));
+  } else {
+    int bin = 0;
+    for (int q = 0; q < sc.n_load_bins - 1; ++q) bin += (edges[q] <= rho) ? 1 : 0;
+    cell = min(na + nd, sc.n_count_bins - 1) * sc.n_load_bins + bin;
+  }
+  const bool in_range = cell >= 0 && cell < sc.n_cells;
+  const bool enters = in_range && (elite_id[cell] < 0 || fit > elite_fit[cell]);
+  fit_pred[i] = fit;
+  cell_pred[i] = in_range ? cell : -1;
+  st_pred[i] = enters ? (uint8_t)0 : (uint8_t)TTO_ST_INVALID;
+}
+
+// Second step: the per-cell winners (best predicted fitness among the
+// children predicted to enter, ties to the lower index) come first; every
+// other child is ranked by its predicted overload term (column 1).
+__global__ __launch_bounds__(256) void k_screen_tier(const float* __restrict__ y,
+                                                     const int* __restrict__ cell_pred,
+                                                     const uint8_t* __restrict__ st_pred,
+                                                     const int* __restrict__ winner, int n,
+                                                     float* __restrict__ score) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int cl = cell_pred[i];
+  const bool first = st_pred[i] == 0 && cl >= 0 && winner[cl] == i;
+  score[i] = first ? -FLT_MAX : y[2 * i + 1];
+}
+
 __global__ __launch_bounds__(256) void k_gather_rows(const int* __restrict__ src,
                                                      const int* __restrict__ list, int k, int G,
                                                      int* __restrict__ dst) {
@@ -523,6 +581,25 @@ hipError_t launch_keep_in_order(const int* idx, int k, int n, int* mask, int* li
   if (k > 0)
     hipLaunchKernelGGL(k_mark, dim3((k + 255) / 256), dim3(256), 0, s, idx, k, n, mask);
   hipLaunchKernelGGL(k_compact_marked, dim3(1), dim3(1024), 0, s, (const int*)mask, n, k, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_predict(const GenomeDev& gd, const int* genomes, int n, const float* y,
+                                 const ScreenScoreCfg& sc, const double* edges,
+                                 const double* elite_fit, const int64_t* elite_id,
+                                 double* fit_pred, int* cell_pred, uint8_t* st_pred,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_screen_predict, dim3((n + 255) / 256), dim3(256), 0, s, gd, genomes, n, y,
+                     sc, edges, elite_fit, elite_id, fit_pred, cell_pred, st_pred);
+  return hipGetLastError();
+}
+
+hipError_t launch_screen_tier(const float* y, const int* cell_pred, const uint8_t* st_pred,
+                              const int* winner, int n, float* score, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_screen_tier, dim3((n + 255) / 256), dim3(256), 0, s, y, cell_pred, st_pred,
+                     winner, n, score);
   return hipGetLastError();
 }
 

@@ -1315,12 +1315,14 @@ tto_status tto_generation(tto_grid* g, const tto_genome_space* gs, const tto_rep
 namespace {
 
 struct ScreenLayout {
-  size_t children, b_mc, off, ids, dense, y, topk, mask, list, kept;
+  size_t children, b_mc, off, ids, dense, y, score, fit_pred, cell_pred, st_pred, wkey, widx,
+      topk, mask, list, kept;
   GenLayout gen;     // expanded batch and outputs of the kept children
   size_t gen_at, total;
 };
 
-ScreenLayout screen_layout(const GenomeDev& d, int n_child, int n_keep, int d_dense) {
+ScreenLayout screen_layout(const GenomeDev& d, int n_child, int n_keep, int d_dense,
+                           int n_cells) {
   ScreenLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t at = o; o += round256(std::max<size_t>(bytes, 4)); return at; };
@@ -1331,6 +1333,12 @@ ScreenLayout screen_layout(const GenomeDev& d, int n_child, int n_keep, int d_de
   L.ids = take(4 * n * G);
   L.dense = take(4 * n * (size_t)d_dense);
   L.y = take(8 * n);
+  L.score = take(4 * n);
+  L.fit_pred = take(8 * n);
+  L.cell_pred = take(4 * n);
+  L.st_pred = take(n);
+  L.wkey = take(8 * (size_t)n_cells);
+  L.widx = take(4 * (size_t)n_cells);
   L.topk = take(4 * k);
   L.mask = take(4 * n);
   L.list = take(4 * k);
@@ -1369,18 +1377,30 @@ tto_status tto_screened_generation_bytes(const tto_grid* g, const tto_genome_spa
   tto_status st = check_screen_args(g, gs, net, n_child, n_keep);
   if (st != TTO_OK) return st;
   if (!bytes) return fail(TTO_E_INVALID, "bytes is NULL");
-  *bytes = screen_layout(gs->d, n_child, n_keep, net->d.d_dense).total;
+  *bytes = screen_layout(gs->d, n_child, n_keep, net->d.d_dense, TTO_MAX_CELLS).total;
   return ok();
 }
 
 tto_status tto_screened_generation(tto_grid* g, const tto_genome_space* gs,
                                    const tto_repertoire* rep, tto_mlp* net,
-                                   const float* dense_row, uint64_t seed, int32_t n_child,
-                                   int32_t n_keep, const tto_outputs* out, void* gen_ws,
+                                   const float* dense_row, const tto_screen_cfg* cfg,
+                                   uint64_t seed, int32_t n_child, int32_t n_keep,
+                                   const tto_outputs* out, int32_t* kept_out, void* gen_ws,
                                    size_t gen_bytes, void* mlp_ws, size_t mlp_bytes,
                                    void* batch_ws, size_t batch_bytes, void* stream) {
   tto_status st = check_screen_args(g, gs, net, n_child, n_keep);
   if (st != TTO_OK) return st;
+  const int rule = cfg ? cfg->rule : TTO_SCREEN_OVERLOAD;
+  if (rule != TTO_SCREEN_OVERLOAD && rule != TTO_SCREEN_GAIN)
+    return fail(TTO_E_INVALID, "screen rule %d unknown", rule);
+  if (rule == TTO_SCREEN_GAIN) {
+    for (int q = 0; q < 2; ++q)
+      if (!isfinite(cfg->y_mu[q]) || !isfinite(cfg->ref[q]) || !(cfg->y_sd[q] > 0.0) ||
+          !isfinite(cfg->y_sd[q]))
+        return fail(TTO_E_INVALID, "screen scaling must be finite with y_sd > 0");
+    if (!(cfg->overload_scale_mw > 0.0) || !isfinite(cfg->overload_scale_mw))
+      return fail(TTO_E_INVALID, "overload_scale_mw must be finite and > 0");
+  }
   if (!rep) return fail(TTO_E_INVALID, "repertoire is NULL");
   const GenomeDev& d = gs->d;
   const int G = d.n_a + d.n_d;
@@ -1396,7 +1416,7 @@ tto_status tto_screened_generation(tto_grid* g, const tto_genome_space* gs,
                 desc_cells);
   const int dd = net->d.d_dense;
   if (dd > 0 && !dense_row) return fail(TTO_E_INVALID, "dense_row is NULL");
-  const ScreenLayout L = screen_layout(d, n_child, n_keep, dd);
+  const ScreenLayout L = screen_layout(d, n_child, n_keep, dd, TTO_MAX_CELLS);
   if (!gen_ws || ((uintptr_t)gen_ws & 255)) return fail(TTO_E_WORKSPACE, "gen_ws NULL or not 256-byte aligned");
   if (gen_bytes < L.total) return fail(TTO_E_WORKSPACE, "gen_ws has %zu bytes, needs %zu", gen_bytes, L.total);
   size_t mlp_need = 0;
@@ -1413,7 +1433,7 @@ tto_status tto_screened_generation(tto_grid* g, const tto_genome_space* gs,
   float* dense = (float*)(w + L.dense);
   float* y = (float*)(w + L.y);
   int* topk = (int*)(w + L.topk);
-  int* list = (int*)(w + L.list);
+  int* list = kept_out ? kept_out : (int*)(w + L.list);   // kept child indices
   int* kept = (int*)(w + L.kept);
   // variation, the children's features, the network's predictions
   HIP_TRY(launch_vary(d, rep->id, rep->genome, rep->n_cells, seed, rep->generation, n_child,
@@ -1422,8 +1442,30 @@ tto_status tto_screened_generation(tto_grid* g, const tto_genome_space* gs,
   if (dd > 0) HIP_TRY(launch_broadcast_row(dense_row, dd, n_child, dense, s));
   const MlpBatch mb = carve_mlp_batch(&net->d, mlp_ws, &mlp_need);
   mlp_forward(net->p, mb, off, ids, dd > 0 ? dense : nullptr, n_child, y, s);
-  // the n_keep smallest predicted overload terms, in child order
-  topk_smallest(y + 1, n_child, 2, n_keep, topk, s);
+  // the n_keep smallest scores (predicted overload term, or minus the
+  // predicted gain over the predicted cell's elite), in child order
+  if (rule == TTO_SCREEN_GAIN) {
+    ScreenScoreCfg sc;
+    for (int q = 0; q < 2; ++q) { sc.mu[q] = cfg->y_mu[q]; sc.sd[q] = cfg->y_sd[q]; sc.ref[q] = cfg->ref[q]; }
+    sc.overload_scale = cfg->overload_scale_mw;
+    sc.desc_kind = g->dev.desc_kind;
+    sc.n_count_bins = g->dev.n_count_bins;
+    sc.n_load_bins = g->dev.n_load_bins;
+    sc.n_cells = rep->n_cells;
+    float* score = (float*)(w + L.score);
+    double* fit_pred = (double*)(w + L.fit_pred);
+    int* cell_pred = (int*)(w + L.cell_pred);
+    uint8_t* st_pred = (uint8_t*)(w + L.st_pred);
+    int* widx = (int*)(w + L.widx);
+    HIP_TRY(launch_screen_predict(d, children, n_child, y, sc, g->dev.edges, rep->fitness,
+                                  rep->id, fit_pred, cell_pred, st_pred, s));
+    HIP_TRY(launch_cell_winners(rep->n_cells, fit_pred, cell_pred, st_pred, n_child,
+                                (unsigned long long*)(w + L.wkey), widx, s));
+    HIP_TRY(launch_screen_tier(y, cell_pred, st_pred, widx, n_child, score, s));
+    topk_smallest(score, n_child, 1, n_keep, topk, s);
+  } else {
+    topk_smallest(y + 1, n_child, 2, n_keep, topk, s);
+  }
   HIP_TRY(launch_keep_in_order(topk, n_keep, n_child, (int*)(w + L.mask), list, s));
   HIP_TRY(launch_gather_rows(children, list, n_keep, G, kept, s));
   // exact evaluation and insertion of the survivors (ids: child index)

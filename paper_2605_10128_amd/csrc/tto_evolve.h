@@ -57,4 +57,27 @@ hipError_t launch_keep_in_order(const int* idx, int k, int n, int* mask, int* li
 hipError_t launch_gather_rows(const int* src, const int* list, int k, int G, int* dst,
                               hipStream_t s);
 
+// Archive-aware screen: the network's outputs de-standardised (raw = y sd +
+// mu + ref), the descriptor of the grid, the repertoire's cells.  Step 1
+// predicts each child's cell, fitness and whether it would enter; the
+// per-cell winners among those come from the archive's winner kernels; step
+// 2 ranks the winners first and every other child by its overload term.
+struct ScreenScoreCfg {
+  double mu[2], sd[2], ref[2];
+  double overload_scale;
+  int desc_kind, n_count_bins, n_load_bins, n_cells;
+};
+hipError_t launch_screen_predict(const GenomeDev& gd, const int* genomes, int n, const float* y,
+                                 const ScreenScoreCfg& sc, const double* edges,
+                                 const double* elite_fit, const int64_t* elite_id,
+                                 double* fit_pred, int* cell_pred, uint8_t* st_pred,
+                                 hipStream_t s);
+hipError_t launch_screen_tier(const float* y, const int* cell_pred, const uint8_t* st_pred,
+                              const int* winner, int n, float* score, hipStream_t s);
+// Per-cell winners of a batch (best fitness among entries whose status has
+// neither ISLANDED nor INVALID, ties to the lowest index; INT_MAX if none).
+hipError_t launch_cell_winners(int n_cells, const double* fit, const int* cell,
+                               const uint8_t* status, int B, unsigned long long* key, int* idx,
+                               hipStream_t s);
+
 }  // namespace tto

@@ -153,9 +153,9 @@ def _load():
         "tto_genome_expand": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, ct.c_int64, _vp]),
         "tto_generation_bytes": (_i32, [_vp, _vp, _i32, P(ct.c_size_t)]),
         "tto_screened_generation_bytes": (_i32, [_vp, _vp, _vp, _i32, _i32, P(ct.c_size_t)]),
-        "tto_screened_generation": (_i32, [_vp, _vp, P(tto_repertoire), _vp, _vp, ct.c_uint64,
-                                           _i32, _i32, _vp, _vp, ct.c_size_t, _vp, ct.c_size_t,
-                                           _vp, ct.c_size_t, _vp]),
+        "tto_screened_generation": (_i32, [_vp, _vp, P(tto_repertoire), _vp, _vp, _vp,
+                                           ct.c_uint64, _i32, _i32, _vp, _vp, _vp, ct.c_size_t,
+                                           _vp, ct.c_size_t, _vp, ct.c_size_t, _vp]),
         "tto_generation": (_i32, [_vp, _vp, P(tto_repertoire), ct.c_uint64, _i32,
                                   P(tto_outputs), _vp, ct.c_size_t, _vp, ct.c_size_t, _vp]),
         "tto_autotune": (_i32, [_vp, P(tto_batch), P(tto_outputs), _vp, ct.c_size_t, _vp,
@@ -512,15 +512,24 @@ def tto_screened_generation_bytes(grid: int, gs: int, net: int, n_child: int,
     return n.value
 
 
+TTO_SCREEN_OVERLOAD, TTO_SCREEN_GAIN = 0, 1
+
+
+class tto_screen_cfg(ct.Structure):
+    _fields_ = [("rule", _i32), ("y_mu", ct.c_double * 2), ("y_sd", ct.c_double * 2),
+                ("ref", ct.c_double * 2), ("overload_scale_mw", ct.c_double)]
+
+
 def tto_screened_generation(grid: int, gs: int, rep: tto_repertoire, net: int, dense_row: int,
-                            seed: int, n_child: int, n_keep: int,
-                            outputs: Optional["tto_outputs"], gen_ws: int, gen_bytes: int,
-                            mlp_ws: int, mlp_bytes: int, batch_ws: int, batch_bytes: int,
-                            stream: int):
+                            cfg: Optional[tto_screen_cfg], seed: int, n_child: int, n_keep: int,
+                            outputs: Optional["tto_outputs"], kept_out: int, gen_ws: int,
+                            gen_bytes: int, mlp_ws: int, mlp_bytes: int, batch_ws: int,
+                            batch_bytes: int, stream: int):
     _check(_lib.tto_screened_generation(
-        _vp(grid), _vp(gs), ct.byref(rep), _vp(net), _vp(dense_row), ct.c_uint64(seed),
-        int(n_child), int(n_keep), ct.byref(outputs) if outputs is not None else None,
-        _vp(gen_ws), gen_bytes, _vp(mlp_ws), mlp_bytes, _vp(batch_ws), batch_bytes, _vp(stream)))
+        _vp(grid), _vp(gs), ct.byref(rep), _vp(net), _vp(dense_row),
+        ct.byref(cfg) if cfg is not None else None, ct.c_uint64(seed), int(n_child), int(n_keep),
+        ct.byref(outputs) if outputs is not None else None, _vp(kept_out), _vp(gen_ws),
+        gen_bytes, _vp(mlp_ws), mlp_bytes, _vp(batch_ws), batch_bytes, _vp(stream)))
 
 
 class Graph:
@@ -1001,8 +1010,12 @@ class ScreenedEvolver:
     device FP32 [d_dense] injection summary of the current injections."""
 
     def __init__(self, session: "Session", gs: GenomeSpace, rep: Repertoire, net: "Surrogate",
-                 n_child: int, n_keep: int, seed: int, dense_row=None, outputs=None):
+                 n_child: int, n_keep: int, seed: int, dense_row=None, outputs=None,
+                 rule: int = 0, y_mu=(0.0, 0.0), y_sd=(1.0, 1.0), ref=(0.0, 0.0),
+                 overload_scale_mw: float = 100.0):
         torch = session.torch
+        self.cfg = tto_screen_cfg(int(rule), (ct.c_double * 2)(*y_mu), (ct.c_double * 2)(*y_sd),
+                                  (ct.c_double * 2)(*ref), float(overload_scale_mw))
         self.session, self.gs, self.rep, self.net = session, gs, rep, net
         self.n_child, self.n_keep, self.seed = int(n_child), int(n_keep), int(seed)
         self.gen_bytes = tto_screened_generation_bytes(session.handle, gs.handle, net.handle,
@@ -1018,6 +1031,7 @@ class ScreenedEvolver:
                             if outputs is not None else None)
         G = gs.G
         self.children = self.gen_ws[: 4 * self.n_child * G].view(torch.int32).view(self.n_child, G)
+        self.kept = torch.empty(self.n_keep, dtype=torch.int32, device=session.device)
 
     def set_dense_row(self, row):
         """Copy a new injection summary into the buffer the calls read."""
@@ -1028,8 +1042,9 @@ class ScreenedEvolver:
     def step(self):
         s = self.session
         tto_screened_generation(s.handle, self.gs.handle, self._rep_struct, self.net.handle,
-                                _ptr(self.dense_row), self.seed, self.n_child, self.n_keep,
-                                self._out_struct, _ptr(self.gen_ws), self.gen_bytes,
+                                _ptr(self.dense_row), self.cfg, self.seed, self.n_child,
+                                self.n_keep, self._out_struct, _ptr(self.kept),
+                                _ptr(self.gen_ws), self.gen_bytes,
                                 _ptr(self.net.bws), self.net.bbytes, _ptr(s.batch_ws),
                                 s.batch_bytes, s.stream)
 

@@ -108,6 +108,7 @@ def test_screen_keeps_the_predicted_best_tenth(tto):
                     n_child).cpu().numpy()
     order = np.argsort(y[:, 1], kind="stable")[:n_keep]
     kept = np.sort(order)
+    assert np.array_equal(sev.kept.cpu().numpy(), kept)
     # outputs of the kept children equal a plain evaluation of them
     db = dev.expand(torch.as_tensor(children[kept], device=dvc).contiguous())
     ref = to_numpy(sess.evaluate(db))
@@ -159,4 +160,68 @@ def test_screened_graph_replays_equal_eager(tto):
         assert torch.equal(a, b)
     log(f"[screened] 4 graph replays equal 4 eager screened generations, "
         f"{int((rep.id >= 0).sum().item())} cells")
+    sess.close()
+
+
+def test_gain_rule_keeps_cell_winners_then_lowest_overload(tto):
+    """TTO_SCREEN_GAIN: the children kept are, first, the best-predicted child
+    of every cell some child is predicted to enter (predicted cell from the
+    genome and the predicted maximum loading, predicted fitness minus the
+    predicted overload, entering when the cell is empty or its elite worse),
+    then the smallest predicted overload terms; recomputed on the host from
+    the device's children, the network's predictions and the repertoire."""
+    import torch
+    w = gg.build_config(2, B=512)
+    n_child, n_keep = 4096, 410
+    sess = make_session(w, tto.TTO_FLOW_F32, max_batch=n_child)
+    dev, _ = spaces(sess, w, 4, 4, 300, seed=5)
+    net = _net(tto, dev, n_child, seed=6)
+    rep = tto.Repertoire(sess, dev)
+    row = np.random.default_rng(2).normal(0, 1, 24).astype(np.float32)
+    mu, sd, ref = (0.2, -0.1), (0.3, 0.5), (1.5, 2.0)
+    outs = sess.alloc_outputs(n_keep)
+    sev = tto.ScreenedEvolver(sess, dev, rep, net, n_child, n_keep, seed=31, dense_row=row,
+                              outputs=outs, rule=tto.TTO_SCREEN_GAIN, y_mu=mu, y_sd=sd, ref=ref)
+    plain = tto.Evolver(sess, dev, rep, 1024, seed=31)
+    for _ in range(4):
+        plain.step()
+    torch.cuda.synchronize()
+    elite_fit = rep.fitness.cpu().numpy()
+    elite_id = rep.id.cpu().numpy()
+    kids, _ = dev.vary(rep, 31, n_child)
+    torch.cuda.synchronize()
+    sev.step()
+    torch.cuda.synchronize()
+    children = sev.children.cpu().numpy()
+    assert np.array_equal(children, kids.cpu().numpy())
+    off, ids = _features(children, dev.n_a, dev.desc.n_disc, dev.desc.n_actions)
+    dvc = torch.device("cuda")
+    dense = torch.as_tensor(np.repeat(row[None, :], n_child, axis=0), device=dvc)
+    y32 = net.forward(torch.as_tensor(off, device=dvc), torch.as_tensor(ids, device=dvc), dense,
+                      n_child).cpu().numpy()
+    y = y32.astype(np.float64)
+    rho = y[:, 0] * sd[0] + mu[0] + ref[0]
+    fit = -100.0 * np.maximum(np.expm1(y[:, 1] * sd[1] + mu[1] + ref[1]), 0.0)
+    a, d = children[:, :dev.n_a], children[:, dev.n_a:]
+    n_sw = ((a >= 0) & (a < dev.desc.n_actions)).sum(1) + ((d >= 0) & (d < dev.desc.n_disc)).sum(1)
+    edges = gg.default_load_edges()
+    cell = np.minimum(n_sw, 31) * 32 + (edges[None, :] <= rho[:, None]).sum(1)
+    enters = (elite_id[cell] < 0) | (fit > elite_fit[cell])
+    first = np.zeros(n_child, bool)
+    for cl in np.unique(cell[enters]):
+        members = np.flatnonzero(enters & (cell == cl))
+        best = members[np.flatnonzero(fit[members] == fit[members].max())[0]]
+        first[best] = True
+    score = np.where(first, -np.finfo(np.float32).max, y32[:, 1]).astype(np.float32)
+    expect = np.sort(np.argsort(score, kind="stable")[:n_keep])
+    kept = sev.kept.cpu().numpy()
+    assert np.array_equal(kept, expect)
+    # the outputs belong to the kept children, in that order
+    db = dev.expand(torch.as_tensor(children[kept], device=dvc).contiguous())
+    refo = to_numpy(sess.evaluate(db))
+    got = to_numpy(outs)
+    for k in refo:
+        assert np.array_equal(got[k], refo[k], equal_nan=True), k
+    log(f"[screened] gain rule: kept {n_keep} of {n_child}: {int(first.sum())} cell winners "
+        f"(of {len(np.unique(cell[enters]))} predicted cells entered), the rest by overload")
     sess.close()
