@@ -12,7 +12,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtto.so")
+# TTO_LIBRARY selects another build of the same library (the host-sanitized
+# libtto_san.so); it is never a substitute for a missing one
+LIB_PATH = os.environ.get("TTO_LIBRARY") or os.path.join(_HERE, "libtto.so")
 
 TTO_OK = 0
 TTO_E_INVALID, TTO_E_GRID, TTO_E_RANK, TTO_E_WORKSPACE, TTO_E_HIP, TTO_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
