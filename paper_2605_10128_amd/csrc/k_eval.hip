@@ -151,7 +151,12 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   __shared__ double s_x[kMaxRank][TT];
   __shared__ int s_wcnt[4];
   __shared__ int s_base, s_n0, s_nisl, s_bad;
-  __shared__ F s_stage[4][64][17];   // record staging, one slab per wave
+  // record staging, one slab per wave (contingency rows); before that the
+  // same LDS holds the S entries among the gather sources (bordered matrix)
+  __shared__ __align__(16) char s_raw[sizeof(F) * 4 * 64 * 17];
+  F (*s_stage)[64][17] = reinterpret_cast<F (*)[64][17]>(s_raw);
+  double* s_sub = reinterpret_cast<double*>(s_raw);
+  static_assert(sizeof(F) * 4 * 64 * 17 >= sizeof(double) * kSubMax * kSubMax, "LDS reuse");
 
   // -- genome parse in stages: slot values, ranges, moved-branch data, checks
   if (tid < bt.no) sh.oval[tid] = bt.open[(size_t)cb * bt.no + tid];
@@ -263,32 +268,44 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     return;
   }
 
+  // S entries among the gather sources (openings, then moved branches), one
+  // load per thread, so that the bordered matrix is built from LDS; more
+  // than kSubMax sources read S directly
+  const int nsrc = sh.nsrc;
+  const bool sub = nsrc <= kSubMax;
+  if (sub)
+    for (int i = tid; i < nsrc * nsrc; i += 256) {
+      const int a = i / nsrc, a2 = i - (i / nsrc) * nsrc;
+      s_sub[i] = g.S[(size_t)sh.src_row[a] * m + sh.src_row[a2]];
+    }
+  __syncthreads();
+  // S between sources a and a2 (a < k: opening a; a >= k: moved branch a - k)
+  auto Sv = [&](int a, int a2) -> double {
+    return sub ? s_sub[a * nsrc + a2] : g.S[(size_t)sh.src_row[a] * m + sh.src_row[a2]];
+  };
+
   // bordered matrix M_c, one entry per thread; H_ab = b_a S_ab
   if (tid < r * r) {
     const int i = tid / r, q = tid - (tid / r) * r;
-    const size_t mm = m;
     double v = 0.0;
     if (i < k) {
-      const size_t ki = (size_t)sh.open[i] * mm;
       if (q < k) {
-        v = (i == q ? 1.0 : 0.0) - sh.bK[i] * g.S[ki + sh.open[q]];
+        v = (i == q ? 1.0 : 0.0) - sh.bK[i] * Sv(i, q);
       } else {
         const int j = q - k;
-        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) v += sh.msg[p] * g.S[ki + sh.mbr[p]];
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) v += sh.msg[p] * Sv(i, k + p);
         v *= sh.bK[i];
       }
     } else {
       const int j = i - k;
       if (q < k) {
-        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p)
-          v += sh.msg[p] * g.S[(size_t)sh.mbr[p] * mm + sh.open[q]];
+        for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) v += sh.msg[p] * Sv(k + p, q);
       } else {
         const int j2 = q - k;
         for (int p = sh.moff[j]; p < sh.moff[j + 1]; ++p) {
-          const size_t bp = (size_t)sh.mbr[p] * mm;
           for (int p2 = sh.moff[j2]; p2 < sh.moff[j2 + 1]; ++p2) {
-            v -= sh.msg[p] * sh.msg[p2] * g.S[bp + sh.mbr[p2]];
-            if (sh.mbr[p] == sh.mbr[p2]) v += sh.msign[p] * sh.msign[p2] * g.b[sh.mbr[p]];
+            v -= sh.msg[p] * sh.msg[p2] * Sv(k + p, k + p2);
+            if (sh.mbr[p] == sh.mbr[p2]) v += sh.msign[p] * sh.msign[p2] * sh.mb[p];
           }
         }
       }
@@ -391,10 +408,10 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     // so that their latency overlaps it
     double f0e[TT];
 #pragma unroll
-    for (int t = 0; t < TT; ++t) f0e[t] = t < T ? g.f0[(size_t)e * T + t] : 0.0;
+    for (int t = 0; t < TT; ++t) f0e[t] = t < T ? g.f0MC[(size_t)t * nMC + ei] : 0.0;
 #pragma unroll
     for (int t = 0; t < TT; ++t) nbad += !isfinite(f0e[t]);
-    const double be = g.b[e], lim = g.lim[e];
+    const double be = g.bMC[ei], lim = g.limM[ei];
     double W[kMaxRank], U[kMaxRank];
     gather_column(g.SMC, nMC, ei, sh, W);
     u_from_w(e, be, W, U);
@@ -457,10 +474,10 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     if (li < nC) {
       l = g.cont[li];
       // row-only loads first (their latency overlaps the column gather)
-      s_ll = g.S[(size_t)l * m + l];
-      b_l = g.b[l];
+      s_ll = g.sllC[li];
+      b_l = g.bMC[nM + li];
 #pragma unroll
-      for (int t = 0; t < TT; ++t) f0l[t] = t < T ? g.f0[(size_t)l * T + t] : 0.0;
+      for (int t = 0; t < TT; ++t) f0l[t] = t < T ? g.f0MC[(size_t)t * nMC + nM + li] : 0.0;
       for (int q = 0; q < k; ++q) opened |= (sh.open[q] == l);
       if (opened) {
         active = true;  // already open: the N-0 state (phi = 0)
@@ -1189,6 +1206,7 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     none.flags = nullptr;
     GridDev gh = g;
     gh.f0 = g.f0_hi;   // FP64-GEMM base flows
+    gh.f0MC = g.f0MC_hi;
     gh.near_margin = -1.0;
     SweepBufs<double> w64 = *rw;
     w64.n_eblk = (g.nM + 63) / 64;

@@ -62,6 +62,39 @@ __global__ __launch_bounds__(256) void k_build_SMC(const double* __restrict__ S,
   SMC[(size_t)s * (nM + nC) + j] = S[(size_t)s * m + col];
 }
 
+// Per-row scalars of the monitored then contingency rows, contiguous in the
+// row index: bMC[j] = b of row j, limM[ei] = limit of M[ei], sllC[li] = S_ll of
+// l = C[li].
+__global__ __launch_bounds__(256) void k_build_rows(const double* __restrict__ S,
+                                                    const double* __restrict__ b,
+                                                    const double* __restrict__ lim,
+                                                    const int* __restrict__ mon,
+                                                    const int* __restrict__ cont, int m, int nM,
+                                                    int nC, double* __restrict__ bMC,
+                                                    double* __restrict__ limM,
+                                                    double* __restrict__ sllC) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= nM + nC) return;
+  const int e = j < nM ? mon[j] : cont[j - nM];
+  bMC[j] = b[e];
+  if (j < nM) limM[j] = lim[e];
+  else sllC[j - nM] = S[(size_t)e * m + e];
+}
+
+// Base flows of the monitored then contingency rows, timestep-major:
+// f0MC[t][j] = f0[row j][t], so that the lanes of a row loop read one
+// contiguous run per timestep.
+__global__ __launch_bounds__(256) void k_f0_rows(const double* __restrict__ f0,
+                                                 const int* __restrict__ mon,
+                                                 const int* __restrict__ cont, int T, int nM,
+                                                 int nC, double* __restrict__ f0MC) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int t = blockIdx.y;
+  if (j >= nM + nC) return;
+  const int e = j < nM ? mon[j] : cont[j - nM];
+  f0MC[(size_t)t * (nM + nC) + j] = f0[(size_t)e * T + t];
+}
+
 // Contingency-major monitored block: HMC[li][ei] = H[M[ei], C[li]], with the
 // line-outage convention that the outaged branch's own entry is H_ll - 1 so
 // that its post-contingency flow f_l + (H'_ll - 1) f_l / (1 - H'_ll) is zero.
@@ -321,6 +354,21 @@ hipError_t launch_build_SMC(const double* S, const int* mon, const int* cont, in
                             int nC, double* SMC, hipStream_t s) {
   hipLaunchKernelGGL(k_build_SMC, dim3(cdiv(nM + nC, 256), m), dim3(256), 0, s, S, mon, cont, m,
                      nM, nC, SMC);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_rows(const double* S, const double* b, const double* lim, const int* mon,
+                             const int* cont, int m, int nM, int nC, double* bMC, double* limM,
+                             double* sllC, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_rows, dim3(cdiv(nM + nC, 256)), dim3(256), 0, s, S, b, lim, mon,
+                     cont, m, nM, nC, bMC, limM, sllC);
+  return hipGetLastError();
+}
+
+hipError_t launch_f0_rows(const double* f0, const int* mon, const int* cont, int T, int nM, int nC,
+                          double* f0MC, hipStream_t s) {
+  hipLaunchKernelGGL(k_f0_rows, dim3(cdiv(nM + nC, 256), T), dim3(256), 0, s, f0, mon, cont, T,
+                     nM, nC, f0MC);
   return hipGetLastError();
 }
 

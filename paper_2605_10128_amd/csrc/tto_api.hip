@@ -73,6 +73,8 @@ struct GridLayout {
   // FP64 copy of the base-flow product for the refinement of FP32 grids, and
   // max |f0 - f0_hi| (device scalar)
   double* f0_hi; void* A64; void* PT64; double* part_hi; double* gemm_err;
+  // row tables of M then C (see GridDev)
+  double* f0MC; double* f0MC_hi; double* bMC; double* limM; double* sllC;
 };
 
 GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
@@ -91,6 +93,11 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   L.HMC32 = cv.take<float>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
   L.HMC64 = cv.take<double>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
   L.f0 = cv.take<double>(m * T);
+  const size_t nMC = (size_t)d->n_monitored + d->n_contingency;
+  L.f0MC = cv.take<double>(T * nMC);
+  L.bMC = cv.take<double>(nMC);
+  L.limM = cv.take<double>(d->n_monitored);
+  L.sllC = cv.take<double>(std::max(d->n_contingency, 1));
   const size_t ld = gemm_ld(d->n_bus), mp = gemm_mpad(d->n_branch);
   const size_t es = gemm_esize(d->gemm_precision);
   L.A = cv.take<char>(mp * ld * es);
@@ -106,12 +113,14 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   if (d->gemm_precision == TTO_GEMM_F64 || d->flow_precision == TTO_FLOW_F64) {
     L.f0_hi = nullptr; L.A64 = nullptr; L.PT64 = nullptr; L.part_hi = nullptr;
     L.gemm_err = nullptr;
+    L.f0MC_hi = nullptr;
   } else {
     L.f0_hi = cv.take<double>(m * T);
     L.A64 = cv.take<double>(mp * ld);
     L.PT64 = cv.take<double>((size_t)kGemmN * ld);
     L.part_hi = cv.take<double>((size_t)L.ksplit * m * kGemmN);
     L.gemm_err = cv.take<double>(1);
+    L.f0MC_hi = cv.take<double>(T * nMC);
   }
   (void)n;
   *bytes = cv.off;
@@ -308,9 +317,14 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
     HIP_TRY(launch_build_HMC(L.S, L.b, L.mon, L.cont, m, d->n_monitored, d->n_contingency, L.HMC32, L.HMC64, s));
   HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, d->gemm_precision, L.A, s));
   if (L.A64) HIP_TRY(launch_convert_ptdf(d->ptdf, m, n, TTO_GEMM_F64, L.A64, s));
+  HIP_TRY(launch_build_rows(L.S, L.b, L.lim, L.mon, L.cont, m, d->n_monitored, d->n_contingency,
+                            L.bMC, L.limM, L.sllC, s));
+  const size_t nMC = (size_t)d->n_monitored + d->n_contingency;
   HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
+  HIP_TRY(hipMemsetAsync(L.f0MC, 0, sizeof(double) * nMC * d->n_timesteps, s));
   if (L.f0_hi) {
     HIP_TRY(hipMemsetAsync(L.f0_hi, 0, sizeof(double) * m * d->n_timesteps, s));
+    HIP_TRY(hipMemsetAsync(L.f0MC_hi, 0, sizeof(double) * nMC * d->n_timesteps, s));
     HIP_TRY(hipMemsetAsync(L.gemm_err, 0, sizeof(double), s));
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -333,6 +347,8 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   v.n_bus = n; v.n_branch = m; v.slack = d->slack; v.T = g->T; v.TT = g->TT; v.nM = g->nM; v.nC = g->nC;
   v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S; v.SMC = L.SMC;
   v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.f0_hi = L.f0_hi ? L.f0_hi : L.f0; v.mon = L.mon; v.cont = L.cont;
+  v.f0MC = L.f0MC; v.f0MC_hi = L.f0MC_hi ? L.f0MC_hi : L.f0MC; v.bMC = L.bMC; v.limM = L.limM;
+  v.sllC = L.sllC;
   v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
   v.desc_kind = TTO_DESC_COUNT_LOAD;
   v.near_margin = -1.0;
@@ -377,11 +393,13 @@ tto_status tto_set_injections(tto_grid* g, const double* p_mw, void* stream) {
   HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, g->gemm_prec, g->L.PT, s));
   HIP_TRY(launch_gemm_f0(g->gemm_prec, g->L.A, g->L.PT, g->m, g->n_bus, g->T, g->L.ksplit,
                          g->L.part32, g->L.part64, g->L.f0, s));
+  HIP_TRY(launch_f0_rows(g->L.f0, g->L.mon, g->L.cont, g->T, g->nM, g->nC, g->L.f0MC, s));
   if (g->L.f0_hi) {
     HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, TTO_GEMM_F64, g->L.PT64, s));
     HIP_TRY(launch_gemm_f0(TTO_GEMM_F64, g->L.A64, g->L.PT64, g->m, g->n_bus, g->T, g->L.ksplit,
                            nullptr, g->L.part_hi, g->L.f0_hi, s));
     HIP_TRY(launch_max_abs_diff(g->L.f0, g->L.f0_hi, (size_t)g->m * g->T, g->L.gemm_err, s));
+    HIP_TRY(launch_f0_rows(g->L.f0_hi, g->L.mon, g->L.cont, g->T, g->nM, g->nC, g->L.f0MC_hi, s));
   }
   return ok();
 }

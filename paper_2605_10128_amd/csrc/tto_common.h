@@ -19,6 +19,7 @@ constexpr double kTauCont = 1e-9;   // |1 - H'_ll| of a contingency
 constexpr double kWorstContTieMW = TTO_WORST_CONT_TIE_MW;  // worst-contingency tie tolerance
 constexpr double kLoadTieRel = TTO_LOAD_TIE_REL;          // worst (branch, timestep) tie band
 constexpr int kGemmN = 32;          // timestep columns of the f0 GEMM (T padded)
+constexpr int kSubMax = 32;         // gather sources whose mutual S entries the set-up stages in LDS
 
 // Record of one active contingency in a candidate's sweep list:
 // phi(t) for t < TT, then V_j for j < 8, padded to a multiple of 4 entries.
@@ -50,6 +51,13 @@ struct GridDev {
   const double* f0_hi;  // [m][T] the same from the FP64 GEMM (refinement pass)
   const int* mon;       // [nM]
   const int* cont;      // [nC]
+  // Tables of the monitored then contingency rows, contiguous in the row
+  // index so that the lanes of a row loop read them coalesced:
+  const double* f0MC;     // [T][nM + nC] base flows f0 at row j
+  const double* f0MC_hi;  // the same from f0_hi
+  const double* bMC;      // [nM + nC] susceptance of row j
+  const double* limM;     // [nM] limit of M[ei]
+  const double* sllC;     // [nC] S_ll of l = C[li]
   const double* edges;  // [n_load_bins - 1]
   double lim_min;       // smallest monitored limit
   int n_count_bins, n_load_bins;
@@ -144,6 +152,11 @@ hipError_t launch_build_SMC(const double* S, const int* mon, const int* cont, in
                             int nC, double* SMC, hipStream_t s);
 hipError_t launch_build_HMC(const double* S, const double* b, const int* mon, const int* cont,
                             int m, int nM, int nC, float* HMC32, double* HMC64, hipStream_t s);
+hipError_t launch_build_rows(const double* S, const double* b, const double* lim, const int* mon,
+                             const int* cont, int m, int nM, int nC, double* bMC, double* limM,
+                             double* sllC, hipStream_t s);
+hipError_t launch_f0_rows(const double* f0, const int* mon, const int* cont, int T, int nM, int nC,
+                          double* f0MC, hipStream_t s);
 hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void* out, hipStream_t s);
 hipError_t launch_pack_injections(const double* p, int n, int T, int prec, void* PT, hipStream_t s);
 hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n, int T,
