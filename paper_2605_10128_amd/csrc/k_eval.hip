@@ -1,10 +1,14 @@
 // Per-candidate kernels of the batched DC N-1 screen.
 //
-//   k_setup    FP64 rank-r update of the pre-computed distribution factors for
+//   k_setup_cand, k_setup_rows
+//              FP64 rank-r update of the pre-computed distribution factors for
 //              the candidate's openings and bus splits (DC-Optimizer: topology
-//              changes enter as low-rank updates of the PTDF), islanding pivot
-//              test, post-switch flows f', per-contingency LODF denominators
-//              1 - H'_ll and the compacted list of non-islanding contingencies.
+//              changes enter as low-rank updates of the PTDF): the bordered
+//              system, its LU factors and the islanding pivot test (one wave
+//              per candidate), then post-switch flows f', per-contingency LODF
+//              denominators 1 - H'_ll and the compacted list of non-islanding
+//              contingencies (one workgroup per candidate, rank fixed at
+//              compile time).
 //   k_sweep    N-1 flows f^(l)_e(t) = f'_e(t) + H'_el f'_l(t) / (1 - H'_ll) for
 //              every monitored e, active contingency l and timestep t, with the
 //              running max |f| fused in (f^max of the Fitness function
@@ -83,7 +87,16 @@ __device__ inline void lu_solve(const double (*s_M)[kMaxRank], const int* s_piv,
 // loops instead of hoisting 8 x TT doubles into registers.
 __device__ inline void keep_in_loop() { __asm__ volatile("" ::: "memory"); }
 
-// Shared description of one candidate inside k_setup.
+// Orders LDS writes and reads among the lanes of one wave (a wave's LDS
+// operations complete in issue order; the fences keep the compiler from
+// moving them across).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Shared description of one candidate inside k_setup_cand.
 struct SetupShared {
   int open[kMaxRank];      // opened branch ids (column q < k)
   double bK[kMaxRank];     // their susceptances
@@ -97,66 +110,36 @@ struct SetupShared {
   double inv_s[kMaxRank];  // 1 / sum_b b_b per split
   double M[kMaxRank][kMaxRank];
   int piv[kMaxRank];
+  int perm[kMaxRank];      // row i of the pivoted system is row perm[i] of M_c
   int hdr[4];              // valid, k, ns, islanded
-  // flattened sources of the column gathers: row src_row[s] of S enters
-  // column slot q with coefficient coef[s][q] (1 for an opening, sg_b b_b for
-  // a moved branch of its split)
   int nsrc;
-  int src_row[kMaxRank + kMaxMoved];
-  double coef[kMaxRank + kMaxMoved][kMaxRank];
+  int src_row[kMaxSrc];    // gather sources: the openings, then the moved branches
   // staging of the genome slots
   int oval[kMaxRank], sval[kMaxRank], slo[kMaxRank], shi[kMaxRank], stot;
   int mfrom[kMaxMoved], mto[kMaxMoved];
   double mb[kMaxMoved];
 };
 
-// Column gather: W[q] = sum_s coef[s][q] tab[src_row[s]][col], i.e. W[q] =
-// S[K_q][e] for openings and W[k+j] = sum_{b in S_j} sg_b b_b S[b][e] for
-// splits.  Eight independent row loads are in flight per step.
-__device__ inline void gather_column(const double* __restrict__ tab, size_t ld, int col,
-                                     const SetupShared& sh, double* W) {
-#pragma unroll
-  for (int q = 0; q < kMaxRank; ++q) W[q] = 0.0;
-  const int nsrc = sh.nsrc;
-  for (int s0 = 0; s0 < nsrc; s0 += 8) {
-    double v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      v[u] = (s0 + u < nsrc) ? tab[(size_t)sh.src_row[s0 + u] * ld + col] : 0.0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (s0 + u < nsrc) {
-#pragma unroll
-        for (int q = 0; q < kMaxRank; ++q) W[q] = fma(sh.coef[s0 + u][q], v[u], W[q]);
-      }
-    }
-  }
-}
-
+// Set-up, first kernel: one wave per candidate.  Genome parse and checks, the
+// rank-r bordered system M_c in FP64 with its LU factors (partial pivoting)
+// and the islanding pivot test, x(t) = M_c^-1 rhs(t), and the candidate's
+// SetupDesc for the row kernel: the gather sources with their coefficients
+// for W (the column of U before the b_e factor) and for the pivoted
+// right-hand side of V_l, the factors, x(t) and the moved-branch fix-ups.
 template <typename F, int TT>
-__global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs<F> w,
-                                               double* __restrict__ base_out) {
-  constexpr int RS = rec_stride(TT);
+__global__ __launch_bounds__(64) void k_setup_cand(GridDev g, BatchDev bt, SweepBufs<F> w) {
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
-  const int m = g.n_branch, T = g.T, nM = g.nM, nC = g.nC;
-  // genome index: refinement passes evaluate map[c] for c < live count
+  const int m = g.n_branch, T = g.T;
   int cb = c;
   if (bt.map) {
     if (c >= min(*bt.live, bt.B)) return;
     cb = bt.map[c];
   }
-
   __shared__ SetupShared sh;
-  __shared__ double s_x[kMaxRank][TT];
-  __shared__ int s_wcnt[4];
-  __shared__ int s_base, s_n0, s_nisl, s_bad;
-  // record staging, one slab per wave (contingency rows); before that the
-  // same LDS holds the S entries among the gather sources (bordered matrix)
-  __shared__ __align__(16) char s_raw[sizeof(F) * 4 * 64 * 17];
-  F (*s_stage)[64][17] = reinterpret_cast<F (*)[64][17]>(s_raw);
-  double* s_sub = reinterpret_cast<double*>(s_raw);
-  static_assert(sizeof(F) * 4 * 64 * 17 >= sizeof(double) * kSubMax * kSubMax, "LDS reuse");
+  __shared__ double s_sub[kSubMax * kSubMax];
+  __shared__ int s_bad;
+  SetupDesc* D = w.desc + c;
 
   // -- genome parse in stages: slot values, ranges, moved-branch data, checks
   if (tid < bt.no) sh.oval[tid] = bt.open[(size_t)cb * bt.no + tid];
@@ -198,9 +181,6 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     sh.hdr[1] = k;
     sh.hdr[2] = s;
     sh.hdr[3] = 0;
-    s_base = 0;
-    s_n0 = 0;
-    s_nisl = 0;
     s_bad = 0;
   }
   __syncthreads();
@@ -217,7 +197,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
       sh.mto[tid] = ok ? g.to[e] : -1;
       sh.mb[tid] = ok ? g.b[e] : 0.0;
     }
-    if (sh.hdr[0] && tid >= 64 && tid - 64 < k0) sh.bK[tid - 64] = g.b[sh.open[tid - 64]];
+    if (sh.hdr[0] && tid < k0) sh.bK[tid] = g.b[sh.open[tid]];
   }
   __syncthreads();
   if (tid == 0 && sh.hdr[0]) {
@@ -239,19 +219,10 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
       }
       sh.inv_s[s] = ssum > 0.0 ? 1.0 / ssum : 0.0;
     }
-    // flattened gather sources
     int ns_ = 0;
-    for (int q = 0; q < k; ++q) {
-      sh.src_row[ns_] = sh.open[q];
-      for (int qq = 0; qq < kMaxRank; ++qq) sh.coef[ns_][qq] = (qq == q) ? 1.0 : 0.0;
-      ++ns_;
-    }
-    for (int p = 0; p < sh.moff[ns]; ++p) {
-      sh.src_row[ns_] = sh.mbr[p] >= 0 && sh.mbr[p] < m ? sh.mbr[p] : 0;
-      const int slot = k + sh.mj[p];
-      for (int qq = 0; qq < kMaxRank; ++qq) sh.coef[ns_][qq] = (qq == slot) ? sh.msg[p] : 0.0;
-      ++ns_;
-    }
+    for (int q = 0; q < k; ++q) sh.src_row[ns_++] = sh.open[q];
+    for (int p = 0; p < sh.moff[ns]; ++p)
+      sh.src_row[ns_++] = sh.mbr[p] >= 0 && sh.mbr[p] < m ? sh.mbr[p] : 0;
     sh.nsrc = ns_;
     sh.hdr[0] = valid;
   }
@@ -261,6 +232,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   CandInfo* inf = w.info + c;
   if (!valid) {
     if (tid == 0) {
+      D->status = TTO_ST_INVALID;
       inf->status = TTO_ST_INVALID;
       inf->r = 0; inf->k = 0; inf->n_act = 0; inf->n_act_pad = 0; inf->n_island = 0;
       inf->n_crit_n0 = 0;
@@ -268,13 +240,13 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     return;
   }
 
-  // S entries among the gather sources (openings, then moved branches), one
-  // load per thread, so that the bordered matrix is built from LDS; more
-  // than kSubMax sources read S directly
+  // S entries among the gather sources (openings, then moved branches), so
+  // that the bordered matrix is built from LDS; more than kSubMax sources
+  // read S directly
   const int nsrc = sh.nsrc;
   const bool sub = nsrc <= kSubMax;
   if (sub)
-    for (int i = tid; i < nsrc * nsrc; i += 256) {
+    for (int i = tid; i < nsrc * nsrc; i += 64) {
       const int a = i / nsrc, a2 = i - (i / nsrc) * nsrc;
       s_sub[i] = g.S[(size_t)sh.src_row[a] * m + sh.src_row[a2]];
     }
@@ -284,7 +256,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     return sub ? s_sub[a * nsrc + a2] : g.S[(size_t)sh.src_row[a] * m + sh.src_row[a2]];
   };
 
-  // bordered matrix M_c, one entry per thread; H_ab = b_a S_ab
+  // bordered matrix M_c, one entry per lane; H_ab = b_a S_ab
   if (tid < r * r) {
     const int i = tid / r, q = tid - (tid / r) * r;
     double v = 0.0;
@@ -316,14 +288,17 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   __syncthreads();
   if (tid == 0) {
     double minpiv = DBL_MAX;
+    for (int q = 0; q < kMaxRank; ++q) sh.perm[q] = q;
     for (int p = 0; p < r; ++p) {
       int best = p;
       double bv = fabs(sh.M[p][p]);
       for (int i = p + 1; i < r; ++i)
         if (fabs(sh.M[i][p]) > bv) { bv = fabs(sh.M[i][p]); best = i; }
       sh.piv[p] = best;
-      if (best != p)
+      if (best != p) {
         for (int q = 0; q < r; ++q) { const double t = sh.M[p][q]; sh.M[p][q] = sh.M[best][q]; sh.M[best][q] = t; }
+        const int t = sh.perm[p]; sh.perm[p] = sh.perm[best]; sh.perm[best] = t;
+      }
       minpiv = fmin(minpiv, bv);
       if (bv > 0.0) {
         for (int i = p + 1; i < r; ++i) {
@@ -338,6 +313,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
   __syncthreads();
   if (sh.hdr[3]) {
     if (tid == 0) {
+      D->status = TTO_ST_ISLANDED;
       inf->status = TTO_ST_ISLANDED;
       inf->r = r; inf->k = k; inf->n_act = 0; inf->n_act_pad = 0; inf->n_island = 0;
       inf->n_moved = sh.moff[ns];
@@ -346,7 +322,7 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     return;
   }
 
-  // x(t) = M_c^{-1} rhs(t), rhs = [f0_K ; (p_j - phi_j) / s_j]
+  // x(t) = M_c^{-1} rhs(t), rhs = [f0_K ; (p_j - phi_j) / s_j], one lane per t
   if (tid < TT) {
     const int t = tid;
     double x[kMaxRank];
@@ -371,84 +347,233 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < kMaxRank; ++q) {
-      s_x[q][t] = (t < T) ? x[q] : 0.0;
+      D->x[t][q] = (t < T) ? x[q] : 0.0;
       bad |= (t < T) && !isfinite(x[q]);
     }
     if (bad) atomicAdd(&s_bad, 1);
   }
-  __syncthreads();
 
+  // the description: coefficient rows per source, zero rows up to the next
+  // multiple of 8 (the row kernel reads sources in groups of 8)
   const int nm = sh.moff[ns];
+  const int nsrc8 = (nsrc + 7) & ~7;
+  for (int i = tid; i < nsrc8 * kMaxRank; i += 64) {
+    const int s = i / kMaxRank, q = i - (i / kMaxRank) * kMaxRank;
+    // column slot of source s and its coefficient: an opening enters its own
+    // slot with 1, a moved branch its split's slot with sg_b b_b
+    int slot = -1;
+    double cf = 0.0;
+    if (s < k) { slot = s; cf = 1.0; }
+    else if (s < nsrc) { slot = k + sh.mj[s - k]; cf = sh.msg[s - k]; }
+    D->coefW[s][q] = (q == slot) ? cf : 0.0;
+    // pivoted right-hand side of V_l: row q takes slot perm[q] scaled by
+    // b_K (openings) or -1/s_j (splits)
+    double cv = 0.0;
+    if (q < r && sh.perm[q] == slot) cv = slot < k ? sh.bK[slot] * cf : -sh.inv_s[slot - k] * cf;
+    D->coefV[s][q] = cv;
+    if (q == 0) D->src_row[s] = s < nsrc ? sh.src_row[s] : 0;
+  }
+  for (int p = tid; p < nm; p += 64) {
+    const int slot = k + sh.mj[p];
+    int pos = 0;
+    for (int q = 0; q < r; ++q) pos = (sh.perm[q] == slot) ? q : pos;
+    D->mbr[p] = sh.mbr[p];
+    D->mslot[p] = slot;
+    D->mpos[p] = pos;
+    D->msg[p] = sh.msg[p];
+    D->madd[p] = sh.msign[p] * sh.inv_s[sh.mj[p]];
+  }
+  {
+    const int i = tid >> 3, q = tid & 7;
+    D->LU[i][q] = (i < r && q < r) ? sh.M[i][q] : 0.0;
+    if (q == 0) {
+      D->inv_diag[i] = i < r ? 1.0 / sh.M[i][i] : 0.0;
+      D->uscale[i] = i < k ? 1.0 : -1.0;
+      D->open[i] = i < k ? sh.open[i] : -1;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    D->status = 0;
+    D->r = r; D->k = k; D->ns = ns; D->nsrc = nsrc; D->nm = nm;
+    D->bad = s_bad;
+  }
+}
+
+// Set-up, second kernel: one workgroup per candidate, one lane per row of
+// M and then of C, rank R fixed at compile time.  The candidate's
+// description is copied to LDS once and read there as broadcasts (reads
+// through the scalar cache would each wait on its latency, and holding the
+// uniform values in scalar registers runs out of them).
+typedef const __attribute__((address_space(4))) SetupDesc CSetupDesc;
+
+// A uniform stride passed through an opaque register copy: the per-timestep
+// offsets of a row are formed inside the iteration rather than kept in
+// scalar registers for the whole loop.
+__device__ __forceinline__ int at_use(int v) {
+  __asm__ volatile("" : "+s"(v));
+  return v;
+}
+
+// Arguments of k_setup_rows: only what the row loops read and write, so that
+// few scalar registers hold kernel arguments.
+template <typename F>
+struct RowsArgs {
+  const int* mon;
+  const int* cont;
+  const double* f0MC;
+  const double* bMC;
+  const double* limM;
+  const double* sllC;
+  const double* SMC;
+  const double* S;     // full S and f0 and b: the optional base-flow output only
+  const double* f0;
+  const double* b;
+  F* fM;
+  F* UM;
+  F* rec;
+  int* act;
+  int* slot;
+  CandInfo* info;
+  const SetupDesc* desc;
+  int m, T, nM, nC;
+};
+
+// Row scratch of k_setup_rows in LDS.
+template <typename F>
+struct RowsShared {
+  static constexpr int SP = 128 / (int)sizeof(F);  // record entries per staging pass
+  F stage[4][64][SP + 1];   // one slab per wave
+  SetupDesc d;              // the candidate's description (the parts in use)
+  int wcnt[2][4];
+  int n0, nisl, bad;
+};
+
+// W_q = sum_s coefW[s][q] tab[src_row[s]][col] (and the pivoted right-hand
+// side Y when V is wanted), eight independent row loads in flight; the
+// coefficient rows past the sources are zero.
+template <int R, bool WITH_V>
+__device__ __forceinline__ void gather_rows(const SetupDesc& D, int nsrc, const double* __restrict__ tab,
+                                            size_t ld, int col, double* W, double* Y) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) { W[q] = 0.0; if (WITH_V) Y[q] = 0.0; }
+  for (int s0 = 0; s0 < nsrc; s0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = (s0 + u < nsrc)
+                 ? tab[(size_t)__builtin_amdgcn_readfirstlane(D.src_row[s0 + u]) * ld + col]
+                 : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        W[q] = fma(D.coefW[s0 + u][q], v[u], W[q]);
+        if (WITH_V) Y[q] = fma(D.coefV[s0 + u][q], v[u], Y[q]);
+      }
+    }
+  }
+}
+
+// Row e is an opening of the candidate / a branch moved by one of its splits.
+__device__ __forceinline__ void row_kind(const SetupDesc& D, int k, int nm, int e, bool* opened,
+                                         bool* moved) {
+  bool op = false, mv = false;
+  for (int q = 0; q < k; ++q) op |= (D.open[q] == e);
+  for (int p = 0; p < nm; ++p) mv |= (D.mbr[p] == e);
+  *opened = op;
+  *moved = mv;
+}
+
+template <typename F, int TT, int R>
+__device__ __forceinline__ void setup_rows(const RowsArgs<F>& a, double* __restrict__ base_out,
+                                           int c, int cb, CSetupDesc* D, RowsShared<F>& sm) {
+  const SetupDesc& L = sm.d;
+  constexpr int RS = rec_stride(TT);
+  constexpr int SP = RowsShared<F>::SP;
+  const int tid = threadIdx.x;
+  const int m = a.m, T = a.T, nM = a.nM, nC = a.nC;
   const size_t nMC = (size_t)nM + nC;
-  // U row of branch e from its column gather: U_q = b_e W_q (openings),
-  // U_{k+j} = -b_e W_{k+j} + sum_{b in S_j, b = e} sg_b b_b (moved-branch term)
-  auto u_from_w = [&](int e, double be, const double* W, double* U) {
+  const int k = D->k, nsrc = D->nsrc, nm = D->nm;
+
+  // U row of branch e: U_q = (+-) b_e W_q, plus sg_b b_b in its split's slot
+  // when e itself is moved (rare: a branch of the candidate)
+  auto finish_u = [&](int e, double be, bool moved, const double* W, double* U) {
 #pragma unroll
-    for (int q = 0; q < kMaxRank; ++q) U[q] = (q < k ? be : -be) * W[q];
-    for (int p = 0; p < nm; ++p) {
-      if (sh.mbr[p] == e) {
-        const int qq = k + sh.mj[p];
+    for (int q = 0; q < R; ++q) U[q] = L.uscale[q] * be * W[q];
+    if (moved) {
+      for (int p = 0; p < nm; ++p) {
+        if (L.mbr[p] == e) {
+          const int qq = L.mslot[p];
 #pragma unroll
-        for (int q = 0; q < kMaxRank; ++q)
-          if (q == qq) U[q] += sh.msg[p];
+          for (int q = 0; q < R; ++q)
+            if (q == qq) U[q] += L.msg[p];
+        }
       }
     }
   };
 
   // monitored rows: f'_M and U_M.  A non-finite grid injection makes every
-  // base flow non-finite (the product with a zero PTDF entry included), so
-  // the monitored rows' f0 see it.
+  // base flow of its timestep non-finite (the product with a zero PTDF entry
+  // included), so the first monitored row sees it.
   int n0 = 0, nbad = 0;
+  F* const fM = a.fM + (size_t)c * TT * nM;       // [t][ei]: coalesced across lanes
+  F* const UM = a.UM + (size_t)c * kVSlots * nM;  // [q][ei]
   for (int ei = tid; ei < nM; ei += 256) {
     keep_in_loop();
-    const int e = g.mon[ei];
-    bool opened = false;
-    for (int q = 0; q < k; ++q) opened |= (sh.open[q] == e);
-    // loads that depend on the row alone go out before the column gather,
-    // so that their latency overlaps it
+    const int sM = at_use(nM), sMC = at_use((int)nMC);
+    const int e = a.mon[ei];
     double f0e[TT];
 #pragma unroll
-    for (int t = 0; t < TT; ++t) f0e[t] = t < T ? g.f0MC[(size_t)t * nMC + ei] : 0.0;
+    for (int t = 0; t < TT; ++t) f0e[t] = a.f0MC[t * sMC + ei];   // zero rows past T
+    if (ei == 0)
 #pragma unroll
-    for (int t = 0; t < TT; ++t) nbad += !isfinite(f0e[t]);
-    const double be = g.bMC[ei], lim = g.limM[ei];
-    double W[kMaxRank], U[kMaxRank];
-    gather_column(g.SMC, nMC, ei, sh, W);
-    u_from_w(e, be, W, U);
-    F* fo = w.fM + (size_t)c * TT * nM + ei;   // [c][t][ei]: coalesced across threads
+      for (int t = 0; t < TT; ++t) nbad += !isfinite(f0e[t]);
+    const double be = a.bMC[ei];
+    bool opened, moved;
+    row_kind(L, k, nm, e, &opened, &moved);
+    // an opened monitored branch carries no flow: never counted, its stored
+    // rows are zeroed below
+    const double lim = opened ? HUGE_VAL : a.limM[ei];
+    double W[R > 0 ? R : 1], U[R > 0 ? R : 1];
+    gather_rows<R, false>(L, nsrc, a.SMC, nMC, ei, W, nullptr);
+    finish_u(e, be, moved, W, U);
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
-      double fp = 0.0;
-      if (t < T && !opened) {
-        fp = f0e[t];
+      double fp = f0e[t];
 #pragma unroll
-        for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
-        n0 += fabs(fp) > lim;
-      }
-      fo[(size_t)t * nM] = (F)fp;
+      for (int q = 0; q < R; ++q) fp += U[q] * L.x[t][q];
+      // past T: x(t) = 0 and f0 = 0, so fp = 0
+      n0 += fabs(fp) > lim;
+      fM[t * sM + ei] = (F)fp;
     }
-    F* uo = w.UM + (size_t)c * kVSlots * nM + ei;   // [c][q][ei]
 #pragma unroll
-    for (int q = 0; q < kVSlots; ++q) uo[(size_t)q * nM] = opened ? (F)0 : (F)U[q];
+    for (int q = 0; q < kVSlots; ++q) UM[q * sM + ei] = q < R ? (F)U[q < R ? q : 0] : (F)0;
+    if (opened) {   // rare: one of the candidate's openings
+#pragma unroll
+      for (int t = 0; t < TT; ++t) fM[t * sM + ei] = (F)0;
+#pragma unroll
+      for (int q = 0; q < R; ++q) UM[q * sM + ei] = (F)0;
+    }
   }
-  if (n0) atomicAdd(&s_n0, n0);
-  if (nbad) atomicAdd(&s_bad, nbad);
+  if (n0) atomicAdd(&sm.n0, n0);
+  if (nbad) atomicAdd(&sm.bad, nbad);
 
   // optional full post-switch base flows
   if (base_out) {
     for (int e = tid; e < m; e += 256) {
       keep_in_loop();
-      bool opened = false;
-      for (int q = 0; q < k; ++q) opened |= (sh.open[q] == e);
-      double W[kMaxRank], U[kMaxRank];
-      gather_column(g.S, (size_t)m, e, sh, W);
-      u_from_w(e, g.b[e], W, U);
+      bool opened, moved;
+      row_kind(L, k, nm, e, &opened, &moved);
+      double W[R > 0 ? R : 1], U[R > 0 ? R : 1];
+      gather_rows<R, false>(L, nsrc, a.S, (size_t)m, e, W, nullptr);
+      finish_u(e, a.b[e], moved, W, U);
       for (int t = 0; t < T; ++t) {
         double fp = 0.0;
         if (!opened) {
-          fp = g.f0[(size_t)e * T + t];
+          fp = a.f0[(size_t)e * T + t];
 #pragma unroll
-          for (int q = 0; q < kMaxRank; ++q) fp += U[q] * s_x[q][t];
+          for (int q = 0; q < R; ++q) fp += U[q] * L.x[t][q];
         }
         base_out[((size_t)cb * m + e) * T + t] = fp;
       }
@@ -457,118 +582,121 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
 
   // contingencies: V_l, denominators, phi_l, ordered compaction
   const int lane = tid & 63, wid = tid >> 6;
-  F* rec = w.rec + (size_t)c * (nC + 1) * RS;
-  int* act = w.act + (size_t)c * (nC + 1);
+  F* rec = a.rec + (size_t)c * (nC + 1) * RS;
+  int* act = a.act + (size_t)c * (nC + 1);
   int nisl = 0;
+  int run = 0;   // records written by the chunks before (same in every lane)
   for (int base = 0; base < nC; base += 256) {
     keep_in_loop();
+    const int sMC = at_use((int)nMC);
     const int li = base + tid;
-    bool active = false, island = false, opened = false;
-    int l = 0;
-    double V[kMaxRank], U[kMaxRank];
-    double inv_d = 0.0;
+    const bool row = li < nC;
+    const int lc = row ? li : nC - 1;
+    const int l = a.cont[lc];
+    // row-only loads first (their latency overlaps the column gather)
+    const double s_ll = a.sllC[lc];
+    const double b_l = a.bMC[nM + lc];
     double f0l[TT];
-    double s_ll = 0.0, b_l = 0.0;
 #pragma unroll
-    for (int q = 0; q < kMaxRank; ++q) { V[q] = 0.0; U[q] = 0.0; }
-    if (li < nC) {
-      l = g.cont[li];
-      // row-only loads first (their latency overlaps the column gather)
-      s_ll = g.sllC[li];
-      b_l = g.bMC[nM + li];
+    for (int t = 0; t < TT; ++t) f0l[t] = a.f0MC[t * sMC + nM + lc];
+    bool opened, moved;
+    row_kind(L, k, nm, l, &opened, &moved);
+    double W[R > 0 ? R : 1], U[R > 0 ? R : 1], V[R > 0 ? R : 1];
+    gather_rows<R, true>(L, nsrc, a.SMC, nMC, nM + lc, W, V);
+    finish_u(l, b_l, moved, W, U);
+    // the contingency itself moved by split j: ps_j = sg_l enters the
+    // right-hand side as sg_l / s_j, in its pivoted position
+    if (moved) {
+      for (int p = 0; p < nm; ++p) {
+        if (L.mbr[p] == l) {
+          const int pp = L.mpos[p];
 #pragma unroll
-      for (int t = 0; t < TT; ++t) f0l[t] = t < T ? g.f0MC[(size_t)t * nMC + nM + li] : 0.0;
-      for (int q = 0; q < k; ++q) opened |= (sh.open[q] == l);
-      if (opened) {
-        active = true;  // already open: the N-0 state (phi = 0)
-      } else {
-        double W[kMaxRank];
-        gather_column(g.SMC, nMC, nM + li, sh, W);
-        const double bl = b_l;
-        // right-hand side of the factor column: R_q = b_{K_q} W_q (openings),
-        // R_{k+j} = (ps_j - W_{k+j}) / s_j with ps_j = sg_l if l is moved by j
-#pragma unroll
-        for (int q = 0; q < kMaxRank; ++q) {
-          double v = 0.0;
-          if (q < k) v = sh.bK[q] * W[q];
-          else if (q < r) v = -W[q] * sh.inv_s[q - k];
-          V[q] = v;
-        }
-        for (int p = 0; p < nm; ++p) {
-          if (sh.mbr[p] == l) {
-            const int qq = k + sh.mj[p];
-            const double add = sh.msign[p] * sh.inv_s[sh.mj[p]];
-#pragma unroll
-            for (int q = 0; q < kMaxRank; ++q)
-              if (q == qq) V[q] += add;
-          }
-        }
-        u_from_w(l, bl, W, U);
-        lu_solve(sh.M, sh.piv, r, V);
-        double hll = bl * s_ll;
-#pragma unroll
-        for (int q = 0; q < kMaxRank; ++q) hll += U[q] * V[q];
-        const double d = 1.0 - hll;
-        if (fabs(d) < kTauCont) {
-          island = true;
-        } else {
-          active = true;
-          inv_d = 1.0 / d;
+          for (int q = 0; q < R; ++q)
+            if (q == pp) V[q] += L.madd[p];
         }
       }
     }
+    // V_l = M_c^-1 rhs from the LU factors (the right-hand side is already
+    // in pivoted order)
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+#pragma unroll
+      for (int q = 0; q < i; ++q) V[i] -= L.LU[i][q] * V[q];
+    }
+#pragma unroll
+    for (int i = R - 1; i >= 0; --i) {
+#pragma unroll
+      for (int q = i + 1; q < R; ++q) V[i] -= L.LU[i][q] * V[q];
+      V[i] *= L.inv_diag[i];
+    }
+    double hll = b_l * s_ll;
+#pragma unroll
+    for (int q = 0; q < R; ++q) hll += U[q] * V[q];
+    const double d = 1.0 - hll;
+    // an already opened contingency is the N-0 state: phi = 0, V = 0
+    const bool island = row && !opened && fabs(d) < kTauCont;
+    const bool active = row && !island;
+    const double inv_d = (opened || island) ? 0.0 : 1.0 / d;
     nisl += island;
+    // ordered compaction: one barrier per chunk, the wave counts double
+    // buffered so that a wave one chunk ahead never overwrites unread counts
     const unsigned long long mask = ballot64(active);
-    if (lane == 0) s_wcnt[wid] = __popcll(mask);
+    const int par = (base >> 8) & 1;
+    if (lane == 0) sm.wcnt[par][wid] = __popcll(mask);
     __syncthreads();
-    int o0 = s_base;
-    for (int q = 0; q < wid; ++q) o0 += s_wcnt[q];
+    int o0 = run;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int v = sm.wcnt[par][q];
+      o0 += q < wid ? v : 0;
+      run += v;
+    }
     const int rank = __popcll(mask & ((1ull << lane) - 1ull));
     const int na = __popcll(mask);
     const int off = o0 + rank;
-    // Records go out through LDS in 16-entry passes so that every store
-    // instruction writes whole contiguous runs (direct per-thread 128-byte
-    // records leave partially written lines thrashing the L2).
+    // Records go out through the wave's own LDS slab, one 128-byte line of
+    // each record per pass, so that every store instruction writes whole
+    // lines (direct per-lane 128-byte records leave partially written lines
+    // thrashing the L2); only the wave's lanes meet there.
+    F (*slab)[SP + 1] = sm.stage[wid];
 #pragma unroll
-    for (int p0 = 0; p0 < RS; p0 += 16) {
+    for (int p0 = 0; p0 < RS; p0 += SP) {
       if (active) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < SP; ++u) {
           const int slot = p0 + u;
           if (slot < RS) {
             double v = 0.0;
             if (slot < TT) {
               // phi_l(t) = f'_l(t) / (1 - H'_ll), zero for an already opened l
-              if (slot < T && !opened) {
+              // (and past T, where f0 and x(t) are zero)
+              if (!opened) {
                 double fl = f0l[slot];
 #pragma unroll
-                for (int q = 0; q < kMaxRank; ++q) fl += U[q] * s_x[q][slot];
+                for (int q = 0; q < R; ++q) fl += U[q] * L.x[slot][q];
                 v = fl * inv_d;
               }
-            } else if (slot < TT + kVSlots) {
-              v = V[slot - TT];
+            } else if (slot < TT + R) {
+              v = opened ? 0.0 : V[slot - TT < R ? slot - TT : 0];
             }
-            s_stage[wid][rank][u] = (F)v;
+            slab[rank][u] = (F)v;
           }
         }
       }
-      __syncthreads();
-      const int nsl = (RS - p0) < 16 ? (RS - p0) : 16;
-      for (int idx = lane; idx < na * 16; idx += 64) {
-        const int i = idx >> 4, u = idx & 15;
-        if (u < nsl) rec[(size_t)(o0 + i) * RS + p0 + u] = s_stage[wid][i][u];
+      wave_lds_sync();
+      const int nsl = (RS - p0) < SP ? (RS - p0) : SP;
+      for (int idx = lane; idx < na * SP; idx += 64) {
+        const int i = idx / SP, u = idx - (idx / SP) * SP;
+        if (u < nsl) rec[(size_t)(o0 + i) * RS + p0 + u] = slab[i][u];
       }
-      __syncthreads();
+      wave_lds_sync();
     }
     if (active) act[off] = li;
-    if (w.slot && li < nC) w.slot[(size_t)c * nC + li] = active ? off : -1;
-    __syncthreads();
-    if (tid == 0) s_base += s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-    __syncthreads();
+    if (a.slot && row) a.slot[(size_t)c * nC + li] = active ? off : -1;
   }
-  if (nisl) atomicAdd(&s_nisl, nisl);
+  if (nisl) atomicAdd(&sm.nisl, nisl);
   __syncthreads();
-  const int n_act = s_base;
+  const int n_act = run;
   // even length for the paired sweep: duplicate the last record (max unchanged)
   if (n_act & 1) {
     const F* src = rec + (size_t)(n_act - 1) * RS;
@@ -576,23 +704,86 @@ __global__ __launch_bounds__(256) void k_setup(GridDev g, BatchDev bt, SweepBufs
     for (int q = tid; q < RS; q += 256) dst[q] = src[q];
     if (tid == 0) act[n_act] = act[n_act - 1];
   }
-  if (tid == 0 && s_bad) {
+  CandInfo* inf = a.info + c;
+  if (tid == 0 && sm.bad) {
     // non-finite injections: no metric is defined, the candidate is skipped
     inf->status = TTO_ST_INVALID | TTO_ST_NONFINITE;
-    inf->r = r; inf->k = k; inf->n_act = 0; inf->n_act_pad = 0; inf->n_island = 0;
-    inf->n_moved = sh.moff[ns];
+    inf->r = R; inf->k = k; inf->n_act = 0; inf->n_act_pad = 0; inf->n_island = 0;
+    inf->n_moved = nm;
     inf->n_crit_n0 = 0;
   } else if (tid == 0) {
     inf->status = 0;
-    inf->r = r;
+    inf->r = R;
     inf->k = k;
     inf->n_act = n_act;
     inf->n_act_pad = n_act + (n_act & 1);
-    inf->n_island = s_nisl;
-    inf->n_crit_n0 = s_n0;
-    inf->n_moved = sh.moff[ns];
-    for (int q = 0; q < kMaxRank; ++q) inf->open_br[q] = q < k ? sh.open[q] : -1;
+    inf->n_island = sm.nisl;
+    inf->n_crit_n0 = sm.n0;
+    inf->n_moved = nm;
+    for (int q = 0; q < kMaxRank; ++q) inf->open_br[q] = L.open[q];
   }
+}
+
+template <typename F, int TT>
+__global__ __launch_bounds__(256) void k_setup_rows(RowsArgs<F> a, const int* __restrict__ map,
+                                                    const int* __restrict__ live, int B,
+                                                    double* __restrict__ base_out) {
+  const int c = blockIdx.x;
+  int cb = c;
+  if (map) {
+    if (c >= min(*live, B)) return;
+    cb = map[c];
+  }
+  __shared__ RowsShared<F> sm;
+  CSetupDesc* D = (CSetupDesc*)(a.desc + c);
+  if (D->status) return;   // invalid or islanded: the first kernel wrote its outputs
+  if (threadIdx.x == 0) { sm.n0 = 0; sm.nisl = 0; sm.bad = D->bad; }
+  // the description's parts in use: openings, sources and their coefficient
+  // rows (padded to 8), moved branches, factors, x(t)
+  {
+    const int tid = threadIdx.x;
+    const int nsrc8 = (D->nsrc + 7) & ~7, nm = D->nm;
+    SetupDesc& L = sm.d;
+    if (tid < 8) { L.open[tid] = D->open[tid]; L.uscale[tid] = D->uscale[tid]; L.inv_diag[tid] = D->inv_diag[tid]; }
+    if (tid < 64) L.LU[tid >> 3][tid & 7] = D->LU[tid >> 3][tid & 7];
+    if (tid < nsrc8) L.src_row[tid] = D->src_row[tid];
+    if (tid < nm) {
+      L.mbr[tid] = D->mbr[tid]; L.mslot[tid] = D->mslot[tid]; L.mpos[tid] = D->mpos[tid];
+      L.msg[tid] = D->msg[tid]; L.madd[tid] = D->madd[tid];
+    }
+    for (int i = tid; i < nsrc8 * kMaxRank; i += 256) {
+      L.coefW[i >> 3][i & 7] = D->coefW[i >> 3][i & 7];
+      L.coefV[i >> 3][i & 7] = D->coefV[i >> 3][i & 7];
+    }
+    for (int i = tid; i < TT * kMaxRank; i += 256) L.x[i >> 3][i & 7] = D->x[i >> 3][i & 7];
+  }
+  __syncthreads();
+  switch (D->r) {
+    case 0: setup_rows<F, TT, 0>(a, base_out, c, cb, D, sm); break;
+    case 1: setup_rows<F, TT, 1>(a, base_out, c, cb, D, sm); break;
+    case 2: setup_rows<F, TT, 2>(a, base_out, c, cb, D, sm); break;
+    case 3: setup_rows<F, TT, 3>(a, base_out, c, cb, D, sm); break;
+    case 4: setup_rows<F, TT, 4>(a, base_out, c, cb, D, sm); break;
+    case 5: setup_rows<F, TT, 5>(a, base_out, c, cb, D, sm); break;
+    case 6: setup_rows<F, TT, 6>(a, base_out, c, cb, D, sm); break;
+    case 7: setup_rows<F, TT, 7>(a, base_out, c, cb, D, sm); break;
+    default: setup_rows<F, TT, 8>(a, base_out, c, cb, D, sm); break;
+  }
+}
+
+// Both set-up kernels of a batch (bt.B workgroups each).
+template <typename F, int TT>
+static void launch_setup_tt(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
+                            double* base_out, hipStream_t s) {
+  hipLaunchKernelGGL((k_setup_cand<F, TT>), dim3(bt.B), dim3(64), 0, s, g, bt, w);
+  RowsArgs<F> a;
+  a.mon = g.mon; a.cont = g.cont; a.f0MC = g.f0MC; a.bMC = g.bMC; a.limM = g.limM;
+  a.sllC = g.sllC; a.SMC = g.SMC; a.S = g.S; a.f0 = g.f0; a.b = g.b;
+  a.fM = w.fM; a.UM = w.UM; a.rec = w.rec; a.act = w.act; a.slot = w.slot; a.info = w.info;
+  a.desc = w.desc;
+  a.m = g.n_branch; a.T = g.T; a.nM = g.nM; a.nC = g.nC;
+  hipLaunchKernelGGL((k_setup_rows<F, TT>), dim3(bt.B), dim3(256), 0, s, a, bt.map, bt.live, bt.B,
+                     base_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,7 +1352,7 @@ static void launch_pass(const GridDev& g, const BatchDev& bt, SweepBufs<F> w,
   if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
   w.n_eblk = (g.nM + 63) / 64;   // partials per candidate: one per 64-branch chunk
   if (ev) hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL((k_setup<F, TT>), dim3(bt.B), dim3(256), 0, s, g, bt, w, o.base_flows);
+  launch_setup_tt<F, TT>(g, bt, w, o.base_flows, s);
   if (ev) hipEventRecord(ev[1], s);
   launch_sweep<F, TT>(g, bt, w, HMC, o.fmax, s, plan);
   if (ev) hipEventRecord(ev[2], s);
@@ -1211,8 +1402,7 @@ static hipError_t launch_eval_tt(const GridDev& g, const BatchDev& bt, const Swe
     SweepBufs<double> w64 = *rw;
     w64.n_eblk = (g.nM + 63) / 64;
     constexpr int kSplit = 8;
-    hipLaunchKernelGGL((k_setup<double, TT>), dim3(rb.B), dim3(256), 0, s, gh, rb, w64,
-                       (double*)nullptr);
+    launch_setup_tt<double, TT>(gh, rb, w64, nullptr, s);
     hipLaunchKernelGGL(k_zero_live_u64, dim3(1024), dim3(256), 0, s, rc.fbuf,
                        (const int*)rc.count, rc.cap, (size_t)TT * g.nM);
     hipLaunchKernelGGL((k_sweep_split<TT>), dim3((rb.B * w64.n_eblk * kSplit + 3) / 4), dim3(256),
@@ -1371,7 +1561,7 @@ static hipError_t launch_worst_k_tt(const GridDev& g, const BatchDev& bt, const 
   const F* HMC;
   if constexpr (sizeof(F) == 4) HMC = g.HMC32; else HMC = g.HMC64;
   const int n_eblk = (g.nM + 255) / 256;
-  hipLaunchKernelGGL((k_setup<F, TT>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr);
+  launch_setup_tt<F, TT>(g, bt, w, nullptr, s);
   if (g.nC > 0)
     hipLaunchKernelGGL((k_cont_energy<F, TT>), dim3(n_eblk, bt.B), dim3(256), 0, s, g, w, HMC,
                        n_eblk, part);
@@ -1397,10 +1587,10 @@ template <typename F>
 hipError_t launch_setup(const GridDev& g, const BatchDev& bt, const SweepBufs<F>& w,
                         hipStream_t s) {
   switch (g.TT) {
-    case 1: hipLaunchKernelGGL((k_setup<F, 1>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
-    case 8: hipLaunchKernelGGL((k_setup<F, 8>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
-    case 24: hipLaunchKernelGGL((k_setup<F, 24>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
-    default: hipLaunchKernelGGL((k_setup<F, 32>), dim3(bt.B), dim3(256), 0, s, g, bt, w, (double*)nullptr); break;
+    case 1: launch_setup_tt<F, 1>(g, bt, w, nullptr, s); break;
+    case 8: launch_setup_tt<F, 8>(g, bt, w, nullptr, s); break;
+    case 24: launch_setup_tt<F, 24>(g, bt, w, nullptr, s); break;
+    default: launch_setup_tt<F, 32>(g, bt, w, nullptr, s); break;
   }
   return hipGetLastError();
 }

@@ -94,7 +94,8 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   L.HMC64 = cv.take<double>((size_t)std::max(d->n_contingency, 1) * d->n_monitored);
   L.f0 = cv.take<double>(m * T);
   const size_t nMC = (size_t)d->n_monitored + d->n_contingency;
-  L.f0MC = cv.take<double>(T * nMC);
+  const size_t TTp = tile_T(d->n_timesteps);   // rows past T stay zero
+  L.f0MC = cv.take<double>(TTp * nMC);
   L.bMC = cv.take<double>(nMC);
   L.limM = cv.take<double>(d->n_monitored);
   L.sllC = cv.take<double>(std::max(d->n_contingency, 1));
@@ -120,7 +121,7 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
     L.PT64 = cv.take<double>((size_t)kGemmN * ld);
     L.part_hi = cv.take<double>((size_t)L.ksplit * m * kGemmN);
     L.gemm_err = cv.take<double>(1);
-    L.f0MC_hi = cv.take<double>(T * nMC);
+    L.f0MC_hi = cv.take<double>(TTp * nMC);
   }
   (void)n;
   *bytes = cv.off;
@@ -139,6 +140,7 @@ SweepBufs<F> carve_batch(int B, int nM, int nC, int TT, void* ws, size_t* bytes)
   w.act = cv.take<int>((size_t)B * (nC + 1));
   w.slot = cv.take<int>((size_t)B * std::max(nC, 1));
   w.part = cv.take<Partial>((size_t)B * w.n_eblk);
+  w.desc = cv.take<SetupDesc>(B);
   *bytes = cv.off;
   return w;
 }
@@ -321,10 +323,10 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
                             L.bMC, L.limM, L.sllC, s));
   const size_t nMC = (size_t)d->n_monitored + d->n_contingency;
   HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
-  HIP_TRY(hipMemsetAsync(L.f0MC, 0, sizeof(double) * nMC * d->n_timesteps, s));
+  HIP_TRY(hipMemsetAsync(L.f0MC, 0, sizeof(double) * nMC * tile_T(d->n_timesteps), s));
   if (L.f0_hi) {
     HIP_TRY(hipMemsetAsync(L.f0_hi, 0, sizeof(double) * m * d->n_timesteps, s));
-    HIP_TRY(hipMemsetAsync(L.f0MC_hi, 0, sizeof(double) * nMC * d->n_timesteps, s));
+    HIP_TRY(hipMemsetAsync(L.f0MC_hi, 0, sizeof(double) * nMC * tile_T(d->n_timesteps), s));
     HIP_TRY(hipMemsetAsync(L.gemm_err, 0, sizeof(double), s));
   }
   HIP_TRY(hipStreamSynchronize(s));

@@ -20,6 +20,8 @@ constexpr double kWorstContTieMW = TTO_WORST_CONT_TIE_MW;  // worst-contingency 
 constexpr double kLoadTieRel = TTO_LOAD_TIE_REL;          // worst (branch, timestep) tie band
 constexpr int kGemmN = 32;          // timestep columns of the f0 GEMM (T padded)
 constexpr int kSubMax = 32;         // gather sources whose mutual S entries the set-up stages in LDS
+constexpr int kMaxSrc = kMaxRank + kMaxMoved;   // gather sources of a candidate
+static_assert(kMaxSrc % 8 == 0, "sources are read in groups of 8");
 
 // Record of one active contingency in a candidate's sweep list:
 // phi(t) for t < TT, then V_j for j < 8, padded to a multiple of 4 entries.
@@ -53,7 +55,7 @@ struct GridDev {
   const int* cont;      // [nC]
   // Tables of the monitored then contingency rows, contiguous in the row
   // index so that the lanes of a row loop read them coalesced:
-  const double* f0MC;     // [T][nM + nC] base flows f0 at row j
+  const double* f0MC;     // [TT][nM + nC] base flows f0 at row j, zero rows past T
   const double* f0MC_hi;  // the same from f0_hi
   const double* bMC;      // [nM + nC] susceptance of row j
   const double* limM;     // [nM] limit of M[ei]
@@ -112,6 +114,32 @@ struct CandInfo {
   int open_br[kMaxRank];
 };
 
+// Per-candidate description left by the first set-up kernel for the second:
+// the gather sources (openings, then moved branches) with their coefficients
+// for W_q (the column of U before the b_e factor) and for the pivoted
+// right-hand side of V_l, the LU factors of the bordered system, x(t) and
+// the moved-branch fix-ups.  Coefficient rows past nsrc are zero up to the
+// next multiple of 8.
+struct SetupDesc {
+  int status;              // 0, or the TTO_ST_* bits of a candidate with no row work
+  int r, k, ns, nsrc, nm;  // rank, openings, splits, sources, moved branches
+  int bad;                 // x(t) not finite
+  int pad_;
+  int open[kMaxRank];      // opened branches, -1 past k
+  int src_row[kMaxSrc];
+  int mbr[kMaxMoved];      // moved branches
+  int mslot[kMaxMoved];    // their split's slot k + j
+  int mpos[kMaxMoved];     // that slot's row in the pivoted order
+  double msg[kMaxMoved];   // sg_b b_b
+  double madd[kMaxMoved];  // sg_b / s_j
+  double uscale[kMaxRank]; // +1 openings, -1 splits: U_q = uscale_q b_e W_q
+  double coefW[kMaxSrc][kMaxRank];
+  double coefV[kMaxSrc][kMaxRank];
+  double LU[kMaxRank][kMaxRank];   // unit L below the diagonal, U on and above
+  double inv_diag[kMaxRank];
+  double x[32][kMaxRank];          // x(t), zero for t >= T
+};
+
 // Per (candidate, monitored block) reduction of the sweep.
 struct Partial {
   double sum_o;     // sum of max(fmax - lim, 0)
@@ -134,6 +162,7 @@ struct SweepBufs {
   int* act;         // [B][nC+1] contingency index of each record
   int* slot;        // [B][nC] record of each contingency or -1 (optional)
   Partial* part;    // [B][n_eblk] one per chunk of 64 monitored branches
+  SetupDesc* desc;  // [B] set-up description of each candidate
   int n_eblk;       // ceil(nM / 64)
 };
 
