@@ -1029,6 +1029,44 @@ __global__ __launch_bounds__(256) void k_sweep(GridDev g, SweepBufs<F> w,
 // candidates whose discrete outputs lie within the flow error margin of a
 // decision (a load-bin edge, a runner-up (e, t) loading, a runner-up
 // contingency at (e*, t*)) are queued for the FP64 pass.
+// |f^(l)| at (e*, t*) for the active contingencies i = lane + 64 u of a
+// candidate, four per lane per step so that their loads are in flight
+// together; the rank is a compile-time bound.  Pass 1 keeps the maximum
+// (and the flows, when vbuf is given).
+template <typename F, int TT, int R>
+__device__ __forceinline__ double fin_flows(const F* __restrict__ HMC, const F* rec,
+                                            const int* act, const F* ua, int nM, int be, int bt,
+                                            F a, int n_act, F* vbuf) {
+  constexpr int RS = rec_stride(TT);
+  const int lane = threadIdx.x;
+  F u[R > 0 ? R : 1];
+#pragma unroll
+  for (int j = 0; j < R; ++j) u[j] = ua[(size_t)j * nM];
+  double bv = -1.0;
+  for (int i0 = lane; i0 < n_act; i0 += 256) {
+    F h[4], ph[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = min(i0 + 64 * q, n_act - 1);
+      const F* ri = rec + (size_t)i * RS;
+      h[q] = HMC[(size_t)act[i] * nM + be];
+      ph[q] = ri[bt];
+#pragma unroll
+      for (int j = 0; j < R; ++j) h[q] = fma_t(u[j], ri[TT + j], h[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + 64 * q;
+      if (i < n_act) {
+        const double v = (double)fabs_t(fma_t(h[q], ph[q], a));
+        if (vbuf) vbuf[i] = (F)v;
+        bv = fmax(bv, v);
+      }
+    }
+  }
+  return bv;
+}
+
 // Dynamic LDS of k_finalize: one flow per active contingency when it fits in
 // 32 KB (else the second pass recomputes the flows).
 template <typename F>
@@ -1121,10 +1159,16 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
       return (double)fabs_t(fma_t(h, ri[bt], a));
     };
     F* vbuf = cache_flows ? (F*)fin_lds : nullptr;   // lane i mod 64 owns entry i
-    for (int i = lane; i < inf.n_act; i += 64) {
-      const double v = flow(i);
-      if (vbuf) vbuf[i] = (F)v;
-      bv = fmax(bv, v);
+    switch (inf.r) {
+      case 0: bv = fin_flows<F, TT, 0>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      case 1: bv = fin_flows<F, TT, 1>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      case 2: bv = fin_flows<F, TT, 2>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      case 3: bv = fin_flows<F, TT, 3>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      case 4: bv = fin_flows<F, TT, 4>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      case 5: bv = fin_flows<F, TT, 5>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      case 6: bv = fin_flows<F, TT, 6>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      case 7: bv = fin_flows<F, TT, 7>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
+      default: bv = fin_flows<F, TT, 8>(HMC, rec, act, ua, nM, be, bt, a, inf.n_act, vbuf); break;
     }
     for (int off = 32; off > 0; off >>= 1) bv = fmax(bv, __shfl_xor(bv, off));
     const double cut = bv - kWorstContTieMW;

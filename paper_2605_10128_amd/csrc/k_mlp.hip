@@ -323,21 +323,47 @@ __global__ __launch_bounds__(256) void k_w1b_grad(const int* __restrict__ start,
                                                   const int* __restrict__ list,
                                                   const unsigned short* __restrict__ dz1, int H,
                                                   float* __restrict__ g) {
-  __shared__ int s_in[kMlpMaxTrain];
+  constexpr int kWords = kMlpMaxTrain / 32;
+  static_assert(kWords <= 256 && kWords % 64 == 0, "one bitmap word per thread, whole waves");
+  __shared__ unsigned s_bits[kWords];
   __shared__ int s_sorted[kMlpMaxTrain];
-  const int i = blockIdx.x;
+  __shared__ int s_wtot[kWords / 64];
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int lo = start[i], L = min(start[i + 1] - lo, kMlpMaxTrain);
-  for (int q = threadIdx.x; q < L; q += 256) s_in[q] = list[lo + q];
+  // the bucket's sample ids (distinct) as a bitmap, then listed in ascending
+  // order: the column sums below add them in sample order, whatever order
+  // the bucketing wrote them in
+  if (tid < kWords) s_bits[tid] = 0u;
   __syncthreads();
-  // rank of each entry among the bucket by sample id (sample ids are distinct)
-  for (int q = threadIdx.x; q < L; q += 256) {
-    const int v = s_in[q];
-    int rank = 0;
-    for (int u = 0; u < L; ++u) rank += s_in[u] < v;
-    s_sorted[rank] = v;
+  for (int q = tid; q < L; q += 256) {
+    const int v = list[lo + q];
+    atomicOr(&s_bits[v >> 5], 1u << (v & 31));
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < H; j += 256) {
+  unsigned word = 0u;
+  int pos = 0;
+  if (tid < kWords) {
+    word = s_bits[tid];
+    const int n = __popc(word);
+    int x = n;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(x, o);
+      if (lane >= o) x += u;
+    }
+    if (lane == 63) s_wtot[tid >> 6] = x;
+    pos = x - n;
+  }
+  __syncthreads();
+  if (tid < kWords) {
+    for (int q = 0; q < (tid >> 6); ++q) pos += s_wtot[q];
+    while (word) {
+      const int b = __ffs(word) - 1;
+      s_sorted[pos++] = tid * 32 + b;
+      word &= word - 1u;
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < H; j += 256) {
     float acc = 0.f;
     for (int q = 0; q < L; ++q) acc += bf16_to_f(dz1[(size_t)s_sorted[q] * H + j]);
     g[(size_t)i * H + j] = acc;
