@@ -25,93 +25,146 @@ __device__ inline unsigned short bf16_rne(float f) {
 __device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // ---------------------------------------------------------------------------
-// Stage a 64 x 32 operand tile into LDS as T[r][k] (k contiguous, row stride
-// 40 halfwords so every 8-element fragment is one aligned 16-byte access).
-// ROWK: the operand is stored [rows][ld] with k contiguous (global row r0+i,
-// column k0+j); otherwise [k][ld] with the rows contiguous.  `vec` selects
-// 16-byte global loads (requires the contiguous extent to be a multiple of 8).
-template <bool ROWK>
-__device__ inline void stage_tile(const unsigned short* __restrict__ X, int rows, int K, int r0,
-                                  int k0, bool vec, unsigned short (*T)[40], int tid) {
-  if constexpr (ROWK) {
-    const int r = tid >> 2, kc = (tid & 3) * 8;
-    const int gr = r0 + r, gk = k0 + kc;
-    v8u16m v;
-    if (vec) {
-      if (gr < rows && gk < K) v = *(const v8u16m*)(X + (size_t)gr * K + gk);
-      else v = v8u16m{0, 0, 0, 0, 0, 0, 0, 0};
-    } else {
+// One TILE x BK operand tile of a GEMM step (TILE = 64 or 128, BK = 32 or
+// 64), held in registers between its global load and its LDS store
+// (TILE BK / 2048 pieces of 16 bytes per thread), stored in LDS as T[r][k]
+// (k contiguous, row stride BK + 8 halfwords so that every 8-element MFMA
+// fragment is one aligned 16-byte read).  ROWK: the operand is stored [rows][ld] with k contiguous; otherwise
+// [k][ld] with the rows contiguous (each piece is 8 rows at one k, written
+// transposed).  k beyond kend and rows beyond `rows` read as zero.  `vec`:
+// 16-byte global loads (the contiguous extent is a multiple of 8).
+template <bool ROWK, int TILE, int BK>
+struct GemmStage {
+  static constexpr int HS = TILE * BK / 2048;   // pieces per thread
+  static constexpr int RG = TILE / 8;           // 8-row groups (non-ROWK)
+  static constexpr int KP = BK / 8;             // pieces per row (ROWK)
+  v8u16m v[HS];
+  __device__ __forceinline__ void load(const unsigned short* __restrict__ X, int rows, int ld,
+                                       int kend, int r0, int k0, bool vec, int tid) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        v[u] = (gr < rows && gk + u < K) ? X[(size_t)gr * K + gk + u] : (unsigned short)0;
+    for (int h = 0; h < HS; ++h) {
+      const int pc = tid + 256 * h;
+      if constexpr (ROWK) {
+        const int gr = r0 + pc / KP, gk = k0 + (pc % KP) * 8;
+        if (vec && gr < rows && gk + 8 <= kend) {
+          v[h] = *(const v8u16m*)(X + (size_t)gr * ld + gk);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            v[h][u] = (gr < rows && gk + u < kend) ? X[(size_t)gr * ld + gk + u] : (unsigned short)0;
+        }
+      } else {
+        const int gk = k0 + pc / RG, gr = r0 + (pc % RG) * 8;
+        if (vec && gk < kend && gr + 8 <= rows) {
+          v[h] = *(const v8u16m*)(X + (size_t)gk * ld + gr);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            v[h][u] = (gk < kend && gr + u < rows) ? X[(size_t)gk * ld + gr + u] : (unsigned short)0;
+        }
+      }
     }
-    *(v8u16m*)&T[r][kc] = v;
-  } else {
-    const int kr = tid >> 3, rc = (tid & 7) * 8;
-    const int gk = k0 + kr, gr = r0 + rc;
-    v8u16m v;
-    if (vec) {
-      if (gk < K && gr < rows) v = *(const v8u16m*)(X + (size_t)gk * rows + gr);
-      else v = v8u16m{0, 0, 0, 0, 0, 0, 0, 0};
-    } else {
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        v[u] = (gk < K && gr + u < rows) ? X[(size_t)gk * rows + gr + u] : (unsigned short)0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) T[rc + u][kr] = v[u];
   }
-}
+  __device__ __forceinline__ void store(unsigned short (*T)[BK + 8], int tid) const {
+#pragma unroll
+    for (int h = 0; h < HS; ++h) {
+      const int pc = tid + 256 * h;
+      if constexpr (ROWK) {
+        *(v8u16m*)&T[pc / KP][(pc % KP) * 8] = v[h];
+      } else {
+        const int kr = pc / RG, rc = (pc % RG) * 8;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) T[rc + u][kr] = v[h][u];
+      }
+    }
+  }
+};
 
 // C[M x N] = op(A) op(B), BF16 operands, FP32 accumulation on
 // v_mfma_f32_16x16x32_bf16.  A_COL: A stored [K][M] (else [M][K]); B_COL: B
-// stored [N][K] (else [K][N]).  Workgroup of 256 threads = 64 x 64 tile, each
-// wave a 32 x 32 quarter (2 x 2 MFMA tiles); K in steps of 32 through LDS,
-// both operands staged k-contiguous so every lane reads 16-byte fragments.
-// Epilogue EPI: 0 = FP32 store, 1 = + bias, ReLU, BF16 store, 2 = times the
-// ReLU mask (mask[i][j] > 0) and BF16 store.
-template <bool A_COL, bool B_COL, int EPI>
+// stored [N][K] (else [K][N]).  Workgroup of 256 threads = TILE x TILE tile
+// (128 for large outputs, 64 when 128-tiles would leave CUs idle), each wave
+// a quarter (TILE / 32 x TILE / 32 MFMA tiles per step); K in steps of 32
+// through two LDS buffers: the next step's tiles are loaded from global
+// memory while the current one is multiplied, then stored to the other
+// buffer, one barrier per step.  Tiles are dealt so that the workgroups of
+// one XCD take consecutive tiles (n fastest): the n tiles that share an A
+// block meet in one L2.  Split K (gridDim.y > 1, EPI 0 only): workgroup y
+// multiplies the K range [y kc, (y + 1) kc) and writes its FP32 partial to
+// Cf + y M N; the partials are added in y order afterwards.  Epilogue EPI:
+// 0 = FP32 store, 1 = + bias, ReLU, BF16 store, 2 = times the ReLU mask
+// (mask[i][j] > 0) and BF16 store.
+template <bool A_COL, bool B_COL, int EPI, int TILE, int BK>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const unsigned short* __restrict__ A,
                                                    const unsigned short* __restrict__ Bm,
-                                                   int M, int N, int K,
+                                                   int M, int N, int K, int kc, int n_tn,
                                                    float* __restrict__ Cf,
                                                    unsigned short* __restrict__ Cb,
                                                    const float* __restrict__ bias,
                                                    const unsigned short* __restrict__ mask) {
-  __shared__ __attribute__((aligned(16))) unsigned short As[64][40];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[64][40];
+  constexpr int WT = TILE / 2, MI = TILE / 32;
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][TILE][BK + 8];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][TILE][BK + 8];
+  const int n_tm = (M + TILE - 1) / TILE;
+  // grid.x is a multiple of 8; hardware deals workgroups to the 8 XCDs in turn
+  const int q = (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3));
+  if (q >= n_tm * n_tn) return;   // whole workgroup
+  const int tm = q / n_tn, tn = q - (q / n_tn) * n_tn;
+  const int m0 = tm * TILE, n0 = tn * TILE;
+  const int kb = (int)blockIdx.y * kc, ke = min(K, kb + kc);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
+  const int wm = (wid >> 1) * WT, wn = (wid & 1) * WT;
   // contiguous extents: A_COL -> M, else K; B_COL -> K, else N
   const bool vec_a = ((A_COL ? M : K) & 7) == 0;
   const bool vec_b = ((B_COL ? K : N) & 7) == 0;
-  v4f32m acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f32m{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    stage_tile<!A_COL>(A, M, K, m0, k0, vec_a, As, tid);
-    stage_tile<B_COL>(Bm, N, K, n0, k0, vec_b, Bs, tid);
+  v4f32m acc[MI][MI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < MI; ++j) acc[i][j] = v4f32m{0.f, 0.f, 0.f, 0.f};
+  GemmStage<!A_COL, TILE, BK> sa;
+  GemmStage<B_COL, TILE, BK> sb;
+  sa.load(A, M, A_COL ? M : K, ke, m0, kb, vec_a, tid);
+  sb.load(Bm, N, B_COL ? K : N, ke, n0, kb, vec_b, tid);
+  sa.store(As[0], tid);
+  sb.store(Bs[0], tid);
   __syncthreads();
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) {
+      sa.load(A, M, A_COL ? M : K, ke, m0, k0 + BK, vec_a, tid);
+      sb.load(Bm, N, B_COL ? K : N, ke, n0, k0 + BK, vec_b, tid);
+    }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const v8u16m a = *(const v8u16m*)&As[wm + i * 16 + fr][fk];
+    for (int kk = 0; kk < BK; kk += 32) {   // 32-deep MFMA steps in k order
+      v8u16m fa[MI], fb[MI];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const v8u16m b = *(const v8u16m*)&Bs[wn + j * 16 + fr][fk];
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16m, a),
-                                                            __builtin_bit_cast(v8bf16m, b),
-                                                            acc[i][j], 0, 0, 0);
-      }
+      for (int i = 0; i < MI; ++i) fa[i] = *(const v8u16m*)&As[buf][wm + i * 16 + fr][kk + fk];
+#pragma unroll
+      for (int j = 0; j < MI; ++j) fb[j] = *(const v8u16m*)&Bs[buf][wn + j * 16 + fr][kk + fk];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < MI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf16m, fa[i]),
+                                                              __builtin_bit_cast(v8bf16m, fb[j]),
+                                                              acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      sa.store(As[buf ^ 1], tid);
+      sb.store(Bs[buf ^ 1], tid);
     }
     __syncthreads();
+    buf ^= 1;
   }
   // ---- epilogue: lane holds rows 4*(lane/16)+v of column lane%16
+  float* Co = Cf ? Cf + (size_t)blockIdx.y * M * N : nullptr;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < MI; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
@@ -120,12 +173,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const unsigned short* __restr
           float x = acc[i][j][v];
           const size_t o = (size_t)row * N + col;
           if constexpr (EPI == 0) {
-            Cf[o] = x;
+            Co[o] = x;
           } else if constexpr (EPI == 1) {
             x += bias[col];
             x = x > 0.f ? x : 0.f;
             Cb[o] = bf16_rne(x);
-            if (Cf) Cf[o] = x;
+            if (Co) Co[o] = x;
           } else {
             x = (mask[o] != 0) ? x : 0.f;   // bf16 activation > 0 <=> nonzero bits
             Cb[o] = bf16_rne(x);
@@ -265,7 +318,8 @@ __global__ __launch_bounds__(256) void k_chunk_sum(const float* __restrict__ par
 // First-layer weight gradient gW1b[i] = sum of dz1[b] over the samples b
 // whose bit set holds i.  The (bit, sample) pairs are bucketed by bit
 // (count, exclusive scan, fill); each bit's bucket is then put in sample
-// order in LDS and summed in that order, so the result is deterministic.
+// order in LDS and summed over fixed runs of it, the runs' partials added in
+// order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void k_zero_i32(int* __restrict__ p, int n) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
 }
@@ -328,6 +382,7 @@ __global__ __launch_bounds__(256) void k_w1b_grad(const int* __restrict__ start,
   __shared__ unsigned s_bits[kWords];
   __shared__ int s_sorted[kMlpMaxTrain];
   __shared__ int s_wtot[kWords / 64];
+  __shared__ float s_part[2048];   // G run partials of H columns (G H = 2048)
   const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int lo = start[i], L = min(start[i + 1] - lo, kMlpMaxTrain);
   // the bucket's sample ids (distinct) as a bitmap, then listed in ascending
@@ -363,9 +418,26 @@ __global__ __launch_bounds__(256) void k_w1b_grad(const int* __restrict__ start,
     }
   }
   __syncthreads();
+  // column sums: each thread takes 8 adjacent columns (one 16-byte load per
+  // sample) over one of G contiguous runs of the sorted bucket; the G run
+  // partials are then added in run order
+  const int nb = H / 8, G = 256 / nb;   // H is a multiple of 64 and at most 2048
+  if (tid < nb * G) {
+    const int cb = tid % nb, gr = tid / nb;
+    const int q0 = (int)(((long)gr * L) / G), q1 = (int)(((long)(gr + 1) * L) / G);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int q = q0; q < q1; ++q) {
+      const v8u16m v = *(const v8u16m*)(dz1 + (size_t)s_sorted[q] * H + cb * 8);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += bf16_to_f(v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s_part[gr * H + cb * 8 + u] = acc[u];
+  }
+  __syncthreads();
   for (int j = tid; j < H; j += 256) {
     float acc = 0.f;
-    for (int q = 0; q < L; ++q) acc += bf16_to_f(dz1[(size_t)s_sorted[q] * H + j]);
+    for (int gr = 0; gr < G; ++gr) acc += s_part[gr * H + j];
     g[(size_t)i * H + j] = acc;
   }
 }
@@ -374,6 +446,23 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ x, si
                                                  unsigned short* __restrict__ y) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) y[i] = bf16_rne(x[i]);
+}
+
+// y[c][r] = bf16(x[r][c]) for x [R][C]: 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void k_to_bf16_t(const float* __restrict__ x, int R, int C,
+                                                   unsigned short* __restrict__ y) {
+  __shared__ float t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int i = ty; i < 32; i += 8) {
+    const int r = r0 + i, c = c0 + tx;
+    t[i][tx] = (r < R && c < C) ? x[(size_t)r * C + c] : 0.f;
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int c = c0 + i, r = r0 + tx;
+    if (c < C && r < R) y[(size_t)c * R + r] = bf16_rne(t[tx][i]);
+  }
 }
 
 // Adam (bias-corrected moments) on FP32 master weights; refreshes the BF16 copy.
@@ -575,11 +664,54 @@ void batch_gather(const int* open, const int* sbus, const int* moff, const int* 
 
 static inline int cdiv_m(long a, int b) { return (int)((a + b - 1) / b); }
 
+// Tile edge of a GEMM: 128 when that still gives at least 512 workgroups
+// (K step 32: 40 KB of LDS, three workgroups per CU), else 64 (K step 64).
+static int gemm_tile(int M, int N) {
+  return cdiv_m(M, 128) * cdiv_m(N, 128) >= 512 ? 128 : 64;
+}
+
+// K splits of a GEMM with FP32 output: enough workgroups to fill the chip
+// (about 1024 with the tiles), each split at least 256 deep, at most 16.
+int gemm_splits(int M, int N, int K) {
+  const int t = gemm_tile(M, N);
+  const int tiles = cdiv_m(M, t) * cdiv_m(N, t);
+  const int s = std::max(1, cdiv_m(1024, tiles));
+  return std::min(s, std::max(1, std::min(16, cdiv_m(K, 256))));
+}
+
+size_t mlp_split_floats(int H, int dd, int Bt) {
+  const size_t a = (size_t)gemm_splits(H, H, Bt) * H * H;
+  const size_t b = dd > 0 ? (size_t)gemm_splits(dd, H, Bt) * dd * H : 0;
+  return std::max(std::max(a, b), (size_t)1);
+}
+
+// part: room for the split partials (gemm_splits(M, N, K) x M x N floats) or
+// NULL for a single pass; splitting applies to the FP32 epilogue only.
 template <bool AC, bool BC, int EPI>
 static void gemm(const unsigned short* A, const unsigned short* B, int M, int N, int K, float* Cf,
-                 unsigned short* Cb, const float* bias, const unsigned short* mask, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_bf16<AC, BC, EPI>), dim3(cdiv_m(N, 64), cdiv_m(M, 64)), dim3(256), 0,
-                     s, A, B, M, N, K, Cf, Cb, bias, mask);
+                 unsigned short* Cb, const float* bias, const unsigned short* mask, float* part,
+                 hipStream_t s) {
+  const int t = gemm_tile(M, N);
+  const int n_tn = cdiv_m(N, t), tiles = cdiv_m(M, t) * n_tn;
+  int kc = K, S = 1;
+  if (EPI == 0 && part) {
+    const int want = gemm_splits(M, N, K);
+    if (want > 1) {
+      kc = cdiv_m(cdiv_m(K, want), 64) * 64;   // whole steps per split
+      S = cdiv_m(K, kc);
+    }
+  }
+  const dim3 grid((unsigned)(cdiv_m(tiles, 8) * 8), (unsigned)S);
+  float* co = S > 1 ? part : Cf;
+  if (t == 128)
+    hipLaunchKernelGGL((k_gemm_bf16<AC, BC, EPI, 128, 32>), grid, dim3(256), 0, s, A, B, M, N, K,
+                       kc, n_tn, co, Cb, bias, mask);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16<AC, BC, EPI, 64, 64>), grid, dim3(256), 0, s, A, B, M, N, K,
+                       kc, n_tn, co, Cb, bias, mask);
+  if (S > 1)
+    hipLaunchKernelGGL(k_chunk_sum, dim3(cdiv_m((long)M * N, 256)), dim3(256), 0, s, part, S,
+                       M * N, Cf);
 }
 
 template <typename T>
@@ -596,13 +728,13 @@ void mlp_forward(const MlpDev& p, const MlpBatch& wb, const int* off, const int*
   if (dd > 0) {
     hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)B * dd, 256)), dim3(256), 0, s, dense,
                        (size_t)B * dd, wb.Xd);
-    gemm<false, false, 0>(wb.Xd, p.W1d_h, B, H, dd, wb.zd, nullptr, nullptr, nullptr, s);
+    gemm<false, true, 0>(wb.Xd, p.W1dt_h, B, H, dd, wb.zd, nullptr, nullptr, nullptr, nullptr, s);
   }
   hipLaunchKernelGGL(k_mlp_l1, dim3(B), dim3(256), 0, s, off, idx,
                      dd > 0 ? (const float*)wb.zd : (const float*)nullptr, p.d_bits, p.W1b_h,
                      p.b1, H, wb.h1);
-  gemm<false, false, 1>(wb.h1, p.W2_h, B, H, H, nullptr, wb.h2, p.b2, nullptr, s);
-  gemm<false, false, 1>(wb.h2, p.W3_h, B, H, H, nullptr, wb.h3, p.b3, nullptr, s);
+  gemm<false, true, 1>(wb.h1, p.W2t_h, B, H, H, nullptr, wb.h2, p.b2, nullptr, nullptr, s);
+  gemm<false, true, 1>(wb.h2, p.W3t_h, B, H, H, nullptr, wb.h3, p.b3, nullptr, nullptr, s);
   hipLaunchKernelGGL(k_mlp_out, dim3(B), dim3(64), 0, s, wb.h3, p.W4, p.b4, H, y);
 }
 
@@ -625,13 +757,13 @@ void mlp_gradients(const MlpDev& p, const MlpBatch& wb, const int* off, const in
   hipLaunchKernelGGL(k_mlp_out_bwd_x, dim3(cdiv_m((long)B * H, 256)), dim3(256), 0, s, wb.h3,
                      wb.dy, p.W4, B, H, wb.dz3);
   // layer 3: gW3 = h2^T dz3, gb3 = colsum dz3, dz2 = (dz3 W3^T) * [h2 > 0]
-  gemm<true, false, 0>(wb.h2, wb.dz3, H, H, B, g.W3, nullptr, nullptr, nullptr, s);
+  gemm<true, false, 0>(wb.h2, wb.dz3, H, H, B, g.W3, nullptr, nullptr, nullptr, wb.gpart, s);
   colsum<unsigned short>(wb.dz3, B, H, wb.part, g.b3, s);
-  gemm<false, true, 2>(wb.dz3, p.W3_h, B, H, H, nullptr, wb.dz2, nullptr, wb.h2, s);
+  gemm<false, true, 2>(wb.dz3, p.W3_h, B, H, H, nullptr, wb.dz2, nullptr, wb.h2, nullptr, s);
   // layer 2
-  gemm<true, false, 0>(wb.h1, wb.dz2, H, H, B, g.W2, nullptr, nullptr, nullptr, s);
+  gemm<true, false, 0>(wb.h1, wb.dz2, H, H, B, g.W2, nullptr, nullptr, nullptr, wb.gpart, s);
   colsum<unsigned short>(wb.dz2, B, H, wb.part, g.b2, s);
-  gemm<false, true, 2>(wb.dz2, p.W2_h, B, H, H, nullptr, wb.dz1, nullptr, wb.h1, s);
+  gemm<false, true, 2>(wb.dz2, p.W2_h, B, H, H, nullptr, wb.dz1, nullptr, wb.h1, nullptr, s);
   // layer 1: gW1b = X^T dz1 over the 0/1 bitmask, gW1d = dense^T dz1
   colsum<unsigned short>(wb.dz1, B, H, wb.part, g.b1, s);
   const int nb = std::min(cdiv_m(B, 256), 1024);
@@ -643,7 +775,7 @@ void mlp_gradients(const MlpDev& p, const MlpBatch& wb, const int* off, const in
                      wb.cursor, wb.list);
   hipLaunchKernelGGL(k_w1b_grad, dim3(db), dim3(256), 0, s, wb.start, wb.list, wb.dz1, H, g.W1b);
   if (dd > 0)   // wb.Xd holds the BF16 dense inputs from the forward pass
-    gemm<true, false, 0>(wb.Xd, wb.dz1, dd, H, B, g.W1d, nullptr, nullptr, nullptr, s);
+    gemm<true, false, 0>(wb.Xd, wb.dz1, dd, H, B, g.W1d, nullptr, nullptr, nullptr, wb.gpart, s);
 }
 
 void mlp_adam(const MlpDev& p, const float* grad, float lr, int step, hipStream_t s) {
@@ -656,17 +788,21 @@ void mlp_adam(const MlpDev& p, const float* grad, float lr, int step, hipStream_
 }
 
 void mlp_refresh_bf16(const MlpDev& p, hipStream_t s) {
-  const size_t H = p.H;
+  const int H = p.H;
   MlpGrad w = mlp_grad_view(p, p.master);
-  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(p.d_bits * H), 256)), dim3(256), 0, s, w.W1b,
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)p.d_bits * H, 256)), dim3(256), 0, s, w.W1b,
                      (size_t)p.d_bits * H, p.W1b_h);
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)H * H, 256)), dim3(256), 0, s, w.W2,
+                     (size_t)H * H, p.W2_h);
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)H * H, 256)), dim3(256), 0, s, w.W3,
+                     (size_t)H * H, p.W3_h);
   if (p.d_dense > 0)
-    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(p.d_dense * H), 256)), dim3(256), 0, s,
-                       w.W1d, (size_t)p.d_dense * H, p.W1d_h);
-  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(H * H), 256)), dim3(256), 0, s, w.W2, H * H,
-                     p.W2_h);
-  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_m((long)(H * H), 256)), dim3(256), 0, s, w.W3, H * H,
-                     p.W3_h);
+    hipLaunchKernelGGL(k_to_bf16_t, dim3(cdiv_m(H, 32), cdiv_m(p.d_dense, 32)), dim3(256), 0, s,
+                       w.W1d, p.d_dense, H, p.W1dt_h);
+  hipLaunchKernelGGL(k_to_bf16_t, dim3(cdiv_m(H, 32), cdiv_m(H, 32)), dim3(256), 0, s, w.W2, H, H,
+                     p.W2t_h);
+  hipLaunchKernelGGL(k_to_bf16_t, dim3(cdiv_m(H, 32), cdiv_m(H, 32)), dim3(256), 0, s, w.W3, H, H,
+                     p.W3t_h);
 }
 
 void topk_smallest(const float* score, int n, int stride, int k, int* out, hipStream_t s) {

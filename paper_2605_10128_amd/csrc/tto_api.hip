@@ -747,9 +747,11 @@ MlpDev carve_mlp_params(const tto_mlp_desc* d, void* ws, size_t* bytes) {
   p.grad = cv.take<float>(p.n_params);
   const size_t H = d->width;
   p.W1b_h = cv.take<unsigned short>((size_t)d->d_bits * H);
-  p.W1d_h = cv.take<unsigned short>(std::max((size_t)d->d_dense * H, (size_t)1));
   p.W2_h = cv.take<unsigned short>(H * H);
   p.W3_h = cv.take<unsigned short>(H * H);
+  p.W1dt_h = cv.take<unsigned short>(std::max((size_t)d->d_dense * H, (size_t)1));
+  p.W2t_h = cv.take<unsigned short>(H * H);
+  p.W3t_h = cv.take<unsigned short>(H * H);
   if (p.master) {
     MlpGrad w = mlp_grad_view(p, p.master);
     p.b1 = w.b1; p.b2 = w.b2; p.b3 = w.b3; p.W4 = w.W4; p.b4 = w.b4;
@@ -781,6 +783,7 @@ MlpBatch carve_mlp_batch(const tto_mlp_desc* d, void* ws, size_t* bytes) {
   b.dy = cv.take<float>(Bt * 2);
   b.lterm = cv.take<float>(Bt);
   b.part = cv.take<float>(((Bt + 63) / 64) * 2 * H);
+  b.gpart = cv.take<float>(mlp_split_floats((int)H, d->d_dense, (int)Bt));
   *bytes = cv.off;
   return b;
 }

@@ -18,10 +18,14 @@ struct MlpDev {
   float* m;
   float* v;
   float* grad;
+  // BF16 copies: W1b, W2 and W3 as stored, and W1d, W2, W3 transposed ([out][in],
+  // the forward GEMMs' operand with k contiguous)
   unsigned short* W1b_h;
-  unsigned short* W1d_h;
   unsigned short* W2_h;
   unsigned short* W3_h;
+  unsigned short* W1dt_h;
+  unsigned short* W2t_h;
+  unsigned short* W3t_h;
   // FP32 views into master used directly by kernels
   const float* b1;
   const float* b2;
@@ -69,7 +73,12 @@ struct MlpBatch {
   float* dy;                         // [B][2]
   float* lterm;                      // [B]
   float* part;                       // [ceil(B / 64)][2 H] chunk partial sums
+  float* gpart;                      // split-K partials of the weight-gradient GEMMs
 };
+
+// Floats of MlpBatch::gpart: the most any split weight-gradient GEMM needs for
+// width H, dense width dd and training batch Bt.
+size_t mlp_split_floats(int H, int dd, int Bt);
 
 void mlp_forward(const MlpDev& p, const MlpBatch& wb, const int* off, const int* idx,
                  const float* dense, int B, float* y, hipStream_t s);
