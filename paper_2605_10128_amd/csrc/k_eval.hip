@@ -547,8 +547,9 @@ __device__ __forceinline__ void setup_rows(const RowsArgs<F>& a, double* __restr
       n0 += fabs(fp) > lim;
       fM[t * sM + ei] = (F)fp;
     }
+    // only the R slots in use: every reader of U stops at the candidate's rank
 #pragma unroll
-    for (int q = 0; q < kVSlots; ++q) UM[q * sM + ei] = q < R ? (F)U[q < R ? q : 0] : (F)0;
+    for (int q = 0; q < R; ++q) UM[q * sM + ei] = (F)U[q];
     if (opened) {   // rare: one of the candidate's openings
 #pragma unroll
       for (int t = 0; t < TT; ++t) fM[t * sM + ei] = (F)0;

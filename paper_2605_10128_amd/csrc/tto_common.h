@@ -157,7 +157,7 @@ template <typename F>
 struct SweepBufs {
   CandInfo* info;   // [B]
   F* fM;            // [B][nM][TT]
-  F* UM;            // [B][nM][8]
+  F* UM;            // [B][8][nM] rank-r factor rows (slots past r not written)
   F* rec;           // [B][nC+1][rec_stride(TT)]
   int* act;         // [B][nC+1] contingency index of each record
   int* slot;        // [B][nC] record of each contingency or -1 (optional)
