@@ -489,7 +489,7 @@ template <typename F, int TT, int R>
 __device__ __forceinline__ void setup_rows(const RowsArgs<F>& a, double* __restrict__ base_out,
                                            int c, int cb, CSetupDesc* D, RowsShared<F>& sm) {
   const SetupDesc& L = sm.d;
-  constexpr int RS = rec_stride(TT);
+  constexpr int RS = rec_stride_r(TT, R);   // this candidate's record stride
   constexpr int SP = RowsShared<F>::SP;
   const int tid = threadIdx.x;
   const int m = a.m, T = a.T, nM = a.nM, nC = a.nC;
@@ -583,7 +583,7 @@ __device__ __forceinline__ void setup_rows(const RowsArgs<F>& a, double* __restr
 
   // contingencies: V_l, denominators, phi_l, ordered compaction
   const int lane = tid & 63, wid = tid >> 6;
-  F* rec = a.rec + (size_t)c * (nC + 1) * RS;
+  F* rec = a.rec + (size_t)c * (nC + 1) * rec_stride(TT);
   int* act = a.act + (size_t)c * (nC + 1);
   int nisl = 0;
   int run = 0;   // records written by the chunks before (same in every lane)
@@ -685,10 +685,12 @@ __device__ __forceinline__ void setup_rows(const RowsArgs<F>& a, double* __restr
         }
       }
       wave_lds_sync();
+      // slots p0 .. p0 + nsl of the wave's na records, every lane busy (one
+      // contiguous run when a record fits in one pass)
       const int nsl = (RS - p0) < SP ? (RS - p0) : SP;
-      for (int idx = lane; idx < na * SP; idx += 64) {
-        const int i = idx / SP, u = idx - (idx / SP) * SP;
-        if (u < nsl) rec[(size_t)(o0 + i) * RS + p0 + u] = slab[i][u];
+      for (int idx = lane; idx < na * nsl; idx += 64) {
+        const int i = idx / nsl, u = idx - (idx / nsl) * nsl;
+        rec[(size_t)(o0 + i) * RS + p0 + u] = slab[i][u];
       }
       wave_lds_sync();
     }
@@ -809,7 +811,7 @@ template <typename F, int TT, int R, int NP>
 __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>& w,
                                            const F* __restrict__ HMC, int c, const int* ei,
                                            int i0, int i1, F (*acc)[TT]) {
-  constexpr int RS = rec_stride(TT);
+  constexpr int RS = rec_stride_r(TT, R);
   const int nM = g.nM, nC = g.nC;
   F U[NP][R > 0 ? R : 1], a[NP][TT];
 #pragma unroll
@@ -821,7 +823,7 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
 #pragma unroll
     for (int j = 0; j < R; ++j) U[p][j] = ua[(size_t)j * nM];
   }
-  const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
+  const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * rec_stride(TT);
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
   if (i1 <= i0) return;
   // Software pipeline: the H entries of the next pair are in flight while the
@@ -1038,7 +1040,7 @@ template <typename F, int TT, int R>
 __device__ __forceinline__ double fin_flows(const F* __restrict__ HMC, const F* rec,
                                             const int* act, const F* ua, int nM, int be, int bt,
                                             F a, int n_act, F* vbuf) {
-  constexpr int RS = rec_stride(TT);
+  constexpr int RS = rec_stride_r(TT, R);
   const int lane = threadIdx.x;
   F u[R > 0 ? R : 1];
 #pragma unroll
@@ -1153,8 +1155,9 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     const F* ua = w.UM + (size_t)c * kVSlots * nM + be;
     const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
     const int* act = w.act + (size_t)c * (nC + 1);
+    const int rs = rec_stride_r(TT, inf.r);
     auto flow = [&](int i) -> double {
-      const F* ri = rec + (size_t)i * RS;
+      const F* ri = rec + (size_t)i * rs;
       F h = HMC[(size_t)act[i] * nM + be];
       for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
       return (double)fabs_t(fma_t(h, ri[bt], a));
@@ -1256,7 +1259,7 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
       for (int t = 0; t < T; ++t) out[t] = 0.0;
       continue;
     }
-    const F* ri = rec + (size_t)slot * RS;
+    const F* ri = rec + (size_t)slot * rec_stride_r(TT, inf.r);
     F h = HMC[(size_t)li * nM + ei];
     for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
     for (int t = 0; t < T; ++t) out[t] = (double)fma_t(h, ri[t], fa[(size_t)t * nM]);
@@ -1518,7 +1521,7 @@ __global__ __launch_bounds__(256) void k_cont_energy(GridDev g, SweepBufs<F> w,
   for (int i0 = 0; i0 < n_act; i0 += 64) {
     const int cnt = min(64, n_act - i0);
     for (int q = 0; q < cnt; ++q) {
-      const F* ri = rec + (size_t)(i0 + q) * RS;
+      const F* ri = rec + (size_t)(i0 + q) * rec_stride_r(TT, r);
       F h = HMC[(size_t)act[i0 + q] * nM + ei_c];
 #pragma unroll
       for (int j = 0; j < kVSlots; ++j)

@@ -23,9 +23,13 @@ constexpr int kSubMax = 32;         // gather sources whose mutual S entries the
 constexpr int kMaxSrc = kMaxRank + kMaxMoved;   // gather sources of a candidate
 static_assert(kMaxSrc % 8 == 0, "sources are read in groups of 8");
 
-// Record of one active contingency in a candidate's sweep list:
-// phi(t) for t < TT, then V_j for j < 8, padded to a multiple of 4 entries.
-__host__ __device__ constexpr int rec_stride(int TT) { return ((TT + kVSlots + 3) / 4) * 4; }
+// Record of one active contingency in a candidate's sweep list: phi(t) for
+// t < TT, then V_j for j < r, padded to a multiple of 4 entries.  A
+// candidate of rank r packs its records at rec_stride_r(TT, r) within its
+// region of the record table, whose size per candidate is set by the largest
+// stride, rec_stride(TT) (r = 8).
+__host__ __device__ constexpr int rec_stride_r(int TT, int r) { return ((TT + r + 3) / 4) * 4; }
+__host__ __device__ constexpr int rec_stride(int TT) { return rec_stride_r(TT, kVSlots); }
 
 // Timestep tile used by the templated kernels: smallest supported >= T.
 inline int tile_T(int T) {
@@ -158,7 +162,7 @@ struct SweepBufs {
   CandInfo* info;   // [B]
   F* fM;            // [B][nM][TT]
   F* UM;            // [B][8][nM] rank-r factor rows (slots past r not written)
-  F* rec;           // [B][nC+1][rec_stride(TT)]
+  F* rec;           // [B][(nC+1) rec_stride(TT)]: records at rec_stride_r(TT, r)
   int* act;         // [B][nC+1] contingency index of each record
   int* slot;        // [B][nC] record of each contingency or -1 (optional)
   Partial* part;    // [B][n_eblk] one per chunk of 64 monitored branches
