@@ -805,6 +805,21 @@ __device__ inline double fma_t(double a, double b, double c) { return __builtin_
 __device__ inline float max3_t(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
 __device__ inline double max3_t(double a, double b, double c) { return fmax(a, fmax(b, c)); }
 
+// Lane entry of one H[M, C] column through a raw buffer load: the resource is
+// based at the column (wave-uniform, built in scalar registers) and the lane's
+// byte offset is fixed for the whole contingency loop, so no per-load vector
+// address arithmetic is issued.  The column holds nM entries and every offset
+// is below that (ei is clamped into the monitored set).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const void* col, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(col), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ float col_ld(__amdgpu_buffer_rsrc_t rs, int off, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+__device__ __forceinline__ double col_ld(__amdgpu_buffer_rsrc_t rs, int off, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+
 // Contingency pairs [i0, i1) of candidate c for the lanes' monitored
 // positions ei[p] (p < NP, clamped into range): acc[p][t] = max |f^(l)|.
 template <typename F, int TT, int R, int NP>
@@ -826,24 +841,27 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * rec_stride(TT);
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
   if (i1 <= i0) return;
-  // Software pipeline: the H entries of the next pair are in flight while the
-  // current pair is consumed (the last prefetch re-reads an in-range pair).
-  F hn0[NP], hn1[NP];
-  {
-    const size_t c0 = (size_t)act[i0] * nM, c1 = (size_t)act[i0 + 1] * nM;
+  // The H entries of a pair are loaded once the previous pair has been
+  // consumed, into the same registers (no copies); the latency is covered by
+  // the other waves of the SIMD.  The resource of each column is based at the
+  // column and the lane's byte offset is fixed, so the loads issue no vector
+  // address arithmetic.
+  const int col_bytes = nM * (int)sizeof(F);
+  int eoff[NP];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) { hn0[p] = HMC[c0 + ei[p]]; hn1[p] = HMC[c1 + ei[p]]; }
-  }
-  for (int i = i0; i < i1; i += 2) {
-    F h0[NP], h1[NP];
+  for (int p = 0; p < NP; ++p) eoff[p] = ei[p] * (int)sizeof(F);
+  F h0[NP], h1[NP];
+  auto load_pair = [&](int i) {
+    const auto q0 = col_rsrc(HMC + (size_t)act[i] * nM, col_bytes);
+    const auto q1 = col_rsrc(HMC + (size_t)act[i + 1] * nM, col_bytes);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) { h0[p] = hn0[p]; h1[p] = hn1[p]; }
-    const int nx = (i + 2 < i1) ? i + 2 : i;
-    {
-      const size_t c0 = (size_t)act[nx] * nM, c1 = (size_t)act[nx + 1] * nM;
-#pragma unroll
-      for (int p = 0; p < NP; ++p) { hn0[p] = HMC[c0 + ei[p]]; hn1[p] = HMC[c1 + ei[p]]; }
+    for (int p = 0; p < NP; ++p) {
+      h0[p] = col_ld(q0, eoff[p], (F*)nullptr);
+      h1[p] = col_ld(q1, eoff[p], (F*)nullptr);
     }
+  };
+  load_pair(i0);
+  for (int i = i0; i < i1; i += 2) {
     const F* r0 = rec + (size_t)i * RS;
     const F* r1 = r0 + RS;
 #pragma unroll
@@ -863,6 +881,7 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
         acc[p][t] = max3_t(acc[p][t], fabs_t(g0), fabs_t(g1));
       }
     }
+    load_pair((i + 2 < i1) ? i + 2 : i);   // the last one re-reads an in-range pair
   }
 }
 
