@@ -5,10 +5,13 @@
 //              the candidate's openings and bus splits (DC-Optimizer: topology
 //              changes enter as low-rank updates of the PTDF): the bordered
 //              system, its LU factors and the islanding pivot test (one wave
-//              per candidate), then post-switch flows f', per-contingency LODF
+//              per candidate), then the U rows of the monitored branches,
+//              per-contingency records (phi_l(t), V_l) with the LODF
 //              denominators 1 - H'_ll and the compacted list of non-islanding
 //              contingencies (one workgroup per candidate, rank fixed at
-//              compile time).
+//              compile time).  The monitored post-switch flows f'_M are not
+//              stored: every reader forms them from the shared base-flow table,
+//              the U row and x(t) (post_flow).
 //   k_sweep    N-1 flows f^(l)_e(t) = f'_e(t) + H'_el f'_l(t) / (1 - H'_ll) for
 //              every monitored e, active contingency l and timestep t, with the
 //              running max |f| fused in (f^max of the Fitness function
@@ -348,6 +351,7 @@ __global__ __launch_bounds__(64) void k_setup_cand(GridDev g, BatchDev bt, Sweep
 #pragma unroll
     for (int q = 0; q < kMaxRank; ++q) {
       D->x[t][q] = (t < T) ? x[q] : 0.0;
+      D->x32[t][q] = (t < T) ? (float)x[q] : 0.0f;
       bad |= (t < T) && !isfinite(x[q]);
     }
     if (bad) atomicAdd(&s_bad, 1);
@@ -407,6 +411,35 @@ __global__ __launch_bounds__(64) void k_setup_cand(GridDev g, BatchDev bt, Sweep
 // uniform values in scalar registers runs out of them).
 typedef const __attribute__((address_space(4))) SetupDesc CSetupDesc;
 
+// Post-switch flow of a monitored branch, f'_e(t) = f0_e(t) + sum_q U_eq x_q(t),
+// formed in the flow type from the stored U row: FP64 flows from the FP64
+// base-flow table and x(t); FP32 flows from their FP32 copies (f0 and x each
+// rounded once), so that the loads land in the flow registers directly.  Every
+// reader takes the steps in increasing q from the table entry, so f'_e(t) is
+// bitwise the same wherever it is formed.  Both tables have zero rows past T,
+// as has x(t).
+template <typename F>
+__device__ __forceinline__ F post_base(const GridDev& g, int ei, int t) {
+  if constexpr (sizeof(F) == 4) return g.f0M32[(size_t)t * g.nM + ei];
+  else return g.f0MC[(size_t)t * ((size_t)g.nM + g.nC) + ei];
+}
+template <typename F, typename D_>
+__device__ __forceinline__ F post_x(const D_* D, int t, int j) {
+  if constexpr (sizeof(F) == 4) return D->x32[t][j];
+  else return D->x[t][j];
+}
+__device__ __forceinline__ float post_step(float u, float x, float fp) { return __builtin_fmaf(u, x, fp); }
+__device__ __forceinline__ double post_step(double u, double x, double fp) { return __builtin_fma(u, x, fp); }
+
+// f'_e(t) of monitored position ei with run-time rank r (U row at ua, stride nM).
+template <typename F>
+__device__ __forceinline__ F post_flow(const GridDev& g, const SetupDesc* D, const F* ua, int r,
+                                       int ei, int t) {
+  F fp = post_base<F>(g, ei, t);
+  for (int j = 0; j < r; ++j) fp = post_step(ua[(size_t)j * g.nM], post_x<F>(D, t, j), fp);
+  return fp;
+}
+
 // A uniform stride passed through an opaque register copy: the per-timestep
 // offsets of a row are formed inside the iteration rather than kept in
 // scalar registers for the whole loop.
@@ -429,7 +462,6 @@ struct RowsArgs {
   const double* S;     // full S and f0 and b: the optional base-flow output only
   const double* f0;
   const double* b;
-  F* fM;
   F* UM;
   F* rec;
   int* act;
@@ -513,12 +545,12 @@ __device__ __forceinline__ void setup_rows(const RowsArgs<F>& a, double* __restr
     }
   };
 
-  // monitored rows: f'_M and U_M.  A non-finite grid injection makes every
-  // base flow of its timestep non-finite (the product with a zero PTDF entry
-  // included), so the first monitored row sees it.
+  // monitored rows: U_M and the N-0 overload count (f'_M itself is formed
+  // by its readers).  A non-finite grid injection makes every base flow of
+  // its timestep non-finite (the product with a zero PTDF entry included), so
+  // the first monitored row sees it.
   int n0 = 0, nbad = 0;
-  F* const fM = a.fM + (size_t)c * TT * nM;       // [t][ei]: coalesced across lanes
-  F* const UM = a.UM + (size_t)c * kVSlots * nM;  // [q][ei]
+  F* const UM = a.UM + (size_t)c * kVSlots * nM;  // [q][ei]: coalesced across lanes
   for (int ei = tid; ei < nM; ei += 256) {
     keep_in_loop();
     const int sM = at_use(nM), sMC = at_use((int)nMC);
@@ -545,17 +577,12 @@ __device__ __forceinline__ void setup_rows(const RowsArgs<F>& a, double* __restr
       for (int q = 0; q < R; ++q) fp += U[q] * L.x[t][q];
       // past T: x(t) = 0 and f0 = 0, so fp = 0
       n0 += fabs(fp) > lim;
-      fM[t * sM + ei] = (F)fp;
     }
-    // only the R slots in use: every reader of U stops at the candidate's rank
+    // only the R slots in use: every reader of U stops at the candidate's rank;
+    // an opened row (rare: one of the candidate's openings) is zero, and every
+    // reader gives it zero flow by its own test
 #pragma unroll
-    for (int q = 0; q < R; ++q) UM[q * sM + ei] = (F)U[q];
-    if (opened) {   // rare: one of the candidate's openings
-#pragma unroll
-      for (int t = 0; t < TT; ++t) fM[t * sM + ei] = (F)0;
-#pragma unroll
-      for (int q = 0; q < R; ++q) UM[q * sM + ei] = (F)0;
-    }
+    for (int q = 0; q < R; ++q) UM[q * sM + ei] = opened ? (F)0 : (F)U[q];
   }
   if (n0) atomicAdd(&sm.n0, n0);
   if (nbad) atomicAdd(&sm.bad, nbad);
@@ -782,7 +809,7 @@ static void launch_setup_tt(const GridDev& g, const BatchDev& bt, const SweepBuf
   RowsArgs<F> a;
   a.mon = g.mon; a.cont = g.cont; a.f0MC = g.f0MC; a.bMC = g.bMC; a.limM = g.limM;
   a.sllC = g.sllC; a.SMC = g.SMC; a.S = g.S; a.f0 = g.f0; a.b = g.b;
-  a.fM = w.fM; a.UM = w.UM; a.rec = w.rec; a.act = w.act; a.slot = w.slot; a.info = w.info;
+  a.UM = w.UM; a.rec = w.rec; a.act = w.act; a.slot = w.slot; a.info = w.info;
   a.desc = w.desc;
   a.m = g.n_branch; a.T = g.T; a.nM = g.nM; a.nC = g.nC;
   hipLaunchKernelGGL((k_setup_rows<F, TT>), dim3(bt.B), dim3(256), 0, s, a, bt.map, bt.live, bt.B,
@@ -829,14 +856,23 @@ __device__ __forceinline__ void sweep_core(const GridDev& g, const SweepBufs<F>&
   constexpr int RS = rec_stride_r(TT, R);
   const int nM = g.nM, nC = g.nC;
   F U[NP][R > 0 ? R : 1], a[NP][TT];
+  CSetupDesc* D = (CSetupDesc*)(w.desc + c);   // x(t): wave-uniform
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    const F* fa = w.fM + (size_t)c * TT * nM + ei[p];
     const F* ua = w.UM + (size_t)c * kVSlots * nM + ei[p];
 #pragma unroll
-    for (int t = 0; t < TT; ++t) { a[p][t] = fa[(size_t)t * nM]; acc[p][t] = (F)0; }
-#pragma unroll
     for (int j = 0; j < R; ++j) U[p][j] = ua[(size_t)j * nM];
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      F fp = post_base<F>(g, ei[p], t);   // f'_e(t), as post_flow forms it
+#pragma unroll
+      for (int j = 0; j < R; ++j) fp = post_step(U[p][j], post_x<F>(D, t, j), fp);
+      a[p][t] = fp;
+      acc[p][t] = (F)0;
+    }
   }
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * rec_stride(TT);
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
@@ -1170,8 +1206,8 @@ __global__ __launch_bounds__(64) void k_finalize(GridDev g, SweepBufs<F> w,
     // every state gives zero flow on an opened branch: first active contingency
     if (inf.n_act > 0 && lane == 0) { bv = 0.0; bi = 0; }
   } else if (be >= 0) {
-    const F a = w.fM[((size_t)c * TT + bt) * nM + be];
     const F* ua = w.UM + (size_t)c * kVSlots * nM + be;
+    const F a = post_flow(g, w.desc + c, ua, inf.r, be, bt);
     const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
     const int* act = w.act + (size_t)c * (nC + 1);
     const int rs = rec_stride_r(TT, inf.r);
@@ -1264,9 +1300,11 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
   const int e = g.mon[ei];
   bool opened = false;
   for (int q = 0; q < inf.k; ++q) opened |= (inf.open_br[q] == e);
-  const F* fa = w.fM + (size_t)c * TT * nM + ei;
   const F* ua = w.UM + (size_t)c * kVSlots * nM + ei;
   const F* rec = w.rec + (size_t)c * (nC + 1) * RS;
+  F fa[TT];
+#pragma unroll
+  for (int t = 0; t < TT; ++t) fa[t] = bad ? (F)0 : post_flow(g, w.desc + c, ua, inf.r, ei, t);
   for (int li = 0; li < nC; ++li) {
     double* out = n1 + (((size_t)c * nC + li) * nM + ei) * T;
     const int slot = bad ? -1 : w.slot[(size_t)c * nC + li];
@@ -1281,7 +1319,9 @@ __global__ __launch_bounds__(256) void k_n1_dump(GridDev g, SweepBufs<F> w,
     const F* ri = rec + (size_t)slot * rec_stride_r(TT, inf.r);
     F h = HMC[(size_t)li * nM + ei];
     for (int j = 0; j < inf.r; ++j) h = fma_t(ua[(size_t)j * nM], ri[TT + j], h);
-    for (int t = 0; t < T; ++t) out[t] = (double)fma_t(h, ri[t], fa[(size_t)t * nM]);
+#pragma unroll
+    for (int t = 0; t < TT; ++t)
+      if (t < T) out[t] = (double)fma_t(h, ri[t], fa[t]);
   }
 }
 
@@ -1527,12 +1567,11 @@ __global__ __launch_bounds__(256) void k_cont_energy(GridDev g, SweepBufs<F> w,
   const bool live = valid && !opened;
   const F lim = (F)g.lim[e];
   F a[TT], U[kVSlots];
-  const F* fa = w.fM + (size_t)c * TT * nM + ei_c;
   const F* ua = w.UM + (size_t)c * kVSlots * nM + ei_c;
 #pragma unroll
-  for (int t = 0; t < TT; ++t) a[t] = fa[(size_t)t * nM];
-#pragma unroll
   for (int j = 0; j < kVSlots; ++j) U[j] = j < r ? ua[(size_t)j * nM] : (F)0;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) a[t] = post_flow(g, w.desc + c, ua, r, ei_c, t);
   const F* __restrict__ rec = w.rec + (size_t)c * (nC + 1) * RS;
   const int* __restrict__ act = w.act + (size_t)c * (nC + 1);
   double* out = part + ((size_t)c * n_eblk + eb) * (nC + 1);

@@ -87,12 +87,15 @@ __global__ __launch_bounds__(256) void k_build_rows(const double* __restrict__ S
 __global__ __launch_bounds__(256) void k_f0_rows(const double* __restrict__ f0,
                                                  const int* __restrict__ mon,
                                                  const int* __restrict__ cont, int T, int nM,
-                                                 int nC, double* __restrict__ f0MC) {
+                                                 int nC, double* __restrict__ f0MC,
+                                                 float* __restrict__ f0M32) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   const int t = blockIdx.y;
   if (j >= nM + nC) return;
   const int e = j < nM ? mon[j] : cont[j - nM];
-  f0MC[(size_t)t * (nM + nC) + j] = f0[(size_t)e * T + t];
+  const double v = f0[(size_t)e * T + t];
+  f0MC[(size_t)t * (nM + nC) + j] = v;
+  if (f0M32 && j < nM) f0M32[(size_t)t * nM + j] = (float)v;
 }
 
 // Contingency-major monitored block: HMC[li][ei] = H[M[ei], C[li]], with the
@@ -366,9 +369,9 @@ hipError_t launch_build_rows(const double* S, const double* b, const double* lim
 }
 
 hipError_t launch_f0_rows(const double* f0, const int* mon, const int* cont, int T, int nM, int nC,
-                          double* f0MC, hipStream_t s) {
+                          double* f0MC, float* f0M32, hipStream_t s) {
   hipLaunchKernelGGL(k_f0_rows, dim3(cdiv(nM + nC, 256), T), dim3(256), 0, s, f0, mon, cont, T,
-                     nM, nC, f0MC);
+                     nM, nC, f0MC, f0M32);
   return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ struct GridLayout {
   double* f0_hi; void* A64; void* PT64; double* part_hi; double* gemm_err;
   // row tables of M then C (see GridDev)
   double* f0MC; double* f0MC_hi; double* bMC; double* limM; double* sllC;
+  float* f0M32;
 };
 
 GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
@@ -96,6 +97,7 @@ GridLayout carve_grid(const tto_grid_desc* d, void* ws, size_t* bytes) {
   const size_t nMC = (size_t)d->n_monitored + d->n_contingency;
   const size_t TTp = tile_T(d->n_timesteps);   // rows past T stay zero
   L.f0MC = cv.take<double>(TTp * nMC);
+  L.f0M32 = cv.take<float>(TTp * d->n_monitored);
   L.bMC = cv.take<double>(nMC);
   L.limM = cv.take<double>(d->n_monitored);
   L.sllC = cv.take<double>(std::max(d->n_contingency, 1));
@@ -134,7 +136,6 @@ SweepBufs<F> carve_batch(int B, int nM, int nC, int TT, void* ws, size_t* bytes)
   SweepBufs<F> w;
   w.n_eblk = (nM + 63) / 64;
   w.info = cv.take<CandInfo>(B);
-  w.fM = cv.take<F>((size_t)B * nM * TT);
   w.UM = cv.take<F>((size_t)B * nM * kVSlots);
   w.rec = cv.take<F>((size_t)B * (nC + 1) * rec_stride(TT));
   w.act = cv.take<int>((size_t)B * (nC + 1));
@@ -324,6 +325,7 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   const size_t nMC = (size_t)d->n_monitored + d->n_contingency;
   HIP_TRY(hipMemsetAsync(L.f0, 0, sizeof(double) * m * d->n_timesteps, s));
   HIP_TRY(hipMemsetAsync(L.f0MC, 0, sizeof(double) * nMC * tile_T(d->n_timesteps), s));
+  HIP_TRY(hipMemsetAsync(L.f0M32, 0, sizeof(float) * d->n_monitored * tile_T(d->n_timesteps), s));
   if (L.f0_hi) {
     HIP_TRY(hipMemsetAsync(L.f0_hi, 0, sizeof(double) * m * d->n_timesteps, s));
     HIP_TRY(hipMemsetAsync(L.f0MC_hi, 0, sizeof(double) * nMC * tile_T(d->n_timesteps), s));
@@ -349,7 +351,7 @@ tto_status tto_grid_create(const tto_grid_desc* d, void* grid_ws, size_t grid_by
   v.n_bus = n; v.n_branch = m; v.slack = d->slack; v.T = g->T; v.TT = g->TT; v.nM = g->nM; v.nC = g->nC;
   v.from = L.from; v.to = L.to; v.b = L.b; v.lim = L.lim; v.S = L.S; v.SMC = L.SMC;
   v.HMC32 = L.HMC32; v.HMC64 = L.HMC64; v.f0 = L.f0; v.f0_hi = L.f0_hi ? L.f0_hi : L.f0; v.mon = L.mon; v.cont = L.cont;
-  v.f0MC = L.f0MC; v.f0MC_hi = L.f0MC_hi ? L.f0MC_hi : L.f0MC; v.bMC = L.bMC; v.limM = L.limM;
+  v.f0MC = L.f0MC; v.f0MC_hi = L.f0MC_hi ? L.f0MC_hi : L.f0MC; v.f0M32 = L.f0M32; v.bMC = L.bMC; v.limM = L.limM;
   v.sllC = L.sllC;
   v.edges = L.edges; v.n_count_bins = 32; v.n_load_bins = 32; v.w_c0 = 200.0; v.w_c = 50.0;
   v.desc_kind = TTO_DESC_COUNT_LOAD;
@@ -395,13 +397,15 @@ tto_status tto_set_injections(tto_grid* g, const double* p_mw, void* stream) {
   HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, g->gemm_prec, g->L.PT, s));
   HIP_TRY(launch_gemm_f0(g->gemm_prec, g->L.A, g->L.PT, g->m, g->n_bus, g->T, g->L.ksplit,
                          g->L.part32, g->L.part64, g->L.f0, s));
-  HIP_TRY(launch_f0_rows(g->L.f0, g->L.mon, g->L.cont, g->T, g->nM, g->nC, g->L.f0MC, s));
+  HIP_TRY(launch_f0_rows(g->L.f0, g->L.mon, g->L.cont, g->T, g->nM, g->nC, g->L.f0MC, g->L.f0M32,
+                         s));
   if (g->L.f0_hi) {
     HIP_TRY(launch_pack_injections(p_mw, g->n_bus, g->T, TTO_GEMM_F64, g->L.PT64, s));
     HIP_TRY(launch_gemm_f0(TTO_GEMM_F64, g->L.A64, g->L.PT64, g->m, g->n_bus, g->T, g->L.ksplit,
                            nullptr, g->L.part_hi, g->L.f0_hi, s));
     HIP_TRY(launch_max_abs_diff(g->L.f0, g->L.f0_hi, (size_t)g->m * g->T, g->L.gemm_err, s));
-    HIP_TRY(launch_f0_rows(g->L.f0_hi, g->L.mon, g->L.cont, g->T, g->nM, g->nC, g->L.f0MC_hi, s));
+    HIP_TRY(launch_f0_rows(g->L.f0_hi, g->L.mon, g->L.cont, g->T, g->nM, g->nC, g->L.f0MC_hi,
+                           nullptr, s));
   }
   return ok();
 }

@@ -61,6 +61,7 @@ struct GridDev {
   // index so that the lanes of a row loop read them coalesced:
   const double* f0MC;     // [TT][nM + nC] base flows f0 at row j, zero rows past T
   const double* f0MC_hi;  // the same from f0_hi
+  const float* f0M32;     // [TT][nM] f0 of the monitored rows in FP32, zero rows past T
   const double* bMC;      // [nM + nC] susceptance of row j
   const double* limM;     // [nM] limit of M[ei]
   const double* sllC;     // [nC] S_ll of l = C[li]
@@ -142,6 +143,7 @@ struct SetupDesc {
   double LU[kMaxRank][kMaxRank];   // unit L below the diagonal, U on and above
   double inv_diag[kMaxRank];
   double x[32][kMaxRank];          // x(t), zero for t >= T
+  float x32[32][kMaxRank];         // x(t) rounded to FP32 (the FP32 flows' f'_M)
 };
 
 // Per (candidate, monitored block) reduction of the sweep.
@@ -160,7 +162,6 @@ struct Partial {
 template <typename F>
 struct SweepBufs {
   CandInfo* info;   // [B]
-  F* fM;            // [B][nM][TT]
   F* UM;            // [B][8][nM] rank-r factor rows (slots past r not written)
   F* rec;           // [B][(nC+1) rec_stride(TT)]: records at rec_stride_r(TT, r)
   int* act;         // [B][nC+1] contingency index of each record
@@ -189,7 +190,7 @@ hipError_t launch_build_rows(const double* S, const double* b, const double* lim
                              const int* cont, int m, int nM, int nC, double* bMC, double* limM,
                              double* sllC, hipStream_t s);
 hipError_t launch_f0_rows(const double* f0, const int* mon, const int* cont, int T, int nM, int nC,
-                          double* f0MC, hipStream_t s);
+                          double* f0MC, float* f0M32, hipStream_t s);
 hipError_t launch_convert_ptdf(const double* ptdf, int m, int n, int prec, void* out, hipStream_t s);
 hipError_t launch_pack_injections(const double* p, int n, int T, int prec, void* PT, hipStream_t s);
 hipError_t launch_gemm_f0(int prec, const void* A, const void* PT, int m, int n, int T,
