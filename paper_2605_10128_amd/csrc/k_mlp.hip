@@ -315,6 +315,24 @@ __global__ __launch_bounds__(256) void k_chunk_sum(const float* __restrict__ par
   out[j] = s;
 }
 
+// The same sum for few columns and many chunks (the bias gradients): 64
+// columns per workgroup, wave w adds the w-th contiguous quarter of the
+// chunks in order, and the four quarter sums are added in order.
+__global__ __launch_bounds__(256) void k_chunk_sum4(const float* __restrict__ part, int R, int n,
+                                                    float* __restrict__ out) {
+  __shared__ float q[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  const int per = (R + 3) / 4;
+  const int r0 = w * per, r1 = min(R, r0 + per);
+  float s = 0.f;
+  if (j < n)
+    for (int r = r0; r < r1; ++r) s += part[(size_t)r * n + j];
+  q[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < n) out[j] = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
+}
+
 // First-layer weight gradient gW1b[i] = sum of dz1[b] over the samples b
 // whose bit set holds i.  The (bit, sample) pairs are bucketed by bit
 // (count, exclusive scan, fill); each bit's bucket is then put in sample
@@ -718,7 +736,7 @@ template <typename T>
 static void colsum(const T* x, int B, int n, float* part, float* out, hipStream_t s) {
   const int R = cdiv_m(B, kRowChunk);
   hipLaunchKernelGGL((k_colsum_part<T>), dim3(cdiv_m(n, 256), R), dim3(256), 0, s, x, B, n, part);
-  hipLaunchKernelGGL(k_chunk_sum, dim3(cdiv_m(n, 256)), dim3(256), 0, s, part, R, n, out);
+  hipLaunchKernelGGL(k_chunk_sum4, dim3(cdiv_m(n, 64)), dim3(256), 0, s, part, R, n, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,7 +769,7 @@ void mlp_gradients(const MlpDev& p, const MlpBatch& wb, const int* off, const in
   const int R = cdiv_m(B, kRowChunk);
   hipLaunchKernelGGL(k_mlp_out_bwd_w_part, dim3(cdiv_m(H, 256), R), dim3(256), 0, s, wb.h3,
                      wb.dy, B, H, wb.part);
-  hipLaunchKernelGGL(k_chunk_sum, dim3(cdiv_m(2 * H, 256)), dim3(256), 0, s, wb.part, R, 2 * H,
+  hipLaunchKernelGGL(k_chunk_sum4, dim3(cdiv_m(2 * H, 64)), dim3(256), 0, s, wb.part, R, 2 * H,
                      g.W4);
   colsum<float>(wb.dy, B, 2, wb.part, g.b4, s);
   hipLaunchKernelGGL(k_mlp_out_bwd_x, dim3(cdiv_m((long)B * H, 256)), dim3(256), 0, s, wb.h3,
