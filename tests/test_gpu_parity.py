@@ -80,6 +80,35 @@ def test_ragged_splits_with_moved_injection(tto, flow):
     assert st["checked"] >= 25
 
 
+@pytest.mark.parametrize("flow", ["f64", "f32"])
+def test_thirty_timesteps_ranked_against_oracle(tto, flow):
+    """T = 30 (the 32-timestep tile), ranks 0..8 with openings and bus
+    splits, 150 monitored branches (two 64-branch chunks and a ragged third,
+    so both the two-branch and the one-branch waves run): every output and
+    the full N-1 tensor against the oracle; in FP32 the one- and two-branch
+    sweep shapes agree bitwise."""
+    import torch
+    fp = tto.TTO_FLOW_F64 if flow == "f64" else tto.TTO_FLOW_F32
+    w = gg.build_config(3, B=40, n_bus=160, n_branch=360, T=30, n_mon=150, n_cont=150)
+    log(f"[T=30 {flow}] gpu")
+    s, out = _run(w, tto, fp, base_flows=True, fmax=True, n1=True)
+    idx = list(range(w.batch.n_cand))
+    ores = oracle_results(w, idx)
+    tol = TOL_F64 if flow == "f64" else TOL_F32
+    st = compare(w, out, idx, ores, tol, strict_discrete=(flow == "f64"), decision_tol=TOL_F64)
+    log(f"[T=30 {flow}] {st}")
+    assert st["checked"] >= 25
+    if flow == "f32":
+        db = tto.device_batch(w.batch)
+        outs = []
+        for npl in (1, 2):
+            s.set_sweep_plan(256, npl, 1, False)
+            outs.append(to_numpy(s.evaluate(db, fmax=True)))
+            torch.cuda.synchronize()
+        for key in outs[0]:
+            np.testing.assert_array_equal(outs[0][key], outs[1][key], err_msg=key)
+
+
 def test_cfg2_full_batch_sampled_parity(tto):
     """500-bus / 800-branch, 4096 candidates in one launch (FP32 flows); the
     oracle re-solves a sample of candidates spread over the batch."""
