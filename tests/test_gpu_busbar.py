@@ -23,10 +23,10 @@ def _busbars(w, n, seed, include_splits=True):
     return np.array(sorted(pick), dtype=np.int32)
 
 
-def _run(cfg, flow, B, n_bb, move_frac=0.0):
+def _run(cfg, flow, B, n_bb, move_frac=0.0, **over):
     import torch
     from paper_2605_10128_amd import tto
-    w = gg.build_config(cfg, B=B, move_frac=move_frac)
+    w = gg.build_config(cfg, B=B, move_frac=move_frac, **over)
     g = w.grid
     fp = tto.TTO_FLOW_F64 if flow == "f64" else tto.TTO_FLOW_F32
     sess = make_session(w, fp, max_batch=B)
@@ -48,12 +48,20 @@ def _run(cfg, flow, B, n_bb, move_frac=0.0):
         f2.cpu().numpy(), sess, bset
 
 
-@pytest.mark.parametrize("cfg,flow,B,n_bb,move", [(1, "f64", 64, 40, 0.0), (2, "f64", 32, 40, 0.5),
-                                                  (2, "f32", 32, 40, 0.5)])
-def test_busbar_outages_match_oracle(cfg, flow, B, n_bb, move):
+# T = 30 runs the 32-timestep tile with ranks 0..8 on a small grid
+_T30 = dict(n_bus=160, n_branch=360, T=30, n_mon=150, n_cont=150)
+
+
+@pytest.mark.parametrize("cfg,flow,B,n_bb,move,over", [(1, "f64", 64, 40, 0.0, {}),
+                                                       (2, "f64", 32, 40, 0.5, {}),
+                                                       (2, "f32", 32, 40, 0.5, {}),
+                                                       (3, "f64", 24, 30, 0.5, _T30),
+                                                       (3, "f32", 24, 30, 0.5, _T30)])
+def test_busbar_outages_match_oracle(cfg, flow, B, n_bb, move, over):
     tol = TOL_F64 if flow == "f64" else TOL_F32
-    w, buses, pre, pre_n, out, lam, nis, f2, sess, bset = _run(cfg, flow, B, n_bb, move)
-    log(f"[busbar] cfg{cfg} {flow} B={B} |O_b|={len(buses)} lambda_b_pre={pre:.3f} ({pre_n} islanding)")
+    w, buses, pre, pre_n, out, lam, nis, f2, sess, bset = _run(cfg, flow, B, n_bb, move, **over)
+    log(f"[busbar] cfg{cfg} {flow} B={B} T={w.P.shape[1]} |O_b|={len(buses)} "
+        f"lambda_b_pre={pre:.3f} ({pre_n} islanding)")
     empty = oracle.Candidate(opened=[], splits=[], moved_p=[], n_slots_filled=0)
     ref = oracle.busbar_metrics(w.grid, w.P, w.M, empty, buses)
     lim = w.grid.limit_mw[w.M]
