@@ -344,7 +344,11 @@ tto_status tto_profile_read(tto_grid* grid, double* ms);
  *                      takes a contiguous candidate-major range (a
  *                      candidate's waves share its records in one L2); 2:
  *                      chunk-major ranges (an XCD streams few column blocks
- *                      of H[M, C] across many candidates)
+ *                      of H[M, C] across many candidates); 3: as 1, in two
+ *                      passes over the batch, each over one half of every
+ *                      candidate's chunks (half of H in flight: far fewer
+ *                      L2 misses for a little more time; the autotuner,
+ *                      which minimises time, does not try it)
  *   persistent         must be 0: the persistent grid returns
  *                      TTO_E_UNSUPPORTED
  * The 64- and 128-lane workgroups and the persistent grid are switched off:
@@ -377,7 +381,7 @@ tto_status tto_get_sweep_plan(tto_grid* grid, int32_t* lanes, int32_t* branches_
  * Autotuner: times the sweep plans on this batch (three tto_evaluate calls
  * each, median of the sweep stage by HIP events) and keeps the fastest.  The
  * search covers the register tile (1 or 2 monitored branches per lane, 2 on
- * FP32 grids only) x the three item orders, at 256 lanes.  With a
+ * FP32 grids only) x item orders 0, 1 and 2, at 256 lanes.  With a
  * non-empty cache_path, a line "<device> <shape>|<lanes> <branches per lane>
  * <order> <persistent>" is looked up first (no timing when found) and
  * appended after tuning.  chosen (optional, int32[5]) receives lanes,

@@ -1053,6 +1053,13 @@ __device__ __forceinline__ void sweep_wave(const GridDev& g, const SweepBufs<F>&
 // Work item u of a sweep: (candidate, wave block) in the plan's order.
 __device__ __forceinline__ void sweep_item(int u, int nc, int n_wb, int order, int* c, int* wb) {
   if (order == 2) { *wb = u / nc; *c = u - *wb * nc; }
+  else if (order == 3) {
+    // two passes over the batch, each candidate-major over one half of the
+    // wave blocks
+    const int h0 = (n_wb + 1) >> 1, h1 = n_wb - h0;
+    if (u < nc * h0) { *c = u / h0; *wb = u - *c * h0; }
+    else { const int v = u - nc * h0; *c = v / h1; *wb = h0 + v - *c * h1; }
+  }
   else { *c = u / n_wb; *wb = u - *c * n_wb; }
 }
 
@@ -1060,7 +1067,9 @@ __device__ __forceinline__ void sweep_item(int u, int nc, int n_wb, int order, i
 // order != 0 remaps workgroup q so that each XCD takes a contiguous range of
 // the item order: order 1 candidate-major (the waves of a candidate share its
 // records in one L2), order 2 block-major (an XCD streams few column blocks
-// of H[M, C] for many candidates).  The grid is a multiple of 8.
+// of H[M, C] for many candidates), order 3 candidate-major over the first
+// half of every candidate's wave blocks and then over the second (half of
+// the H column blocks in flight at a time).  The grid is a multiple of 8.
 template <typename F, int TT, int NPL>
 __global__ __launch_bounds__(256) void k_sweep(GridDev g, SweepBufs<F> w,
                                                const F* __restrict__ HMC,

@@ -574,7 +574,7 @@ static tto_status apply_plan(tto_grid* g, int lanes, int npl, int order, int per
   if (npl != 1 && npl != 2) return fail(TTO_E_INVALID, "branches per lane must be 1 or 2");
   if (npl == 2 && g->flow_prec != TTO_FLOW_F32)
     return fail(TTO_E_UNSUPPORTED, "2 branches per lane need FP32 flows");
-  if (order < 0 || order > 2) return fail(TTO_E_INVALID, "order must be 0, 1 or 2");
+  if (order < 0 || order > 3) return fail(TTO_E_INVALID, "order must be 0, 1, 2 or 3");
   if (persistent != 0 && persistent != 1) return fail(TTO_E_INVALID, "persistent must be 0 or 1");
   // Only 256-lane, non-persistent launches are enabled: an earlier sweep
   // (tiles of 64 or 128 lanes, a persistent grid pulling rank-ordered tiles)

@@ -161,7 +161,7 @@ def test_repeat_runs_bitwise_identical(tto):
 
 
 # (lanes, branches per lane, order, persistent): the enabled launch shapes
-PLANS = [(256, npl, order, False) for npl in (1, 2) for order in (0, 1, 2)]
+PLANS = [(256, npl, order, False) for npl in (1, 2) for order in (0, 1, 2, 3)]
 # Shapes the library refuses (TTO_E_UNSUPPORTED): an earlier sweep in these
 # shapes (64/128-lane tiles, a persistent grid pulling rank-ordered tiles) did
 # not finish within a GPU test's time limit and no cause was found in its
@@ -177,7 +177,7 @@ def test_sweep_plan_arguments_checked(tto):
     w = gg.build_config(1)
     s = make_session(w, tto.TTO_FLOW_F64)
     for plan, code in (((32, 1, 0, 0), tto.TTO_E_INVALID), ((512, 1, 0, 0), tto.TTO_E_INVALID),
-                       ((256, 3, 0, 0), tto.TTO_E_INVALID), ((256, 1, 3, 0), tto.TTO_E_INVALID),
+                       ((256, 3, 0, 0), tto.TTO_E_INVALID), ((256, 1, 4, 0), tto.TTO_E_INVALID),
                        ((256, 1, 0, 2), tto.TTO_E_INVALID), ((256, 2, 0, 0), tto.TTO_E_UNSUPPORTED),
                        *((p, tto.TTO_E_UNSUPPORTED) for p in DISABLED_PLANS if p[1] == 1)):
         with pytest.raises(tto.TTOError) as ei:
